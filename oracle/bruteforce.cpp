@@ -1,0 +1,243 @@
+/*
+ * BRUTE-FORCE CHECKER -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Pins the oracle against the plain definition of persistence. It shares no
+ * code with the oracle: simplices are enumerated from the tetrahedra down
+ * (every face of every Kuhn tetrahedron), not from the oracle's id tables.
+ *
+ *  - bf_diagram: the whole lexicographic filtration (Sec. 2.2), reduced by
+ *    Z2 column reduction (PairSimplices is boundary-matrix reduction,
+ *    Sec. 2.5), with clearing (dimension separability, Sec. 4.1(a)). Pairs
+ *    are reported in vertex-order space: (dim, rank of the birth simplex's
+ *    highest vertex, rank of the death simplex's highest vertex); pairs of
+ *    zero persistence (same highest vertex) are dropped, since the method
+ *    skips exactly those (Sec. 4.1(c)).
+ *  - bf_lower_link_betti: reduced Betti numbers of the lower link of every
+ *    vertex; the expansion-based gradient has exactly that many critical
+ *    cells per dimension in each lower star (Sec. 1.1, Sec. 2.6).
+ *  - bf_counts: numbers of vertices, edges, triangles and tetrahedra.
+ */
+#include <algorithm>
+#include <array>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <set>
+#include <vector>
+
+namespace {
+
+typedef int64_t i64;
+typedef std::array<i64, 4> Verts;  /* ascending vertex ids, padded with -1 at the end */
+
+struct Complex {
+    std::vector<Verts> simp;
+    std::vector<int> dim;
+};
+
+/* Kuhn triangulation: each unit cube is cut into the 6 monotone lattice
+ * paths from its lowest to its highest corner. */
+void tetrahedra(i64 nx, i64 ny, i64 nz, std::vector<std::array<i64, 4>>& tets) {
+    const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    tets.clear();
+    for (i64 z = 0; z + 1 < nz; ++z)
+        for (i64 y = 0; y + 1 < ny; ++y)
+            for (i64 x = 0; x + 1 < nx; ++x)
+                for (int p = 0; p < 6; ++p) {
+                    i64 c[3] = {x, y, z};
+                    std::array<i64, 4> t;
+                    t[0] = c[0] + nx * (c[1] + ny * c[2]);
+                    for (int s = 0; s < 3; ++s) {
+                        c[perm[p][s]] += 1;
+                        t[s + 1] = c[0] + nx * (c[1] + ny * c[2]);
+                    }
+                    std::sort(t.begin(), t.end());
+                    tets.push_back(t);
+                }
+}
+
+void all_simplices(i64 nx, i64 ny, i64 nz, Complex& K) {
+    std::vector<std::array<i64, 4>> tets;
+    tetrahedra(nx, ny, nz, tets);
+    std::set<Verts> seen;
+    for (auto& t : tets)
+        for (int m = 1; m < 16; ++m) {
+            Verts v = {-1, -1, -1, -1};
+            int k = 0;
+            for (int i = 0; i < 4; ++i)
+                if (m & (1 << i)) v[k++] = t[i];
+            seen.insert(v);
+        }
+    K.simp.assign(seen.begin(), seen.end());
+    K.dim.resize(K.simp.size());
+    for (size_t i = 0; i < K.simp.size(); ++i) {
+        int d = -1;
+        for (int j = 0; j < 4; ++j) d += (K.simp[i][j] >= 0);
+        K.dim[i] = d;
+    }
+}
+
+/* sorted-decreasing ranks padded with -1: the lexicographic comparison */
+std::array<i64, 4> lex_key(const Verts& v, const uint32_t* rank) {
+    std::array<i64, 4> k = {-1, -1, -1, -1};
+    int n = 0;
+    for (int i = 0; i < 4; ++i)
+        if (v[i] >= 0) k[n++] = rank[v[i]];
+    std::sort(k.begin(), k.begin() + n, [](i64 a, i64 b) { return a > b; });
+    return k;
+}
+
+void sym_diff(std::vector<int>& a, const std::vector<int>& b, std::vector<int>& tmp) {
+    tmp.clear();
+    size_t i = 0, j = 0;
+    while (i < a.size() || j < b.size()) {
+        if (j == b.size() || (i < a.size() && a[i] < b[j])) tmp.push_back(a[i++]);
+        else if (i == a.size() || b[j] < a[i]) tmp.push_back(b[j++]);
+        else { ++i; ++j; }
+    }
+    a.swap(tmp);
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t bf_counts(int64_t nx, int64_t ny, int64_t nz, int64_t* counts4) {
+    Complex K;
+    all_simplices(nx, ny, nz, K);
+    for (int d = 0; d < 4; ++d) counts4[d] = 0;
+    for (int d : K.dim) counts4[d]++;
+    return (int64_t)K.simp.size();
+}
+
+/* Output: finite pairs as (dim, birth rank, death rank) triples into pairs
+ * (capacity cap triples), essential classes as (dim, birth rank) into ess
+ * (capacity cap_e). Returns the number of finite pairs with positive
+ * persistence; *n_ess receives the number of essential classes. */
+int64_t bf_diagram(int64_t nx, int64_t ny, int64_t nz, const uint32_t* rank, int64_t* pairs,
+                   int64_t cap, int64_t* ess, int64_t cap_e, int64_t* n_ess) {
+    Complex K;
+    all_simplices(nx, ny, nz, K);
+    const size_t n = K.simp.size();
+    std::vector<std::array<i64, 4>> key(n);
+    for (size_t i = 0; i < n; ++i) key[i] = lex_key(K.simp[i], rank);
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+    std::vector<int> pos(n);
+    for (size_t i = 0; i < n; ++i) pos[order[i]] = (int)i;
+    std::map<Verts, int> index;
+    for (size_t i = 0; i < n; ++i) index[K.simp[i]] = (int)i;
+
+    /* columns in filtration order, rows = filtration positions of facets */
+    std::vector<std::vector<int>> col(n);
+    for (size_t j = 0; j < n; ++j) {
+        int s = order[j];
+        int d = K.dim[s];
+        if (d == 0) continue;
+        for (int drop = 0; drop <= d; ++drop) {
+            Verts f = {-1, -1, -1, -1};
+            int k = 0;
+            for (int i = 0; i <= d; ++i)
+                if (i != drop) f[k++] = K.simp[s][i];
+            col[j].push_back(pos[index.at(f)]);
+        }
+        std::sort(col[j].begin(), col[j].end());
+    }
+    std::vector<int> owner(n, -1);    /* row -> column whose reduced pivot it is */
+    std::vector<char> cleared(n, 0);  /* column known to reduce to zero */
+    std::vector<char> is_birth(n, 0), is_death(n, 0);
+    std::vector<int> tmp;
+    std::vector<std::array<i64, 3>> out;
+    for (int d = 3; d >= 1; --d) {
+        for (size_t j = 0; j < n; ++j) {
+            if (K.dim[order[j]] != d) continue;
+            if (cleared[j]) { col[j].clear(); continue; }
+            std::vector<int>& c = col[j];
+            while (!c.empty() && owner[c.back()] >= 0) sym_diff(c, col[owner[c.back()]], tmp);
+            if (c.empty()) continue;
+            int low = c.back();
+            owner[low] = (int)j;
+            cleared[low] = 1;
+            is_birth[low] = 1;
+            is_death[j] = 1;
+            i64 b = key[order[low]][0], e = key[order[j]][0];
+            if (b != e) out.push_back({d - 1, b, e});
+        }
+    }
+    std::sort(out.begin(), out.end());
+    int64_t m = (int64_t)out.size();
+    for (int64_t i = 0; i < m && i < cap; ++i)
+        for (int k = 0; k < 3; ++k) pairs[i * 3 + k] = out[i][k];
+    std::vector<std::array<i64, 2>> es;
+    for (size_t i = 0; i < n; ++i)
+        if (!is_birth[i] && !is_death[i]) es.push_back({K.dim[order[i]], key[order[i]][0]});
+    std::sort(es.begin(), es.end());
+    *n_ess = (int64_t)es.size();
+    for (size_t i = 0; i < es.size() && (int64_t)i < cap_e; ++i) {
+        ess[i * 2] = es[i][0];
+        ess[i * 2 + 1] = es[i][1];
+    }
+    return m;
+}
+
+/* Reduced Betti numbers (b~_{-1}, b~_0, b~_1, b~_2) of the lower link of
+ * every vertex: the link of x is the set of faces, opposite to x, of the
+ * tetrahedra around x; the lower link keeps those whose vertices are all
+ * lower than x. */
+void bf_lower_link_betti(int64_t nx, int64_t ny, int64_t nz, const uint32_t* rank, int32_t* out) {
+    std::vector<std::array<i64, 4>> tets;
+    tetrahedra(nx, ny, nz, tets);
+    const i64 V = nx * ny * nz;
+    std::vector<std::vector<int>> around(V);
+    for (size_t t = 0; t < tets.size(); ++t)
+        for (int i = 0; i < 4; ++i) around[tets[t][i]].push_back((int)t);
+    for (i64 x = 0; x < V; ++x) {
+        std::set<i64> lv;
+        std::set<std::pair<i64, i64>> le;
+        std::set<std::array<i64, 3>> lt;
+        bool interior = true;
+        i64 c[3] = {x % nx, (x / nx) % ny, x / (nx * ny)};
+        i64 n[3] = {nx, ny, nz};
+        for (int a = 0; a < 3; ++a) interior = interior && c[a] > 0 && c[a] + 1 < n[a];
+        for (int t : around[x]) {
+            std::array<i64, 3> o;
+            int k = 0;
+            for (int i = 0; i < 4; ++i)
+                if (tets[t][i] != x) o[k++] = tets[t][i];
+            bool l[3];
+            for (int i = 0; i < 3; ++i) l[i] = rank[o[i]] < rank[x];
+            for (int i = 0; i < 3; ++i)
+                if (l[i]) lv.insert(o[i]);
+            for (int i = 0; i < 3; ++i)
+                for (int j = i + 1; j < 3; ++j)
+                    if (l[i] && l[j]) le.insert({o[i], o[j]});
+            if (l[0] && l[1] && l[2]) lt.insert(o);
+        }
+        int32_t* b = out + 4 * x;
+        b[0] = lv.empty() ? 1 : 0;
+        if (lv.empty()) { b[1] = b[2] = b[3] = 0; continue; }
+        std::map<i64, i64> par;
+        for (i64 v : lv) par[v] = v;
+        auto find = [&](i64 v) {
+            while (par[v] != v) v = par[v] = par[par[v]];
+            return v;
+        };
+        i64 comps = (i64)lv.size();
+        for (auto& e : le) {
+            i64 a = find(e.first), bb = find(e.second);
+            if (a != bb) { par[a] = bb; --comps; }
+        }
+        /* whole link of an interior vertex = a 2-sphere: b2 = 1, else 0 */
+        i64 full = 0;
+        for (int t : around[x]) { (void)t; ++full; }
+        int b2 = (interior && (i64)lt.size() == full) ? 1 : 0;
+        i64 chi = (i64)lv.size() - (i64)le.size() + (i64)lt.size();
+        b[1] = (int32_t)(comps - 1);
+        b[2] = (int32_t)(comps - chi + b2);
+        b[3] = b2;
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+"""Shared test helpers: simplex id arithmetic in numpy (written for the tests,
+independent of both the oracle's C++ and the HIP library)."""
+from __future__ import annotations
+
+import numpy as np
+
+NTYPES = (1, 7, 12, 6)
+STEPS = {
+    1: [[1], [2], [3], [4], [5], [6], [7]],
+    2: [[1, 2], [1, 4], [1, 6], [2, 1], [2, 4], [2, 5], [3, 4], [4, 1], [4, 2], [4, 3],
+        [5, 2], [6, 1]],
+    3: [[1, 2, 4], [1, 4, 2], [2, 1, 4], [2, 4, 1], [4, 1, 2], [4, 2, 1]],
+}
+
+
+def coords(shape, v):
+    nz, ny, nx = shape
+    v = np.asarray(v, dtype=np.int64)
+    return np.stack([v % nx, (v // nx) % ny, v // (nx * ny)], axis=-1)
+
+
+def vertices(shape, dim, ids):
+    """(n, dim+1) vertex ids in chain order; -1 rows for ids outside the grid."""
+    nz, ny, nx = shape
+    ids = np.asarray(ids, dtype=np.int64)
+    if dim == 0:
+        return ids[:, None].copy()
+    anchor, typ = ids // NTYPES[dim], ids % NTYPES[dim]
+    c = coords(shape, anchor)
+    out = np.empty((ids.size, dim + 1), dtype=np.int64)
+    out[:, 0] = anchor
+    ok = anchor < nx * ny * nz
+    table = np.array(STEPS[dim])
+    n = np.array([nx, ny, nz])
+    for s in range(dim):
+        m = table[typ, s]
+        for a in range(3):
+            c[:, a] += (m >> a) & 1
+        ok &= (c < n).all(axis=1)
+        out[:, s + 1] = c[:, 0] + nx * (c[:, 1] + ny * c[:, 2])
+    out[~ok] = -1
+    return out
+
+
+def ids_from_vertices(shape, dim, verts):
+    """Inverse of vertices(): rows of ascending vertex ids -> simplex ids."""
+    verts = np.asarray(verts, dtype=np.int64)
+    if dim == 0:
+        return verts[:, 0].copy()
+    lut = {tuple(s): t for t, s in enumerate(STEPS[dim])}
+    c = coords(shape, verts)
+    masks = []
+    for s in range(dim):
+        d = c[:, s + 1] - c[:, s]
+        assert ((d == 0) | (d == 1)).all()
+        masks.append(d[:, 0] | (d[:, 1] << 1) | (d[:, 2] << 2))
+    masks = np.stack(masks, axis=1)
+    typ = np.array([lut[tuple(m)] for m in masks.tolist()], dtype=np.int64)
+    return verts[:, 0] * NTYPES[dim] + typ
+
+
+def facets(shape, dim, ids):
+    """(n, dim+1) facet ids (dropping vertex 0, 1, ...)."""
+    vs = vertices(shape, dim, ids)
+    cols = []
+    for drop in range(dim + 1):
+        keep = [i for i in range(dim + 1) if i != drop]
+        cols.append(ids_from_vertices(shape, dim - 1, vs[:, keep]))
+    return np.stack(cols, axis=1)
+
+
+def existing(shape, dim):
+    nz, ny, nx = shape
+    ids = np.arange(nx * ny * nz * NTYPES[dim], dtype=np.int64)
+    ok = vertices(shape, dim, ids)[:, 0] >= 0
+    return ids[ok]
+
+
+def as_set(rows):
+    return sorted(map(tuple, np.asarray(rows).tolist()))
