@@ -1,0 +1,140 @@
+/*
+ * dms.h -- C ABI of the Discrete Morse Sandwich library for MI355X (gfx950).
+ *
+ * Computes the persistence diagrams D0, D1 and D2 of a piecewise-linear scalar
+ * field on a 3D regular grid, triangulated implicitly (Freudenthal/Kuhn, 6
+ * tetrahedra per cube; Sec. 2.1 of Guillou, Vidal, Tierny, "Discrete Morse
+ * Sandwich"). The problem statement (Sec. 1 and 2.4): a scalar field on the
+ * vertices of a simplicial complex goes in; persistence pairs (birth
+ * p-simplex, death (p+1)-simplex) per dimension come out, plus the classes of
+ * infinite persistence (Sec. 6).
+ *
+ * Conventions (part of the ABI):
+ *  - Vertex id v = x + nx*(y + ny*z), x fastest; a field is float32,
+ *    contiguous, shaped [nz][ny][nx].
+ *  - Vertex order: by (f(v), v), ties broken by the lower id (the paper's
+ *    symbolic perturbation, Sec. 2.1); -0 == +0; NaN is an error.
+ *  - Simplex id = anchor * T_k + type, T = {1, 7, 12, 6} for k = 0..3, the
+ *    anchor being the vertex with the smallest coordinates. A simplex is the
+ *    chain anchor, anchor+s0, anchor+s0+s1, ... with steps given as axis masks
+ *    (bit0 = x, bit1 = y, bit2 = z):
+ *      edges      type t: step (t+1)
+ *      triangles  types 0..11: (1,2) (1,4) (1,6) (2,1) (2,4) (2,5) (3,4) (4,1)
+ *                              (4,2) (4,3) (5,2) (6,1)
+ *      tetrahedra types 0..5:  (1,2,4) (1,4,2) (2,1,4) (2,4,1) (4,1,2) (4,2,1)
+ *  - Pairs are sorted by (birth, death) as int64, classes of infinite
+ *    persistence (death = -1) last.
+ *  - All pointers named d_* are device pointers on the context's device.
+ *    The caller owns them; the library only borrows them for the duration of
+ *    the call's work on the context's stream.
+ *
+ * Errors: every call returns DMS_OK or a negative code; dms_last_error()
+ * returns a text. A context is not thread-safe: use one context per stream.
+ */
+#ifndef DMS_H
+#define DMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dms_ctx dms_ctx;
+
+typedef struct {
+    int32_t nx, ny, nz; /* vertex counts per axis, each >= 2, 12*nx*ny*nz < 2^32 */
+} dms_grid;
+
+typedef struct {
+    int64_t birth, death; /* simplex ids; death = -1 for infinite persistence */
+} dms_pair;
+
+typedef struct {
+    int64_t n_crit[4]; /* critical simplices per dimension (Alg. "Zero-persistence skip") */
+} dms_gradient_info;
+
+typedef struct {
+    /* caller-owned device buffers, one per dimension (D0, D1, D2) */
+    dms_pair* pairs[3];
+    int64_t cap[3];  /* capacity in pairs */
+    int64_t n[3];    /* out: pairs written, or required on DMS_E_CAPACITY */
+    /* optional (NULL allowed): highest vertex of birth / death simplex (-1 for
+       infinite death) and its value (infinite death: the maximum of f, Sec. 6) */
+    int64_t* birth_vertex[3];
+    int64_t* death_vertex[3];
+    float* birth_value[3];
+    float* death_value[3];
+} dms_diagram_out;
+
+enum {
+    DMS_OK = 0,
+    DMS_E_INVAL = -1,    /* bad argument (grid too small or too large, NULL)        */
+    DMS_E_NAN = -2,      /* the field holds a NaN                                    */
+    DMS_E_NOMEM = -3,    /* the hbm_budget_bytes of the context would be exceeded    */
+    DMS_E_CAPACITY = -4, /* an output buffer is too small; n[] holds the need        */
+    DMS_E_HIP = -5,      /* a HIP runtime call failed                                */
+    DMS_E_STATE = -6,    /* calls out of order (pairs before gradient, D1 before D0/D2) */
+    DMS_E_INTERNAL = -7  /* an internal consistency check failed                     */
+};
+
+enum {
+    DMS_VIRTUAL_MAX = 1u << 0 /* outside of the domain = one maximum of value +inf
+                                 (Sec. 5.2, domains with boundary); required */
+};
+
+/* Create a context on `device`, enqueuing on `hip_stream` (NULL = the null
+ * stream). hbm_budget_bytes = 0 means no limit. The context owns all internal
+ * device state (order, gradient, critical sets, union-find owners, boundary
+ * heap), which persists from dms_gradient() to the next dms_gradient() /
+ * dms_diagram() or dms_destroy(). */
+int dms_create(dms_ctx** out, int device, void* hip_stream, size_t hbm_budget_bytes);
+void dms_destroy(dms_ctx* ctx);
+const char* dms_last_error(const dms_ctx* ctx);
+
+/* Vertex order (Sec. 2.1), discrete gradient by expansions and critical
+ * simplices sorted by the lexicographic order (Sec. 2.2, 2.6 and Alg.
+ * "Zero-persistence skip"). d_field: nx*ny*nz floats. info may be NULL. */
+int dms_gradient(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t flags, dms_gradient_info* info);
+
+/* D0 (Sec. 5.1) and D2 (Sec. 5.2) from the gradient left by dms_gradient.
+ * Writes the pairs (sorted, infinite classes last) to d0 / d2 (device).
+ * On DMS_E_CAPACITY the required counts are in *n0 / *n2 and nothing is
+ * written. Returns DMS_E_STATE without a prior dms_gradient. */
+int dms_pairs_d0_d2(dms_ctx* ctx, dms_pair* d0, int64_t cap0, int64_t* n0, dms_pair* d2, int64_t cap2,
+                    int64_t* n2);
+
+/* D1 by PairCriticalSimplices on the 2-saddles left unpaired by D2 (Sec. 3
+ * and 4, Alg. "PairCriticalSimplices"), with boundary caching and clearing.
+ * Requires dms_pairs_d0_d2 first (DMS_E_STATE otherwise). */
+int dms_pairs_d1(dms_ctx* ctx, dms_pair* d1, int64_t cap1, int64_t* n1);
+
+/* The whole pipeline: gradient, D0/D2, D1, infinite classes (Sec. 6). */
+int dms_diagram(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t flags, dms_diagram_out* out);
+
+/* Inspection of internal state for tests: copies the device buffer `what`
+ * (see DMS_BUF_*) to host memory `dst` of `cap` bytes; returns the byte
+ * size of the buffer (or a negative error). */
+enum {
+    DMS_BUF_RANK = 0,      /* u32[V] vertex order                                 */
+    DMS_BUF_GRADIENT = 1,  /* u8[26*V] gradient byte planes                       */
+    DMS_BUF_CRIT0 = 2,     /* u32 critical ids sorted by the lexicographic order, */
+    DMS_BUF_CRIT1 = 3,     /*   dimensions 0..3 (2..5)                            */
+    DMS_BUF_CRIT2 = 4,
+    DMS_BUF_CRIT3 = 5,
+    DMS_BUF_ARCS0 = 6,     /* u32[2*n] D0 arcs (rank of minimum a, b) per C1      */
+    DMS_BUF_ARCS2 = 7      /* u32[2*n] D2 arcs (age of maximum a, b), C2 reversed */
+};
+int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap);
+
+/* Milliseconds of the last call's stages, measured with HIP events on the
+ * context's stream: [0] order, [1] gradient+critical, [2] critical sort,
+ * [3] D0+D2, [4] D1, [5] output assembly, [6] total. */
+int dms_stage_ms(const dms_ctx* ctx, float ms[7]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMS_H */

@@ -1,0 +1,60 @@
+// D1: PairCriticalSimplices on the 2-saddles left unpaired by D2.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "dms_device.h"
+
+namespace dms {
+
+struct D1Inputs {
+    GridDev g;
+    const uint8_t* G;
+    const uint32_t* rank;
+    const uint32_t* order;
+    const uint32_t* c1;   // critical edges, ascending
+    int64_t m1;
+    const uint32_t* c2;   // critical triangles, ascending
+    int64_t m2;
+    const uint8_t* paired1;       // per C1 position: paired in D0
+    const uint8_t* paired2_desc;  // per decreasing C2 position: paired in D2
+    int bpr;
+    uint32_t* flags;
+};
+
+struct D1State {
+    void* cols = nullptr;     // u32 unpaired 2-saddles (ascending)
+    size_t cols_cap = 0;
+    void* colflag = nullptr;  // u32 scratch for compaction
+    size_t colflag_cap = 0;
+    void* scanpart = nullptr;
+    size_t scanpart_cap = 0;
+    void* owner1 = nullptr;   // u32[7V] owner column of a critical edge (sparse)
+    size_t owner1_cap = 0;
+    void* bndptr = nullptr;   // u64 per column: published boundary (offset << 24 | length)
+    size_t bndptr_cap = 0;
+    void* heap = nullptr;     // u64 published boundaries (bump allocated)
+    size_t heap_cap = 0;      // bytes
+    void* scratch = nullptr;  // u64 per-thread working heaps
+    size_t scratch_cap = 0;
+    void* ctrs = nullptr;     // u64 counters: [0] heap top, [1] next column
+    int64_t ncols = 0;
+    int64_t work_k = 2048;    // entries per working heap
+    int64_t threads = 32768;
+    size_t bytes = 0;
+    // per-run data for emission
+    GridDev g{};
+    const uint32_t* order = nullptr;
+    int bpr = 1;
+};
+
+int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, std::string& err);
+void d1_emit(D1State& s, int64_t m1, const uint8_t* paired1, const uint32_t* c1, uint64_t* key, uint32_t* death,
+             uint32_t* cnt, hipStream_t st);
+void d1_emit_essential2(D1State& s, int64_t m2, const uint8_t* paired2_desc, const uint32_t* c2, uint64_t* key,
+                        uint32_t* death, uint32_t* cnt, hipStream_t st);
+void d1_free(D1State& s);
+
+}  // namespace dms

@@ -1,0 +1,683 @@
+// C-ABI of the DMS library: context, buffers, stage orchestration.
+// Declarations and the contract of every entry point are in include/dms.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/dms.h"
+#include "dms_internal.h"
+#include "d1.h"
+
+using namespace dms;
+
+namespace {
+
+struct Buf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+enum { EV_START = 0, EV_ORDER, EV_GRAD, EV_SORT, EV_D02, EV_D1, EV_OUT, NEV };
+
+}  // namespace
+
+struct dms_ctx {
+    int device = 0;
+    hipStream_t st = nullptr;
+    size_t budget = 0;
+    size_t used = 0;
+    std::string err;
+    GridDev g{};
+    int bpr = 1;
+    int stage = 0;  // 0: nothing, 1: gradient, 2: D0/D2, 3: D1
+    int64_t ncrit[4] = {0, 0, 0, 0};
+    uint32_t cap[4] = {0, 0, 0, 0};
+    Buf rank, keysA, keysB, valsA, valsB, G, hist, part, flags, counters;
+    Buf cid[4], ck[4], ck2[4];  // unsorted critical ids and keys (hi / lo)
+    Buf csorted[4];             // ids sorted by the lexicographic order
+    uint32_t* order = nullptr;  // rank -> vertex (inside valsA / valsB)
+    // D0 / D2
+    Buf na0, nb0, owner0, bnd0, paired1, na2, nb2, owner2, bnd2, paired2, tet2pos;
+    int64_t n_d0_pairs = 0, n_d2_pairs = 0;
+    // D1
+    D1State d1;
+    // output staging
+    Buf ob, od, okey, ocnt;
+    hipEvent_t ev[NEV] = {};
+    bool ev_ok[NEV] = {};
+    float ms[7] = {0, 0, 0, 0, 0, 0, 0};
+};
+
+namespace {
+
+int fail(dms_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return fail(ctx, DMS_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int ensure(dms_ctx* ctx, Buf& b, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    if (b.cap >= bytes) return DMS_OK;
+    size_t want = bytes + bytes / 8;
+    if (ctx->budget && ctx->used - b.cap + want > ctx->budget) {
+        want = bytes;
+        if (ctx->used - b.cap + want > ctx->budget)
+            return fail(ctx, DMS_E_NOMEM, "HBM budget exceeded (" + std::to_string(ctx->used - b.cap + want) +
+                                              " > " + std::to_string(ctx->budget) + " bytes)");
+    }
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        (void)e;
+        ctx->used -= b.cap;
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, DMS_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    b.cap = want;
+    ctx->used += want;
+    return DMS_OK;
+}
+
+#define ENSURE(buf, bytes)                                   \
+    do {                                                     \
+        int r_ = ensure(ctx, (buf), (size_t)(bytes));        \
+        if (r_ != DMS_OK) return r_;                         \
+    } while (0)
+
+template <typename T>
+T* P(Buf& b) {
+    return (T*)b.p;
+}
+
+void record(dms_ctx* ctx, int i) {
+    if (hipEventRecord(ctx->ev[i], ctx->st) == hipSuccess) ctx->ev_ok[i] = true;
+}
+
+int bits_for(uint64_t v) {
+    int b = 1;
+    while (b < 64 && (v >> b)) ++b;
+    return b;
+}
+
+// ---- output assembly kernels ------------------------------------------------
+constexpr int OB = 256;
+inline unsigned nb_of(int64_t n) { return (unsigned)((n + OB - 1) / OB); }
+
+// D0: paired column j -> (vertex of dying minimum, edge); unowned minima ->
+// infinite classes (key bit 32 set so that they sort last).
+__global__ void k_emit_d0(const uint64_t* bnd, const uint8_t* paired, const uint32_t* order, const uint32_t* c1,
+                          int64_t m1, const uint32_t* c0, const uint32_t* rank, const uint32_t* owner0, int64_t m0,
+                          uint64_t* key, uint32_t* death, uint32_t* cnt) {
+    const int64_t i = (int64_t)blockIdx.x * OB + threadIdx.x;
+    if (i < m1 && paired[i]) {
+        const uint32_t at = atomicAdd(cnt, 1u);
+        key[at] = order[(uint32_t)(bnd[i] >> 32)];
+        death[at] = c1[i];
+    }
+    if (i < m0) {
+        const uint32_t v = c0[i];
+        if (owner0[rank[v]] == EMPTY32) {
+            const uint32_t at = atomicAdd(cnt, 1u);
+            key[at] = (1ull << 32) | v;
+            death[at] = EMPTY32;
+        }
+    }
+}
+
+// D2: paired column j (decreasing triangles) -> (triangle, tet of the pivot age).
+__global__ void k_emit_d2(const uint64_t* bnd, const uint8_t* paired, const uint32_t* c2, int64_t m2,
+                          const uint32_t* c3, int64_t m3, uint64_t* key, uint32_t* death, uint32_t* cnt) {
+    const int64_t j = (int64_t)blockIdx.x * OB + threadIdx.x;
+    if (j >= m2 || !paired[j]) return;
+    const uint32_t pos = (uint32_t)(bnd[j] >> 32);  // 1 = highest maximum
+    const uint32_t at = atomicAdd(cnt, 1u);
+    key[at] = c2[m2 - 1 - j];
+    death[at] = c3[m3 - pos];
+}
+
+__device__ inline int64_t max_vertex_of(const GridDev& g, const uint32_t* rank, int dim, int64_t id) {
+    const int64_t a = id / ntypes(dim);
+    const int t = (int)(id % ntypes(dim));
+    int st[3] = {0, 0, 0};
+    if (dim == 1) st[0] = t + 1;
+    if (dim == 2) { st[0] = tri_step(t, 0); st[1] = tri_step(t, 1); }
+    if (dim == 3) { st[0] = tet_step(t, 0); st[1] = tet_step(t, 1); st[2] = tet_step(t, 2); }
+    int64_t v = a, best = a;
+    for (int s = 0; s < dim; ++s) {
+        v += lin_of_mask(g, st[s]);
+        if (rank[v] > rank[best]) best = v;
+    }
+    return best;
+}
+
+__global__ void k_write_pairs(const uint64_t* key_sorted, const uint32_t* idx, const uint32_t* death, int64_t n,
+                              dms_pair* out, int64_t* bv, int64_t* dv, float* bval, float* dval, GridDev g,
+                              const uint32_t* rank, const float* field, float fmax_dummy, int dim,
+                              const uint32_t* order) {
+    const int64_t i = (int64_t)blockIdx.x * OB + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t k = key_sorted[i];
+    const int64_t b = (int64_t)(k & 0xFFFFFFFFull);
+    const uint32_t d = death[idx[i]];
+    const int64_t dd = d == EMPTY32 ? -1 : (int64_t)d;
+    out[i].birth = b;
+    out[i].death = dd;
+    if (bv || bval) {
+        const int64_t v = max_vertex_of(g, rank, dim, b);
+        if (bv) bv[i] = v;
+        if (bval) bval[i] = field[v];
+    }
+    if (dv || dval) {
+        const int64_t v = dd < 0 ? -1 : max_vertex_of(g, rank, dim + 1, dd);
+        if (dv) dv[i] = v;
+        if (dval) dval[i] = v < 0 ? field[order[g.V - 1]] : field[v];
+    }
+    (void)fmax_dummy;
+}
+
+}  // namespace
+
+// ---- internal helpers used by the entry points --------------------------------
+
+static int sort_ids(dms_ctx* ctx, int d) {
+    const int64_t m = ctx->ncrit[d];
+    hipStream_t st = ctx->st;
+    ENSURE(ctx->csorted[d], 4 * m);
+    if (m == 0) return DMS_OK;
+    ENSURE(ctx->keysA, 8 * m);
+    ENSURE(ctx->keysB, 8 * m);
+    ENSURE(ctx->valsA, 4 * m);
+    ENSURE(ctx->valsB, 4 * m);
+    ENSURE(ctx->hist, 4 * 256 * sort_tiles(m));
+    ENSURE(ctx->part, 4 * scan_part_size(256 * sort_tiles(m)));
+    uint32_t* hist = P<uint32_t>(ctx->hist);
+    uint32_t* part = P<uint32_t>(ctx->part);
+    const int bpr = ctx->bpr;
+    uint32_t* perm = nullptr;
+    if (d == 0) {
+        int r = radix_sort_pairs<uint32_t>(P<uint32_t>(ctx->ck[0]), P<uint32_t>(ctx->valsA), P<uint32_t>(ctx->keysA),
+                                           P<uint32_t>(ctx->valsB), m, 0, bpr, true, hist, part, st);
+        perm = r ? P<uint32_t>(ctx->valsB) : P<uint32_t>(ctx->valsA);
+    } else if (d == 1) {
+        int r = radix_sort_pairs<uint64_t>(P<uint64_t>(ctx->ck[1]), P<uint32_t>(ctx->valsA), P<uint64_t>(ctx->keysA),
+                                           P<uint32_t>(ctx->valsB), m, 0, 2 * bpr, true, hist, part, st);
+        perm = r ? P<uint32_t>(ctx->valsB) : P<uint32_t>(ctx->valsA);
+    } else {
+        // two stable passes: low part first, then high part
+        const bool tri = d == 2;
+        int r;
+        if (tri)
+            r = radix_sort_pairs<uint32_t>(P<uint32_t>(ctx->ck2[2]), P<uint32_t>(ctx->valsA), P<uint32_t>(ctx->keysA),
+                                           P<uint32_t>(ctx->valsB), m, 0, bpr, true, hist, part, st);
+        else
+            r = radix_sort_pairs<uint64_t>(P<uint64_t>(ctx->ck2[3]), P<uint32_t>(ctx->valsA), P<uint64_t>(ctx->keysA),
+                                           P<uint32_t>(ctx->valsB), m, 0, 2 * bpr, true, hist, part, st);
+        uint32_t* p1 = r ? P<uint32_t>(ctx->valsB) : P<uint32_t>(ctx->valsA);
+        uint32_t* p1_other = r ? P<uint32_t>(ctx->valsA) : P<uint32_t>(ctx->valsB);
+        // hi keys in permuted order -> keysB (as u64)
+        gather_u64(P<uint64_t>(ctx->ck[d]), p1, P<uint64_t>(ctx->keysB), m, st);
+        int r2 = radix_sort_pairs<uint64_t>(P<uint64_t>(ctx->keysB), p1, P<uint64_t>(ctx->keysA), p1_other, m, 0,
+                                            2 * bpr, false, hist, part, st);
+        perm = r2 ? p1_other : p1;
+    }
+    gather_u32(P<uint32_t>(ctx->cid[d]), perm, P<uint32_t>(ctx->csorted[d]), m, st);
+    return DMS_OK;
+}
+
+// Sort emitted (key, death) pairs by key and write them out.
+static int finish_pairs(dms_ctx* ctx, int dim, int64_t n, dms_pair* out, int64_t* bv, int64_t* dv, float* bval,
+                        float* dval, const float* field) {
+    hipStream_t st = ctx->st;
+    if (n == 0) return DMS_OK;
+    ENSURE(ctx->hist, 4 * 256 * sort_tiles(n));
+    ENSURE(ctx->part, 4 * scan_part_size(256 * sort_tiles(n)));
+    ENSURE(ctx->keysB, 8 * n);
+    ENSURE(ctx->valsA, 4 * n);
+    ENSURE(ctx->valsB, 4 * n);
+    int r = radix_sort_pairs<uint64_t>(P<uint64_t>(ctx->okey), P<uint32_t>(ctx->valsA), P<uint64_t>(ctx->keysB),
+                                       P<uint32_t>(ctx->valsB), n, 0, 40, true, P<uint32_t>(ctx->hist),
+                                       P<uint32_t>(ctx->part), st);
+    uint64_t* ks = r ? P<uint64_t>(ctx->keysB) : P<uint64_t>(ctx->okey);
+    uint32_t* idx = r ? P<uint32_t>(ctx->valsB) : P<uint32_t>(ctx->valsA);
+    hipLaunchKernelGGL(k_write_pairs, dim3(nb_of(n)), dim3(OB), 0, st, ks, idx, P<uint32_t>(ctx->od), n, out, bv, dv,
+                       bval, dval, ctx->g, P<uint32_t>(ctx->rank), field, 0.0f, dim, ctx->order);
+    return DMS_OK;
+}
+
+static int read_counter(dms_ctx* ctx, uint32_t* host) {
+    HIPCHK(hipMemcpyAsync(host, ctx->ocnt.p, 4, hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    return DMS_OK;
+}
+
+static int check_flags(dms_ctx* ctx) {
+    uint32_t f = 0;
+    HIPCHK(hipMemcpyAsync(&f, ctx->flags.p, 4, hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    if (f & FLAG_NAN) return fail(ctx, DMS_E_NAN, "the scalar field holds a NaN");
+    if (f & FLAG_GUARD) return fail(ctx, DMS_E_INTERNAL, "a pairing loop exceeded its iteration bound");
+    if (f & FLAG_HEAP) return fail(ctx, DMS_E_INTERNAL, "the D1 boundary heap overflowed");
+    return DMS_OK;
+}
+
+extern "C" {
+
+int dms_create(dms_ctx** out, int device, void* hip_stream, size_t hbm_budget_bytes) {
+    if (!out) return DMS_E_INVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return DMS_E_INVAL;
+    if (hipSetDevice(device) != hipSuccess) return DMS_E_HIP;
+    dms_ctx* ctx = new dms_ctx();
+    ctx->device = device;
+    ctx->st = (hipStream_t)hip_stream;
+    ctx->budget = hbm_budget_bytes;
+    for (int i = 0; i < NEV; ++i)
+        if (hipEventCreate(&ctx->ev[i]) != hipSuccess) {
+            delete ctx;
+            return DMS_E_HIP;
+        }
+    int r = ensure(ctx, ctx->flags, 64);
+    if (r == DMS_OK) r = ensure(ctx, ctx->counters, 64);
+    if (r == DMS_OK) r = ensure(ctx, ctx->ocnt, 64);
+    if (r != DMS_OK) {
+        delete ctx;
+        return r;
+    }
+    *out = ctx;
+    return DMS_OK;
+}
+
+void dms_destroy(dms_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->st);
+    Buf* all[] = {&ctx->rank, &ctx->keysA, &ctx->keysB, &ctx->valsA, &ctx->valsB, &ctx->G, &ctx->hist,
+                  &ctx->part, &ctx->flags, &ctx->counters, &ctx->na0, &ctx->nb0, &ctx->owner0, &ctx->bnd0,
+                  &ctx->paired1, &ctx->na2, &ctx->nb2, &ctx->owner2, &ctx->bnd2, &ctx->paired2, &ctx->tet2pos,
+                  &ctx->ob, &ctx->od, &ctx->okey, &ctx->ocnt};
+    for (Buf* b : all)
+        if (b->p) (void)hipFree(b->p);
+    for (int d = 0; d < 4; ++d) {
+        if (ctx->cid[d].p) (void)hipFree(ctx->cid[d].p);
+        if (ctx->ck[d].p) (void)hipFree(ctx->ck[d].p);
+        if (ctx->ck2[d].p) (void)hipFree(ctx->ck2[d].p);
+        if (ctx->csorted[d].p) (void)hipFree(ctx->csorted[d].p);
+    }
+    d1_free(ctx->d1);
+    for (int i = 0; i < NEV; ++i)
+        if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    delete ctx;
+}
+
+const char* dms_last_error(const dms_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+int dms_gradient(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t flags, dms_gradient_info* info) {
+    if (!ctx) return DMS_E_INVAL;
+    if (!d_field) return fail(ctx, DMS_E_INVAL, "d_field is NULL");
+    if (grid.nx < 2 || grid.ny < 2 || grid.nz < 2) return fail(ctx, DMS_E_INVAL, "every grid side must be >= 2");
+    const int64_t V = (int64_t)grid.nx * grid.ny * grid.nz;
+    if (12 * V >= (int64_t)0xFFFFFFFFll) return fail(ctx, DMS_E_INVAL, "grid too large: 12*V must stay below 2^32");
+    if (!(flags & DMS_VIRTUAL_MAX)) return fail(ctx, DMS_E_INVAL, "DMS_VIRTUAL_MAX is required");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->st;
+    ctx->stage = 0;
+    ctx->g.nx = grid.nx;
+    ctx->g.ny = grid.ny;
+    ctx->g.nz = grid.nz;
+    ctx->g.V = V;
+    ctx->g.sy = grid.nx;
+    ctx->g.sz = (int64_t)grid.nx * grid.ny;
+    ctx->bpr = bits_for((uint64_t)(V - 1));
+    for (int i = 0; i < NEV; ++i) ctx->ev_ok[i] = false;
+
+    // ---- a0: vertex order ----
+    ENSURE(ctx->rank, 4 * V);
+    ENSURE(ctx->keysA, 8 * V);
+    ENSURE(ctx->keysB, 8 * V);
+    ENSURE(ctx->valsA, 4 * V);
+    ENSURE(ctx->valsB, 4 * V);
+    ENSURE(ctx->hist, 4 * 256 * sort_tiles(V));
+    ENSURE(ctx->part, 4 * scan_part_size(256 * sort_tiles(V)));
+    HIPCHK(hipMemsetAsync(ctx->flags.p, 0, 64, st));
+    record(ctx, EV_START);
+    float_keys(d_field, V, P<uint32_t>(ctx->keysA), P<uint32_t>(ctx->flags), st);
+    int r = radix_sort_pairs<uint32_t>(P<uint32_t>(ctx->keysA), P<uint32_t>(ctx->valsA), P<uint32_t>(ctx->keysB),
+                                       P<uint32_t>(ctx->valsB), V, 0, 32, true, P<uint32_t>(ctx->hist),
+                                       P<uint32_t>(ctx->part), st);
+    uint32_t* order = r ? P<uint32_t>(ctx->valsB) : P<uint32_t>(ctx->valsA);
+    rank_scatter(order, V, P<uint32_t>(ctx->rank), st);
+    record(ctx, EV_ORDER);
+    // keep the order (rank -> vertex) in a buffer of its own
+    ENSURE(ctx->ob, 4 * V);
+    HIPCHK(hipMemcpyAsync(ctx->ob.p, order, 4 * V, hipMemcpyDeviceToDevice, st));
+    ctx->order = P<uint32_t>(ctx->ob);
+
+    // ---- a1 + a2: gradient and critical cells ----
+    ENSURE(ctx->G, (size_t)PLANES * V);
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        for (int d = 0; d < 4; ++d) {
+            if (ctx->cap[d] == 0) ctx->cap[d] = (uint32_t)std::min<int64_t>(V / (d == 0 || d == 3 ? 4 : 2) + 256,
+                                                                           0xF0000000ll);
+            ENSURE(ctx->cid[d], 4ull * ctx->cap[d]);
+            ENSURE(ctx->ck[d], (d == 0 ? 4ull : 8ull) * ctx->cap[d]);
+            if (d >= 2) ENSURE(ctx->ck2[d], (d == 2 ? 4ull : 8ull) * ctx->cap[d]);
+        }
+        CritLists cl;
+        cl.count = P<uint32_t>(ctx->counters);
+        for (int d = 0; d < 4; ++d) cl.cap[d] = ctx->cap[d];
+        cl.id0 = P<uint32_t>(ctx->cid[0]);
+        cl.key0 = P<uint32_t>(ctx->ck[0]);
+        cl.id1 = P<uint32_t>(ctx->cid[1]);
+        cl.key1 = P<uint64_t>(ctx->ck[1]);
+        cl.id2 = P<uint32_t>(ctx->cid[2]);
+        cl.key2hi = P<uint64_t>(ctx->ck[2]);
+        cl.key2lo = P<uint32_t>(ctx->ck2[2]);
+        cl.id3 = P<uint32_t>(ctx->cid[3]);
+        cl.key3hi = P<uint64_t>(ctx->ck[3]);
+        cl.key3lo = P<uint64_t>(ctx->ck2[3]);
+        HIPCHK(hipMemsetAsync(ctx->counters.p, 0, 16, st));
+        launch_gradient(ctx->g, P<uint32_t>(ctx->rank), P<uint8_t>(ctx->G), ctx->bpr, cl, st);
+        record(ctx, EV_GRAD);
+        uint32_t cnt[4];
+        HIPCHK(hipMemcpyAsync(cnt, ctx->counters.p, 16, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipGetLastError());
+        bool over = false;
+        for (int d = 0; d < 4; ++d) {
+            ctx->ncrit[d] = cnt[d];
+            if (cnt[d] > ctx->cap[d]) {
+                over = true;
+                ctx->cap[d] = cnt[d] + 256;
+            }
+        }
+        if (!over) break;
+        if (attempt == 1) return fail(ctx, DMS_E_INTERNAL, "critical list capacity");
+    }
+    r = check_flags(ctx);
+    if (r != DMS_OK) return r;
+
+    // ---- a3: sort critical simplices by the lexicographic order ----
+    for (int d = 0; d < 4; ++d) {
+        r = sort_ids(ctx, d);
+        if (r != DMS_OK) return r;
+    }
+    record(ctx, EV_SORT);
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    if (info)
+        for (int d = 0; d < 4; ++d) info->n_crit[d] = ctx->ncrit[d];
+    ctx->stage = 1;
+    return DMS_OK;
+}
+
+static int run_d0_d2(dms_ctx* ctx) {
+    hipStream_t st = ctx->st;
+    const int64_t V = ctx->g.V;
+    const int64_t m0 = ctx->ncrit[0], m1 = ctx->ncrit[1], m2 = ctx->ncrit[2], m3 = ctx->ncrit[3];
+    // D0 (Sec. 5.1)
+    ENSURE(ctx->na0, 4 * m1);
+    ENSURE(ctx->nb0, 4 * m1);
+    ENSURE(ctx->owner0, 4 * V);
+    ENSURE(ctx->bnd0, 8 * m1);
+    ENSURE(ctx->paired1, m1);
+    trace_d0(ctx->g, P<uint8_t>(ctx->G), P<uint32_t>(ctx->rank), P<uint32_t>(ctx->csorted[1]), m1,
+             P<uint32_t>(ctx->na0), P<uint32_t>(ctx->nb0), P<uint32_t>(ctx->flags), st);
+    fill_u32(P<uint32_t>(ctx->owner0), EMPTY32, V, st);
+    fill_u64(P<uint64_t>(ctx->bnd0), EMPTY64, m1, st);
+    reduce_pairs(P<uint32_t>(ctx->na0), P<uint32_t>(ctx->nb0), m1, P<uint32_t>(ctx->owner0), P<uint64_t>(ctx->bnd0),
+                 P<uint32_t>(ctx->flags), st);
+    settled_columns(P<uint64_t>(ctx->bnd0), P<uint32_t>(ctx->owner0), m1, P<uint8_t>(ctx->paired1), st);
+    // D2 (Sec. 5.2), virtual maximum = age 0
+    ENSURE(ctx->tet2pos, 4 * 6 * V);
+    ENSURE(ctx->na2, 4 * m2);
+    ENSURE(ctx->nb2, 4 * m2);
+    ENSURE(ctx->owner2, 4 * (m3 + 1));
+    ENSURE(ctx->bnd2, 8 * m2);
+    ENSURE(ctx->paired2, m2);
+    tet_positions(P<uint32_t>(ctx->csorted[3]), m3, P<uint32_t>(ctx->tet2pos), st);
+    trace_d2(ctx->g, P<uint8_t>(ctx->G), P<uint32_t>(ctx->tet2pos), P<uint32_t>(ctx->csorted[2]), m2,
+             P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2), P<uint32_t>(ctx->flags), st);
+    fill_u32(P<uint32_t>(ctx->owner2), EMPTY32, m3 + 1, st);
+    fill_u64(P<uint64_t>(ctx->bnd2), EMPTY64, m2, st);
+    reduce_pairs(P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2), m2, P<uint32_t>(ctx->owner2), P<uint64_t>(ctx->bnd2),
+                 P<uint32_t>(ctx->flags), st);
+    settled_columns(P<uint64_t>(ctx->bnd2), P<uint32_t>(ctx->owner2), m2, P<uint8_t>(ctx->paired2), st);
+    (void)m0;
+    return DMS_OK;
+}
+
+static int emit_d0(dms_ctx* ctx, dms_pair* d0, int64_t cap0, int64_t* n0, int64_t* bv, int64_t* dv, float* bval,
+                   float* dval, const float* field) {
+    hipStream_t st = ctx->st;
+    const int64_t m0 = ctx->ncrit[0], m1 = ctx->ncrit[1];
+    const int64_t cap = m0 + 16;
+    ENSURE(ctx->okey, 8 * cap);
+    ENSURE(ctx->od, 4 * cap);
+    HIPCHK(hipMemsetAsync(ctx->ocnt.p, 0, 4, st));
+    const int64_t n = std::max(m0, m1);
+    if (n > 0)
+        hipLaunchKernelGGL(k_emit_d0, dim3(nb_of(n)), dim3(OB), 0, st, P<uint64_t>(ctx->bnd0),
+                           P<uint8_t>(ctx->paired1), ctx->order, P<uint32_t>(ctx->csorted[1]), m1,
+                           P<uint32_t>(ctx->csorted[0]), P<uint32_t>(ctx->rank), P<uint32_t>(ctx->owner0), m0,
+                           P<uint64_t>(ctx->okey), P<uint32_t>(ctx->od), P<uint32_t>(ctx->ocnt));
+    uint32_t cnt = 0;
+    int r = read_counter(ctx, &cnt);
+    if (r != DMS_OK) return r;
+    *n0 = cnt;
+    if ((int64_t)cnt > cap0) return fail(ctx, DMS_E_CAPACITY, "D0 output buffer too small");
+    return finish_pairs(ctx, 0, cnt, d0, bv, dv, bval, dval, field);
+}
+
+static int emit_d2(dms_ctx* ctx, dms_pair* d2, int64_t cap2, int64_t* n2, int64_t* bv, int64_t* dv, float* bval,
+                   float* dval, const float* field, bool with_essential) {
+    hipStream_t st = ctx->st;
+    const int64_t m2 = ctx->ncrit[2], m3 = ctx->ncrit[3];
+    const int64_t cap = m2 + 16;
+    ENSURE(ctx->okey, 8 * cap);
+    ENSURE(ctx->od, 4 * cap);
+    HIPCHK(hipMemsetAsync(ctx->ocnt.p, 0, 4, st));
+    if (m2 > 0)
+        hipLaunchKernelGGL(k_emit_d2, dim3(nb_of(m2)), dim3(OB), 0, st, P<uint64_t>(ctx->bnd2),
+                           P<uint8_t>(ctx->paired2), P<uint32_t>(ctx->csorted[2]), m2, P<uint32_t>(ctx->csorted[3]),
+                           m3, P<uint64_t>(ctx->okey), P<uint32_t>(ctx->od), P<uint32_t>(ctx->ocnt));
+    if (with_essential) d1_emit_essential2(ctx->d1, m2, P<uint8_t>(ctx->paired2), P<uint32_t>(ctx->csorted[2]),
+                                           P<uint64_t>(ctx->okey), P<uint32_t>(ctx->od), P<uint32_t>(ctx->ocnt), st);
+    uint32_t cnt = 0;
+    int r = read_counter(ctx, &cnt);
+    if (r != DMS_OK) return r;
+    *n2 = cnt;
+    if ((int64_t)cnt > cap2) return fail(ctx, DMS_E_CAPACITY, "D2 output buffer too small");
+    return finish_pairs(ctx, 2, cnt, d2, bv, dv, bval, dval, field);
+}
+
+int dms_pairs_d0_d2(dms_ctx* ctx, dms_pair* d0, int64_t cap0, int64_t* n0, dms_pair* d2, int64_t cap2,
+                    int64_t* n2) {
+    if (!ctx) return DMS_E_INVAL;
+    if (ctx->stage < 1) return fail(ctx, DMS_E_STATE, "dms_pairs_d0_d2 needs dms_gradient first");
+    if (!n0 || !n2) return fail(ctx, DMS_E_INVAL, "n0 / n2 is NULL");
+    HIPCHK(hipSetDevice(ctx->device));
+    int r = run_d0_d2(ctx);
+    if (r != DMS_OK) return r;
+    record(ctx, EV_D02);
+    r = check_flags(ctx);
+    if (r != DMS_OK) return r;
+    ctx->stage = 2;
+    int64_t a = 0, b = 0;
+    int r0 = emit_d0(ctx, d0, cap0, &a, nullptr, nullptr, nullptr, nullptr, nullptr);
+    *n0 = a;
+    if (r0 != DMS_OK && r0 != DMS_E_CAPACITY) return r0;
+    int r2 = emit_d2(ctx, d2, cap2, &b, nullptr, nullptr, nullptr, nullptr, nullptr, false);
+    *n2 = b;
+    if (r2 != DMS_OK && r2 != DMS_E_CAPACITY) return r2;
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    if (r0 == DMS_E_CAPACITY || r2 == DMS_E_CAPACITY) return fail(ctx, DMS_E_CAPACITY, "output buffer too small");
+    return DMS_OK;
+}
+
+static int run_d1(dms_ctx* ctx) {
+    D1Inputs in;
+    in.g = ctx->g;
+    in.G = P<uint8_t>(ctx->G);
+    in.rank = P<uint32_t>(ctx->rank);
+    in.order = ctx->order;
+    in.c1 = P<uint32_t>(ctx->csorted[1]);
+    in.m1 = ctx->ncrit[1];
+    in.c2 = P<uint32_t>(ctx->csorted[2]);
+    in.m2 = ctx->ncrit[2];
+    in.paired1 = P<uint8_t>(ctx->paired1);
+    in.paired2_desc = P<uint8_t>(ctx->paired2);
+    in.bpr = ctx->bpr;
+    in.flags = P<uint32_t>(ctx->flags);
+    std::string err;
+    int r = d1_run(ctx->d1, in, ctx->st, ctx->budget ? ctx->budget - std::min(ctx->budget, ctx->used) : 0, err);
+    if (r != DMS_OK) return fail(ctx, r, err);
+    return DMS_OK;
+}
+
+static int emit_d1(dms_ctx* ctx, dms_pair* d1, int64_t cap1, int64_t* n1, int64_t* bv, int64_t* dv, float* bval,
+                   float* dval, const float* field) {
+    hipStream_t st = ctx->st;
+    const int64_t m1 = ctx->ncrit[1];
+    const int64_t cap = m1 + 16;
+    ENSURE(ctx->okey, 8 * cap);
+    ENSURE(ctx->od, 4 * cap);
+    HIPCHK(hipMemsetAsync(ctx->ocnt.p, 0, 4, st));
+    d1_emit(ctx->d1, m1, P<uint8_t>(ctx->paired1), P<uint32_t>(ctx->csorted[1]), P<uint64_t>(ctx->okey),
+            P<uint32_t>(ctx->od), P<uint32_t>(ctx->ocnt), st);
+    uint32_t cnt = 0;
+    int r = read_counter(ctx, &cnt);
+    if (r != DMS_OK) return r;
+    *n1 = cnt;
+    if ((int64_t)cnt > cap1) return fail(ctx, DMS_E_CAPACITY, "D1 output buffer too small");
+    return finish_pairs(ctx, 1, cnt, d1, bv, dv, bval, dval, field);
+}
+
+int dms_pairs_d1(dms_ctx* ctx, dms_pair* d1, int64_t cap1, int64_t* n1) {
+    if (!ctx) return DMS_E_INVAL;
+    if (ctx->stage < 2) return fail(ctx, DMS_E_STATE, "dms_pairs_d1 needs dms_pairs_d0_d2 first");
+    if (!n1) return fail(ctx, DMS_E_INVAL, "n1 is NULL");
+    HIPCHK(hipSetDevice(ctx->device));
+    int r = run_d1(ctx);
+    if (r != DMS_OK) return r;
+    record(ctx, EV_D1);
+    r = check_flags(ctx);
+    if (r != DMS_OK) return r;
+    ctx->stage = 3;
+    r = emit_d1(ctx, d1, cap1, n1, nullptr, nullptr, nullptr, nullptr, nullptr);
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    return r;
+}
+
+int dms_diagram(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t flags, dms_diagram_out* out) {
+    if (!ctx) return DMS_E_INVAL;
+    if (!out) return fail(ctx, DMS_E_INVAL, "out is NULL");
+    int r = dms_gradient(ctx, d_field, grid, flags, nullptr);
+    if (r != DMS_OK) return r;
+    r = run_d0_d2(ctx);
+    if (r != DMS_OK) return r;
+    record(ctx, EV_D02);
+    r = check_flags(ctx);
+    if (r != DMS_OK) return r;
+    ctx->stage = 2;
+    r = run_d1(ctx);
+    if (r != DMS_OK) return r;
+    record(ctx, EV_D1);
+    r = check_flags(ctx);
+    if (r != DMS_OK) return r;
+    ctx->stage = 3;
+    int64_t n[3] = {0, 0, 0};
+    int rr[3];
+    rr[0] = emit_d0(ctx, out->pairs[0], out->cap[0], &n[0], out->birth_vertex[0], out->death_vertex[0],
+                    out->birth_value[0], out->death_value[0], d_field);
+    rr[1] = emit_d1(ctx, out->pairs[1], out->cap[1], &n[1], out->birth_vertex[1], out->death_vertex[1],
+                    out->birth_value[1], out->death_value[1], d_field);
+    rr[2] = emit_d2(ctx, out->pairs[2], out->cap[2], &n[2], out->birth_vertex[2], out->death_vertex[2],
+                    out->birth_value[2], out->death_value[2], d_field, true);
+    record(ctx, EV_OUT);
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    bool cap_fail = false;
+    for (int d = 0; d < 3; ++d) {
+        out->n[d] = n[d];
+        if (rr[d] == DMS_E_CAPACITY) cap_fail = true;
+        else if (rr[d] != DMS_OK) return rr[d];
+    }
+    if (cap_fail) return fail(ctx, DMS_E_CAPACITY, "an output buffer is too small; n[] holds the need");
+    return DMS_OK;
+}
+
+int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap) {
+    if (!ctx) return DMS_E_INVAL;
+    const int64_t V = ctx->g.V;
+    void* src = nullptr;
+    int64_t bytes = 0;
+    switch (what) {
+        case DMS_BUF_RANK: src = ctx->rank.p; bytes = 4 * V; break;
+        case DMS_BUF_GRADIENT: src = ctx->G.p; bytes = (int64_t)PLANES * V; break;
+        case DMS_BUF_CRIT0: case DMS_BUF_CRIT1: case DMS_BUF_CRIT2: case DMS_BUF_CRIT3: {
+            const int d = what - DMS_BUF_CRIT0;
+            src = ctx->csorted[d].p;
+            bytes = 4 * ctx->ncrit[d];
+            break;
+        }
+        case DMS_BUF_ARCS0: bytes = 8 * ctx->ncrit[1]; break;
+        case DMS_BUF_ARCS2: bytes = 8 * ctx->ncrit[2]; break;
+        default: return fail(ctx, DMS_E_INVAL, "unknown buffer");
+    }
+    if (ctx->stage < 1) return fail(ctx, DMS_E_STATE, "no gradient computed yet");
+    if (!dst) return bytes;
+    if (cap < bytes) return fail(ctx, DMS_E_CAPACITY, "destination too small");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    if (what == DMS_BUF_ARCS0 || what == DMS_BUF_ARCS2) {
+        if (ctx->stage < 2) return fail(ctx, DMS_E_STATE, "no D0/D2 computed yet");
+        const int64_t m = bytes / 8;
+        uint32_t* h = (uint32_t*)dst;
+        Buf& a = what == DMS_BUF_ARCS0 ? ctx->na0 : ctx->na2;
+        Buf& b = what == DMS_BUF_ARCS0 ? ctx->nb0 : ctx->nb2;
+        if (m) {
+            HIPCHK(hipMemcpy(h, a.p, 4 * m, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(h + m, b.p, 4 * m, hipMemcpyDeviceToHost));
+        }
+        return bytes;
+    }
+    if (bytes) HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+    return bytes;
+}
+
+int dms_stage_ms(const dms_ctx* ctx, float ms[7]) {
+    if (!ctx || !ms) return DMS_E_INVAL;
+    const int pairs[6][2] = {{EV_START, EV_ORDER}, {EV_ORDER, EV_GRAD}, {EV_GRAD, EV_SORT},
+                             {EV_SORT, EV_D02},    {EV_D02, EV_D1},     {EV_D1, EV_OUT}};
+    for (int i = 0; i < 6; ++i) {
+        ms[i] = -1.0f;
+        if (ctx->ev_ok[pairs[i][0]] && ctx->ev_ok[pairs[i][1]]) {
+            float t = 0;
+            if (hipEventElapsedTime(&t, ctx->ev[pairs[i][0]], ctx->ev[pairs[i][1]]) == hipSuccess) ms[i] = t;
+        }
+    }
+    ms[6] = -1.0f;
+    int last = -1;
+    for (int i = NEV - 1; i > 0; --i)
+        if (ctx->ev_ok[i]) { last = i; break; }
+    if (ctx->ev_ok[EV_START] && last > 0) {
+        float t = 0;
+        if (hipEventElapsedTime(&t, ctx->ev[EV_START], ctx->ev[last]) == hipSuccess) ms[6] = t;
+    }
+    return DMS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// Device-side definitions shared by the DMS kernels (gfx950).
+//
+// Implicit Freudenthal/Kuhn triangulation of an nx*ny*nz vertex grid (Sec. 2.1
+// of the paper: regular grids are triangulated implicitly, 14-vertex
+// neighbourhood in 3D). Vertex id v = x + nx*(y + ny*z). Every simplex is a
+// chain w0 < w1 < ... < wk inside one unit cube whose steps are non-empty,
+// pairwise disjoint axis sets (3-bit masks: bit0 = x, bit1 = y, bit2 = z).
+// Simplex id = anchor * T_k + type with anchor = w0 and T = {1, 7, 12, 6}.
+//
+// Discrete gradient storage: 26 byte planes of V bytes each, indexed by the
+// anchor vertex: plane 0 = vertices, 1..7 = edge types, 8..19 = triangle
+// types, 20..25 = tetrahedron types. A byte holds the partner of the simplex:
+//   c < 27      partner = cofacet obtained by adding vertex anchor + off27(c),
+//               off27(c) = (c%3-1, c/3%3-1, c/9-1)
+//   0x80 | i    partner = facet obtained by removing the chain vertex i
+//   0xFF        critical simplex
+//   0xFE        no such simplex (it would leave the grid)
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dms {
+
+constexpr int NSLOT = 74;   // cells of the open star of a vertex: 14 + 36 + 24
+constexpr int NNB = 14;     // Freudenthal neighbours
+constexpr uint8_t CODE_CRIT = 0xFF;
+constexpr uint8_t CODE_NONE = 0xFE;
+constexpr int PLANES = 26;
+
+__host__ __device__ constexpr int ntypes(int dim) { return dim == 0 ? 1 : dim == 1 ? 7 : dim == 2 ? 12 : 6; }
+__host__ __device__ constexpr int plane_base(int dim) { return dim == 0 ? 0 : dim == 1 ? 1 : dim == 2 ? 8 : 20; }
+
+// Step tables (axis masks) of each simplex type.
+__host__ __device__ inline int tri_step(int type, int s) {
+    const uint8_t t[12] = {0x21, 0x41, 0x61, 0x12, 0x42, 0x52, 0x43, 0x14, 0x24, 0x34, 0x25, 0x16};
+    return s == 0 ? (t[type] & 15) : (t[type] >> 4);
+}
+__host__ __device__ inline int tet_step(int type, int s) {
+    const uint16_t t[6] = {0x421, 0x241, 0x412, 0x142, 0x214, 0x124};
+    return (t[type] >> (4 * s)) & 15;
+}
+__host__ __device__ inline int tri_type(int a, int b) {
+    // inverse of tri_step: (A, B) -> type, -1 if not a triangle step pair
+    for (int t = 0; t < 12; ++t)
+        if (tri_step(t, 0) == a && tri_step(t, 1) == b) return t;
+    return -1;
+}
+__host__ __device__ inline int tet_type(int a, int b, int c) {
+    for (int t = 0; t < 6; ++t)
+        if (tet_step(t, 0) == a && tet_step(t, 1) == b && tet_step(t, 2) == c) return t;
+    return -1;
+}
+
+struct GridDev {
+    int32_t nx, ny, nz;
+    int64_t V;
+    int64_t sy, sz;  // strides: nx, nx*ny
+};
+
+__device__ inline int64_t lin_of_mask(const GridDev& g, int m) {
+    return (m & 1 ? 1 : 0) + (m & 2 ? g.sy : 0) + (m & 4 ? g.sz : 0);
+}
+
+__device__ inline void coords_of(const GridDev& g, int64_t v, int& x, int& y, int& z) {
+    x = (int)(v % g.nx);
+    int64_t r = v / g.nx;
+    y = (int)(r % g.ny);
+    z = (int)(r / g.ny);
+}
+
+// Does a chain with total step mask `m` starting at (x, y, z) stay in the grid?
+__device__ inline bool fits(const GridDev& g, int x, int y, int z, int m) {
+    return (x + (m & 1) < g.nx) && (y + ((m >> 1) & 1) < g.ny) && (z + ((m >> 2) & 1) < g.nz);
+}
+
+// off27 code -> linear offset
+__device__ inline int64_t lin27(const GridDev& g, int c) {
+    int dx = c % 3 - 1, dy = (c / 3) % 3 - 1, dz = c / 9 - 1;
+    return dx + dy * g.sy + dz * g.sz;
+}
+
+// Monotone 32-bit key of a float: -0 and +0 collapse, NaN flagged by caller.
+__device__ inline uint32_t float_key(float f) {
+    uint32_t b = __float_as_uint(f);
+    if ((b & 0x7FFFFFFFu) == 0) b = 0;            // -0 -> +0
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ inline bool is_nan_bits(float f) {
+    uint32_t b = __float_as_uint(f);
+    return (b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu) != 0;
+}
+
+// ---- star tables (filled on the host at library initialisation) ----------
+// Neighbour n of x: offset nbv[n] = +mask(n+1) for n < 7, -mask(n-6) else.
+// Slot s of the open star: 0..13 edge {x, n}; 14..49 triangle {x, a, b}
+// for the 36 link edges; 50..73 tetrahedron {x, a, b, c} for the 24 link
+// triangles.
+struct StarTables {
+    int8_t nbv[NNB][3];
+    int8_t l27[NNB];          // nbv.x + 3 nbv.y + 9 nbv.z
+    uint16_t lessc[NNB];      // neighbours with a smaller coordinate sum
+    uint8_t cpos_pos[NNB];    // 1 if the coordinate sum of n is > 0 (x precedes n)
+    uint16_t cellnb[NSLOT];   // neighbour set of each slot
+    uint64_t face[NSLOT];     // facets inside the star (slot bitmask, all < 64)
+    uint64_t cof_lo[NSLOT];   // cofacets inside the star, slots 0..63
+    uint16_t cof_hi[NSLOT];   // cofacets, slots 64..73 (bit s-64)
+    uint8_t plane[NSLOT];     // gradient byte plane of the slot's simplex
+    int8_t aoff[NSLOT][3];    // anchor offset relative to x
+    int8_t al27[NSLOT];       // aoff.x + 3 aoff.y + 9 aoff.z
+    uint8_t dim[NSLOT];
+    uint8_t type[NSLOT];
+};
+
+}  // namespace dms

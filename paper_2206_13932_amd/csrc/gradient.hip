@@ -1,0 +1,326 @@
+// Discrete gradient by expansions (ProcessLowerStars, Robins et al.) fused with
+// critical-cell extraction -- the paper's Alg. "Zero-persistence skip" and
+// Sec. 2.6; parallel over vertices as in Sec. 7.2.
+//
+// One lane per vertex x. The lower star L(x) holds the cells of the open star
+// of x whose other vertices are all lower than x. With the lower neighbours
+// relabelled 0..k-1 by rank, a cell of L(x) is the bitmask of its lower
+// neighbours, and the lexicographic order of Sec. 2.2 restricted to L(x) is
+// the integer order of these masks (the highest differing vertex decides; a
+// face is a mask missing only lower bits). Both priority queues are then
+// 74-bit slot sets whose minimum is found by comparing 14-bit keys held in
+// LDS, so the simulation is exact and needs no per-lane heap.
+//
+// Output: gradient byte planes (see dms_device.h) and the critical cells of
+// each dimension appended, with their packed lexicographic keys, to per-
+// dimension lists (one atomic per wavefront and dimension).
+#include "dms_device.h"
+#include "dms_internal.h"
+#include "star_tables.h"
+
+namespace dms {
+
+namespace {
+
+constexpr int GB = 256;  // threads per block
+
+struct LdsTables {
+    uint64_t face[NSLOT];
+    uint64_t cof_lo[NSLOT];
+    uint16_t cof_hi[NSLOT];
+    uint16_t cellnb[NSLOT];
+    uint8_t plane[NSLOT];
+    int8_t al27[NSLOT];
+    int8_t l27[NNB];
+    uint16_t lessc[NNB];
+    uint8_t cpos_pos[NNB];
+    int64_t aofflin[NSLOT];
+};
+
+__device__ inline int popc64(uint64_t v) { return __builtin_popcountll(v); }
+
+__device__ inline uint32_t wave_exclusive(uint32_t v, uint32_t& total) {
+    const int lane = threadIdx.x & 63;
+    uint32_t incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+    }
+    total = __shfl(incl, 63, 64);
+    return incl - v;
+}
+
+// Reserve `cnt` entries of a list: one atomicAdd per wavefront.
+__device__ inline uint32_t wave_reserve(uint32_t cnt, uint32_t* counter) {
+    uint32_t total;
+    uint32_t ex = wave_exclusive(cnt, total);
+    uint32_t base = 0;
+    if ((threadIdx.x & 63) == 63 && total) base = atomicAdd(counter, total);
+    base = __shfl(base, 63, 64);
+    return base + ex;
+}
+
+__global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __restrict__ rank,
+                                                 uint8_t* __restrict__ G, int bpr, CritLists cl) {
+    __shared__ LdsTables T;
+    __shared__ uint16_t skey[NSLOT * GB];
+    __shared__ uint32_t snr[NNB * GB];
+    const int tid = threadIdx.x;
+    // cooperative copy of the star tables into LDS
+    for (int i = tid; i < NSLOT; i += GB) {
+        T.face[i] = kStar.face[i];
+        T.cof_lo[i] = kStar.cof_lo[i];
+        T.cof_hi[i] = kStar.cof_hi[i];
+        T.cellnb[i] = kStar.cellnb[i];
+        T.plane[i] = kStar.plane[i];
+        T.al27[i] = kStar.al27[i];
+        T.aofflin[i] = (int64_t)kStar.aoff[i][0] + kStar.aoff[i][1] * g.sy + kStar.aoff[i][2] * g.sz;
+    }
+    for (int i = tid; i < NNB; i += GB) {
+        T.l27[i] = kStar.l27[i];
+        T.lessc[i] = kStar.lessc[i];
+        T.cpos_pos[i] = kStar.cpos_pos[i];
+    }
+    __syncthreads();
+
+    const int64_t x = (int64_t)blockIdx.x * GB + tid;
+    const bool active = x < g.V;
+    const int64_t V = g.V;
+#define KEY(s) skey[(s) * GB + tid]
+#define NR(n) snr[(n) * GB + tid]
+
+    uint64_t crit_lo = 0;
+    uint32_t crit_hi = 0;
+    bool crit_vertex = false;
+    uint32_t rx = 0;
+    int cx = 0, cy = 0, cz = 0;
+
+    if (active) {
+        coords_of(g, x, cx, cy, cz);
+        rx = rank[x];
+        uint32_t lower = 0;
+        uint32_t r[NNB];
+#pragma unroll
+        for (int n = 0; n < NNB; ++n) {
+            const int dx = kStar.nbv[n][0], dy = kStar.nbv[n][1], dz = kStar.nbv[n][2];
+            const bool in = (unsigned)(cx + dx) < (unsigned)g.nx && (unsigned)(cy + dy) < (unsigned)g.ny &&
+                            (unsigned)(cz + dz) < (unsigned)g.nz;
+            uint32_t rv = 0xFFFFFFFFu;
+            if (in) rv = rank[x + dx + dy * g.sy + dz * g.sz];
+            r[n] = rv;
+            NR(n) = rv;
+            if (in && rv < rx) lower |= 1u << n;
+        }
+        // non-existent simplices anchored at x (upper faces of the grid)
+        if (cx == g.nx - 1 || cy == g.ny - 1 || cz == g.nz - 1) {
+            for (int t = 0; t < 7; ++t)
+                if (!fits(g, cx, cy, cz, t + 1)) G[(int64_t)(1 + t) * V + x] = CODE_NONE;
+            for (int t = 0; t < 12; ++t)
+                if (!fits(g, cx, cy, cz, tri_step(t, 0) | tri_step(t, 1))) G[(int64_t)(8 + t) * V + x] = CODE_NONE;
+            for (int t = 0; t < 6; ++t) G[(int64_t)(20 + t) * V + x] = CODE_NONE;
+        }
+        if (lower == 0) {
+            G[x] = CODE_CRIT;  // minimum
+            crit_vertex = true;
+        } else {
+            // relabel the lower neighbours by rank: rel[n] = #lower neighbours below n
+            uint64_t relpack = 0;
+            int n0 = 0;
+#pragma unroll
+            for (int n = 0; n < NNB; ++n) {
+                uint32_t c = 0;
+#pragma unroll
+                for (int m = 0; m < NNB; ++m)
+                    if (m != n) c += ((lower >> m) & 1) && r[m] < r[n];
+                relpack |= (uint64_t)c << (4 * n);
+                if (((lower >> n) & 1) && c == 0) n0 = n;
+            }
+            // cells of L(x) and their keys
+            uint64_t in_lo = 0;
+            uint32_t in_hi = 0;
+#pragma unroll
+            for (int s = 0; s < NSLOT; ++s) {
+                const uint32_t nb = kStar.cellnb[s];
+                const bool inl = (nb & ~lower) == 0;
+                uint32_t key = 0;
+#pragma unroll
+                for (int n = 0; n < NNB; ++n)
+                    if (nb & (1u << n)) key |= 1u << ((relpack >> (4 * n)) & 15);
+                if (inl) {
+                    KEY(s) = (uint16_t)key;
+                    if (s < 64) in_lo |= (uint64_t)1 << s;
+                    else in_hi |= 1u << (s - 64);
+                }
+            }
+            auto anchor = [&](int s) { return x + T.aofflin[s]; };
+            auto gput = [&](int s, uint8_t code) { G[(int64_t)T.plane[s] * V + anchor(s)] = code; };
+            auto unpaired = [&](int s, uint64_t cls_lo) { return popc64(T.face[s] & ~cls_lo); };
+            // pair (p, a): p is a facet of a; w = the neighbour of a not in p
+            auto pair_cells = [&](int p, int a) {
+                const uint32_t w = __builtin_ctz((uint32_t)(T.cellnb[a] & ~T.cellnb[p]));
+                const int pos = __builtin_popcount(T.cellnb[a] & T.lessc[w]) + T.cpos_pos[w];
+                gput(a, (uint8_t)(0x80 | pos));
+                gput(p, (uint8_t)(13 + T.l27[w] - T.al27[p]));
+            };
+            // x pairs with its lowest edge delta = {x, n0}
+            G[x] = (uint8_t)(13 + T.l27[n0]);
+            gput(n0, (uint8_t)(0x80 | T.cpos_pos[n0]));
+            uint64_t cls_lo = (uint64_t)1 << n0;
+            uint32_t cls_hi = 0;
+            uint64_t z_lo = (in_lo & 0x3FFFull) & ~cls_lo;  // other edges
+            uint32_t z_hi = 0;
+            uint64_t o_lo = 0;
+            uint32_t o_hi = 0;
+            auto push_cofaces = [&](int s) {
+                uint64_t c = T.cof_lo[s] & in_lo & ~cls_lo;
+                while (c) {
+                    const int b = __builtin_ctzll(c);
+                    c &= c - 1;
+                    if (unpaired(b, cls_lo) == 1) o_lo |= (uint64_t)1 << b;
+                }
+                uint32_t ch = T.cof_hi[s] & in_hi & ~cls_hi;
+                while (ch) {
+                    const int b = __builtin_ctz(ch);
+                    ch &= ch - 1;
+                    if (unpaired(64 + b, cls_lo) == 1) o_hi |= 1u << b;
+                }
+            };
+            auto pop_min = [&](uint64_t& lo, uint32_t& hi) {
+                int best = -1;
+                uint32_t bk = 0xFFFFFFFFu;
+                uint64_t m = lo;
+                while (m) {
+                    const int s = __builtin_ctzll(m);
+                    m &= m - 1;
+                    const uint32_t k = KEY(s);
+                    if (k < bk) { bk = k; best = s; }
+                }
+                uint32_t h = hi;
+                while (h) {
+                    const int s = 64 + __builtin_ctz(h);
+                    h &= h - 1;
+                    const uint32_t k = KEY(s);
+                    if (k < bk) { bk = k; best = s; }
+                }
+                if (best < 64) lo &= ~((uint64_t)1 << best);
+                else hi &= ~(1u << (best - 64));
+                return best;
+            };
+            push_cofaces(n0);
+            for (int guard = 0; guard < 4 * NSLOT; ++guard) {
+                while (o_lo | o_hi) {
+                    const int a = pop_min(o_lo, o_hi);
+                    const bool done = a < 64 ? ((cls_lo >> a) & 1) : ((cls_hi >> (a - 64)) & 1);
+                    if (done) continue;
+                    const uint64_t u = T.face[a] & ~cls_lo;
+                    if (u == 0) {
+                        if (a < 64) z_lo |= (uint64_t)1 << a;
+                        else z_hi |= 1u << (a - 64);
+                        continue;
+                    }
+                    const int p = __builtin_ctzll(u);
+                    pair_cells(p, a);
+                    cls_lo |= (uint64_t)1 << p;
+                    if (a < 64) cls_lo |= (uint64_t)1 << a;
+                    else cls_hi |= 1u << (a - 64);
+                    z_lo &= ~((uint64_t)1 << p);
+                    push_cofaces(a);
+                    push_cofaces(p);
+                }
+                if (!(z_lo | z_hi)) break;
+                const int c = pop_min(z_lo, z_hi);
+                if (c < 64) { cls_lo |= (uint64_t)1 << c; crit_lo |= (uint64_t)1 << c; }
+                else { cls_hi |= 1u << (c - 64); crit_hi |= 1u << (c - 64); }
+                gput(c, CODE_CRIT);
+                push_cofaces(c);
+            }
+        }
+    }
+
+    // ---- critical-cell lists (all lanes take part in the wave scans) ----
+    const uint64_t E_MASK = 0x3FFFull, T_MASK = ((1ull << 50) - 1) & ~0x3FFFull;
+    const uint64_t Q_LO = ~((1ull << 50) - 1);
+    uint32_t c0 = crit_vertex ? 1 : 0;
+    uint32_t c1 = popc64(crit_lo & E_MASK);
+    uint32_t c2 = popc64(crit_lo & T_MASK);
+    uint32_t c3 = popc64(crit_lo & Q_LO) + __builtin_popcount(crit_hi);
+    {
+        uint32_t at = wave_reserve(c0, &cl.count[0]);
+        if (c0 && at < cl.cap[0]) { cl.id0[at] = (uint32_t)x; cl.key0[at] = rx; }
+    }
+    {
+        uint32_t at = wave_reserve(c1, &cl.count[1]);
+        uint64_t m = crit_lo & E_MASK;
+        while (m) {
+            const int s = __builtin_ctzll(m);
+            m &= m - 1;
+            if (at < cl.cap[1]) {
+                const int64_t a = x + T.aofflin[s];
+                cl.id1[at] = (uint32_t)(a * 7 + (T.plane[s] - 1));
+                cl.key1[at] = ((uint64_t)rx << bpr) | NR(s);
+            }
+            ++at;
+        }
+    }
+    {
+        uint32_t at = wave_reserve(c2, &cl.count[2]);
+        uint64_t m = crit_lo & T_MASK;
+        while (m) {
+            const int s = __builtin_ctzll(m);
+            m &= m - 1;
+            if (at < cl.cap[2]) {
+                const int64_t a = x + T.aofflin[s];
+                cl.id2[at] = (uint32_t)(a * 12 + (T.plane[s] - 8));
+                const uint32_t nb = T.cellnb[s];
+                const int na = __builtin_ctz(nb), nbb = 31 - __builtin_clz(nb);
+                const uint32_t ra = NR(na), rb = NR(nbb);
+                const uint32_t hi = ra > rb ? ra : rb, lo = ra > rb ? rb : ra;
+                cl.key2hi[at] = ((uint64_t)rx << bpr) | hi;
+                cl.key2lo[at] = lo;
+            }
+            ++at;
+        }
+    }
+    {
+        uint32_t at = wave_reserve(c3, &cl.count[3]);
+        uint64_t m = crit_lo & Q_LO;
+        uint32_t h = crit_hi;
+        while (m | h) {
+            int s;
+            if (m) { s = __builtin_ctzll(m); m &= m - 1; }
+            else { s = 64 + __builtin_ctz(h); h &= h - 1; }
+            if (at < cl.cap[3]) {
+                const int64_t a = x + T.aofflin[s];
+                cl.id3[at] = (uint32_t)(a * 6 + (T.plane[s] - 20));
+                uint32_t nb = T.cellnb[s];
+                uint32_t rr[3];
+                for (int i = 0; i < 3; ++i) {
+                    const int n = __builtin_ctz(nb);
+                    nb &= nb - 1;
+                    rr[i] = NR(n);
+                }
+                // sort three ranks descending
+                uint32_t t0 = rr[0], t1 = rr[1], t2 = rr[2], t;
+                if (t0 < t1) { t = t0; t0 = t1; t1 = t; }
+                if (t1 < t2) { t = t1; t1 = t2; t2 = t; }
+                if (t0 < t1) { t = t0; t0 = t1; t1 = t; }
+                cl.key3hi[at] = ((uint64_t)rx << bpr) | t0;
+                cl.key3lo[at] = ((uint64_t)t1 << bpr) | t2;
+            }
+            ++at;
+        }
+    }
+#undef KEY
+#undef NR
+}
+
+}  // namespace
+
+void launch_gradient(const GridDev& g, const uint32_t* rank, uint8_t* G, int bpr, const CritLists& cl,
+                     hipStream_t st) {
+    const int64_t blocks = (g.V + GB - 1) / GB;
+    hipLaunchKernelGGL(k_gradient, dim3((unsigned)blocks), dim3(GB), 0, st, g, rank, G, bpr, cl);
+}
+
+}  // namespace dms

@@ -1,0 +1,232 @@
+// Extremum-saddle pairs: D0 (Sec. 5.1) and D2 (Sec. 5.2).
+//
+// Tracing. D0: each critical edge follows its two descending v-paths (a
+// regular vertex continues through its paired edge) to minima. D2: each
+// critical triangle follows, on both sides, the dual v-path through
+// tetrahedra (a regular tet is left through its paired triangle into the tet
+// on the other side) to a maximum or, across the domain boundary, to the
+// virtual maximum. Each saddle gives an arc (node_a, node_b); node ids are
+// ages: larger id = younger (D0: vertex rank; D2: position in the
+// decreasing list of maxima, 0 = virtual maximum, the oldest).
+//
+// Pairing. Processing the arcs in order with a union-find (younger root
+// dies, older root represents) is the reduction of a boundary matrix whose
+// columns have two entries (the paper derives the union-find from exactly
+// that reduction, Sec. 5.1(c)). It is run lock-free in parallel with the
+// compare-and-swap rule of Sec. 7.2: every column reduces independently; it
+// claims its pivot (younger node) if free, adds the published boundary of an
+// earlier owner, or evicts a later owner and carries on reducing the evicted
+// column. Reduced pivots are unique, so the pairs equal the sequential ones.
+#include "dms_internal.h"
+
+namespace dms {
+
+namespace {
+
+constexpr int PB = 256;
+inline unsigned nblocks(int64_t n) { return (unsigned)((n + PB - 1) / PB); }
+
+constexpr int64_t PATH_GUARD = (int64_t)1 << 22;
+
+__device__ inline int64_t descend(const GridDev& g, const uint8_t* __restrict__ G0, int64_t v, uint32_t* flags) {
+    for (int64_t guard = 0; guard < PATH_GUARD; ++guard) {
+        const uint8_t c = G0[v];
+        if (c >= 27) return v;  // 0xFF: minimum
+        v += lin27(g, c);
+    }
+    atomicOr(flags, FLAG_GUARD);
+    return v;
+}
+
+__global__ void k_trace_d0(GridDev g, const uint8_t* __restrict__ G, const uint32_t* __restrict__ rank,
+                           const uint32_t* __restrict__ c1, int64_t m, uint32_t* __restrict__ na,
+                           uint32_t* __restrict__ nb, uint32_t* flags) {
+    const int64_t j = (int64_t)blockIdx.x * PB + threadIdx.x;
+    if (j >= m) return;
+    const uint32_t e = c1[j];
+    const int64_t a = e / 7;
+    const int64_t b = a + lin_of_mask(g, e % 7 + 1);
+    const int64_t ma = descend(g, G, a, flags), mb = descend(g, G, b, flags);
+    na[j] = rank[ma];
+    nb[j] = rank[mb];
+}
+
+// ---- tetrahedra / triangles in anchor+type form ----------------------------
+struct Simp {
+    int64_t anchor;
+    int type;
+};
+
+__device__ inline bool in_grid(const GridDev& g, int64_t anchor, int mask_total, int neg_mask) {
+    int x, y, z;
+    coords_of(g, anchor, x, y, z);
+    (void)neg_mask;
+    return fits(g, x, y, z, mask_total);
+}
+
+// The two tetrahedra containing triangle (anchor; A, B); ok[i] false if outside.
+__device__ inline void tri_cofacets(const GridDev& g, int64_t anchor, int A, int B, Simp out[2], bool ok[2]) {
+    int x, y, z;
+    coords_of(g, anchor, x, y, z);
+    const int pa = __builtin_popcount(A), pb = __builtin_popcount(B);
+    if (pa + pb == 3) {
+        if (pa == 2) {
+            const int a1 = A & -A, a2 = A ^ a1;
+            out[0] = {anchor, tet_type(a1, a2, B)};
+            out[1] = {anchor, tet_type(a2, a1, B)};
+        } else {
+            const int b1 = B & -B, b2 = B ^ b1;
+            out[0] = {anchor, tet_type(A, b1, b2)};
+            out[1] = {anchor, tet_type(A, b2, b1)};
+        }
+        ok[0] = ok[1] = true;  // same cube as the triangle
+        return;
+    }
+    const int C = 7 ^ (A | B);
+    const int cc[3] = {x, y, z};
+    const int ax = C == 1 ? 0 : C == 2 ? 1 : 2;
+    ok[0] = cc[ax] > 0;
+    out[0] = {anchor - lin_of_mask(g, C), tet_type(C, A, B)};
+    ok[1] = fits(g, x, y, z, 7);
+    out[1] = {anchor, tet_type(A, B, C)};
+}
+
+// Triangle of tet (anchor; s0, s1, s2) opposite chain vertex i.
+__device__ inline void tet_facet(const GridDev& g, int64_t anchor, int type, int i, int64_t& ta, int& A, int& B) {
+    const int s0 = tet_step(type, 0), s1 = tet_step(type, 1), s2 = tet_step(type, 2);
+    ta = anchor;
+    if (i == 0) { ta = anchor + lin_of_mask(g, s0); A = s1; B = s2; }
+    else if (i == 1) { A = s0 | s1; B = s2; }
+    else if (i == 2) { A = s0; B = s1 | s2; }
+    else { A = s0; B = s1; }
+}
+
+__device__ inline uint32_t ascend(const GridDev& g, const uint8_t* __restrict__ G,
+                                  const uint32_t* __restrict__ tet2pos, Simp T, bool ok, uint32_t* flags) {
+    const int64_t V = g.V;
+    for (int64_t guard = 0; ok; ++guard) {
+        if (guard >= PATH_GUARD) {
+            atomicOr(flags, FLAG_GUARD);
+            return 0;
+        }
+        const uint8_t c = G[(int64_t)(20 + T.type) * V + T.anchor];
+        if (c == CODE_CRIT) return tet2pos[T.anchor * 6 + T.type];
+        int64_t ta;
+        int A, B;
+        tet_facet(g, T.anchor, T.type, c & 3, ta, A, B);
+        Simp cf[2];
+        bool cok[2];
+        tri_cofacets(g, ta, A, B, cf, cok);
+        const bool first_is_T = cf[0].anchor == T.anchor && cf[0].type == T.type;
+        const int o = first_is_T ? 1 : 0;
+        ok = cok[o];
+        T = cf[o];
+    }
+    return 0;  // virtual maximum
+}
+
+__global__ void k_trace_d2(GridDev g, const uint8_t* __restrict__ G, const uint32_t* __restrict__ tet2pos,
+                           const uint32_t* __restrict__ c2, int64_t m, uint32_t* __restrict__ na,
+                           uint32_t* __restrict__ nb, uint32_t* flags) {
+    const int64_t j = (int64_t)blockIdx.x * PB + threadIdx.x;
+    if (j >= m) return;
+    const uint32_t t = c2[m - 1 - j];  // decreasing order
+    const int64_t anchor = t / 12;
+    const int type = t % 12;
+    Simp cf[2];
+    bool ok[2];
+    tri_cofacets(g, anchor, tri_step(type, 0), tri_step(type, 1), cf, ok);
+    na[j] = ascend(g, G, tet2pos, cf[0], ok[0], flags);
+    nb[j] = ascend(g, G, tet2pos, cf[1], ok[1], flags);
+}
+
+__global__ void k_tet_positions(const uint32_t* __restrict__ c3, int64_t m, uint32_t* __restrict__ tet2pos) {
+    const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
+    if (i < m) tet2pos[c3[i]] = (uint32_t)(m - i);  // highest tet -> 1
+}
+
+// ---- lock-free two-entry column reduction ----------------------------------
+__device__ inline uint32_t ld_acq(uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint64_t ld_acq64(uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_rel64(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline bool cas32(uint32_t* p, uint32_t expect, uint32_t desired) {
+    return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_reduce_pairs(const uint32_t* __restrict__ na, const uint32_t* __restrict__ nb, int64_t m,
+                               uint32_t* owner, uint64_t* bnd, uint32_t* flags) {
+    const int64_t j = (int64_t)blockIdx.x * PB + threadIdx.x;
+    if (j >= m) return;
+    uint32_t c = (uint32_t)j;
+    uint32_t p = na[j], q = nb[j];
+    if (p < q) { uint32_t t = p; p = q; q = t; }
+    const int64_t limit = (int64_t)1 << 26;
+    for (int64_t guard = 0;; ++guard) {
+        if (guard > limit) { atomicOr(flags, FLAG_GUARD); return; }
+        if (p == q) return;  // column reduced to zero: a positive arc
+        const uint32_t o = ld_acq(&owner[p]);
+        if (o == EMPTY32) {
+            st_rel64(&bnd[c], ((uint64_t)p << 32) | q);
+            if (cas32(&owner[p], EMPTY32, c)) return;
+            continue;
+        }
+        if (o < c) {
+            const uint64_t b = ld_acq64(&bnd[o]);
+            if ((uint32_t)(b >> 32) != p) continue;  // owner moved on; look again
+            const uint32_t r = (uint32_t)b;
+            // {p, q} + {p, r} = {q, r}
+            if (q > r) { p = q; q = r; }
+            else { p = r; }
+            continue;
+        }
+        // o > c: c is earlier and takes the pivot; the evicted column o is
+        // carried on by this thread.
+        st_rel64(&bnd[c], ((uint64_t)p << 32) | q);
+        if (cas32(&owner[p], o, c)) {
+            const uint64_t b = ld_acq64(&bnd[o]);
+            c = o;
+            p = (uint32_t)(b >> 32);
+            q = (uint32_t)b;
+        }
+    }
+}
+
+__global__ void k_settled(const uint64_t* __restrict__ bnd, const uint32_t* __restrict__ owner, int64_t m,
+                          uint8_t* __restrict__ paired) {
+    const int64_t j = (int64_t)blockIdx.x * PB + threadIdx.x;
+    if (j >= m) return;
+    const uint64_t b = bnd[j];
+    paired[j] = (b != EMPTY64 && owner[(uint32_t)(b >> 32)] == (uint32_t)j) ? 1 : 0;
+}
+
+}  // namespace
+
+void trace_d0(const GridDev& g, const uint8_t* G, const uint32_t* rank, const uint32_t* c1, int64_t m,
+              uint32_t* na, uint32_t* nb, uint32_t* flags, hipStream_t st) {
+    if (m > 0) hipLaunchKernelGGL(k_trace_d0, dim3(nblocks(m)), dim3(PB), 0, st, g, G, rank, c1, m, na, nb, flags);
+}
+void tet_positions(const uint32_t* c3_sorted, int64_t m, uint32_t* tet2pos, hipStream_t st) {
+    if (m > 0) hipLaunchKernelGGL(k_tet_positions, dim3(nblocks(m)), dim3(PB), 0, st, c3_sorted, m, tet2pos);
+}
+void trace_d2(const GridDev& g, const uint8_t* G, const uint32_t* tet2pos, const uint32_t* c2_sorted, int64_t m,
+              uint32_t* na, uint32_t* nb, uint32_t* flags, hipStream_t st) {
+    if (m > 0)
+        hipLaunchKernelGGL(k_trace_d2, dim3(nblocks(m)), dim3(PB), 0, st, g, G, tet2pos, c2_sorted, m, na, nb,
+                           flags);
+}
+void reduce_pairs(const uint32_t* na, const uint32_t* nb, int64_t m, uint32_t* owner, uint64_t* bnd,
+                  uint32_t* flags, hipStream_t st) {
+    if (m > 0) hipLaunchKernelGGL(k_reduce_pairs, dim3(nblocks(m)), dim3(PB), 0, st, na, nb, m, owner, bnd, flags);
+}
+void settled_columns(const uint64_t* bnd, const uint32_t* owner, int64_t m, uint8_t* paired, hipStream_t st) {
+    if (m > 0) hipLaunchKernelGGL(k_settled, dim3(nblocks(m)), dim3(PB), 0, st, bnd, owner, m, paired);
+}
+
+}  // namespace dms

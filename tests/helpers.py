@@ -47,15 +47,17 @@ def ids_from_vertices(shape, dim, verts):
     verts = np.asarray(verts, dtype=np.int64)
     if dim == 0:
         return verts[:, 0].copy()
-    lut = {tuple(s): t for t, s in enumerate(STEPS[dim])}
+    lut = np.full(8 ** dim, -1, dtype=np.int64)
+    for t, st in enumerate(STEPS[dim]):
+        lut[sum(m << (3 * i) for i, m in enumerate(st))] = t
     c = coords(shape, verts)
-    masks = []
+    code = np.zeros(len(verts), dtype=np.int64)
     for s in range(dim):
         d = c[:, s + 1] - c[:, s]
         assert ((d == 0) | (d == 1)).all()
-        masks.append(d[:, 0] | (d[:, 1] << 1) | (d[:, 2] << 2))
-    masks = np.stack(masks, axis=1)
-    typ = np.array([lut[tuple(m)] for m in masks.tolist()], dtype=np.int64)
+        code |= (d[:, 0] | (d[:, 1] << 1) | (d[:, 2] << 2)) << (3 * s)
+    typ = lut[code]
+    assert (typ >= 0).all()
     return verts[:, 0] * NTYPES[dim] + typ
 
 
@@ -78,3 +80,43 @@ def existing(shape, dim):
 
 def as_set(rows):
     return sorted(map(tuple, np.asarray(rows).tolist()))
+
+
+PLANE_BASE = (0, 1, 8, 20)
+
+
+def decode_gradient(shape, G):
+    """GPU gradient byte planes (26*V bytes) -> tagged partner ids per
+    dimension, in the oracle's convention (id*4+dim, -1 critical, -2 absent)."""
+    nz, ny, nx = shape
+    V = nx * ny * nz
+    G = np.asarray(G, dtype=np.uint8).reshape(26, V)
+    out = []
+    for dim in range(4):
+        res = np.empty(NTYPES[dim] * V, dtype=np.int64)
+        for t in range(NTYPES[dim]):
+            code = G[PLANE_BASE[dim] + t].astype(np.int64)
+            ids = np.arange(V, dtype=np.int64) * NTYPES[dim] + t
+            r = np.full(V, -3, dtype=np.int64)
+            r[code == 0xFF] = -1
+            r[code == 0xFE] = -2
+            up = code < 27
+            if up.any():
+                vs = vertices(shape, dim, ids[up])
+                a = coords(shape, vs[:, 0])
+                c = code[up]
+                w = a + np.stack([c % 3 - 1, (c // 3) % 3 - 1, c // 9 - 1], axis=1)
+                wid = w[:, 0] + nx * (w[:, 1] + ny * w[:, 2])
+                allv = np.sort(np.concatenate([vs, wid[:, None]], axis=1), axis=1)
+                r[up] = ids_from_vertices(shape, dim + 1, allv) * 4 + dim + 1
+            dn = (code >= 0x80) & (code < 0x84)
+            if dn.any():
+                vs = vertices(shape, dim, ids[dn])
+                i = code[dn] & 3
+                keep = np.ones(vs.shape, dtype=bool)
+                keep[np.arange(len(vs)), i] = False
+                sub = vs[keep].reshape(len(vs), dim)
+                r[dn] = ids_from_vertices(shape, dim - 1, sub) * 4 + dim - 1
+            res[t::NTYPES[dim]] = r
+        out.append(res)
+    return out

@@ -1,0 +1,197 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integer results -- vertex order, gradient, critical sets, arcs and the
+(birth, death) simplex pairs of D0, D1, D2 -- must be bit-identical.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synthfields as sf
+from tests import helpers as H
+
+SMALL_FIELDS = {
+    "noise16_s0": lambda: sf.noise((16, 16, 16), 0),
+    "noise16_s1": lambda: sf.noise((16, 16, 16), 1),
+    "noise16_s2": lambda: sf.noise((16, 16, 16), 2),
+    "noise_aniso": lambda: sf.noise((5, 9, 7), 3),
+    "noise_thin": lambda: sf.noise((2, 2, 9), 4),
+    "noise_slab": lambda: sf.noise((3, 17, 2), 5),
+    "cube2": lambda: np.arange(8, dtype=np.float32)[::-1].reshape(2, 2, 2).copy(),
+    "ties": lambda: np.random.default_rng(6).integers(0, 4, size=(9, 8, 7)).astype(np.float32),
+    "smooth20": lambda: sf.gaussians((20, 22, 18), 7, k=8, noise_frac=0.01),
+    "elevation": lambda: sf.elevation((7, 6, 5)),
+    "radial": lambda: sf.radial((17, 17, 17)),
+    "neg_zero": lambda: np.where(sf.noise((6, 6, 6), 8) < 0.5, np.float32(-0.0), np.float32(0.0)),
+}
+
+
+def _encode_oracle(shape, partner):
+    """Oracle partners -> gradient byte codes (test-side encoder, used to
+    check the decoder on the CPU)."""
+    nz, ny, nx = shape
+    V = nx * ny * nz
+    G = np.zeros((26, V), dtype=np.uint8)
+    for dim in range(4):
+        P = partner[dim]
+        for t in range(H.NTYPES[dim]):
+            ids = np.arange(V) * H.NTYPES[dim] + t
+            p = P[ids]
+            code = np.zeros(V, dtype=np.uint8)
+            code[p == -1] = 0xFF
+            code[p == -2] = 0xFE
+            ok = p >= 0
+            pd, pid = p & 3, p >> 2
+            vs_all = H.vertices(shape, dim, ids)
+            for sel_up in (True, False):
+                sel = ok & ((pd == dim + 1) if sel_up else (pd == dim - 1))
+                if not sel.any():
+                    continue
+                vs = vs_all[sel]
+                ws = H.vertices(shape, pd[sel][0] if False else (dim + 1 if sel_up else dim - 1), pid[sel])
+                if sel_up:
+                    extra = np.array([list(set(w) - set(v))[0] for v, w in zip(vs.tolist(), ws.tolist())])
+                    a = H.coords(shape, vs[:, 0])
+                    e = H.coords(shape, extra)
+                    d = e - a
+                    code[sel] = (13 + d[:, 0] + 3 * d[:, 1] + 9 * d[:, 2]).astype(np.uint8)
+                else:
+                    pos = np.array([[i for i, x in enumerate(v) if x not in set(w)][0]
+                                    for v, w in zip(vs.tolist(), ws.tolist())])
+                    code[sel] = (0x80 | pos).astype(np.uint8)
+            G[H.PLANE_BASE[dim] + t] = code
+    return G
+
+
+def test_gradient_decoder_roundtrip_cpu():
+    f = sf.noise((5, 6, 7), 2)
+    res = oracle.run(f)
+    G = _encode_oracle(res.shape, res.partner)
+    dec = H.decode_gradient(res.shape, G)
+    for d in range(4):
+        assert np.array_equal(dec[d], res.partner[d])
+
+
+def _gpu_ctx():
+    import torch
+    from paper_2206_13932_amd import dms
+    return torch, dms, dms.Context(0)
+
+
+def _check_all(name, f, ctx, torch, dms):
+    print(f"[parity] case={name} shape={f.shape}", flush=True)
+    res = oracle.run(f)
+    ft = torch.from_numpy(f).cuda()
+    ncrit = ctx.gradient(ft)
+    assert ncrit == [len(c) for c in res.crit], name
+    rank = ctx.debug(dms.BUF_RANK)
+    assert np.array_equal(rank, res.rank), name
+    G = ctx.debug(dms.BUF_GRADIENT, np.uint8)
+    dec = H.decode_gradient(res.shape, G)
+    for d in range(4):
+        assert np.array_equal(dec[d], res.partner[d]), (name, d)
+    for d in range(4):
+        got = ctx.debug(dms.BUF_CRIT0 + d).astype(np.int64)
+        assert np.array_equal(got, res.crit[d]), (name, "crit", d)
+    d0, d2 = ctx.pairs_d0_d2()
+    arcs0 = ctx.debug(dms.BUF_ARCS0).reshape(2, -1).T.astype(np.int64)
+    exp0 = res.rank[res.arcs0[:, :2]].astype(np.int64)
+    assert np.array_equal(arcs0, exp0), (name, "arcs0")
+    assert np.array_equal(d0.cpu().numpy(), res.pairs[0]), (name, "D0")
+    exp2 = res.pairs[2][res.pairs[2][:, 1] >= 0]
+    assert np.array_equal(d2.cpu().numpy(), exp2), (name, "D2")
+    d1 = ctx.pairs_d1()
+    assert np.array_equal(d1.cpu().numpy(), res.pairs[1]), (name, "D1")
+    out = ctx.diagram(ft)
+    for d in range(3):
+        assert np.array_equal(out[d].cpu().numpy(), res.pairs[d]), (name, "diagram", d)
+    return res
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", sorted(SMALL_FIELDS))
+def test_parity_small(name):
+    torch, dms, ctx = _gpu_ctx()
+    _check_all(name, SMALL_FIELDS[name](), ctx, torch, dms)
+    ctx.close()
+
+
+@pytest.mark.gpu
+def test_parity_many_noise_seeds_one_context():
+    torch, dms, ctx = _gpu_ctx()
+    for seed in range(10, 26):
+        f = sf.noise((16, 16, 16), seed)
+        res = oracle.run(f)
+        out = ctx.diagram(torch.from_numpy(f).cuda())
+        for d in range(3):
+            assert np.array_equal(out[d].cpu().numpy(), res.pairs[d]), (seed, d)
+    ctx.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape,kind", [((40, 40, 40), "noise"), ((64, 64, 64), "smooth"),
+                                        ((33, 47, 61), "smooth")])
+def test_parity_multi_tile(shape, kind):
+    torch, dms, ctx = _gpu_ctx()
+    f = sf.noise(shape, 9) if kind == "noise" else sf.gaussians(shape, 9, k=16, noise_frac=0.01)
+    _check_all(f"{kind}{shape}", f, ctx, torch, dms)
+    ctx.close()
+
+
+@pytest.mark.gpu
+def test_diagram_values():
+    torch, dms, ctx = _gpu_ctx()
+    f = sf.gaussians((24, 20, 16), 3, k=6, noise_frac=0.01)
+    res = oracle.run(f)
+    out = ctx.diagram(torch.from_numpy(f).cuda(), with_values=True)
+    fv = f.ravel()
+    for d in range(3):
+        o = out[d]
+        p = o["pairs"].cpu().numpy()
+        assert np.array_equal(p, res.pairs[d])
+        bv = oracle.simplex_vertices(res.shape, d, p[:, 0])
+        exp_b = bv[np.arange(len(bv)), res.rank[bv].argmax(axis=1)]
+        assert np.array_equal(o["birth_vertex"].cpu().numpy(), exp_b)
+        assert np.array_equal(o["birth_value"].cpu().numpy(), fv[exp_b])
+        fin = p[:, 1] >= 0
+        dvv = o["death_vertex"].cpu().numpy()
+        assert (dvv[~fin] == -1).all()
+        assert np.array_equal(o["death_value"].cpu().numpy()[~fin], np.full((~fin).sum(), fv.max(), np.float32))
+        if fin.any():
+            dv = oracle.simplex_vertices(res.shape, d + 1, p[fin, 1])
+            exp_d = dv[np.arange(len(dv)), res.rank[dv].argmax(axis=1)]
+            assert np.array_equal(dvv[fin], exp_d)
+    ctx.close()
+
+
+@pytest.mark.gpu
+def test_error_paths():
+    torch, dms, ctx = _gpu_ctx()
+    import ctypes
+    f = torch.from_numpy(sf.noise((6, 6, 6), 0)).cuda()
+    n0, n2 = ctypes.c_int64(), ctypes.c_int64()
+    rc = ctx.lib.dms_pairs_d0_d2(ctx.h, None, 0, ctypes.byref(n0), None, 0, ctypes.byref(n2))
+    assert rc == dms.DMS_E_STATE
+    g = f.clone()
+    g[2, 3, 4] = float("nan")
+    with pytest.raises(dms.DmsError) as e:
+        ctx.gradient(g)
+    assert e.value.code == dms.DMS_E_NAN
+    with pytest.raises(dms.DmsError) as e:
+        ctx.gradient(torch.zeros((1, 5, 5), device="cuda"))
+    assert e.value.code == dms.DMS_E_INVAL
+    ctx.gradient(f)
+    n1 = ctypes.c_int64()
+    rc = ctx.lib.dms_pairs_d1(ctx.h, None, 0, ctypes.byref(n1))
+    assert rc == dms.DMS_E_STATE
+    n0, n2 = ctypes.c_int64(), ctypes.c_int64()
+    buf = torch.empty((1, 2), dtype=torch.int64, device="cuda")
+    rc = ctx.lib.dms_pairs_d0_d2(ctx.h, ctypes.c_void_p(buf.data_ptr()), 1, ctypes.byref(n0),
+                                 ctypes.c_void_p(buf.data_ptr()), 1, ctypes.byref(n2))
+    assert rc == dms.DMS_E_CAPACITY and n0.value > 1
+    ctx.close()
+    small = dms.Context(0, hbm_budget=1 << 16)
+    with pytest.raises(dms.DmsError) as e:
+        small.gradient(torch.from_numpy(sf.noise((32, 32, 32), 0)).cuda())
+    assert e.value.code == dms.DMS_E_NOMEM
+    small.close()
