@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Throughput of the full Discrete Morse Sandwich pipeline (D0 + D1 + D2) on
+one MI355X.
+
+One step = one dms_diagram call on a 512^3 float32 field resident in HBM:
+vertex order, gradient + critical cells, critical sorts, D0/D2, D1 and the
+sorted pair lists in HBM. Prints ONE JSON line (rank 0) with the throughput in
+Mvertices/s, the roofline of the gradient kernel (measured with HIP events on
+the library's stream) and the CPU oracle timed on a bounded crop of the same
+field.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+WORKLOADS = {
+    "smooth512": dict(shape=(512, 512, 512), kind="gaussians", k=64, r=0.005, seed=0,
+                      text="512^3 float32, 64 Gaussians + 0.5% uniform noise, seed 0"),
+    "noise512": dict(shape=(512, 512, 512), kind="noise", seed=0,
+                     text="512^3 float32 i.i.d. uniform noise, seed 0"),
+    "smooth256": dict(shape=(256, 256, 256), kind="gaussians", k=32, r=0.01, seed=0,
+                      text="256^3 float32, 32 Gaussians + 1% uniform noise, seed 0"),
+    "noise256": dict(shape=(256, 256, 256), kind="noise", seed=0,
+                     text="256^3 float32 i.i.d. uniform noise, seed 0"),
+}
+METRIC = "Mvertices/s full D0+D1+D2 (512^3 f32), % HBM peak; served req/s + p99"
+HBM_PEAK_GBS = 8000.0
+
+
+def make_field(name):
+    import synthfields as sf
+    w = WORKLOADS[name]
+    if w["kind"] == "noise":
+        return sf.noise(w["shape"], w["seed"])
+    return sf.gaussians(w["shape"], w["seed"], w["k"], w["r"])
+
+
+def gradient_algorithmic_bytes(V, ncrit):
+    """Bytes the gradient kernel must move: read the order (4 B/vertex; the
+    neighbours come from cache), write the 26 gradient byte planes, append
+    critical ids + packed keys (C0: 4+4, C1: 4+8, C2: 4+8+4, C3: 4+8+8)."""
+    return 4 * V + 26 * V + 8 * ncrit[0] + 12 * ncrit[1] + 16 * ncrit[2] + 20 * ncrit[3]
+
+
+def cpu_baseline(field, crop):
+    import oracle
+    sub = field[:crop, :crop, :crop].copy()
+    t0 = time.perf_counter()
+    oracle.run(sub)
+    dt = time.perf_counter() - t0
+    return {"value": round(sub.size / dt / 1e6, 4), "unit": "Mvertices/s", "cores": 1, "kind": "oracle",
+            "sample": f"sequential oracle, whole pipeline on the {crop}^3 corner crop of the same field "
+                      f"({sub.size} vertices, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="smooth512", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-crop", type=int, default=80)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the method's pipeline is built and measured on a single "
+              f"MI355X (asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2206_13932_amd import dms
+
+    t_gen = time.perf_counter()
+    f = make_field(args.workload)
+    print(f"[bench] workload={args.workload} shape={f.shape} generated in {time.perf_counter() - t_gen:.1f}s",
+          file=sys.stderr, flush=True)
+    V = f.size
+    dev = torch.device("cuda", 0)
+    field = torch.from_numpy(f).to(dev)
+    ctx = dms.Context(0)
+    torch.cuda.synchronize()
+
+    for i in range(args.warmup):
+        ctx.diagram(field)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {i} ms={ctx.stage_ms()}", file=sys.stderr, flush=True)
+
+    grad_ms, stages = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out = ctx.diagram(field)
+        s = ctx.stage_ms()  # events were recorded on the library's stream
+        grad_ms.append(s[7])
+        stages.append(s)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = V / (ms_per_step / 1e3) / 1e6
+
+    ncrit = ctx.gradient(field)  # counts for the byte model (after the timed region)
+    torch.cuda.synchronize()
+    nd = [int(out[d].shape[0]) for d in range(3)]
+    gbytes = gradient_algorithmic_bytes(V, ncrit)
+    g_avg_ms = float(np.mean(grad_ms))
+    achieved = gbytes / (g_avg_ms / 1e3) / 1e9
+    st = np.mean(np.array(stages), axis=0).tolist()
+    print(f"[bench] stage ms (order, gradient+counts, sort, D0D2, D1, output, total, gradient kernel): "
+          f"{[round(x, 3) for x in st]}", file=sys.stderr, flush=True)
+    print(f"[bench] n_crit={ncrit} pairs={nd}", file=sys.stderr, flush=True)
+    ctx.diagram(field)
+    stats = ctx.debug(dms.BUF_STATS, np.uint64).tolist()
+    print(f"[bench] work counters (D0 steps, evictions, D2 steps, evictions, D1 steps, evictions, adds, "
+          f"deferrals, published, restarts): {stats[:10]}; D1 passes (columns, us): {stats[10:20]}",
+          file=sys.stderr, flush=True)
+    lens = (ctx.debug(dms.BUF_D1LEN, np.uint64) & 0xFFFFFF).astype(np.int64)
+    if lens.size:
+        q = np.percentile(lens, [50, 90, 99, 99.9, 100]).tolist()
+        print(f"[bench] D1 cached boundary length p50/p90/p99/p99.9/max: {q}; columns > 1000: "
+              f"{int((lens > 1000).sum())}, > 10000: {int((lens > 10000).sum())}", file=sys.stderr, flush=True)
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Mvertices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]['text']}",
+                   "n_crit": ncrit, "pairs": nd,
+                   "stage_ms": {k: round(v, 3) for k, v in zip(
+                       ["order", "gradient_and_counts", "critical_sort", "d0_d2", "d1", "output", "total",
+                        "gradient_kernel"], st)}},
+        "roofline": {"kernel": "k_gradient", "bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "algorithmic_bytes": int(gbytes),
+                     "avg_kernel_ms": round(g_avg_ms, 4)},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(f, args.cpu_crop)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    main()

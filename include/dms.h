@@ -124,14 +124,21 @@ enum {
     DMS_BUF_CRIT2 = 4,
     DMS_BUF_CRIT3 = 5,
     DMS_BUF_ARCS0 = 6,     /* u32[2*n] D0 arcs (rank of minimum a, b) per C1      */
-    DMS_BUF_ARCS2 = 7      /* u32[2*n] D2 arcs (age of maximum a, b), C2 reversed */
+    DMS_BUF_ARCS2 = 7,     /* u32[2*n] D2 arcs (age of maximum a, b), C2 reversed */
+    DMS_BUF_STATS = 8,     /* u64[32] work counters of the last call: D0 steps,
+                              evictions; D2 steps, evictions; D1 steps, evictions,
+                              boundary additions, deferrals, published entries,
+                              restarts; then per D1 pass (columns, microseconds)  */
+    DMS_BUF_D1LEN = 9      /* u64 per D1 column: last cached boundary
+                              (offset << 24 | length)                             */
 };
 int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap);
 
 /* Milliseconds of the last call's stages, measured with HIP events on the
- * context's stream: [0] order, [1] gradient+critical, [2] critical sort,
- * [3] D0+D2, [4] D1, [5] output assembly, [6] total. */
-int dms_stage_ms(const dms_ctx* ctx, float ms[7]);
+ * context's stream: [0] order, [1] gradient+critical (with the count
+ * read-back), [2] critical sort, [3] D0+D2, [4] D1, [5] output assembly,
+ * [6] total, [7] the gradient kernel alone. -1 for a stage not run. */
+int dms_stage_ms(const dms_ctx* ctx, float ms[8]);
 
 #ifdef __cplusplus
 }

@@ -37,13 +37,19 @@ struct D1State {
     size_t bndptr_cap = 0;
     void* heap = nullptr;     // u64 published boundaries (bump allocated)
     size_t heap_cap = 0;      // bytes
-    void* scratch = nullptr;  // u64 per-thread working heaps
+    void* scratch = nullptr;  // u64 per-thread working heaps (interleaved)
     size_t scratch_cap = 0;
-    void* ctrs = nullptr;     // u64 counters: [0] heap top, [1] next column
+    void* dq = nullptr;       // deferral queues
+    size_t dq_cap = 0;
+    void* ctrs = nullptr;     // u64 counters (heap top, work cursor, deferrals, work counts)
     int64_t ncols = 0;
-    int64_t work_k = 2048;    // entries per working heap
-    int64_t threads = 32768;
     size_t bytes = 0;
+    // last run: [0] loop steps, [1] evictions, [2] cached-boundary additions,
+    // [3] deferrals, [4] published entries, [5] restarts
+    uint64_t stats[6] = {0, 0, 0, 0, 0, 0};
+    // per pass: columns to process, microseconds
+    uint64_t pass_work[5] = {0, 0, 0, 0, 0};
+    uint64_t pass_us[5] = {0, 0, 0, 0, 0};
     // per-run data for emission
     GridDev g{};
     const uint32_t* order = nullptr;

@@ -12,18 +12,25 @@
 //   tau critical, free or owned by a later one   -> cache the boundary and
 //       claim tau with compare-and-swap; a later owner is evicted and its
 //       reduction is carried on by this thread (Sec. 7.2).
-// The boundary is a max-heap in a per-thread global scratch region, with
-// mod-2 cancellation of equal keys when they meet at the top. Cached
-// boundaries are immutable, bump-allocated arrays (sorted decreasing), so a
-// reader that sees tau at their head has a consistent copy.
+// The working boundary is a max-heap in per-thread scratch (interleaved
+// across threads), with mod-2 cancellation of equal keys when they meet at
+// the top. Cached boundaries are immutable arrays (sorted decreasing) bump-
+// allocated from a publication heap and accessed with coherent (agent-scope)
+// loads and stores, so a reader that finds tau at their head has a complete
+// copy. A column whose boundary outgrows its thread's heap is saved to the
+// publication heap and deferred to a later pass with larger heaps and fewer
+// threads; the result does not depend on when a column is processed.
 //
 // The result equals the sequential algorithm: with the expansion-based
-// gradient, the highest edge of a boundary whose top is critical is also
-// the top of its projection onto the Morse complex (all smaller edges of
-// that lower star were classified before the critical one was popped, so
-// their v-paths only reach smaller critical edges); the loop is therefore a
-// column reduction of the Morse boundary matrix, whose pivots do not depend
-// on the order in which earlier columns are added.
+// gradient, the highest edge of a boundary whose top is critical is also the
+// top of its projection onto the Morse complex (all smaller edges of that
+// lower star were classified before the critical one was popped, so their
+// v-paths only reach smaller critical edges); the loop is therefore a column
+// reduction of the Morse boundary matrix, whose pivots do not depend on the
+// order in which earlier columns are added.
+#include <algorithm>
+#include <chrono>
+
 #include "d1.h"
 #include "dms_internal.h"
 
@@ -34,7 +41,11 @@ namespace {
 constexpr int DB = 256;
 constexpr uint32_t OWN_D0 = 0xFFFFFFFEu;
 constexpr uint64_t NONE = ~0ull;
+constexpr int MAX_PASSES = 5;
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + DB - 1) / DB); }
+
+// counters in D1State::ctrs
+enum { C_HEAP = 0, C_NEXT = 1, C_DEFER = 2, C_STEPS = 3, C_EVICT = 4, C_ADDS = 5 };
 
 struct D1K {
     GridDev g;
@@ -43,6 +54,12 @@ struct D1K {
     const uint32_t* order;
     const uint32_t* cols;
     int64_t ncols;
+    // work of this pass: columns 0..ncols-1 (first pass) or deferred records
+    const uint64_t* work;  // (column << 40 | record offset), or null in the first pass
+    const uint32_t* work_len;
+    int64_t nwork;
+    uint64_t* defer;  // deferred (column << 40 | offset) of this pass
+    uint32_t* defer_len;
     int bpr;
     uint32_t* owner1;
     uint64_t* bndptr;
@@ -55,35 +72,38 @@ struct D1K {
     uint32_t* flags;
 };
 
-__device__ inline uint32_t ld_acq(uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ inline uint32_t ld_rlx(uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline uint64_t ld_acq64(uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ inline uint64_t ld_rlx64(const uint64_t* p) {
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline void st_rel64(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ inline void st_rlx64(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ inline void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); /* vmcnt(0) */ }
 __device__ inline bool cas32(uint32_t* p, uint32_t expect, uint32_t desired) {
-    return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+    return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ inline uint64_t ekey(const D1K& P, int64_t a, int64_t b) {
-    const uint32_t ra = P.rank[a], rb = P.rank[b];
-    return ra > rb ? (((uint64_t)ra << P.bpr) | rb) : (((uint64_t)rb << P.bpr) | ra);
+__device__ inline uint64_t ekey_r(int bpr, uint32_t ra, uint32_t rb) {
+    return ra > rb ? (((uint64_t)ra << bpr) | rb) : (((uint64_t)rb << bpr) | ra);
 }
 
 // edge key -> endpoints (va higher), anchor, step mask, id
 struct EdgeDec {
     int64_t va, vb, lo;
+    uint32_t ra, rb;
     int mask;
     uint32_t id;
 };
 __device__ inline EdgeDec edecode(const GridDev& g, const uint32_t* order, int bpr, uint64_t key) {
     EdgeDec e;
-    e.va = order[key >> bpr];
-    e.vb = order[key & ((1ull << bpr) - 1)];
+    e.ra = (uint32_t)(key >> bpr);
+    e.rb = (uint32_t)(key & ((1ull << bpr) - 1));
+    e.va = order[e.ra];
+    e.vb = order[e.rb];
     e.lo = e.va < e.vb ? e.va : e.vb;
     int64_t d = (e.va < e.vb ? e.vb : e.va) - e.lo;
     int m = 0;
@@ -97,38 +117,40 @@ __device__ inline EdgeDec edecode(const GridDev& g, const uint32_t* order, int b
 
 // ---- per-thread max-heap with mod-2 cancellation -----------------------------
 struct Heap {
-    uint64_t* h;
+    uint64_t* base;  // element i at base[i * stride]
+    int64_t stride;
     int64_t n;
     int64_t K;
+    __device__ uint64_t& at(int64_t i) { return base[i * stride]; }
     __device__ void push(uint64_t x) {
         int64_t i = n++;
         while (i > 0) {
             const int64_t p = (i - 1) >> 1;
-            const uint64_t hp = h[p];
+            const uint64_t hp = at(p);
             if (hp >= x) break;
-            h[i] = hp;
+            at(i) = hp;
             i = p;
         }
-        h[i] = x;
+        at(i) = x;
     }
     __device__ uint64_t pop() {
-        const uint64_t top = h[0];
-        const uint64_t x = h[--n];
+        const uint64_t top = at(0);
+        const uint64_t x = at(--n);
         int64_t i = 0;
         for (;;) {
             const int64_t l = 2 * i + 1;
             if (l >= n) break;
             int64_t c = l;
-            uint64_t hc = h[l];
+            uint64_t hc = at(l);
             if (l + 1 < n) {
-                const uint64_t hr = h[l + 1];
+                const uint64_t hr = at(l + 1);
                 if (hr > hc) { c = l + 1; hc = hr; }
             }
             if (hc <= x) break;
-            h[i] = hc;
+            at(i) = hc;
             i = c;
         }
-        if (n > 0) h[i] = x;
+        if (n > 0) at(i) = x;
         return top;
     }
     // highest key present an odd number of times, removed; NONE if empty
@@ -136,7 +158,7 @@ struct Heap {
         while (n > 0) {
             const uint64_t t = pop();
             int cnt = 1;
-            while (n > 0 && h[0] == t) {
+            while (n > 0 && at(0) == t) {
                 pop();
                 ++cnt;
             }
@@ -152,16 +174,15 @@ struct Heap {
         for (;;) {
             const uint64_t t = extract_max();
             if (t == NONE) break;
-            h[n0 - 1 - out] = t;
+            at(n0 - 1 - out) = t;
             ++out;
         }
-        // outputs sit in [n0-out, n0), increasing from left; reverse, then shift
         for (int64_t i = 0; i < out / 2; ++i) {
-            const uint64_t a = h[n0 - out + i];
-            h[n0 - out + i] = h[n0 - 1 - i];
-            h[n0 - 1 - i] = a;
+            const uint64_t a = at(n0 - out + i);
+            at(n0 - out + i) = at(n0 - 1 - i);
+            at(n0 - 1 - i) = a;
         }
-        for (int64_t i = 0; i < out; ++i) h[i] = h[n0 - out + i];
+        for (int64_t i = 0; i < out; ++i) at(i) = at(n0 - out + i);
         n = out;
     }
     __device__ bool room(int64_t extra) {
@@ -171,35 +192,76 @@ struct Heap {
     }
 };
 
+// Copy {top (optional)} + heap (compacted) to the publication heap; returns
+// the packed (offset << 24 | length) or NONE when the heap is full.
+__device__ inline uint64_t publish(const D1K& P, Heap& H, bool with_top, uint64_t top) {
+    H.compact();
+    const uint64_t len = (uint64_t)H.n + (with_top ? 1 : 0);
+    if (len >= (1ull << 24)) return NONE;
+    const uint64_t off = atomicAdd(&P.ctrs[C_HEAP], (unsigned long long)len);
+    if (off + len > P.heap_cap) return NONE;
+    uint64_t* A = P.heap + off;
+    int64_t k = 0;
+    if (with_top) st_rlx64(&A[k++], top);
+    for (int64_t i = 0; i < H.n; ++i) st_rlx64(&A[k++], H.at(i));
+    wait_stores();
+    return (off << 24) | len;
+}
+
+__device__ inline void defer_column(const D1K& P, uint32_t c, uint64_t off, uint64_t len) {
+    const uint64_t d = atomicAdd(&P.ctrs[C_DEFER], 1ull);
+    P.defer[d] = ((uint64_t)c << 40) | off;
+    P.defer_len[d] = (uint32_t)len;
+}
+
 __global__ __launch_bounds__(DB) void k_d1(D1K P) {
     const int64_t tid = (int64_t)blockIdx.x * DB + threadIdx.x;
     if (tid >= P.nthreads) return;  // scratch exists for nthreads lanes only
     Heap H;
-    H.h = P.scratch + tid * P.K;
+    H.base = P.scratch + tid;
+    H.stride = P.nthreads;
     H.K = P.K;
     const int64_t V = P.g.V;
+    unsigned long long steps = 0, evictions = 0, adds = 0;
     for (;;) {
-        const uint64_t next = atomicAdd(&P.ctrs[1], 1ull);
-        if ((int64_t)next >= P.ncols) return;
-        uint32_t c = (uint32_t)next;
+        const uint64_t next = atomicAdd(&P.ctrs[C_NEXT], 1ull);
+        if ((int64_t)next >= P.nwork) break;
+        uint32_t c;
         H.n = 0;
-        {
+        if (!P.work) {
+            c = (uint32_t)next;
             const uint32_t t = P.cols[c];
             const int64_t a = t / 12;
             const int ty = t % 12;
             const int64_t v1 = a + lin_of_mask(P.g, tri_step(ty, 0));
             const int64_t v2 = v1 + lin_of_mask(P.g, tri_step(ty, 1));
-            H.push(ekey(P, a, v1));
-            H.push(ekey(P, v1, v2));
-            H.push(ekey(P, a, v2));
+            const uint32_t r0 = P.rank[a], r1 = P.rank[v1], r2 = P.rank[v2];
+            H.push(ekey_r(P.bpr, r0, r1));
+            H.push(ekey_r(P.bpr, r1, r2));
+            H.push(ekey_r(P.bpr, r0, r2));
+        } else {
+            // resume a deferred column from its saved, decreasing boundary
+            const uint64_t w = P.work[next];
+            c = (uint32_t)(w >> 40);
+            const uint64_t off = w & ((1ull << 40) - 1);
+            const int64_t len = P.work_len[next];
+            if (len > H.K) {
+                atomicOr(P.flags, FLAG_WORK);
+                break;
+            }
+            for (int64_t i = 0; i < len; ++i) H.at(i) = ld_rlx64(P.heap + off + i);
+            H.n = len;
         }
         bool have = false;
         uint64_t tau = 0;
+        bool stop = false;  // leave the thread (error)
         for (int64_t guard = 0;; ++guard) {
             if (guard > ((int64_t)1 << 24)) {
                 atomicOr(P.flags, FLAG_GUARD);
-                return;
+                stop = true;
+                break;
             }
+            ++steps;
             if (!have) {
                 tau = H.extract_max();
                 if (tau == NONE) break;  // zero column
@@ -208,76 +270,96 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
             const EdgeDec e = edecode(P.g, P.order, P.bpr, tau);
             if (e.mask == 0) {  // not an edge: corrupted key
                 atomicOr(P.flags, FLAG_GUARD);
-                return;
+                stop = true;
+                break;
             }
             const uint8_t code = P.G[(int64_t)e.mask * V + e.lo];
+            bool defer = false;
             if (code != CODE_CRIT) {
                 if (code >= 27) {  // the top of a cycle cannot be a vertex's partner
                     atomicOr(P.flags, FLAG_GUARD);
-                    return;
+                    stop = true;
+                    break;
                 }
                 const int64_t w = e.lo + lin27(P.g, code);
-                have = false;  // tau cancels against the boundary of its partner
-                if (!H.room(2)) {
-                    atomicOr(P.flags, FLAG_HEAP);
-                    return;
+                if (H.room(2)) {
+                    have = false;  // tau cancels against the boundary of its partner
+                    const uint32_t rw = P.rank[w];
+                    H.push(ekey_r(P.bpr, e.ra, rw));
+                    H.push(ekey_r(P.bpr, e.rb, rw));
+                    continue;
                 }
-                H.push(ekey(P, e.va, w));
-                H.push(ekey(P, e.vb, w));
-                continue;
-            }
-            const uint32_t o = ld_acq(&P.owner1[e.id]);
-            if (o == OWN_D0) {
-                atomicOr(P.flags, FLAG_GUARD);
-                return;
-            }
-            if (o == EMPTY32 || o > c) {
-                // cache Boundary(c) = {tau} + heap, then claim tau
-                H.compact();
-                const uint64_t len = (uint64_t)H.n + 1;
-                const uint64_t off = atomicAdd(&P.ctrs[0], (unsigned long long)len);
-                if (off + len > P.heap_cap || len >= (1ull << 24)) {
-                    atomicOr(P.flags, FLAG_HEAP);
-                    return;
+                defer = true;
+            } else {
+                const uint32_t o = ld_rlx(&P.owner1[e.id]);
+                if (o == OWN_D0) {
+                    atomicOr(P.flags, FLAG_GUARD);
+                    stop = true;
+                    break;
                 }
-                uint64_t* A = P.heap + off;
-                A[0] = tau;
-                for (int64_t i = 0; i < H.n; ++i) A[i + 1] = H.h[i];
-                st_rel64(&P.bndptr[c], (off << 24) | len);
-                if (!cas32(&P.owner1[e.id], o, c)) continue;  // owner changed: look again
-                if (o == EMPTY32) break;                       // column settled
-                // evicted o: carry on reducing it from its cached boundary
-                const uint64_t b = ld_acq64(&P.bndptr[o]);
+                if (o == EMPTY32 || o > c) {
+                    // cache Boundary(c) = {tau} + heap, then claim tau
+                    const uint64_t b = publish(P, H, true, tau);
+                    if (b == NONE) {
+                        atomicOr(P.flags, FLAG_HEAP);
+                        stop = true;
+                        break;
+                    }
+                    st_rlx64(&P.bndptr[c], b);
+                    wait_stores();
+                    if (!cas32(&P.owner1[e.id], o, c)) continue;  // owner changed: look again
+                    if (o == EMPTY32) break;                       // column settled
+                    // evicted o: carry on reducing it from its cached boundary
+                    ++evictions;
+                    const uint64_t bo = ld_rlx64(&P.bndptr[o]);
+                    const uint64_t* B = P.heap + (bo >> 24);
+                    const int64_t bl = (int64_t)(bo & 0xFFFFFF);
+                    if (ld_rlx64(&B[0]) != tau) {
+                        atomicOr(P.flags, FLAG_GUARD);
+                        stop = true;
+                        break;
+                    }
+                    c = o;
+                    if (bl > H.K) {  // too large for this pass: defer it as it stands
+                        defer_column(P, c, bo >> 24, bl);
+                        break;
+                    }
+                    for (int64_t i = 1; i < bl; ++i) H.at(i - 1) = ld_rlx64(&B[i]);
+                    H.n = bl - 1;
+                    have = true;  // tau (= B[0]) is its top
+                    continue;
+                }
+                // o < c: add the cached boundary of the earlier owner
+                const uint64_t b = ld_rlx64(&P.bndptr[o]);
+                if (b == EMPTY64) continue;
                 const uint64_t* B = P.heap + (b >> 24);
                 const int64_t bl = (int64_t)(b & 0xFFFFFF);
-                if (B[0] != tau) {
-                    atomicOr(P.flags, FLAG_GUARD);
-                    return;
+                if (ld_rlx64(&B[0]) != tau) continue;  // o moved on: look again
+                if (H.room(bl - 1)) {
+                    have = false;
+                    ++adds;
+                    for (int64_t i = 1; i < bl; ++i) H.push(ld_rlx64(&B[i]));
+                    continue;
                 }
-                if (bl - 1 > H.K) {
+                defer = true;
+            }
+            if (defer) {
+                // save {tau} + heap and hand the column to the next pass
+                const uint64_t b = publish(P, H, have, tau);
+                if (b == NONE) {
                     atomicOr(P.flags, FLAG_HEAP);
-                    return;
+                    stop = true;
+                    break;
                 }
-                for (int64_t i = 1; i < bl; ++i) H.h[i - 1] = B[i];
-                H.n = bl - 1;
-                c = o;
-                have = true;  // tau (= B[0]) is its top
-                continue;
+                defer_column(P, c, b >> 24, b & 0xFFFFFF);
+                break;
             }
-            // o < c: add the cached boundary of the earlier owner
-            const uint64_t b = ld_acq64(&P.bndptr[o]);
-            if (b == EMPTY64) continue;
-            const uint64_t* B = P.heap + (b >> 24);
-            const int64_t bl = (int64_t)(b & 0xFFFFFF);
-            if (B[0] != tau) continue;  // o moved on: look again
-            have = false;
-            if (!H.room(bl - 1)) {
-                atomicOr(P.flags, FLAG_HEAP);
-                return;
-            }
-            for (int64_t i = 1; i < bl; ++i) H.push(B[i]);
         }
+        if (stop) break;
     }
+    atomicAdd(&P.ctrs[C_STEPS], steps);
+    atomicAdd(&P.ctrs[C_EVICT], evictions);
+    atomicAdd(&P.ctrs[C_ADDS], adds);
 }
 
 __global__ void k_init_owner(const uint32_t* c1, const uint8_t* paired1, int64_t m1, uint32_t* owner1) {
@@ -363,19 +445,20 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         err = std::string("D1: cannot allocate ") + what;
         return -3;  // DMS_E_NOMEM
     };
-    if (!s.ctrs && hipMalloc(&s.ctrs, 64) != hipSuccess) return oom("counters");
+    if (!s.ctrs && hipMalloc(&s.ctrs, 128) != hipSuccess) return oom("counters");
     if (grow(s.colflag, s.colflag_cap, 4 * (m2 + 1), s.bytes)) return oom("column flags");
     if (grow(s.cols, s.cols_cap, 4 * (m2 + 1), s.bytes)) return oom("columns");
     if (grow(s.scanpart, s.scanpart_cap, 4 * scan_part_size(m2 + 1), s.bytes)) return oom("scan");
     if (grow(s.owner1, s.owner1_cap, 4 * 7 * V, s.bytes)) return oom("owners");
+    for (int d = 0; d < 6; ++d) s.stats[d] = 0;
+    for (int d = 0; d < 5; ++d) s.pass_work[d] = s.pass_us[d] = 0;
     // unpaired 2-saddles, ascending
     uint32_t* flag = (uint32_t*)s.colflag;
     uint32_t* cols = (uint32_t*)s.cols;
     int64_t ncols = 0;
     if (m2 > 0) {
         hipLaunchKernelGGL(k_colflags, dim3(nblocks(m2)), dim3(DB), 0, st, in.paired2_desc, m2, flag);
-        // positions into cols (reuse cols as scan output would alias: use a second region after flags)
-        uint32_t* pos = cols;  // scan in place into cols, then compact into flag space reversed below
+        uint32_t* pos = cols;  // scan output; the compacted list goes through flag's buffer
         exclusive_scan_u32(flag, pos, m2, (uint32_t*)s.scanpart, st);
         uint32_t last_pos = 0, last_flag = 0;
         if (hipMemcpyAsync(&last_pos, pos + m2 - 1, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -385,7 +468,6 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             return -5;
         }
         ncols = (int64_t)last_pos + last_flag;
-        // compact: cols must not alias pos, so scatter into flag's buffer then copy
         hipLaunchKernelGGL(k_compact, dim3(nblocks(m2)), dim3(DB), 0, st, in.c2, in.paired2_desc, pos, m2, flag);
         if (ncols > 0 && hipMemcpyAsync(cols, flag, 4 * ncols, hipMemcpyDeviceToDevice, st) != hipSuccess) {
             err = "D1: copy failed";
@@ -394,53 +476,101 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
     }
     s.ncols = ncols;
     if (grow(s.bndptr, s.bndptr_cap, 8 * (ncols + 1), s.bytes)) return oom("boundary pointers");
-    if (s.heap_cap == 0) {
-        size_t want = (size_t)8 * std::max<int64_t>(1 << 22, 64 * ncols);
-        if (grow(s.heap, s.heap_cap, want, s.bytes)) return oom("boundary heap");
+    // two deferral queues (this pass / next pass): u64 (column, offset) + u32 length
+    if (grow(s.dq, s.dq_cap, 2 * (size_t)(ncols + 1) * 12, s.bytes)) return oom("deferral queues");
+    if (s.heap_cap < (size_t)8 * 32 * ncols) {
+        if (grow(s.heap, s.heap_cap, std::max<size_t>((size_t)8 << 22, (size_t)8 * 32 * ncols), s.bytes))
+            return oom("boundary heap");
     }
-    for (int attempt = 0; attempt < 6; ++attempt) {
-        const int64_t T = std::max<int64_t>(1, std::min<int64_t>(ncols, s.threads));
-        if (grow(s.scratch, s.scratch_cap, (size_t)8 * T * s.work_k, s.bytes)) return oom("working heaps");
-        if (hipMemsetAsync(s.ctrs, 0, 64, st) != hipSuccess) return -5;
+    const int64_t lanes = (int64_t)1 << 18;  // first pass: 262144 threads x 64 entries
+    const int64_t k0 = 64;
+    if (grow(s.scratch, s.scratch_cap, (size_t)8 * lanes * k0, s.bytes)) return oom("working heaps");
+    if (in.m1 > 0)
+        hipLaunchKernelGGL(k_init_owner, dim3(nblocks(in.m1)), dim3(DB), 0, st, in.c1, in.paired1, in.m1,
+                           (uint32_t*)s.owner1);
+    if (ncols == 0) return 0;
+    for (int restart = 0; restart < 4; ++restart) {
+        if (hipMemsetAsync(s.ctrs, 0, 128, st) != hipSuccess) return -5;
         if (hipMemsetAsync(in.flags, 0, 4, st) != hipSuccess) return -5;
         fill_u64((uint64_t*)s.bndptr, EMPTY64, ncols, st);
-        if (in.m1 > 0)
+        if (restart > 0 && in.m1 > 0)
             hipLaunchKernelGGL(k_init_owner, dim3(nblocks(in.m1)), dim3(DB), 0, st, in.c1, in.paired1, in.m1,
                                (uint32_t*)s.owner1);
-        if (ncols == 0) return 0;
-        D1K P;
-        P.g = in.g;
-        P.G = in.G;
-        P.rank = in.rank;
-        P.order = in.order;
-        P.cols = cols;
-        P.ncols = ncols;
-        P.bpr = in.bpr;
-        P.owner1 = (uint32_t*)s.owner1;
-        P.bndptr = (uint64_t*)s.bndptr;
-        P.heap = (uint64_t*)s.heap;
-        P.heap_cap = s.heap_cap / 8;
-        P.scratch = (uint64_t*)s.scratch;
-        P.K = s.work_k;
-        P.nthreads = T;
-        P.ctrs = (unsigned long long*)s.ctrs;
-        P.flags = in.flags;
-        hipLaunchKernelGGL(k_d1, dim3(nblocks(T)), dim3(DB), 0, st, P);
-        uint32_t f = 0;
-        if (hipMemcpyAsync(&f, in.flags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess) {
-            err = "D1: kernel failed";
-            return -5;
+        uint64_t* q[2] = {(uint64_t*)s.dq, (uint64_t*)s.dq + (ncols + 1)};
+        uint32_t* qlen = (uint32_t*)((uint64_t*)s.dq + 2 * (ncols + 1));
+        uint32_t* ql[2] = {qlen, qlen + (ncols + 1)};
+        int64_t nwork = ncols;
+        int cur = 0;
+        bool overflow = false;
+        int64_t K = k0;
+        unsigned long long hc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int pass = 0; pass < MAX_PASSES && nwork > 0; ++pass) {
+            const int64_t T = std::max<int64_t>(1, std::min<int64_t>(nwork, (lanes * k0) / K));
+            const auto t_pass = std::chrono::steady_clock::now();
+            D1K P;
+            P.g = in.g;
+            P.G = in.G;
+            P.rank = in.rank;
+            P.order = in.order;
+            P.cols = cols;
+            P.ncols = ncols;
+            P.work = pass == 0 ? nullptr : q[cur];
+            P.work_len = pass == 0 ? nullptr : ql[cur];
+            P.nwork = nwork;
+            P.defer = q[cur ^ 1];
+            P.defer_len = ql[cur ^ 1];
+            P.bpr = in.bpr;
+            P.owner1 = (uint32_t*)s.owner1;
+            P.bndptr = (uint64_t*)s.bndptr;
+            P.heap = (uint64_t*)s.heap;
+            P.heap_cap = s.heap_cap / 8;
+            P.scratch = (uint64_t*)s.scratch;
+            P.K = K;
+            P.nthreads = T;
+            P.ctrs = (unsigned long long*)s.ctrs;
+            P.flags = in.flags;
+            // fresh work cursor, deferral count and work counters for this pass
+            if (hipMemsetAsync((unsigned long long*)s.ctrs + C_NEXT, 0, 5 * 8, st) != hipSuccess) return -5;
+            hipLaunchKernelGGL(k_d1, dim3(nblocks(T)), dim3(DB), 0, st, P);
+            uint32_t f = 0;
+            if (hipMemcpyAsync(&f, in.flags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipMemcpyAsync(hc, s.ctrs, 64, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                err = "D1: kernel failed";
+                return -5;
+            }
+            if (f & FLAG_GUARD) {
+                err = "D1: consistency check failed";
+                return -7;
+            }
+            s.pass_work[pass] = (uint64_t)nwork;
+            s.pass_us[pass] = (uint64_t)std::chrono::duration_cast<std::chrono::microseconds>(
+                                  std::chrono::steady_clock::now() - t_pass)
+                                  .count();
+            s.stats[0] += hc[C_STEPS];
+            s.stats[1] += hc[C_EVICT];
+            s.stats[2] += hc[C_ADDS];
+            s.stats[3] += hc[C_DEFER];
+            if (f & (FLAG_HEAP | FLAG_WORK)) {
+                overflow = true;
+                break;
+            }
+            nwork = (int64_t)hc[C_DEFER];
+            cur ^= 1;
+            K *= 16;
         }
-        if (f & FLAG_GUARD) {
-            err = "D1: consistency check failed";
-            return -7;
+        s.stats[4] = hc[C_HEAP];
+        s.stats[5] = restart;
+        if (!overflow) {
+            if (nwork > 0) {
+                err = "D1: columns left after the last pass";
+                return -7;
+            }
+            return 0;
         }
-        if (!(f & FLAG_HEAP)) return 0;
-        // overflow: larger working heaps (fewer threads) and a larger cache
-        s.work_k *= 4;
-        s.threads = std::max<int64_t>(1024, s.threads / 2);
-        if (grow(s.heap, s.heap_cap, s.heap_cap * 4, s.bytes)) return oom("boundary heap");
+        // publication heap exhausted: grow it and redo D1 from the start
+        const size_t want = std::max<size_t>(2 * s.heap_cap, (size_t)16 * hc[C_HEAP]);
+        if (grow(s.heap, s.heap_cap, want, s.bytes)) return oom("boundary heap");
     }
     err = "D1: boundary storage kept overflowing";
     return -3;
@@ -469,7 +599,7 @@ void d1_emit_essential2(D1State& s, int64_t m2, const uint8_t* paired2_desc, con
 }
 
 void d1_free(D1State& s) {
-    void* ps[] = {s.cols, s.colflag, s.scanpart, s.owner1, s.bndptr, s.heap, s.scratch, s.ctrs};
+    void* ps[] = {s.cols, s.colflag, s.scanpart, s.owner1, s.bndptr, s.heap, s.scratch, s.ctrs, s.dq};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     s = D1State();

@@ -20,7 +20,7 @@ struct Buf {
     size_t cap = 0;
 };
 
-enum { EV_START = 0, EV_ORDER, EV_GRAD, EV_SORT, EV_D02, EV_D1, EV_OUT, NEV };
+enum { EV_START = 0, EV_ORDER, EV_GK, EV_GRAD, EV_SORT, EV_D02, EV_D1, EV_OUT, NEV };
 
 }  // namespace
 
@@ -35,7 +35,7 @@ struct dms_ctx {
     int stage = 0;  // 0: nothing, 1: gradient, 2: D0/D2, 3: D1
     int64_t ncrit[4] = {0, 0, 0, 0};
     uint32_t cap[4] = {0, 0, 0, 0};
-    Buf rank, keysA, keysB, valsA, valsB, G, hist, part, flags, counters;
+    Buf rank, keysA, keysB, valsA, valsB, G, hist, part, flags, counters, stats;
     Buf cid[4], ck[4], ck2[4];  // unsorted critical ids and keys (hi / lo)
     Buf csorted[4];             // ids sorted by the lexicographic order
     uint32_t* order = nullptr;  // rank -> vertex (inside valsA / valsB)
@@ -48,7 +48,7 @@ struct dms_ctx {
     Buf ob, od, okey, ocnt;
     hipEvent_t ev[NEV] = {};
     bool ev_ok[NEV] = {};
-    float ms[7] = {0, 0, 0, 0, 0, 0, 0};
+    float ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -292,6 +292,7 @@ int dms_create(dms_ctx** out, int device, void* hip_stream, size_t hbm_budget_by
         }
     int r = ensure(ctx, ctx->flags, 64);
     if (r == DMS_OK) r = ensure(ctx, ctx->counters, 64);
+    if (r == DMS_OK) r = ensure(ctx, ctx->stats, 64);
     if (r == DMS_OK) r = ensure(ctx, ctx->ocnt, 64);
     if (r != DMS_OK) {
         delete ctx;
@@ -306,7 +307,7 @@ void dms_destroy(dms_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->st);
     Buf* all[] = {&ctx->rank, &ctx->keysA, &ctx->keysB, &ctx->valsA, &ctx->valsB, &ctx->G, &ctx->hist,
-                  &ctx->part, &ctx->flags, &ctx->counters, &ctx->na0, &ctx->nb0, &ctx->owner0, &ctx->bnd0,
+                  &ctx->part, &ctx->flags, &ctx->counters, &ctx->stats, &ctx->na0, &ctx->nb0, &ctx->owner0, &ctx->bnd0,
                   &ctx->paired1, &ctx->na2, &ctx->nb2, &ctx->owner2, &ctx->bnd2, &ctx->paired2, &ctx->tet2pos,
                   &ctx->ob, &ctx->od, &ctx->okey, &ctx->ocnt};
     for (Buf* b : all)
@@ -390,6 +391,7 @@ int dms_gradient(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t fla
         cl.key3hi = P<uint64_t>(ctx->ck[3]);
         cl.key3lo = P<uint64_t>(ctx->ck2[3]);
         HIPCHK(hipMemsetAsync(ctx->counters.p, 0, 16, st));
+        record(ctx, EV_GK);
         launch_gradient(ctx->g, P<uint32_t>(ctx->rank), P<uint8_t>(ctx->G), ctx->bpr, cl, st);
         record(ctx, EV_GRAD);
         uint32_t cnt[4];
@@ -428,6 +430,8 @@ static int run_d0_d2(dms_ctx* ctx) {
     hipStream_t st = ctx->st;
     const int64_t V = ctx->g.V;
     const int64_t m0 = ctx->ncrit[0], m1 = ctx->ncrit[1], m2 = ctx->ncrit[2], m3 = ctx->ncrit[3];
+    HIPCHK(hipMemsetAsync(ctx->stats.p, 0, 64, st));
+    unsigned long long* stats = P<unsigned long long>(ctx->stats);
     // D0 (Sec. 5.1)
     ENSURE(ctx->na0, 4 * m1);
     ENSURE(ctx->nb0, 4 * m1);
@@ -439,7 +443,7 @@ static int run_d0_d2(dms_ctx* ctx) {
     fill_u32(P<uint32_t>(ctx->owner0), EMPTY32, V, st);
     fill_u64(P<uint64_t>(ctx->bnd0), EMPTY64, m1, st);
     reduce_pairs(P<uint32_t>(ctx->na0), P<uint32_t>(ctx->nb0), m1, P<uint32_t>(ctx->owner0), P<uint64_t>(ctx->bnd0),
-                 P<uint32_t>(ctx->flags), st);
+                 P<uint32_t>(ctx->flags), stats, st);
     settled_columns(P<uint64_t>(ctx->bnd0), P<uint32_t>(ctx->owner0), m1, P<uint8_t>(ctx->paired1), st);
     // D2 (Sec. 5.2), virtual maximum = age 0
     ENSURE(ctx->tet2pos, 4 * 6 * V);
@@ -454,7 +458,7 @@ static int run_d0_d2(dms_ctx* ctx) {
     fill_u32(P<uint32_t>(ctx->owner2), EMPTY32, m3 + 1, st);
     fill_u64(P<uint64_t>(ctx->bnd2), EMPTY64, m2, st);
     reduce_pairs(P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2), m2, P<uint32_t>(ctx->owner2), P<uint64_t>(ctx->bnd2),
-                 P<uint32_t>(ctx->flags), st);
+                 P<uint32_t>(ctx->flags), stats + 2, st);
     settled_columns(P<uint64_t>(ctx->bnd2), P<uint32_t>(ctx->owner2), m2, P<uint8_t>(ctx->paired2), st);
     (void)m0;
     return DMS_OK;
@@ -635,6 +639,31 @@ int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap) {
         }
         case DMS_BUF_ARCS0: bytes = 8 * ctx->ncrit[1]; break;
         case DMS_BUF_ARCS2: bytes = 8 * ctx->ncrit[2]; break;
+        case DMS_BUF_STATS: {
+            if (ctx->stage < 1) return fail(ctx, DMS_E_STATE, "no gradient computed yet");
+            bytes = 8 * 32;
+            if (!dst) return bytes;
+            if (cap < bytes) return fail(ctx, DMS_E_CAPACITY, "destination too small");
+            uint64_t* h = (uint64_t*)dst;
+            std::memset(h, 0, bytes);
+            HIPCHK(hipStreamSynchronize(ctx->st));
+            HIPCHK(hipMemcpy(h, ctx->stats.p, 32, hipMemcpyDeviceToHost));
+            for (int i = 0; i < 6; ++i) h[4 + i] = ctx->d1.stats[i];
+            for (int i = 0; i < 5; ++i) {
+                h[10 + 2 * i] = ctx->d1.pass_work[i];
+                h[11 + 2 * i] = ctx->d1.pass_us[i];
+            }
+            return bytes;
+        }
+        case DMS_BUF_D1LEN: {
+            if (ctx->stage < 3) return fail(ctx, DMS_E_STATE, "no D1 computed yet");
+            bytes = 8 * ctx->d1.ncols;
+            if (!dst) return bytes;
+            if (cap < bytes) return fail(ctx, DMS_E_CAPACITY, "destination too small");
+            HIPCHK(hipStreamSynchronize(ctx->st));
+            if (bytes) HIPCHK(hipMemcpy(dst, ctx->d1.bndptr, bytes, hipMemcpyDeviceToHost));
+            return bytes;
+        }
         default: return fail(ctx, DMS_E_INVAL, "unknown buffer");
     }
     if (ctx->stage < 1) return fail(ctx, DMS_E_STATE, "no gradient computed yet");
@@ -658,10 +687,15 @@ int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap) {
     return bytes;
 }
 
-int dms_stage_ms(const dms_ctx* ctx, float ms[7]) {
+int dms_stage_ms(const dms_ctx* ctx, float ms[8]) {
     if (!ctx || !ms) return DMS_E_INVAL;
     const int pairs[6][2] = {{EV_START, EV_ORDER}, {EV_ORDER, EV_GRAD}, {EV_GRAD, EV_SORT},
                              {EV_SORT, EV_D02},    {EV_D02, EV_D1},     {EV_D1, EV_OUT}};
+    ms[7] = -1.0f;
+    if (ctx->ev_ok[EV_GK] && ctx->ev_ok[EV_GRAD]) {
+        float t = 0;
+        if (hipEventElapsedTime(&t, ctx->ev[EV_GK], ctx->ev[EV_GRAD]) == hipSuccess) ms[7] = t;
+    }
     for (int i = 0; i < 6; ++i) {
         ms[i] = -1.0f;
         if (ctx->ev_ok[pairs[i][0]] && ctx->ev_ok[pairs[i][1]]) {

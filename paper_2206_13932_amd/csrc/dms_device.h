@@ -61,11 +61,14 @@ __device__ inline int64_t lin_of_mask(const GridDev& g, int m) {
     return (m & 1 ? 1 : 0) + (m & 2 ? g.sy : 0) + (m & 4 ? g.sz : 0);
 }
 
+// vertex ids stay below 2^32 (the library rejects larger grids): 32-bit division
 __device__ inline void coords_of(const GridDev& g, int64_t v, int& x, int& y, int& z) {
-    x = (int)(v % g.nx);
-    int64_t r = v / g.nx;
-    y = (int)(r % g.ny);
-    z = (int)(r / g.ny);
+    const uint32_t u = (uint32_t)v;
+    const uint32_t r = u / (uint32_t)g.nx;
+    x = (int)(u - r * (uint32_t)g.nx);
+    const uint32_t zz = r / (uint32_t)g.ny;
+    y = (int)(r - zz * (uint32_t)g.ny);
+    z = (int)zz;
 }
 
 // Does a chain with total step mask `m` starting at (x, y, z) stay in the grid?
@@ -90,7 +93,7 @@ __device__ inline bool is_nan_bits(float f) {
     return (b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu) != 0;
 }
 
-// ---- star tables (filled on the host at library initialisation) ----------
+// ---- star tables (computed at compile time, star_tables.h) -----------------
 // Neighbour n of x: offset nbv[n] = +mask(n+1) for n < 7, -mask(n-6) else.
 // Slot s of the open star: 0..13 edge {x, n}; 14..49 triangle {x, a, b}
 // for the 36 link edges; 50..73 tetrahedron {x, a, b, c} for the 24 link

@@ -31,7 +31,7 @@ constexpr uint32_t EMPTY32 = 0xFFFFFFFFu;
 constexpr uint64_t EMPTY64 = ~0ull;
 
 // error flag bits
-enum : uint32_t { FLAG_NAN = 1u, FLAG_GUARD = 2u, FLAG_HEAP = 4u };
+enum : uint32_t { FLAG_NAN = 1u, FLAG_GUARD = 2u, FLAG_HEAP = 4u, FLAG_WORK = 8u };
 
 // gradient.hip
 void launch_gradient(const GridDev& g, const uint32_t* rank, uint8_t* G, int bpr, const CritLists& cl,
@@ -61,7 +61,7 @@ void tet_positions(const uint32_t* c3_sorted, int64_t m, uint32_t* tet2pos, hipS
 void trace_d2(const GridDev& g, const uint8_t* G, const uint32_t* tet2pos, const uint32_t* c2_sorted, int64_t m,
               uint32_t* na, uint32_t* nb, uint32_t* flags, hipStream_t st);
 void reduce_pairs(const uint32_t* na, const uint32_t* nb, int64_t m, uint32_t* owner, uint64_t* bnd,
-                  uint32_t* flags, hipStream_t st);
+                  uint32_t* flags, unsigned long long* stats, hipStream_t st);
 void settled_columns(const uint64_t* bnd, const uint32_t* owner, int64_t m, uint8_t* paired, hipStream_t st);
 
 }  // namespace dms

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __re
                                                  uint8_t* __restrict__ G, int bpr, CritLists cl) {
     __shared__ LdsTables T;
     __shared__ uint16_t skey[NSLOT * GB];
-    __shared__ uint32_t snr[NNB * GB];
+    __shared__ uint8_t scode[NSLOT * GB];  // partner code of each slot, written out coalesced
     const int tid = threadIdx.x;
     // cooperative copy of the star tables into LDS
     for (int i = tid; i < NSLOT; i += GB) {
@@ -88,10 +88,12 @@ __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __re
     const bool active = x < g.V;
     const int64_t V = g.V;
 #define KEY(s) skey[(s) * GB + tid]
-#define NR(n) snr[(n) * GB + tid]
+#define CODE(s) scode[(s) * GB + tid]
 
     uint64_t crit_lo = 0;
     uint32_t crit_hi = 0;
+    uint64_t in_lo = 0;
+    uint32_t in_hi = 0;
     bool crit_vertex = false;
     uint32_t rx = 0;
     int cx = 0, cy = 0, cz = 0;
@@ -109,7 +111,6 @@ __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __re
             uint32_t rv = 0xFFFFFFFFu;
             if (in) rv = rank[x + dx + dy * g.sy + dz * g.sz];
             r[n] = rv;
-            NR(n) = rv;
             if (in && rv < rx) lower |= 1u << n;
         }
         // non-existent simplices anchored at x (upper faces of the grid)
@@ -137,8 +138,6 @@ __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __re
                 if (((lower >> n) & 1) && c == 0) n0 = n;
             }
             // cells of L(x) and their keys
-            uint64_t in_lo = 0;
-            uint32_t in_hi = 0;
 #pragma unroll
             for (int s = 0; s < NSLOT; ++s) {
                 const uint32_t nb = kStar.cellnb[s];
@@ -154,7 +153,8 @@ __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __re
                 }
             }
             auto anchor = [&](int s) { return x + T.aofflin[s]; };
-            auto gput = [&](int s, uint8_t code) { G[(int64_t)T.plane[s] * V + anchor(s)] = code; };
+            auto gput = [&](int s, uint8_t code) { CODE(s) = code; };
+            (void)anchor;
             auto unpaired = [&](int s, uint64_t cls_lo) { return popc64(T.face[s] & ~cls_lo); };
             // pair (p, a): p is a facet of a; w = the neighbour of a not in p
             auto pair_cells = [&](int p, int a) {
@@ -238,7 +238,16 @@ __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __re
         }
     }
 
+    // ---- gradient codes: one store per slot, consecutive lanes -> consecutive bytes ----
+    for (int s = 0; s < NSLOT; ++s) {
+        const bool w = s < 64 ? ((in_lo >> s) & 1) : ((in_hi >> (s - 64)) & 1);
+        if (w) G[(int64_t)T.plane[s] * V + x + T.aofflin[s]] = CODE(s);
+    }
+
     // ---- critical-cell lists (all lanes take part in the wave scans) ----
+    auto nbrank = [&](int n) {
+        return rank[x + kStar.nbv[n][0] + kStar.nbv[n][1] * g.sy + kStar.nbv[n][2] * g.sz];
+    };
     const uint64_t E_MASK = 0x3FFFull, T_MASK = ((1ull << 50) - 1) & ~0x3FFFull;
     const uint64_t Q_LO = ~((1ull << 50) - 1);
     uint32_t c0 = crit_vertex ? 1 : 0;
@@ -258,7 +267,7 @@ __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __re
             if (at < cl.cap[1]) {
                 const int64_t a = x + T.aofflin[s];
                 cl.id1[at] = (uint32_t)(a * 7 + (T.plane[s] - 1));
-                cl.key1[at] = ((uint64_t)rx << bpr) | NR(s);
+                cl.key1[at] = ((uint64_t)rx << bpr) | nbrank(s);
             }
             ++at;
         }
@@ -274,7 +283,7 @@ __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __re
                 cl.id2[at] = (uint32_t)(a * 12 + (T.plane[s] - 8));
                 const uint32_t nb = T.cellnb[s];
                 const int na = __builtin_ctz(nb), nbb = 31 - __builtin_clz(nb);
-                const uint32_t ra = NR(na), rb = NR(nbb);
+                const uint32_t ra = nbrank(na), rb = nbrank(nbb);
                 const uint32_t hi = ra > rb ? ra : rb, lo = ra > rb ? rb : ra;
                 cl.key2hi[at] = ((uint64_t)rx << bpr) | hi;
                 cl.key2lo[at] = lo;
@@ -298,7 +307,7 @@ __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __re
                 for (int i = 0; i < 3; ++i) {
                     const int n = __builtin_ctz(nb);
                     nb &= nb - 1;
-                    rr[i] = NR(n);
+                    rr[i] = nbrank(n);
                 }
                 // sort three ranks descending
                 uint32_t t0 = rr[0], t1 = rr[1], t2 = rr[2], t;
@@ -312,7 +321,7 @@ __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __re
         }
     }
 #undef KEY
-#undef NR
+#undef CODE
 }
 
 }  // namespace

@@ -146,39 +146,47 @@ __global__ void k_tet_positions(const uint32_t* __restrict__ c3, int64_t m, uint
 }
 
 // ---- lock-free two-entry column reduction ----------------------------------
-__device__ inline uint32_t ld_acq(uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Shared state is accessed with relaxed agent-scope atomics: they are coherent
+// across the XCDs without cache-wide writeback/invalidate. The only ordering
+// needed -- a column's published boundary is complete before its claim -- is
+// a wait for the store to complete before the compare-and-swap.
+__device__ inline uint32_t ld_rlx(uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline uint64_t ld_acq64(uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ inline uint64_t ld_rlx64(uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline void st_rel64(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ inline void st_rlx64(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ inline void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); /* vmcnt(0) */ }
 __device__ inline bool cas32(uint32_t* p, uint32_t expect, uint32_t desired) {
-    return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+    return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void k_reduce_pairs(const uint32_t* __restrict__ na, const uint32_t* __restrict__ nb, int64_t m,
-                               uint32_t* owner, uint64_t* bnd, uint32_t* flags) {
+                               uint32_t* owner, uint64_t* bnd, uint32_t* flags, unsigned long long* stats) {
     const int64_t j = (int64_t)blockIdx.x * PB + threadIdx.x;
     if (j >= m) return;
     uint32_t c = (uint32_t)j;
     uint32_t p = na[j], q = nb[j];
     if (p < q) { uint32_t t = p; p = q; q = t; }
     const int64_t limit = (int64_t)1 << 26;
+    unsigned long long steps = 0, evictions = 0;
     for (int64_t guard = 0;; ++guard) {
-        if (guard > limit) { atomicOr(flags, FLAG_GUARD); return; }
-        if (p == q) return;  // column reduced to zero: a positive arc
-        const uint32_t o = ld_acq(&owner[p]);
+        if (guard > limit) { atomicOr(flags, FLAG_GUARD); break; }
+        if (p == q) break;  // column reduced to zero: a positive arc
+        ++steps;
+        const uint32_t o = ld_rlx(&owner[p]);
         if (o == EMPTY32) {
-            st_rel64(&bnd[c], ((uint64_t)p << 32) | q);
-            if (cas32(&owner[p], EMPTY32, c)) return;
+            st_rlx64(&bnd[c], ((uint64_t)p << 32) | q);
+            wait_stores();
+            if (cas32(&owner[p], EMPTY32, c)) break;
             continue;
         }
         if (o < c) {
-            const uint64_t b = ld_acq64(&bnd[o]);
+            const uint64_t b = ld_rlx64(&bnd[o]);
             if ((uint32_t)(b >> 32) != p) continue;  // owner moved on; look again
             const uint32_t r = (uint32_t)b;
             // {p, q} + {p, r} = {q, r}
@@ -188,13 +196,19 @@ __global__ void k_reduce_pairs(const uint32_t* __restrict__ na, const uint32_t* 
         }
         // o > c: c is earlier and takes the pivot; the evicted column o is
         // carried on by this thread.
-        st_rel64(&bnd[c], ((uint64_t)p << 32) | q);
+        st_rlx64(&bnd[c], ((uint64_t)p << 32) | q);
+        wait_stores();
         if (cas32(&owner[p], o, c)) {
-            const uint64_t b = ld_acq64(&bnd[o]);
+            ++evictions;
+            const uint64_t b = ld_rlx64(&bnd[o]);
             c = o;
             p = (uint32_t)(b >> 32);
             q = (uint32_t)b;
         }
+    }
+    if (stats) {
+        atomicAdd(&stats[0], steps);
+        atomicAdd(&stats[1], evictions);
     }
 }
 
@@ -222,8 +236,9 @@ void trace_d2(const GridDev& g, const uint8_t* G, const uint32_t* tet2pos, const
                            flags);
 }
 void reduce_pairs(const uint32_t* na, const uint32_t* nb, int64_t m, uint32_t* owner, uint64_t* bnd,
-                  uint32_t* flags, hipStream_t st) {
-    if (m > 0) hipLaunchKernelGGL(k_reduce_pairs, dim3(nblocks(m)), dim3(PB), 0, st, na, nb, m, owner, bnd, flags);
+                  uint32_t* flags, unsigned long long* stats, hipStream_t st) {
+    if (m > 0)
+        hipLaunchKernelGGL(k_reduce_pairs, dim3(nblocks(m)), dim3(PB), 0, st, na, nb, m, owner, bnd, flags, stats);
 }
 void settled_columns(const uint64_t* bnd, const uint32_t* owner, int64_t m, uint8_t* paired, hipStream_t st) {
     if (m > 0) hipLaunchKernelGGL(k_settled, dim3(nblocks(m)), dim3(PB), 0, st, bnd, owner, m, paired);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libdms.so")
 DMS_OK, DMS_E_INVAL, DMS_E_NAN, DMS_E_NOMEM, DMS_E_CAPACITY, DMS_E_HIP, DMS_E_STATE, DMS_E_INTERNAL = \
     0, -1, -2, -3, -4, -5, -6, -7
 DMS_VIRTUAL_MAX = 1
-BUF_RANK, BUF_GRADIENT, BUF_CRIT0, BUF_ARCS0, BUF_ARCS2 = 0, 1, 2, 6, 7
+BUF_RANK, BUF_GRADIENT, BUF_CRIT0, BUF_ARCS0, BUF_ARCS2, BUF_STATS, BUF_D1LEN = 0, 1, 2, 6, 7, 8, 9
 _ERRNAMES = {-1: "DMS_E_INVAL", -2: "DMS_E_NAN", -3: "DMS_E_NOMEM", -4: "DMS_E_CAPACITY", -5: "DMS_E_HIP",
              -6: "DMS_E_STATE", -7: "DMS_E_INTERNAL"}
 
@@ -73,7 +73,7 @@ def load_library() -> ctypes.CDLL:
     lib.dms_diagram.restype = ctypes.c_int
     lib.dms_debug_copy.argtypes = [_p, ctypes.c_int, _p, i64]
     lib.dms_debug_copy.restype = i64
-    lib.dms_stage_ms.argtypes = [_p, ctypes.POINTER(ctypes.c_float * 7)]
+    lib.dms_stage_ms.argtypes = [_p, ctypes.POINTER(ctypes.c_float * 8)]
     lib.dms_stage_ms.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -207,7 +207,7 @@ class Context:
         return buf.view(dtype)
 
     def stage_ms(self):
-        arr = (ctypes.c_float * 7)()
+        arr = (ctypes.c_float * 8)()
         self.lib.dms_stage_ms(self.h, ctypes.byref(arr))
         return list(arr)
 

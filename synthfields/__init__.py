@@ -47,8 +47,11 @@ def gaussians(shape, seed: int, k: int, noise_frac: float,
     xs = np.arange(nx, dtype=np.float64) / max(nx - 1, 1)
     ys = np.arange(ny, dtype=np.float64) / max(ny - 1, 1)
     zs = np.arange(nz, dtype=np.float64) / max(nz - 1, 1)
-    g = np.zeros((nz, ny, nx), dtype=np.float64)
-    for _ in range(k):
+    # g[z, y, x] = sum_i a_i gz_i[z] gy_i[y] gx_i[x], evaluated as one
+    # (nz x k) @ (k x ny*nx) product of the separable factors, slab by slab
+    A = np.empty((nz, k))
+    B = np.empty((k, ny, nx))
+    for i in range(k):
         c = rng.random(3)
         s = rng.uniform(sigma_range[0], sigma_range[1])
         a = rng.uniform(-1.0, 1.0)
@@ -56,11 +59,15 @@ def gaussians(shape, seed: int, k: int, noise_frac: float,
         gx = np.exp(-((xs - c[0]) ** 2) * inv)
         gy = np.exp(-((ys - c[1]) ** 2) * inv)
         gz = np.exp(-((zs - c[2]) ** 2) * inv)
-        g += a * (gz[:, None, None] * gy[None, :, None] * gx[None, None, :])
+        A[:, i] = a * gz
+        B[i] = gy[:, None] * gx[None, :]
+    g = (A @ B.reshape(k, ny * nx)).reshape(nz, ny, nx)
     if noise_frac > 0.0:
         span = float(g.max() - g.min())
-        eta = rng.random(nz * ny * nx).reshape(nz, ny, nx)
-        g += noise_frac * span * eta
+        step = max(1, (1 << 24) // max(1, ny * nx))
+        for z0 in range(0, nz, step):  # noise drawn in C order, slab by slab
+            z1 = min(nz, z0 + step)
+            g[z0:z1] += (noise_frac * span) * rng.random((z1 - z0) * ny * nx).reshape(z1 - z0, ny, nx)
     return np.ascontiguousarray(g.astype(np.float32))
 
 
