@@ -29,6 +29,19 @@ WORKLOADS = {
 }
 METRIC = "Mvertices/s full D0+D1+D2 (512^3 f32), % HBM peak; served req/s + p99"
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the gradient kernel on smooth512, from FETCH_SIZE and WRITE_SIZE
+# (profiles/gradient_hbm_counters_smooth512.md), valid for the kernel sources with this hash only
+GRADIENT_TRAFFIC = {"sources_sha256_16": "6c4699554efca1ec", "workload": "smooth512", "bytes": 2071644205 + 9124781728}
+
+
+def gradient_sources_hash():
+    import hashlib
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2206_13932_amd", "csrc")
+    h = hashlib.sha256()
+    for name in ("gradient.hip", "star_tables.h", "dms_device.h"):
+        with open(os.path.join(here, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def make_field(name):
@@ -65,6 +78,9 @@ def main():
     ap.add_argument("--workload", default="smooth512", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-crop", type=int, default=80)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="diagram", choices=["diagram", "gradient"],
+                    help="gradient: time dms_gradient alone and a 1 GiB device copy "
+                         "(the reference kernel for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the method's pipeline is built and measured on a single "
@@ -84,6 +100,23 @@ def main():
     field = torch.from_numpy(f).to(dev)
     ctx = dms.Context(0)
     torch.cuda.synchronize()
+
+    if args.mode == "gradient":
+        for i in range(args.warmup + args.steps):
+            ncrit = ctx.gradient(field)
+            torch.cuda.synchronize()
+        g_ms = ctx.stage_ms()[7]
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        gbytes = gradient_algorithmic_bytes(V, ncrit)
+        print(json.dumps({"mode": "gradient", "workload": args.workload, "gradient_kernel_ms": round(g_ms, 4),
+                          "algorithmic_bytes": int(gbytes), "n_crit": ncrit,
+                          "copy_bytes_each_way": int(src.numel() * 4)}), flush=True)
+        ctx.close()
+        return
 
     for i in range(args.warmup):
         ctx.diagram(field)
@@ -116,7 +149,7 @@ def main():
     ctx.diagram(field)
     stats = ctx.debug(dms.BUF_STATS, np.uint64).tolist()
     print(f"[bench] work counters (D0 steps, evictions, D2 steps, evictions, D1 steps, evictions, adds, "
-          f"deferrals, published, restarts): {stats[:10]}; D1 passes (columns, us): {stats[10:20]}",
+          f"deferrals, published, restarts): {stats[:10]}; D1 passes (columns, us): {stats[10:20]}; wide (rounds, expanded, moved): {stats[20:23]}",
           file=sys.stderr, flush=True)
     lens = (ctx.debug(dms.BUF_D1LEN, np.uint64) & 0xFFFFFF).astype(np.int64)
     if lens.size:
@@ -124,6 +157,10 @@ def main():
         print(f"[bench] D1 cached boundary length p50/p90/p99/p99.9/max: {q}; columns > 1000: "
               f"{int((lens > 1000).sum())}, > 10000: {int((lens > 10000).sum())}", file=sys.stderr, flush=True)
 
+    traffic = None
+    if (GRADIENT_TRAFFIC["workload"] == args.workload
+            and GRADIENT_TRAFFIC["sources_sha256_16"] == gradient_sources_hash()):
+        traffic = GRADIENT_TRAFFIC["bytes"]
     line = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -144,7 +181,7 @@ def main():
                         "gradient_kernel"], st)}},
         "roofline": {"kernel": "k_gradient", "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "algorithmic_bytes": int(gbytes),
+                     "traffic": traffic, "algorithmic_bytes": int(gbytes),
                      "avg_kernel_ms": round(g_avg_ms, 4)},
     }
     if not args.no_cpu_baseline:

@@ -128,7 +128,8 @@ enum {
     DMS_BUF_STATS = 8,     /* u64[32] work counters of the last call: D0 steps,
                               evictions; D2 steps, evictions; D1 steps, evictions,
                               boundary additions, deferrals, published entries,
-                              restarts; then per D1 pass (columns, microseconds)  */
+                              restarts; per D1 pass (columns, microseconds);
+                              workgroup rounds, edges expanded, entries moved  */
     DMS_BUF_D1LEN = 9      /* u64 per D1 column: last cached boundary
                               (offset << 24 | length)                             */
 };

@@ -50,6 +50,8 @@ struct D1State {
     // per pass: columns to process, microseconds
     uint64_t pass_work[5] = {0, 0, 0, 0, 0};
     uint64_t pass_us[5] = {0, 0, 0, 0, 0};
+    // workgroup passes: rounds, edges expanded, boundary entries moved by merges
+    uint64_t wide[3] = {0, 0, 0};
     // per-run data for emission
     GridDev g{};
     const uint32_t* order = nullptr;

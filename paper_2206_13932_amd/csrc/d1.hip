@@ -30,6 +30,7 @@
 // order in which earlier columns are added.
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 
 #include "d1.h"
 #include "dms_internal.h"
@@ -45,7 +46,8 @@ constexpr int MAX_PASSES = 5;
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + DB - 1) / DB); }
 
 // counters in D1State::ctrs
-enum { C_HEAP = 0, C_NEXT = 1, C_DEFER = 2, C_STEPS = 3, C_EVICT = 4, C_ADDS = 5 };
+enum { C_HEAP = 0, C_NEXT = 1, C_DEFER = 2, C_STEPS = 3, C_EVICT = 4, C_ADDS = 5, C_ROUNDS = 6, C_EXPANDED = 7,
+       C_MOVED = 8 };
 
 struct D1K {
     GridDev g;
@@ -68,6 +70,7 @@ struct D1K {
     uint64_t* scratch;
     int64_t K;
     int64_t nthreads;
+    int lds;  // working heaps in LDS (K entries per thread) instead of global scratch
     unsigned long long* ctrs;
     uint32_t* flags;
 };
@@ -215,11 +218,17 @@ __device__ inline void defer_column(const D1K& P, uint32_t c, uint64_t off, uint
 }
 
 __global__ __launch_bounds__(DB) void k_d1(D1K P) {
-    const int64_t tid = (int64_t)blockIdx.x * DB + threadIdx.x;
+    extern __shared__ uint64_t lds_heaps[];
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (tid >= P.nthreads) return;  // scratch exists for nthreads lanes only
     Heap H;
-    H.base = P.scratch + tid;
-    H.stride = P.nthreads;
+    if (P.lds) {
+        H.base = lds_heaps + (int64_t)threadIdx.x * P.K;
+        H.stride = 1;
+    } else {
+        H.base = P.scratch + tid;
+        H.stride = P.nthreads;
+    }
     H.K = P.K;
     const int64_t V = P.g.V;
     unsigned long long steps = 0, evictions = 0, adds = 0;
@@ -362,6 +371,356 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
     atomicAdd(&P.ctrs[C_ADDS], adds);
 }
 
+
+// ---- one workgroup per large column ------------------------------------------
+// The boundary is a sorted array, ascending, in per-block global scratch, so
+// that its top is at the end and a merge only rewrites the suffix from the
+// smallest key it inserts or removes. A round looks at the top WB edges:
+// every regular tail above the first critical (or non-tail) edge is expanded
+// at once -- adding the boundary of a partner triangle leaves the column's
+// Morse projection unchanged, so the expansions commute -- and the new edges
+// are sorted, cancelled mod 2 and merged in. When the top is critical, the
+// owner rule runs as in k_d1, with cached boundaries merged in chunks.
+// Published boundaries keep the decreasing layout (top first).
+constexpr int WB = 256;
+constexpr int NW = 2 * WB;
+constexpr uint64_t PAD = ~0ull;
+
+struct WideShared {
+    uint64_t raw[NW];   // new keys of a round, sorted here
+    uint64_t src[NW];   // keys to merge (ascending, unique)
+    uint64_t surv[NW];  // keys of src not present in B
+    uint32_t lb[NW];    // number of B-suffix elements smaller than src[j]
+    uint32_t lbs[NW];   // lb of the survivors
+    uint32_t canc[NW];  // B-suffix indices cancelled by src, ascending
+    uint32_t flag[NW];
+    uint32_t scan[WB];
+    int ints[8];
+    uint64_t u64s[4];
+};
+
+__device__ inline uint32_t block_excl_scan(WideShared& L, uint32_t v, uint32_t& total) {
+    const int t = threadIdx.x;
+    L.scan[t] = v;
+    __syncthreads();
+    for (int d = 1; d < WB; d <<= 1) {
+        const uint32_t a = t >= d ? L.scan[t - d] : 0;
+        __syncthreads();
+        L.scan[t] += a;
+        __syncthreads();
+    }
+    total = L.scan[WB - 1];
+    const uint32_t ex = L.scan[t] - v;
+    __syncthreads();
+    return ex;
+}
+
+// number of elements of the ascending array A[0..n) smaller than x
+template <typename T>
+__device__ inline uint32_t count_less(const T* A, uint32_t n, T x) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (A[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// B[0..n) ^= L.src[0..m) (both ascending, unique), in place, tmp holding the
+// rewritten suffix; returns the new size.
+__device__ uint32_t merge_xor(WideShared& L, uint64_t* B, uint32_t n, uint32_t m, uint64_t* tmp,
+                              unsigned long long& moved) {
+    const int t = threadIdx.x;
+    if (m == 0) return n;
+    const uint32_t p = count_less<uint64_t>(B, n, L.src[0]);
+    uint64_t* Bp = B + p;
+    const uint32_t len = n - p;
+    moved += len;
+    for (uint32_t j = t; j < (uint32_t)NW; j += WB) {
+        uint32_t c = 0, f = 0;
+        if (j < m) {
+            c = count_less<uint64_t>(Bp, len, L.src[j]);
+            f = (c < len && Bp[c] == L.src[j]) ? 1u : 0u;
+        }
+        L.lb[j] = c;
+        L.flag[j] = f;
+    }
+    __syncthreads();
+    const uint32_t j0 = 2 * t, j1 = 2 * t + 1;
+    const uint32_t f0 = j0 < m ? L.flag[j0] : 0, f1 = j1 < m ? L.flag[j1] : 0;
+    const uint32_t s0 = (j0 < m && !f0) ? 1 : 0, s1 = (j1 < m && !f1) ? 1 : 0;
+    uint32_t nc, ns;
+    const uint32_t ec = block_excl_scan(L, f0 + f1, nc);
+    const uint32_t es = block_excl_scan(L, s0 + s1, ns);
+    {
+        uint32_t a = ec, b = es;
+        if (f0) L.canc[a++] = L.lb[j0];
+        if (f1) L.canc[a++] = L.lb[j1];
+        if (s0) { L.surv[b] = L.src[j0]; L.lbs[b] = L.lb[j0]; ++b; }
+        if (s1) { L.surv[b] = L.src[j1]; L.lbs[b] = L.lb[j1]; ++b; }
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < len; i += WB) {
+        const uint64_t x = Bp[i];
+        const uint32_t cl = count_less<uint32_t>(L.canc, nc, i);
+        if (cl < nc && L.canc[cl] == i) continue;  // cancelled
+        const uint32_t sl = count_less<uint64_t>(L.surv, ns, x);
+        tmp[i - cl + sl] = x;
+    }
+    for (uint32_t k = t; k < ns; k += WB) {
+        const uint32_t cl = count_less<uint32_t>(L.canc, nc, L.lbs[k]);
+        tmp[k + L.lbs[k] - cl] = L.surv[k];
+    }
+    __syncthreads();
+    const uint32_t r = len - nc + ns;
+    for (uint32_t i = t; i < r; i += WB) Bp[i] = tmp[i];
+    __syncthreads();
+    return p + r;
+}
+
+// sort L.raw[0..np) ascending (np a power of two, PAD last), cancel equal keys
+// mod 2 into L.src; returns the number of keys kept
+__device__ uint32_t sort_cancel(WideShared& L, int np) {
+    const int t = threadIdx.x;
+    for (int size = 2; size <= np; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const int i = 2 * t - (t & (stride - 1));
+            const int j = i + stride;
+            if (j < np) {
+                const bool asc = (i & size) == 0;
+                const uint64_t a = L.raw[i], b = L.raw[j];
+                if ((a > b) == asc) {
+                    L.raw[i] = b;
+                    L.raw[j] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    uint32_t keep[2];
+    for (int q = 0; q < 2; ++q) {
+        const int j = 2 * t + q;
+        const uint64_t x = j < np ? L.raw[j] : PAD;
+        uint32_t k = 0;
+        if (x != PAD && (j == 0 || L.raw[j - 1] != x)) {
+            int r = 1;
+            while (j + r < np && L.raw[j + r] == x) ++r;
+            k = r & 1;
+        }
+        keep[q] = k;
+    }
+    uint32_t total;
+    const uint32_t ex = block_excl_scan(L, keep[0] + keep[1], total);
+    uint32_t a = ex;
+    if (keep[0]) L.src[a++] = L.raw[2 * t];
+    if (keep[1]) L.src[a++] = L.raw[2 * t + 1];
+    __syncthreads();
+    return total;
+}
+
+// Save the ascending boundary B[0..n) to the publication heap in the
+// decreasing layout; returns the offset or PAD when the heap is full.
+__device__ uint64_t save_desc(const D1K& P, WideShared& L, const uint64_t* B, uint32_t n) {
+    const int t = threadIdx.x;
+    if (t == 0) L.u64s[1] = atomicAdd(&P.ctrs[C_HEAP], (unsigned long long)n);
+    __syncthreads();
+    const uint64_t off = L.u64s[1];
+    __syncthreads();
+    if (off + n > P.heap_cap) return PAD;
+    for (uint32_t i = t; i < n; i += WB) st_rlx64(P.heap + off + i, B[n - 1 - i]);
+    wait_stores();
+    __syncthreads();
+    return off;
+}
+
+__global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
+    __shared__ WideShared L;
+    const int t = threadIdx.x;
+    uint64_t* B = P.scratch + (int64_t)blockIdx.x * 2 * P.K;
+    uint64_t* tmp = B + P.K;
+    const int64_t V = P.g.V;
+    unsigned long long steps = 0, evictions = 0, adds = 0, rounds = 0, expanded = 0, moved = 0;
+    for (;;) {
+        if (t == 0) L.u64s[0] = atomicAdd(&P.ctrs[C_NEXT], 1ull);
+        __syncthreads();
+        const uint64_t next = L.u64s[0];
+        __syncthreads();
+        if ((int64_t)next >= P.nwork) break;
+        const uint64_t w = P.work[next];
+        uint32_t c = (uint32_t)(w >> 40);
+        uint32_t n;
+        {
+            const uint64_t off = w & ((1ull << 40) - 1);
+            n = P.work_len[next];
+            if ((int64_t)n > P.K) {
+                if (t == 0) atomicOr(P.flags, FLAG_WORK);
+                break;
+            }
+            for (uint32_t i = t; i < n; i += WB) B[i] = ld_rlx64(P.heap + off + (n - 1 - i));
+        }
+        __syncthreads();
+        bool stop = false;
+        for (int64_t guard = 0;; ++guard) {
+            if (guard > ((int64_t)1 << 24)) {
+                if (t == 0) atomicOr(P.flags, FLAG_GUARD);
+                stop = true;
+                break;
+            }
+            ++steps;
+            if (n == 0) break;  // zero column
+            // scan the top: regular tails before the first other edge
+            if (t == 0) L.ints[0] = WB;
+            __syncthreads();
+            const uint32_t k = n < (uint32_t)WB ? n : (uint32_t)WB;
+            int64_t nw_w = 0;
+            EdgeDec e;
+            if ((uint32_t)t < k) {
+                const uint64_t key = B[n - 1 - t];
+                e = edecode(P.g, P.order, P.bpr, key);
+                const uint8_t code = e.mask ? P.G[(int64_t)e.mask * V + e.lo] : (uint8_t)0xFE;
+                if (code < 27) nw_w = e.lo + lin27(P.g, code);
+                else atomicMin(&L.ints[0], t);
+            }
+            __syncthreads();
+            const uint32_t cstar = (uint32_t)min(L.ints[0], (int)k);
+            __syncthreads();
+            if (cstar > 0) {
+                // expand the top cstar edges together
+                if ((uint32_t)t < cstar) {
+                    const uint32_t rw = P.rank[nw_w];
+                    L.raw[2 * t] = ekey_r(P.bpr, e.ra, rw);
+                    L.raw[2 * t + 1] = ekey_r(P.bpr, e.rb, rw);
+                } else {
+                    L.raw[2 * t] = PAD;
+                    L.raw[2 * t + 1] = PAD;
+                }
+                __syncthreads();
+                int np = 2;
+                while (np < (int)(2 * cstar)) np <<= 1;
+                const uint32_t m = sort_cancel(L, np);
+                ++rounds;
+                expanded += cstar;
+                if ((int64_t)(n - cstar) + m > P.K) {
+                    // no room: save the column unchanged for the next pass
+                    const uint64_t off = save_desc(P, L, B, n);
+                    if (off == PAD) {
+                        if (t == 0) atomicOr(P.flags, FLAG_HEAP);
+                        stop = true;
+                        break;
+                    }
+                    if (t == 0) defer_column(P, c, off, n);
+                    break;
+                }
+                n = merge_xor(L, B, n - cstar, m, tmp, moved);
+                continue;
+            }
+            // the top edge is not a regular tail
+            if (t == 0) {
+                const EdgeDec te = edecode(P.g, P.order, P.bpr, B[n - 1]);
+                const uint8_t code = te.mask ? P.G[(int64_t)te.mask * V + te.lo] : (uint8_t)0xFE;
+                int action = 0;
+                uint32_t o = 0;
+                if (code != CODE_CRIT) {
+                    action = -1;  // the top of a cycle cannot be a vertex's partner
+                } else {
+                    o = ld_rlx(&P.owner1[te.id]);
+                    if (o == OWN_D0) action = -1;
+                    else if (o == EMPTY32 || o > c) action = 1;  // claim
+                    else action = 2;                             // add the owner's boundary
+                }
+                L.ints[2] = action;
+                L.ints[3] = (int)o;
+                L.ints[4] = (int)te.id;
+            }
+            __syncthreads();
+            const int action = L.ints[2];
+            const uint32_t o = (uint32_t)L.ints[3];
+            const uint32_t eid = (uint32_t)L.ints[4];
+            const uint64_t tau = B[n - 1];
+            __syncthreads();
+            if (action < 0) {
+                if (t == 0) atomicOr(P.flags, FLAG_GUARD);
+                stop = true;
+                break;
+            }
+            if (action == 1) {
+                const uint64_t off = save_desc(P, L, B, n);
+                if (off == PAD) {
+                    if (t == 0) atomicOr(P.flags, FLAG_HEAP);
+                    stop = true;
+                    break;
+                }
+                if (t == 0) {
+                    st_rlx64(&P.bndptr[c], (off << 24) | n);
+                    wait_stores();
+                    L.ints[5] = cas32(&P.owner1[eid], o, c) ? 1 : 0;
+                    if (L.ints[5] && o != EMPTY32) L.u64s[2] = ld_rlx64(&P.bndptr[o]);
+                }
+                __syncthreads();
+                const int won = L.ints[5];
+                const uint64_t bo = L.u64s[2];
+                __syncthreads();
+                if (!won) continue;
+                if (o == EMPTY32) break;  // settled
+                ++evictions;
+                c = o;
+                const uint32_t bl = (uint32_t)(bo & 0xFFFFFF);
+                const uint64_t boff = bo >> 24;
+                if ((int64_t)bl > P.K) {
+                    if (t == 0) defer_column(P, c, boff, bl);
+                    break;
+                }
+                for (uint32_t i = t; i < bl; i += WB) B[i] = ld_rlx64(P.heap + boff + (bl - 1 - i));
+                __syncthreads();
+                n = bl;
+                continue;
+            }
+            // action 2: B += Boundary(o), merged in chunks (largest keys first)
+            if (t == 0) {
+                const uint64_t b = ld_rlx64(&P.bndptr[o]);
+                L.u64s[3] = b;
+                L.ints[6] = (b != EMPTY64 && ld_rlx64(P.heap + (b >> 24)) == tau) ? 1 : 0;
+            }
+            __syncthreads();
+            const uint64_t b = L.u64s[3];
+            const int ok = L.ints[6];
+            __syncthreads();
+            if (!ok) continue;  // o moved on: look again
+            const uint64_t aoff = b >> 24;
+            const uint32_t alen = (uint32_t)(b & 0xFFFFFF);
+            if ((int64_t)n + alen > P.K) {
+                // the sum might not fit: hand the column, unchanged, to the next pass
+                const uint64_t off = save_desc(P, L, B, n);
+                if (off == PAD) {
+                    if (t == 0) atomicOr(P.flags, FLAG_HEAP);
+                    stop = true;
+                    break;
+                }
+                if (t == 0) defer_column(P, c, off, n);
+                break;
+            }
+            ++adds;
+            for (uint32_t base = 0; base < alen; base += NW) {
+                const uint32_t m = min((uint32_t)NW, alen - base);
+                for (uint32_t j = t; j < m; j += WB) L.src[j] = ld_rlx64(P.heap + aoff + base + (m - 1 - j));
+                __syncthreads();
+                n = merge_xor(L, B, n, m, tmp, moved);
+            }
+        }
+        __syncthreads();
+        if (stop) break;
+    }
+    if (t == 0) {
+        atomicAdd(&P.ctrs[C_STEPS], steps);
+        atomicAdd(&P.ctrs[C_EVICT], evictions);
+        atomicAdd(&P.ctrs[C_ADDS], adds);
+        atomicAdd(&P.ctrs[C_ROUNDS], rounds);
+        atomicAdd(&P.ctrs[C_EXPANDED], expanded);
+        atomicAdd(&P.ctrs[C_MOVED], moved);
+    }
+}
+
 __global__ void k_init_owner(const uint32_t* c1, const uint8_t* paired1, int64_t m1, uint32_t* owner1) {
     const int64_t i = (int64_t)blockIdx.x * DB + threadIdx.x;
     if (i < m1) owner1[c1[i]] = paired1[i] ? OWN_D0 : EMPTY32;
@@ -452,6 +811,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
     if (grow(s.owner1, s.owner1_cap, 4 * 7 * V, s.bytes)) return oom("owners");
     for (int d = 0; d < 6; ++d) s.stats[d] = 0;
     for (int d = 0; d < 5; ++d) s.pass_work[d] = s.pass_us[d] = 0;
+    for (int d = 0; d < 3; ++d) s.wide[d] = 0;
     // unpaired 2-saddles, ascending
     uint32_t* flag = (uint32_t*)s.colflag;
     uint32_t* cols = (uint32_t*)s.cols;
@@ -482,9 +842,8 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         if (grow(s.heap, s.heap_cap, std::max<size_t>((size_t)8 << 22, (size_t)8 * 32 * ncols), s.bytes))
             return oom("boundary heap");
     }
-    const int64_t lanes = (int64_t)1 << 18;  // first pass: 262144 threads x 64 entries
-    const int64_t k0 = 64;
-    if (grow(s.scratch, s.scratch_cap, (size_t)8 * lanes * k0, s.bytes)) return oom("working heaps");
+    const int64_t lanes = (int64_t)1 << 18;  // first pass: 262144 threads x 256 entries
+    const int64_t k0 = 256;
     if (in.m1 > 0)
         hipLaunchKernelGGL(k_init_owner, dim3(nblocks(in.m1)), dim3(DB), 0, st, in.c1, in.paired1, in.m1,
                            (uint32_t*)s.owner1);
@@ -502,11 +861,22 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         int64_t nwork = ncols;
         int cur = 0;
         bool overflow = false;
-        int64_t K = k0;
-        unsigned long long hc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        unsigned long long hc[16] = {0};
+        // pass plan: thread-per-column with small heaps, then one workgroup per
+        // column with boundaries of up to plan_k entries
+        int64_t plan_k[MAX_PASSES] = {k0, (int64_t)1 << 15, (int64_t)1 << 20, (int64_t)1 << 24, 0};
+        int64_t plan_t[MAX_PASSES] = {lanes, 1024, 32, 2, 0};
+        if (std::getenv("DMS_D1_TEST_PLAN")) {  // test hook: tiny capacities, every pass used
+            plan_k[0] = 4;
+            plan_k[1] = 24;
+        }
         for (int pass = 0; pass < MAX_PASSES && nwork > 0; ++pass) {
-            const int64_t T = std::max<int64_t>(1, std::min<int64_t>(nwork, (lanes * k0) / K));
+            const int64_t K = plan_k[pass];
+            if (K == 0) break;
+            const int64_t T = std::max<int64_t>(1, std::min<int64_t>(nwork, plan_t[pass]));
             const auto t_pass = std::chrono::steady_clock::now();
+            const size_t need = pass == 0 ? (size_t)8 * T * K : (size_t)8 * 2 * T * K;
+            if (grow(s.scratch, s.scratch_cap, need, s.bytes)) return oom("working boundaries");
             D1K P;
             P.g = in.g;
             P.G = in.G;
@@ -527,14 +897,18 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             P.scratch = (uint64_t*)s.scratch;
             P.K = K;
             P.nthreads = T;
+            P.lds = 0;
             P.ctrs = (unsigned long long*)s.ctrs;
             P.flags = in.flags;
             // fresh work cursor, deferral count and work counters for this pass
-            if (hipMemsetAsync((unsigned long long*)s.ctrs + C_NEXT, 0, 5 * 8, st) != hipSuccess) return -5;
-            hipLaunchKernelGGL(k_d1, dim3(nblocks(T)), dim3(DB), 0, st, P);
+            if (hipMemsetAsync((unsigned long long*)s.ctrs + C_NEXT, 0, 8 * 8, st) != hipSuccess) return -5;
+            if (pass == 0)
+                hipLaunchKernelGGL(k_d1, dim3(nblocks(T)), dim3(DB), 0, st, P);
+            else
+                hipLaunchKernelGGL(k_d1_wide, dim3((unsigned)T), dim3(WB), 0, st, P);
             uint32_t f = 0;
             if (hipMemcpyAsync(&f, in.flags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
-                hipMemcpyAsync(hc, s.ctrs, 64, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipMemcpyAsync(hc, s.ctrs, 128, hipMemcpyDeviceToHost, st) != hipSuccess ||
                 hipStreamSynchronize(st) != hipSuccess) {
                 err = "D1: kernel failed";
                 return -5;
@@ -551,13 +925,15 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             s.stats[1] += hc[C_EVICT];
             s.stats[2] += hc[C_ADDS];
             s.stats[3] += hc[C_DEFER];
+            s.wide[0] += hc[C_ROUNDS];
+            s.wide[1] += hc[C_EXPANDED];
+            s.wide[2] += hc[C_MOVED];
             if (f & (FLAG_HEAP | FLAG_WORK)) {
                 overflow = true;
                 break;
             }
             nwork = (int64_t)hc[C_DEFER];
             cur ^= 1;
-            K *= 16;
         }
         s.stats[4] = hc[C_HEAP];
         s.stats[5] = restart;

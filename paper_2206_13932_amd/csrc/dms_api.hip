@@ -653,6 +653,7 @@ int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap) {
                 h[10 + 2 * i] = ctx->d1.pass_work[i];
                 h[11 + 2 * i] = ctx->d1.pass_us[i];
             }
+            for (int i = 0; i < 3; ++i) h[20 + i] = ctx->d1.wide[i];
             return bytes;
         }
         case DMS_BUF_D1LEN: {

@@ -52,7 +52,7 @@ def test_simplex_counts_closed_form(shape):
         assert int((res.partner[d] != -2).sum()) == _closed_counts(shape)[d]
 
 
-def test_closed_form_values_printed_in_survey_table():
+def test_closed_form_values_at_16_and_512():
     # counts at 16^3 and 512^3 (the second is formula-only)
     assert _closed_counts((16, 16, 16)) == [4096, 25695, 41850, 20250]
     assert _closed_counts((512, 512, 512)) == [134217728, 936381439, 1602760698, 800596986]
@@ -284,3 +284,17 @@ def test_noise_extrema_statistics():
     assert abs(e_min - 312.63) < 0.01
     assert abs(np.mean(mins) - e_min) < 4 * np.sqrt(e_min / len(mins))
     assert abs(np.mean(maxs) - e_max) < 4 * np.sqrt(e_max / len(maxs))
+
+
+def test_golden_simplex_counts():
+    """tests/golden/simplex_counts.json (closed forms) against the brute-force
+    enumeration of all faces of all Kuhn tetrahedra."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "simplex_counts.json")
+    gold = json.load(open(path))
+    for key, val in gold.items():
+        nx, ny, nz = map(int, key.split("x"))
+        if nx * ny * nz <= 4096:
+            assert list(oracle.bf_counts((nz, ny, nx))) == val, key
+    assert gold["512x512x512"] == [134217728, 936381439, 1602760698, 800596986]
