@@ -383,7 +383,9 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
 // owner rule runs as in k_d1, with cached boundaries merged in chunks.
 // Published boundaries keep the decreasing layout (top first).
 constexpr int WB = 256;
-constexpr int NW = 2 * WB;
+constexpr int NW = 4 * WB;  // keys merged per step: 2 new keys + 1 kept entry per window slot
+constexpr int IPW = NW / WB;
+constexpr uint32_t BATCH_ADD_MAX = 32;  // longest cached boundary added out of order in a round
 constexpr uint64_t PAD = ~0ull;
 
 struct WideShared {
@@ -395,6 +397,9 @@ struct WideShared {
     uint32_t canc[NW];  // B-suffix indices cancelled by src, ascending
     uint32_t flag[NW];
     uint32_t scan[WB];
+    uint64_t scan64[WB];
+    uint64_t zoff[WB];  // per window entry: cached boundary to add (offset of its second entry)
+    uint32_t zlen[WB];  //   and the number of entries after its head; 0 = none
     int ints[8];
     uint64_t u64s[4];
 };
@@ -411,6 +416,22 @@ __device__ inline uint32_t block_excl_scan(WideShared& L, uint32_t v, uint32_t& 
     }
     total = L.scan[WB - 1];
     const uint32_t ex = L.scan[t] - v;
+    __syncthreads();
+    return ex;
+}
+
+// exclusive prefix maximum of v over the block (0 for thread 0)
+__device__ inline uint64_t block_excl_max(WideShared& L, uint64_t v) {
+    const int t = threadIdx.x;
+    L.scan64[t] = v;
+    __syncthreads();
+    for (int d = 1; d < WB; d <<= 1) {
+        const uint64_t a = t >= d ? L.scan64[t - d] : 0;
+        __syncthreads();
+        if (a > L.scan64[t]) L.scan64[t] = a;
+        __syncthreads();
+    }
+    const uint64_t ex = t > 0 ? L.scan64[t - 1] : 0;
     __syncthreads();
     return ex;
 }
@@ -447,18 +468,29 @@ __device__ uint32_t merge_xor(WideShared& L, uint64_t* B, uint32_t n, uint32_t m
         L.flag[j] = f;
     }
     __syncthreads();
-    const uint32_t j0 = 2 * t, j1 = 2 * t + 1;
-    const uint32_t f0 = j0 < m ? L.flag[j0] : 0, f1 = j1 < m ? L.flag[j1] : 0;
-    const uint32_t s0 = (j0 < m && !f0) ? 1 : 0, s1 = (j1 < m && !f1) ? 1 : 0;
+    uint32_t fc = 0, sc = 0;
+    for (int q = 0; q < IPW; ++q) {
+        const uint32_t j = IPW * t + q;
+        if (j < m) {
+            fc += L.flag[j];
+            sc += 1 - L.flag[j];
+        }
+    }
     uint32_t nc, ns;
-    const uint32_t ec = block_excl_scan(L, f0 + f1, nc);
-    const uint32_t es = block_excl_scan(L, s0 + s1, ns);
+    const uint32_t ec = block_excl_scan(L, fc, nc);
+    const uint32_t es = block_excl_scan(L, sc, ns);
     {
         uint32_t a = ec, b = es;
-        if (f0) L.canc[a++] = L.lb[j0];
-        if (f1) L.canc[a++] = L.lb[j1];
-        if (s0) { L.surv[b] = L.src[j0]; L.lbs[b] = L.lb[j0]; ++b; }
-        if (s1) { L.surv[b] = L.src[j1]; L.lbs[b] = L.lb[j1]; ++b; }
+        for (int q = 0; q < IPW; ++q) {
+            const uint32_t j = IPW * t + q;
+            if (j >= m) break;
+            if (L.flag[j]) L.canc[a++] = L.lb[j];
+            else {
+                L.surv[b] = L.src[j];
+                L.lbs[b] = L.lb[j];
+                ++b;
+            }
+        }
     }
     __syncthreads();
     for (uint32_t i = t; i < len; i += WB) {
@@ -485,9 +517,9 @@ __device__ uint32_t sort_cancel(WideShared& L, int np) {
     const int t = threadIdx.x;
     for (int size = 2; size <= np; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            const int i = 2 * t - (t & (stride - 1));
-            const int j = i + stride;
-            if (j < np) {
+            for (int pp = t; pp < np / 2; pp += WB) {
+                const int i = 2 * pp - (pp & (stride - 1));
+                const int j = i + stride;
                 const bool asc = (i & size) == 0;
                 const uint64_t a = L.raw[i], b = L.raw[j];
                 if ((a > b) == asc) {
@@ -498,9 +530,10 @@ __device__ uint32_t sort_cancel(WideShared& L, int np) {
             __syncthreads();
         }
     }
-    uint32_t keep[2];
-    for (int q = 0; q < 2; ++q) {
-        const int j = 2 * t + q;
+    uint32_t keep[IPW];
+    uint32_t kc = 0;
+    for (int q = 0; q < IPW; ++q) {
+        const int j = IPW * t + q;
         const uint64_t x = j < np ? L.raw[j] : PAD;
         uint32_t k = 0;
         if (x != PAD && (j == 0 || L.raw[j - 1] != x)) {
@@ -509,12 +542,13 @@ __device__ uint32_t sort_cancel(WideShared& L, int np) {
             k = r & 1;
         }
         keep[q] = k;
+        kc += k;
     }
     uint32_t total;
-    const uint32_t ex = block_excl_scan(L, keep[0] + keep[1], total);
+    const uint32_t ex = block_excl_scan(L, kc, total);
     uint32_t a = ex;
-    if (keep[0]) L.src[a++] = L.raw[2 * t];
-    if (keep[1]) L.src[a++] = L.raw[2 * t + 1];
+    for (int q = 0; q < IPW; ++q)
+        if (keep[q]) L.src[a++] = L.raw[IPW * t + q];
     __syncthreads();
     return total;
 }
@@ -569,39 +603,79 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
             }
             ++steps;
             if (n == 0) break;  // zero column
-            // scan the top: regular tails before the first other edge
+            // scan the top window. Above the first stopping edge, every regular tail
+            // (add its partner's boundary) and every critical edge owned by an earlier
+            // column with a short cached boundary (add it) is processed this round.
+            // Edges that are never a pivot (vertex partners, D0-paired edges) are
+            // kept without stopping. A possible pivot (free or later-owned critical
+            // edge) stops the round, and so does an earlier-owned one with a long
+            // cached boundary, which is added in order when it reaches the top: adding
+            // long boundaries out of order inflates the boundaries cached later. The
+            // top must be processable, otherwise the owner rule runs.
+            const uint32_t k = n < (uint32_t)WB ? n : (uint32_t)WB;
+            for (int q = 0; q < IPW; ++q) L.raw[IPW * t + q] = PAD;
+            L.zlen[t] = 0;
+            L.flag[t] = 0;
             if (t == 0) L.ints[0] = WB;
             __syncthreads();
-            const uint32_t k = n < (uint32_t)WB ? n : (uint32_t)WB;
-            int64_t nw_w = 0;
-            EdgeDec e;
+            uint64_t wkey = 0;
+            uint64_t nk0 = PAD, nk1 = PAD;
+            int cls = 0;  // 0 none/stop, 1 processable, 2 kept (never a pivot)
             if ((uint32_t)t < k) {
-                const uint64_t key = B[n - 1 - t];
-                e = edecode(P.g, P.order, P.bpr, key);
+                wkey = B[n - 1 - t];
+                const EdgeDec e = edecode(P.g, P.order, P.bpr, wkey);
                 const uint8_t code = e.mask ? P.G[(int64_t)e.mask * V + e.lo] : (uint8_t)0xFE;
-                if (code < 27) nw_w = e.lo + lin27(P.g, code);
-                else atomicMin(&L.ints[0], t);
+                if (code < 27) {
+                    const uint32_t rw = P.rank[e.lo + lin27(P.g, code)];
+                    nk0 = ekey_r(P.bpr, e.ra, rw);
+                    nk1 = ekey_r(P.bpr, e.rb, rw);
+                    cls = 1;
+                } else if (code == CODE_CRIT) {
+                    const uint32_t o = ld_rlx(&P.owner1[e.id]);
+                    if (o == OWN_D0) {
+                        cls = 2;
+                    } else if (o != EMPTY32 && o < c && t > 0) {
+                        // (a critical top goes through the owner rule below)
+                        const uint64_t bo = ld_rlx64(&P.bndptr[o]);
+                        const uint32_t zl = (uint32_t)(bo & 0xFFFFFF) - 1;
+                        if (bo != EMPTY64 && zl <= BATCH_ADD_MAX && ld_rlx64(P.heap + (bo >> 24)) == wkey) {
+                            L.zoff[t] = (bo >> 24) + 1;
+                            L.zlen[t] = zl;
+                            cls = 1;
+                        }
+                    }
+                } else if (code >= 0x80 && code < 0xFE) {
+                    cls = 2;  // vertex partner
+                }
+            }
+            if ((uint32_t)t < k && cls == 0) atomicMin(&L.ints[0], t);
+            __syncthreads();
+            const uint32_t stop_at = (uint32_t)L.ints[0];
+            if ((uint32_t)t < k) {
+                const bool go = cls == 1 && (uint32_t)t < stop_at;
+                if (go) {
+                    L.raw[2 * t] = nk0;
+                    L.raw[2 * t + 1] = nk1;
+                } else {
+                    L.zlen[t] = 0;
+                    L.raw[2 * k + t] = wkey;  // kept: re-inserted below
+                }
+                L.flag[t] = go ? 1u : 0u;
             }
             __syncthreads();
-            const uint32_t cstar = (uint32_t)min(L.ints[0], (int)k);
+            const bool top_go = L.flag[0] != 0;
             __syncthreads();
-            if (cstar > 0) {
-                // expand the top cstar edges together
-                if ((uint32_t)t < cstar) {
-                    const uint32_t rw = P.rank[nw_w];
-                    L.raw[2 * t] = ekey_r(P.bpr, e.ra, rw);
-                    L.raw[2 * t + 1] = ekey_r(P.bpr, e.rb, rw);
-                } else {
-                    L.raw[2 * t] = PAD;
-                    L.raw[2 * t + 1] = PAD;
-                }
-                __syncthreads();
+            if (top_go) {
+                uint32_t zsum;
+                block_excl_scan(L, L.zlen[t], zsum);
+                uint32_t nproc;
+                block_excl_scan(L, L.flag[t], nproc);
                 int np = 2;
-                while (np < (int)(2 * cstar)) np <<= 1;
+                while (np < (int)(3 * k)) np <<= 1;
                 const uint32_t m = sort_cancel(L, np);
                 ++rounds;
-                expanded += cstar;
-                if ((int64_t)(n - cstar) + m > P.K) {
+                expanded += nproc;
+                if ((int64_t)(n - k) + m + zsum > P.K) {
                     // no room: save the column unchanged for the next pass
                     const uint64_t off = save_desc(P, L, B, n);
                     if (off == PAD) {
@@ -612,7 +686,20 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
                     if (t == 0) defer_column(P, c, off, n);
                     break;
                 }
-                n = merge_xor(L, B, n - cstar, m, tmp, moved);
+                // the window leaves; new keys and the kept entries come back in
+                n = merge_xor(L, B, n - k, m, tmp, moved);
+                for (uint32_t q = 1; q < k; ++q) {
+                    const uint32_t zl = L.zlen[q];
+                    if (zl == 0) continue;
+                    ++adds;
+                    const uint64_t zo = L.zoff[q];
+                    for (uint32_t base = 0; base < zl; base += NW) {
+                        const uint32_t mm = min((uint32_t)NW, zl - base);
+                        for (uint32_t j = t; j < mm; j += WB) L.src[j] = ld_rlx64(P.heap + zo + base + (mm - 1 - j));
+                        __syncthreads();
+                        n = merge_xor(L, B, n, mm, tmp, moved);
+                    }
+                }
                 continue;
             }
             // the top edge is not a regular tail
