@@ -650,15 +650,42 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
             }
             if ((uint32_t)t < k && cls == 0) atomicMin(&L.ints[0], t);
             __syncthreads();
-            const uint32_t stop_at = (uint32_t)L.ints[0];
-            if ((uint32_t)t < k) {
-                const bool go = cls == 1 && (uint32_t)t < stop_at;
-                if (go) {
-                    L.raw[2 * t] = nk0;
-                    L.raw[2 * t + 1] = nk1;
-                } else {
-                    L.zlen[t] = 0;
-                    L.raw[2 * k + t] = wkey;  // kept: re-inserted below
+            uint32_t stop_at = (uint32_t)L.ints[0];
+            // room in the merge list: every window entry reserves one slot (a kept
+            // entry needs exactly that); a processed tail needs one more, a batched
+            // cached boundary its length minus one more. Stop where it would overflow.
+            {
+                uint32_t extra = 0;
+                if ((uint32_t)t < k && cls == 1) extra = (L.zlen[t] ? L.zlen[t] : 2) - 1;
+                uint32_t tot;
+                const uint32_t ex = block_excl_scan(L, extra, tot);
+                if (t == 0) L.ints[1] = WB;
+                __syncthreads();
+                if ((uint32_t)t < k && k + ex + extra > (uint32_t)NW) atomicMin(&L.ints[1], t);
+                __syncthreads();
+                if ((uint32_t)L.ints[1] < stop_at) stop_at = (uint32_t)L.ints[1];
+                __syncthreads();
+            }
+            uint32_t slot = 0;
+            {
+                uint32_t need = 0;
+                const bool go = (uint32_t)t < k && cls == 1 && (uint32_t)t < stop_at;
+                if ((uint32_t)t < k) need = go ? (L.zlen[t] ? L.zlen[t] : 2) : 1;
+                uint32_t tot;
+                slot = block_excl_scan(L, need, tot);
+                L.ints[7] = (int)tot;  // same value from every thread
+                if ((uint32_t)t < k) {
+                    if (go) {
+                        if (L.zlen[t]) {
+                            const uint64_t zo = L.zoff[t];
+                            for (uint32_t j = 0; j < L.zlen[t]; ++j) L.raw[slot + j] = ld_rlx64(P.heap + zo + j);
+                        } else {
+                            L.raw[slot] = nk0;
+                            L.raw[slot + 1] = nk1;
+                        }
+                    } else {
+                        L.raw[slot] = wkey;  // kept: re-inserted below
+                    }
                 }
                 L.flag[t] = go ? 1u : 0u;
             }
@@ -666,16 +693,15 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
             const bool top_go = L.flag[0] != 0;
             __syncthreads();
             if (top_go) {
-                uint32_t zsum;
-                block_excl_scan(L, L.zlen[t], zsum);
+                const uint32_t total = (uint32_t)L.ints[7];
                 uint32_t nproc;
                 block_excl_scan(L, L.flag[t], nproc);
                 int np = 2;
-                while (np < (int)(3 * k)) np <<= 1;
+                while (np < (int)total) np <<= 1;
                 const uint32_t m = sort_cancel(L, np);
                 ++rounds;
                 expanded += nproc;
-                if ((int64_t)(n - k) + m + zsum > P.K) {
+                if ((int64_t)(n - k) + m > P.K) {
                     // no room: save the column unchanged for the next pass
                     const uint64_t off = save_desc(P, L, B, n);
                     if (off == PAD) {
@@ -686,20 +712,8 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
                     if (t == 0) defer_column(P, c, off, n);
                     break;
                 }
-                // the window leaves; new keys and the kept entries come back in
+                // the window leaves; new keys, batched boundaries and kept entries come in
                 n = merge_xor(L, B, n - k, m, tmp, moved);
-                for (uint32_t q = 1; q < k; ++q) {
-                    const uint32_t zl = L.zlen[q];
-                    if (zl == 0) continue;
-                    ++adds;
-                    const uint64_t zo = L.zoff[q];
-                    for (uint32_t base = 0; base < zl; base += NW) {
-                        const uint32_t mm = min((uint32_t)NW, zl - base);
-                        for (uint32_t j = t; j < mm; j += WB) L.src[j] = ld_rlx64(P.heap + zo + base + (mm - 1 - j));
-                        __syncthreads();
-                        n = merge_xor(L, B, n, mm, tmp, moved);
-                    }
-                }
                 continue;
             }
             // the top edge is not a regular tail
