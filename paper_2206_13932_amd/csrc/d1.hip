@@ -48,6 +48,12 @@ inline unsigned nblocks(int64_t n) { return (unsigned)((n + DB - 1) / DB); }
 // counters in D1State::ctrs
 enum { C_HEAP = 0, C_NEXT = 1, C_DEFER = 2, C_STEPS = 3, C_EVICT = 4, C_ADDS = 5, C_ROUNDS = 6, C_EXPANDED = 7,
        C_MOVED = 8 };
+// The publication heap is split into NSEG segments with one bump counter each
+// (counters 128 bytes apart, after the 16 counters above), so that millions of
+// publications do not serialise on one atomic.
+constexpr int NSEG = 64;
+constexpr int SEG_STRIDE = 16;
+constexpr int SEG_BASE = 16;
 
 struct D1K {
     GridDev g;
@@ -66,7 +72,8 @@ struct D1K {
     uint32_t* owner1;
     uint64_t* bndptr;
     uint64_t* heap;
-    uint64_t heap_cap;
+    uint64_t heap_cap;  // entries
+    uint64_t seg_cap;   // entries per segment
     uint64_t* scratch;
     int64_t K;
     int64_t nthreads;
@@ -195,14 +202,21 @@ struct Heap {
     }
 };
 
+// Reserve len entries of the publication heap in segment seg; NONE when full.
+__device__ inline uint64_t heap_alloc(const D1K& P, uint32_t seg, uint64_t len) {
+    const uint64_t off = atomicAdd(&P.ctrs[SEG_BASE + SEG_STRIDE * (seg % NSEG)], (unsigned long long)len);
+    if (off + len > P.seg_cap) return NONE;
+    return (uint64_t)(seg % NSEG) * P.seg_cap + off;
+}
+
 // Copy {top (optional)} + heap (compacted) to the publication heap; returns
 // the packed (offset << 24 | length) or NONE when the heap is full.
 __device__ inline uint64_t publish(const D1K& P, Heap& H, bool with_top, uint64_t top) {
     H.compact();
     const uint64_t len = (uint64_t)H.n + (with_top ? 1 : 0);
     if (len >= (1ull << 24)) return NONE;
-    const uint64_t off = atomicAdd(&P.ctrs[C_HEAP], (unsigned long long)len);
-    if (off + len > P.heap_cap) return NONE;
+    const uint64_t off = heap_alloc(P, (uint32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), len);
+    if (off == NONE) return NONE;
     uint64_t* A = P.heap + off;
     int64_t k = 0;
     if (with_top) st_rlx64(&A[k++], top);
@@ -233,8 +247,10 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
     const int64_t V = P.g.V;
     unsigned long long steps = 0, evictions = 0, adds = 0;
     for (;;) {
-        const uint64_t next = atomicAdd(&P.ctrs[C_NEXT], 1ull);
-        if ((int64_t)next >= P.nwork) break;
+        // columns are taken in increasing order: the frontier of columns in flight
+        // stays narrow, which keeps evictions rare
+        const int64_t next = (int64_t)atomicAdd(&P.ctrs[C_NEXT], 1ull);
+        if (next >= P.nwork) break;
         uint32_t c;
         H.n = 0;
         if (!P.work) {
@@ -557,11 +573,11 @@ __device__ uint32_t sort_cancel(WideShared& L, int np) {
 // decreasing layout; returns the offset or PAD when the heap is full.
 __device__ uint64_t save_desc(const D1K& P, WideShared& L, const uint64_t* B, uint32_t n) {
     const int t = threadIdx.x;
-    if (t == 0) L.u64s[1] = atomicAdd(&P.ctrs[C_HEAP], (unsigned long long)n);
+    if (t == 0) L.u64s[1] = heap_alloc(P, blockIdx.x, n);
     __syncthreads();
     const uint64_t off = L.u64s[1];
     __syncthreads();
-    if (off + n > P.heap_cap) return PAD;
+    if (off == NONE) return PAD;
     for (uint32_t i = t; i < n; i += WB) st_rlx64(P.heap + off + i, B[n - 1 - i]);
     wait_stores();
     __syncthreads();
@@ -905,7 +921,8 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         err = std::string("D1: cannot allocate ") + what;
         return -3;  // DMS_E_NOMEM
     };
-    if (!s.ctrs && hipMalloc(&s.ctrs, 128) != hipSuccess) return oom("counters");
+    const size_t ctr_bytes = 8 * (SEG_BASE + SEG_STRIDE * NSEG);
+    if (!s.ctrs && hipMalloc(&s.ctrs, ctr_bytes) != hipSuccess) return oom("counters");
     if (grow(s.colflag, s.colflag_cap, 4 * (m2 + 1), s.bytes)) return oom("column flags");
     if (grow(s.cols, s.cols_cap, 4 * (m2 + 1), s.bytes)) return oom("columns");
     if (grow(s.scanpart, s.scanpart_cap, 4 * scan_part_size(m2 + 1), s.bytes)) return oom("scan");
@@ -950,7 +967,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
                            (uint32_t*)s.owner1);
     if (ncols == 0) return 0;
     for (int restart = 0; restart < 4; ++restart) {
-        if (hipMemsetAsync(s.ctrs, 0, 128, st) != hipSuccess) return -5;
+        if (hipMemsetAsync(s.ctrs, 0, ctr_bytes, st) != hipSuccess) return -5;
         if (hipMemsetAsync(in.flags, 0, 4, st) != hipSuccess) return -5;
         fill_u64((uint64_t*)s.bndptr, EMPTY64, ncols, st);
         if (restart > 0 && in.m1 > 0)
@@ -995,6 +1012,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             P.bndptr = (uint64_t*)s.bndptr;
             P.heap = (uint64_t*)s.heap;
             P.heap_cap = s.heap_cap / 8;
+            P.seg_cap = P.heap_cap / NSEG;
             P.scratch = (uint64_t*)s.scratch;
             P.K = K;
             P.nthreads = T;
@@ -1036,6 +1054,14 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             nwork = (int64_t)hc[C_DEFER];
             cur ^= 1;
         }
+        {
+            uint64_t used = 0, segs[SEG_STRIDE * NSEG];
+            if (hipMemcpy(segs, (unsigned long long*)s.ctrs + SEG_BASE, sizeof(segs), hipMemcpyDeviceToHost) !=
+                hipSuccess)
+                return -5;
+            for (int q = 0; q < NSEG; ++q) used += segs[SEG_STRIDE * q];
+            hc[C_HEAP] = used;
+        }
         s.stats[4] = hc[C_HEAP];
         s.stats[5] = restart;
         if (!overflow) {
@@ -1046,7 +1072,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             return 0;
         }
         // publication heap exhausted: grow it and redo D1 from the start
-        const size_t want = std::max<size_t>(2 * s.heap_cap, (size_t)16 * hc[C_HEAP]);
+        const size_t want = std::max<size_t>(2 * s.heap_cap, (size_t)16 * hc[C_HEAP]);  // segments fill unevenly
         if (grow(s.heap, s.heap_cap, want, s.bytes)) return oom("boundary heap");
     }
     err = "D1: boundary storage kept overflowing";

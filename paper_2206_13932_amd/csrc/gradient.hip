@@ -64,7 +64,6 @@ __device__ inline uint32_t wave_reserve(uint32_t cnt, uint32_t* counter) {
 __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __restrict__ rank,
                                                  uint8_t* __restrict__ G, int bpr, CritLists cl) {
     __shared__ LdsTables T;
-    __shared__ uint16_t skey[NSLOT * GB];
     __shared__ uint8_t scode[NSLOT * GB];  // partner code of each slot, written out coalesced
     const int tid = threadIdx.x;
     // cooperative copy of the star tables into LDS
@@ -87,7 +86,6 @@ __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __re
     const int64_t x = (int64_t)blockIdx.x * GB + tid;
     const bool active = x < g.V;
     const int64_t V = g.V;
-#define KEY(s) skey[(s) * GB + tid]
 #define CODE(s) scode[(s) * GB + tid]
 
     uint64_t crit_lo = 0;
@@ -137,21 +135,26 @@ __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __re
                 relpack |= (uint64_t)c << (4 * n);
                 if (((lower >> n) & 1) && c == 0) n0 = n;
             }
-            // cells of L(x) and their keys
+            // cells of L(x)
 #pragma unroll
             for (int s = 0; s < NSLOT; ++s) {
                 const uint32_t nb = kStar.cellnb[s];
-                const bool inl = (nb & ~lower) == 0;
-                uint32_t key = 0;
-#pragma unroll
-                for (int n = 0; n < NNB; ++n)
-                    if (nb & (1u << n)) key |= 1u << ((relpack >> (4 * n)) & 15);
-                if (inl) {
-                    KEY(s) = (uint16_t)key;
+                if ((nb & ~lower) == 0) {
                     if (s < 64) in_lo |= (uint64_t)1 << s;
                     else in_hi |= 1u << (s - 64);
                 }
             }
+            // key of a cell of L(x): bitmask of its lower neighbours' rank labels
+            auto key_of = [&](int s) {
+                uint32_t nb = T.cellnb[s];
+                uint32_t key = 0;
+                while (nb) {
+                    const int n = __builtin_ctz(nb);
+                    nb &= nb - 1;
+                    key |= 1u << ((uint32_t)(relpack >> (4 * n)) & 15u);
+                }
+                return key;
+            };
             auto anchor = [&](int s) { return x + T.aofflin[s]; };
             auto gput = [&](int s, uint8_t code) { CODE(s) = code; };
             (void)anchor;
@@ -193,14 +196,14 @@ __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __re
                 while (m) {
                     const int s = __builtin_ctzll(m);
                     m &= m - 1;
-                    const uint32_t k = KEY(s);
+                    const uint32_t k = key_of(s);
                     if (k < bk) { bk = k; best = s; }
                 }
                 uint32_t h = hi;
                 while (h) {
                     const int s = 64 + __builtin_ctz(h);
                     h &= h - 1;
-                    const uint32_t k = KEY(s);
+                    const uint32_t k = key_of(s);
                     if (k < bk) { bk = k; best = s; }
                 }
                 if (best < 64) lo &= ~((uint64_t)1 << best);

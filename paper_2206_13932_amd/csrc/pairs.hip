@@ -168,13 +168,13 @@ __device__ inline bool cas32(uint32_t* p, uint32_t expect, uint32_t desired) {
 __global__ void k_reduce_pairs(const uint32_t* __restrict__ na, const uint32_t* __restrict__ nb, int64_t m,
                                uint32_t* owner, uint64_t* bnd, uint32_t* flags, unsigned long long* stats) {
     const int64_t j = (int64_t)blockIdx.x * PB + threadIdx.x;
-    if (j >= m) return;
+    const bool live = j < m;  // every lane reaches the wavefront reduction below
     uint32_t c = (uint32_t)j;
-    uint32_t p = na[j], q = nb[j];
+    uint32_t p = live ? na[j] : 0, q = live ? nb[j] : 0;
     if (p < q) { uint32_t t = p; p = q; q = t; }
     const int64_t limit = (int64_t)1 << 26;
     unsigned long long steps = 0, evictions = 0;
-    for (int64_t guard = 0;; ++guard) {
+    for (int64_t guard = 0; live; ++guard) {
         if (guard > limit) { atomicOr(flags, FLAG_GUARD); break; }
         if (p == q) break;  // column reduced to zero: a positive arc
         ++steps;
@@ -206,9 +206,16 @@ __global__ void k_reduce_pairs(const uint32_t* __restrict__ na, const uint32_t* 
             q = (uint32_t)b;
         }
     }
-    if (stats) {
-        atomicAdd(&stats[0], steps);
-        atomicAdd(&stats[1], evictions);
+    if (stats) {  // one atomic per wavefront
+        unsigned long long a = steps, b = evictions;
+        for (int d = 32; d > 0; d >>= 1) {
+            a += __shfl_xor(a, d, 64);
+            b += __shfl_xor(b, d, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(&stats[0], a);
+            atomicAdd(&stats[1], b);
+        }
     }
 }
 
