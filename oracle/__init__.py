@@ -70,6 +70,8 @@ def _lib(name: str) -> ctypes.CDLL:
         lib.bf_diagram.argtypes = [i64, i64, i64, p, p, i64, p, i64, p]
         lib.bf_diagram.restype = i64
         lib.bf_lower_link_betti.argtypes = [i64, i64, i64, p, p]
+        lib.bf_d0_kruskal.argtypes = [i64, i64, i64, p, p, i64]
+        lib.bf_d0_kruskal.restype = i64
     _loaded[name] = lib
     return lib
 
@@ -163,6 +165,17 @@ def bf_diagram(shape, rank: np.ndarray):
     n_ess = ctypes.c_int64()
     m = lib.bf_diagram(nx, ny, nz, _ptr(r), _ptr(pairs), cap, _ptr(ess), 64, ctypes.byref(n_ess))
     return pairs[:m].copy(), ess[: min(n_ess.value, 64)].copy()
+
+
+def bf_d0_kruskal(shape, rank: np.ndarray) -> np.ndarray:
+    """D0 of the lexicographic filtration from Kruskal's union-find over all
+    edges: (birth rank, death rank) pairs with positive persistence, sorted."""
+    nz, ny, nx = shape
+    r = np.ascontiguousarray(rank, dtype=np.uint32)
+    cap = nx * ny * nz
+    out = np.empty((cap, 2), dtype=np.int64)
+    m = _lib("bruteforce").bf_d0_kruskal(nx, ny, nz, _ptr(r), _ptr(out), cap)
+    return out[:m].copy()
 
 
 def bf_lower_link_betti(shape, rank: np.ndarray) -> np.ndarray:

@@ -241,3 +241,58 @@ void bf_lower_link_betti(int64_t nx, int64_t ny, int64_t nz, const uint32_t* ran
 }
 
 }  // extern "C"
+
+extern "C" {
+
+/* D0 in vertex-order space from the plain definition: Kruskal over every
+ * edge of the triangulation in lexicographic order, with the elder rule
+ * (the younger of two merging components dies). PairSimplices restricted to
+ * dimension 0 is exactly this union-find (Sec. 2.5). Edges are enumerated
+ * from vertex pairs whose coordinates differ by a non-zero 0/1 vector, not
+ * from any id table. Output: (birth rank, death rank) of every pair with
+ * positive persistence, sorted; returns their number. */
+int64_t bf_d0_kruskal(int64_t nx, int64_t ny, int64_t nz, const uint32_t* rank, int64_t* out, int64_t cap) {
+    const int64_t V = nx * ny * nz;
+    std::vector<uint64_t> keys;
+    keys.reserve((size_t)(7 * V));
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                const int64_t v = x + nx * (y + ny * z);
+                for (int m = 1; m < 8; ++m) {
+                    const int64_t dx = m & 1, dy = (m >> 1) & 1, dz = (m >> 2) & 1;
+                    if (x + dx >= nx || y + dy >= ny || z + dz >= nz) continue;
+                    const int64_t w = (x + dx) + nx * ((y + dy) + ny * (z + dz));
+                    const uint64_t a = rank[v], b = rank[w];
+                    keys.push_back(a > b ? (a << 32) | b : (b << 32) | a);
+                }
+            }
+    std::sort(keys.begin(), keys.end());
+    /* union-find over ranks; the root of a component is its oldest (lowest) rank */
+    std::vector<uint32_t> parent((size_t)V);
+    for (int64_t i = 0; i < V; ++i) parent[(size_t)i] = (uint32_t)i;
+    auto find = [&](uint32_t a) {
+        while (parent[a] != a) {
+            parent[a] = parent[parent[a]];
+            a = parent[a];
+        }
+        return a;
+    };
+    std::vector<std::pair<int64_t, int64_t>> pairs;
+    for (uint64_t k : keys) {
+        const uint32_t hi = (uint32_t)(k >> 32), lo = (uint32_t)k;
+        uint32_t ra = find(hi), rb = find(lo);
+        if (ra == rb) continue;
+        const uint32_t young = ra > rb ? ra : rb, old = ra > rb ? rb : ra;
+        parent[young] = old;
+        if (young != hi) pairs.push_back({young, hi});  /* death at the edge's top vertex */
+    }
+    std::sort(pairs.begin(), pairs.end());
+    for (size_t i = 0; i < pairs.size() && (int64_t)i < cap; ++i) {
+        out[2 * i] = pairs[i].first;
+        out[2 * i + 1] = pairs[i].second;
+    }
+    return (int64_t)pairs.size();
+}
+
+}  // extern "C"

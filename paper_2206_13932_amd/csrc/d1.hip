@@ -30,6 +30,7 @@
 // order in which earlier columns are added.
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstdlib>
 
 #include "d1.h"
@@ -1036,6 +1037,11 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
                 err = "D1: consistency check failed";
                 return -7;
             }
+            if (std::getenv("DMS_LOG"))
+                std::fprintf(stderr, "[dms] D1 pass %d: %lld columns, heap %lld entries/thread, %.1f ms\n", pass,
+                             (long long)nwork, (long long)K,
+                             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_pass)
+                                 .count());
             s.pass_work[pass] = (uint64_t)nwork;
             s.pass_us[pass] = (uint64_t)std::chrono::duration_cast<std::chrono::microseconds>(
                                   std::chrono::steady_clock::now() - t_pass)

@@ -120,3 +120,40 @@ def decode_gradient(shape, G):
             res[t::NTYPES[dim]] = r
         out.append(res)
     return out
+
+
+def decode_cells(shape, G, tagged):
+    """Partners (tagged id*4+dim, -1 critical, -2 absent) of the tagged cells,
+    read from the GPU gradient planes G (26, V) uint8."""
+    nz, ny, nx = shape
+    tagged = np.asarray(tagged, dtype=np.int64)
+    out = np.full(tagged.size, -3, dtype=np.int64)
+    for dim in range(4):
+        sel = np.nonzero((tagged & 3) == dim)[0]
+        if sel.size == 0:
+            continue
+        ids = tagged[sel] >> 2
+        anchor, typ = ids // NTYPES[dim], ids % NTYPES[dim]
+        code = G[PLANE_BASE[dim] + typ, anchor].astype(np.int64)
+        r = np.full(sel.size, -3, dtype=np.int64)
+        r[code == 0xFF] = -1
+        r[code == 0xFE] = -2
+        up = code < 27
+        if up.any():
+            vs = vertices(shape, dim, ids[up])
+            a = coords(shape, vs[:, 0])
+            c = code[up]
+            w = a + np.stack([c % 3 - 1, (c // 3) % 3 - 1, c // 9 - 1], axis=1)
+            wid = w[:, 0] + nx * (w[:, 1] + ny * w[:, 2])
+            allv = np.sort(np.concatenate([vs, wid[:, None]], axis=1), axis=1)
+            r[up] = ids_from_vertices(shape, dim + 1, allv) * 4 + dim + 1
+        dn = (code >= 0x80) & (code < 0x84)
+        if dn.any():
+            vs = vertices(shape, dim, ids[dn])
+            i = code[dn] & 3
+            keep = np.ones(vs.shape, dtype=bool)
+            keep[np.arange(len(vs)), i] = False
+            sub = vs[keep].reshape(len(vs), dim)
+            r[dn] = ids_from_vertices(shape, dim - 1, sub) * 4 + dim - 1
+        out[sel] = r
+    return out

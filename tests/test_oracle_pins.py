@@ -298,3 +298,14 @@ def test_golden_simplex_counts():
         if nx * ny * nz <= 4096:
             assert list(oracle.bf_counts((nz, ny, nx))) == val, key
     assert gold["512x512x512"] == [134217728, 936381439, 1602760698, 800596986]
+
+
+@pytest.mark.parametrize("field", [sf.noise((16, 16, 16), 31), sf.gaussians((20, 18, 16), 2, 6, 0.01),
+                                   sf.noise((3, 7, 5), 1)])
+def test_kruskal_d0_matches_oracle(field):
+    """The Kruskal checker used at full size agrees with the oracle's D0 (and
+    so, by the brute-force pins, with boundary-matrix reduction)."""
+    res = oracle.run(field)
+    fin, _ = oracle.order_space(res)
+    d0 = sorted((b, d) for (dim, b, d) in fin if dim == 0)
+    assert d0 == [tuple(x) for x in oracle.bf_d0_kruskal(res.shape, res.rank).tolist()]
