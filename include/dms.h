@@ -125,11 +125,19 @@ enum {
     DMS_BUF_CRIT3 = 5,
     DMS_BUF_ARCS0 = 6,     /* u32[2*n] D0 arcs (rank of minimum a, b) per C1      */
     DMS_BUF_ARCS2 = 7,     /* u32[2*n] D2 arcs (age of maximum a, b), C2 reversed */
-    DMS_BUF_STATS = 8,     /* u64[32] work counters of the last call: D0 steps,
+    DMS_BUF_STATS = 8,     /* u64[48] work counters of the last call: D0 steps,
                               evictions; D2 steps, evictions; D1 steps, evictions,
                               boundary additions, deferrals, published entries,
                               restarts; per D1 pass (columns, microseconds);
-                              workgroup rounds, edges expanded, entries moved  */
+                              workgroup rounds, edges expanded, entries moved;
+                              per column of the workgroup passes: longest and
+                              total microseconds, most rounds, most boundary
+                              additions, longest boundary, columns over 1 ms;
+                              microseconds of those columns per phase (window
+                              scan, slot assignment, batched loads, sort, low
+                              merge, top merge, owner rule, additions, claims
+                              and reloads, refills), then their rounds and
+                              additions                                         */
     DMS_BUF_D1LEN = 9      /* u64 per D1 column: last cached boundary
                               (offset << 24 | length)                             */
 };

@@ -52,6 +52,14 @@ struct D1State {
     uint64_t pass_us[5] = {0, 0, 0, 0, 0};
     // workgroup passes: rounds, edges expanded, boundary entries moved by merges
     uint64_t wide[3] = {0, 0, 0};
+    // workgroup passes, per column taken from the queue: longest (us), total (us),
+    // most rounds, most cached-boundary additions, longest boundary, columns over 1 ms
+    uint64_t wide_t[6] = {0, 0, 0, 0, 0, 0};
+    // microseconds per phase summed over the columns over 1 ms: window scan,
+    // slot assignment, batched loads, sort, merge into the low part, merge into
+    // the top, owner rule, cached-boundary additions, claims and reloads,
+    // refills; then those columns' rounds and additions
+    uint64_t wide_ph[12] = {0};
     // per-run data for emission
     GridDev g{};
     const uint32_t* order = nullptr;

@@ -44,17 +44,19 @@ constexpr int DB = 256;
 constexpr uint32_t OWN_D0 = 0xFFFFFFFEu;
 constexpr uint64_t NONE = ~0ull;
 constexpr int MAX_PASSES = 5;
+constexpr uint32_t MAX_RETRIES = 1u << 16;  // consecutive look-agains before a column is declared corrupt
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + DB - 1) / DB); }
 
 // counters in D1State::ctrs
 enum { C_HEAP = 0, C_NEXT = 1, C_DEFER = 2, C_STEPS = 3, C_EVICT = 4, C_ADDS = 5, C_ROUNDS = 6, C_EXPANDED = 7,
-       C_MOVED = 8 };
+       C_MOVED = 8, C_TMAX = 9, C_TSUM = 10, C_RMAX = 11, C_AMAX = 12, C_NMAX = 13, C_SLOW = 14, C_PHASE = 16,
+       N_PHASE = 10, N_CTRS = 32 };
 // The publication heap is split into NSEG segments with one bump counter each
-// (counters 128 bytes apart, after the 16 counters above), so that millions of
-// publications do not serialise on one atomic.
+// (counters 128 bytes apart, after the N_CTRS counters above), so that
+// millions of publications do not serialise on one atomic.
 constexpr int NSEG = 64;
 constexpr int SEG_STRIDE = 16;
-constexpr int SEG_BASE = 16;
+constexpr int SEG_BASE = N_CTRS;
 
 struct D1K {
     GridDev g;
@@ -281,8 +283,9 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
         bool have = false;
         uint64_t tau = 0;
         bool stop = false;  // leave the thread (error)
+        uint32_t retries = 0;
         for (int64_t guard = 0;; ++guard) {
-            if (guard > ((int64_t)1 << 24)) {
+            if (guard > ((int64_t)1 << 24) || retries > MAX_RETRIES) {
                 atomicOr(P.flags, FLAG_GUARD);
                 stop = true;
                 break;
@@ -333,7 +336,10 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
                     }
                     st_rlx64(&P.bndptr[c], b);
                     wait_stores();
-                    if (!cas32(&P.owner1[e.id], o, c)) continue;  // owner changed: look again
+                    if (!cas32(&P.owner1[e.id], o, c)) {  // owner changed: look again
+                        ++retries;
+                        continue;
+                    }
                     if (o == EMPTY32) break;                       // column settled
                     // evicted o: carry on reducing it from its cached boundary
                     ++evictions;
@@ -357,10 +363,17 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
                 }
                 // o < c: add the cached boundary of the earlier owner
                 const uint64_t b = ld_rlx64(&P.bndptr[o]);
-                if (b == EMPTY64) continue;
+                if (b == EMPTY64) {
+                    ++retries;
+                    continue;
+                }
                 const uint64_t* B = P.heap + (b >> 24);
                 const int64_t bl = (int64_t)(b & 0xFFFFFF);
-                if (ld_rlx64(&B[0]) != tau) continue;  // o moved on: look again
+                if (ld_rlx64(&B[0]) != tau) {  // o moved on: look again
+                    ++retries;
+                    continue;
+                }
+                retries = 0;
                 if (H.room(bl - 1)) {
                     have = false;
                     ++adds;
@@ -390,70 +403,121 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
 
 
 // ---- one workgroup per large column ------------------------------------------
-// The boundary is a sorted array, ascending, in per-block global scratch, so
-// that its top is at the end and a merge only rewrites the suffix from the
-// smallest key it inserts or removes. A round looks at the top WB edges:
+// The boundary is kept sorted ascending in two parts: its largest entries
+// (up to TOPCAP) in LDS ("top"), the rest in per-block global scratch ("low";
+// every low key is below every top key). A round looks at the top WB edges:
 // every regular tail above the first critical (or non-tail) edge is expanded
 // at once -- adding the boundary of a partner triangle leaves the column's
 // Morse projection unchanged, so the expansions commute -- and the new edges
-// are sorted, cancelled mod 2 and merged in. When the top is critical, the
-// owner rule runs as in k_d1, with cached boundaries merged in chunks.
-// Published boundaries keep the decreasing layout (top first).
+// are sorted, cancelled mod 2 and merged in: keys above the low part's
+// maximum into the top (LDS to LDS), the others into the low part (staged
+// through LDS in segments). A top that outgrows TOPCAP spills its smaller
+// entries to the end of the low part; a top that falls below WB entries is
+// refilled from it. When the top is critical, the owner rule runs as in k_d1,
+// with cached boundaries merged in chunks. Published boundaries keep the
+// decreasing layout (top first). Block-wide scans and counts use wave
+// ballots and shuffles with one barrier each.
 constexpr int WB = 256;
-constexpr int NW = 4 * WB;  // keys merged per step: 2 new keys + 1 kept entry per window slot
+constexpr int NWAVE = WB / 64;
+constexpr int NW = 4 * WB;  // keys merged per step
 constexpr int IPW = NW / WB;
+constexpr int TOPCAP = 2048;  // LDS top capacity; also the staging segment of low merges
+constexpr int TOPKEEP = 1024; // top entries kept after a spill, or loaded by a refill
+constexpr int PCAP = NW;      // pending keys below the top, merged into low in batches
 constexpr uint32_t BATCH_ADD_MAX = 32;  // longest cached boundary added out of order in a round
 constexpr uint64_t PAD = ~0ull;
+static_assert(TOPKEEP >= WB && TOPKEEP + WB <= TOPCAP, "top refill must fit");
+
+// rows of WideShared::ws (wave totals); a row is written again only after
+// another barrier has passed
+enum { WS_CNT0 = 0, WS_CNT1 = 1, WS_ROUND = 2, WS_SORT = 3, WS_MERGE = 4, WS_ROWS = 5 };
 
 struct WideShared {
+    uint64_t top[2][TOPCAP];  // the top (one buffer) and a merge target / staging area
     uint64_t raw[NW];   // new keys of a round, sorted here
     uint64_t src[NW];   // keys to merge (ascending, unique)
-    uint64_t surv[NW];  // keys of src not present in B
-    uint32_t lb[NW];    // number of B-suffix elements smaller than src[j]
+    uint64_t surv[NW];  // keys of src not present in the target; heap offsets while a round is built
+    uint32_t lb[NW];    // number of target entries smaller than src[j]
     uint32_t lbs[NW];   // lb of the survivors
-    uint32_t canc[NW];  // B-suffix indices cancelled by src, ascending
+    uint32_t canc[NW];  // target indices cancelled by src, ascending
     uint32_t flag[NW];
-    uint32_t scan[WB];
-    uint64_t scan64[WB];
-    uint64_t zoff[WB];  // per window entry: cached boundary to add (offset of its second entry)
-    uint32_t zlen[WB];  //   and the number of entries after its head; 0 = none
+    uint32_t ws[WS_ROWS][NWAVE];
+    uint32_t wstop[NWAVE];
+    uint32_t wcnt[NWAVE];
+    uint32_t wend[NWAVE];
     int ints[8];
     uint64_t u64s[4];
 };
 
-__device__ inline uint32_t block_excl_scan(WideShared& L, uint32_t v, uint32_t& total) {
-    const int t = threadIdx.x;
-    L.scan[t] = v;
-    __syncthreads();
-    for (int d = 1; d < WB; d <<= 1) {
-        const uint32_t a = t >= d ? L.scan[t - d] : 0;
-        __syncthreads();
-        L.scan[t] += a;
-        __syncthreads();
-    }
-    total = L.scan[WB - 1];
-    const uint32_t ex = L.scan[t] - v;
-    __syncthreads();
-    return ex;
+// inclusive prefix sum over the 64 lanes of a wave with DPP row shifts and
+// row broadcasts (no LDS round trips)
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+    return v;
 }
 
-// exclusive prefix maximum of v over the block (0 for thread 0)
-__device__ inline uint64_t block_excl_max(WideShared& L, uint64_t v) {
-    const int t = threadIdx.x;
-    L.scan64[t] = v;
-    __syncthreads();
-    for (int d = 1; d < WB; d <<= 1) {
-        const uint64_t a = t >= d ? L.scan64[t - d] : 0;
-        __syncthreads();
-        if (a > L.scan64[t]) L.scan64[t] = a;
-        __syncthreads();
+// value of lane (lane ^ d) of the same wave, d a power of two below 64: quad
+// permutes, row shifts and the gfx950 permlane swaps, all without LDS
+__device__ inline uint32_t lane_xor(uint32_t x, uint32_t d) {
+    const uint32_t lane = threadIdx.x & 63;
+    switch (d) {
+    case 1: return __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xf, 0xf, false);  // quad_perm [1,0,3,2]
+    case 2: return __builtin_amdgcn_update_dpp(x, x, 0x4E, 0xf, 0xf, false);  // quad_perm [2,3,0,1]
+    case 4: {
+        const uint32_t a = __builtin_amdgcn_update_dpp(x, x, 0x104, 0xf, 0xf, false);  // row_shl:4
+        const uint32_t b = __builtin_amdgcn_update_dpp(x, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+        return (lane & 4) ? b : a;
     }
-    const uint64_t ex = t > 0 ? L.scan64[t - 1] : 0;
-    __syncthreads();
-    return ex;
+    case 8: {
+        const uint32_t a = __builtin_amdgcn_update_dpp(x, x, 0x108, 0xf, 0xf, false);  // row_shl:8
+        const uint32_t b = __builtin_amdgcn_update_dpp(x, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+        return (lane & 8) ? b : a;
+    }
+    case 16: {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        return (lane & 16) ? r[0] : r[1];
+    }
+    default: {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        return (lane & 32) ? r[0] : r[1];
+    }
+    }
 }
 
-// number of elements of the ascending array A[0..n) smaller than x
+// exclusive prefix sum of v over the block; ws is a row of wave totals
+__device__ inline uint32_t block_excl_scan(uint32_t* ws, uint32_t v, uint32_t& total) {
+    const int t = threadIdx.x, w = t >> 6;
+    const uint32_t inc = wave_incl_scan(v);
+    if ((t & 63) == 63) ws[w] = inc;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NWAVE; ++i) {
+        const uint32_t s = ws[i];
+        before += i < w ? s : 0u;
+        tot += s;
+    }
+    total = tot;
+    return before + inc - v;
+}
+
+// number of threads of the block with pred set
+__device__ inline uint32_t block_count(uint32_t* ws, bool pred) {
+    const uint64_t b = __ballot(pred);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = (uint32_t)__popcll(b);
+    __syncthreads();
+    uint32_t tot = 0;
+#pragma unroll
+    for (int i = 0; i < NWAVE; ++i) tot += ws[i];
+    return tot;
+}
+
+// number of elements of the ascending array A[0..n) smaller than x (LDS)
 template <typename T>
 __device__ inline uint32_t count_less(const T* A, uint32_t n, T x) {
     uint32_t lo = 0, hi = n;
@@ -465,24 +529,54 @@ __device__ inline uint32_t count_less(const T* A, uint32_t n, T x) {
     return lo;
 }
 
-// B[0..n) ^= L.src[0..m) (both ascending, unique), in place, tmp holding the
-// rewritten suffix; returns the new size.
-__device__ uint32_t merge_xor(WideShared& L, uint64_t* B, uint32_t n, uint32_t m, uint64_t* tmp,
-                              unsigned long long& moved) {
-    const int t = threadIdx.x;
-    if (m == 0) return n;
-    const uint32_t p = count_less<uint64_t>(B, n, L.src[0]);
-    uint64_t* Bp = B + p;
-    const uint32_t len = n - p;
-    moved += len;
-    for (uint32_t j = t; j < (uint32_t)NW; j += WB) {
-        uint32_t c = 0, f = 0;
-        if (j < m) {
-            c = count_less<uint64_t>(Bp, len, L.src[j]);
-            f = (c < len && Bp[c] == L.src[j]) ? 1u : 0u;
-        }
+// The same for an array in global memory, found by the whole block: each
+// level loads one sample per thread (the last entry of WB equal segments)
+// and keeps the segment where the samples cross x.
+__device__ uint32_t count_less_block(WideShared& L, const uint64_t* A, uint32_t n, uint64_t x) {
+    const uint32_t t = threadIdx.x;
+    uint32_t lo = 0, len = n;
+    int row = 0;
+    while (len > (uint32_t)WB) {
+        const uint32_t step = (len + WB - 1) / WB;
+        const uint32_t nseg = (len + step - 1) / step;
+        bool pred = false;
+        if (t < nseg) pred = A[lo + min((t + 1) * step, len) - 1] < x;
+        const uint32_t c = block_count(L.ws[WS_CNT0 + row], pred);
+        row ^= 1;
+        if (c == nseg) return lo + len;
+        lo += c * step;
+        len = min(step, len - c * step);
+    }
+    const bool pred = t < len && A[lo + t] < x;
+    return lo + block_count(L.ws[WS_CNT0 + row], pred);
+}
+
+// dst[0..len) <- src[0..len) (global to LDS), by the block, len <= TOPCAP
+__device__ inline void stage(uint64_t* dst, const uint64_t* src, uint32_t len) {
+    if (len == 0) return;
+    const uint32_t t = threadIdx.x;
+    uint64_t v[TOPCAP / WB];
+#pragma unroll
+    for (int q = 0; q < TOPCAP / WB; ++q) v[q] = src[min((uint32_t)(q * WB) + t, len - 1)];
+#pragma unroll
+    for (int q = 0; q < TOPCAP / WB; ++q)
+        if ((uint32_t)(q * WB) + t < len) dst[q * WB + t] = v[q];
+}
+
+// Merge X[0..len) (LDS) with S[0..m) (LDS; both ascending, unique; equal
+// keys cancel). Output entries o < sp go to gdst[o], the others to
+// ldst[o - sp], where sp = 0 if the result fits in cap entries and
+// result - keep otherwise (cap = 0: everything to gdst). Returns the
+// result length; sp is set. The caller synchronises before the outputs or
+// the shared arrays are used again. When sp > 0, L.u64s[0] receives the
+// largest key sent to gdst.
+__device__ uint32_t merge_seg(WideShared& L, const uint64_t* X, uint32_t len, const uint64_t* S, uint32_t m,
+                              uint64_t* gdst, uint64_t* ldst, uint32_t cap, uint32_t keep, uint32_t& sp) {
+    const uint32_t t = threadIdx.x;
+    for (uint32_t j = t; j < m; j += WB) {
+        const uint32_t c = count_less<uint64_t>(X, len, S[j]);
         L.lb[j] = c;
-        L.flag[j] = f;
+        L.flag[j] = (c < len && X[c] == S[j]) ? 1u : 0u;
     }
     __syncthreads();
     uint32_t fc = 0, sc = 0;
@@ -493,93 +587,404 @@ __device__ uint32_t merge_xor(WideShared& L, uint64_t* B, uint32_t n, uint32_t m
             sc += 1 - L.flag[j];
         }
     }
-    uint32_t nc, ns;
-    const uint32_t ec = block_excl_scan(L, fc, nc);
-    const uint32_t es = block_excl_scan(L, sc, ns);
+    // both counts in one scan (each at most NW < 2^16)
+    uint32_t both;
+    const uint32_t ex = block_excl_scan(L.ws[WS_MERGE], fc | (sc << 16), both);
+    const uint32_t nc = both & 0xFFFF, ns = both >> 16;
     {
-        uint32_t a = ec, b = es;
+        uint32_t a = ex & 0xFFFF, b = ex >> 16;
         for (int q = 0; q < IPW; ++q) {
             const uint32_t j = IPW * t + q;
             if (j >= m) break;
             if (L.flag[j]) L.canc[a++] = L.lb[j];
             else {
-                L.surv[b] = L.src[j];
+                L.surv[b] = S[j];
                 L.lbs[b] = L.lb[j];
                 ++b;
             }
         }
     }
     __syncthreads();
-    for (uint32_t i = t; i < len; i += WB) {
-        const uint64_t x = Bp[i];
-        const uint32_t cl = count_less<uint32_t>(L.canc, nc, i);
-        if (cl < nc && L.canc[cl] == i) continue;  // cancelled
-        const uint32_t sl = count_less<uint64_t>(L.surv, ns, x);
-        tmp[i - cl + sl] = x;
+    const uint32_t r = len - nc + ns;
+    const uint32_t split = cap == 0 ? r : (r > cap ? r - keep : 0u);
+    sp = split;
+    auto put = [&](uint32_t o, uint64_t x) {
+        if (o < split) {
+            gdst[o] = x;
+            if (o + 1 == split) L.u64s[0] = x;
+        } else {
+            ldst[o - split] = x;
+        }
+    };
+    // canc (indices of cancelled entries) and lbs (entries placed before each
+    // survivor) are ascending: each thread walks a contiguous run of X with
+    // two cursors. Entry i moves to i - #(cancelled before i) + #(survivors
+    // with lbs <= i); survivor k goes to k + lbs[k] - #(cancelled before lbs[k]).
+    {
+        const uint32_t per = (len + WB - 1) / WB;
+        const uint32_t i0 = min(len, t * per), i1 = min(len, i0 + per);
+        if (i0 < i1) {
+            uint32_t cc = count_less<uint32_t>(L.canc, nc, i0);
+            uint32_t ss = count_less<uint32_t>(L.lbs, ns, i0 + 1);
+            uint32_t nextc = cc < nc ? L.canc[cc] : ~0u;
+            uint32_t nexts = ss < ns ? L.lbs[ss] : ~0u;
+            for (uint32_t i = i0; i < i1; ++i) {
+                const uint64_t x = X[i];
+                while (nexts <= i) {
+                    ++ss;
+                    nexts = ss < ns ? L.lbs[ss] : ~0u;
+                }
+                if (nextc == i) {
+                    ++cc;
+                    nextc = cc < nc ? L.canc[cc] : ~0u;
+                    continue;
+                }
+                put(i - cc + ss, x);
+            }
+        }
     }
     for (uint32_t k = t; k < ns; k += WB) {
         const uint32_t cl = count_less<uint32_t>(L.canc, nc, L.lbs[k]);
-        tmp[k + L.lbs[k] - cl] = L.surv[k];
+        put(k + L.lbs[k] - cl, L.surv[k]);
     }
-    __syncthreads();
-    const uint32_t r = len - nc + ns;
-    for (uint32_t i = t; i < r; i += WB) Bp[i] = tmp[i];
-    __syncthreads();
-    return p + r;
+    return r;
 }
 
-// sort L.raw[0..np) ascending (np a power of two, PAD last), cancel equal keys
-// mod 2 into L.src; returns the number of keys kept
-__device__ uint32_t sort_cancel(WideShared& L, int np) {
-    const int t = threadIdx.x;
-    for (int size = 2; size <= np; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int pp = t; pp < np / 2; pp += WB) {
-                const int i = 2 * pp - (pp & (stride - 1));
-                const int j = i + stride;
-                const bool asc = (i & size) == 0;
-                const uint64_t a = L.raw[i], b = L.raw[j];
-                if ((a > b) == asc) {
-                    L.raw[i] = b;
-                    L.raw[j] = a;
-                }
-            }
-            __syncthreads();
+// low[0..n) ^= S[0..m) (S in LDS; both ascending, unique), in place in global
+// memory; returns the new size. Only the suffix from S[0] changes. The top
+// TOPCAP entries of low are staged in LDS (in stg); when the suffix lies
+// inside them it is merged straight back. A longer suffix is found by a block
+// search and merged segment by segment (TOPCAP entries each, with the keys
+// below the next segment's first key) into tmp, then copied back.
+__device__ uint32_t merge_low(WideShared& L, uint64_t* low, uint32_t n, const uint64_t* S, uint32_t m,
+                              uint64_t* tmp, uint64_t* stg, unsigned long long& moved) {
+    const uint32_t t = threadIdx.x;
+    if (m == 0) return n;
+    uint32_t sp;
+    const uint32_t h = min(n, (uint32_t)TOPCAP);
+    stage(stg, low + (n - h), h);
+    __syncthreads();
+    if (h == n || S[0] > stg[0]) {
+        const uint32_t q = count_less<uint64_t>(stg, h, S[0]);
+        moved += h - q;
+        const uint32_t r = merge_seg(L, stg + q, h - q, S, m, low + (n - h + q), nullptr, 0, 0, sp);
+        __syncthreads();
+        return n - h + q + r;
+    }
+    const uint32_t p = count_less_block(L, low, n, S[0]);
+    uint64_t* Bp = low + p;
+    const uint32_t len = n - p;
+    moved += len;
+    uint32_t out = 0, j0 = 0;
+    for (uint32_t sb = 0; sb < len; sb += TOPCAP) {
+        const uint32_t sl = min((uint32_t)TOPCAP, len - sb);
+        stage(stg, Bp + sb, sl);
+        uint32_t ja = m;
+        if (sb + sl < len) ja = j0 + count_less<uint64_t>(S + j0, m - j0, Bp[sb + sl]);
+        __syncthreads();
+        out += merge_seg(L, stg, sl, S + j0, ja - j0, tmp + out, nullptr, 0, 0, sp);
+        __syncthreads();
+        j0 = ja;
+    }
+    for (uint32_t base = 0; base < out; base += 8 * WB) {
+        uint64_t v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t i = base + q * WB + t;
+            v[q] = i < out ? tmp[i] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t i = base + q * WB + t;
+            if (i < out) Bp[i] = v[q];
         }
     }
+    __syncthreads();
+    return p + out;
+}
+
+// sort L.raw[0..total) ascending (total <= NW) and cancel equal keys mod 2
+// into out (which may be L.raw); returns the number of keys kept. A bitonic network over the next
+// power of two (PAD beyond total), each thread holding IPW consecutive
+// entries: exchanges inside a thread are register moves, inside a wave lane
+// permutes, and only strides of a wave's span or more go through LDS.
+__device__ inline uint64_t lane_xor64(uint64_t x, uint32_t d) {
+    const uint32_t lo = lane_xor((uint32_t)x, d), hi = lane_xor((uint32_t)(x >> 32), d);
+    return ((uint64_t)hi << 32) | lo;
+}
+// the bitonic network over NP entries (NP a power of two, 4 <= NP <= NW),
+// unrolled so that every exchange distance is a compile-time constant
+template <uint32_t NP>
+__device__ inline void bitonic(WideShared& L, uint64_t (&e)[IPW]) {
+    const uint32_t t = threadIdx.x;
+#pragma unroll
+    for (uint32_t k = 2; k <= NP; k <<= 1) {
+#pragma unroll
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            uint64_t b[IPW];
+            if (j == 1) {
+                b[0] = e[1], b[1] = e[0], b[2] = e[3], b[3] = e[2];
+            } else if (j == 2) {
+                b[0] = e[2], b[1] = e[3], b[2] = e[0], b[3] = e[1];
+            } else if (j < (uint32_t)(IPW * 64)) {
+#pragma unroll
+                for (int q = 0; q < IPW; ++q) b[q] = lane_xor64(e[q], j / IPW);
+            } else {
+#pragma unroll
+                for (int q = 0; q < IPW; ++q) L.raw[IPW * t + q] = e[q];
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < IPW; ++q) b[q] = L.raw[(IPW * t + q) ^ j];
+                __syncthreads();
+            }
+#pragma unroll
+            for (int q = 0; q < IPW; ++q) {
+                const uint32_t i = IPW * t + q;
+                const bool asc = (i & k) == 0, first = (i & j) == 0;
+                const uint64_t lo = e[q] < b[q] ? e[q] : b[q], hi = e[q] < b[q] ? b[q] : e[q];
+                e[q] = first == asc ? lo : hi;
+            }
+        }
+    }
+}
+
+// the same with one entry per thread (entry index = thread index), NP <= WB
+template <uint32_t NP>
+__device__ inline void bitonic1(WideShared& L, uint64_t& x) {
+    const uint32_t t = threadIdx.x;
+#pragma unroll
+    for (uint32_t k = 2; k <= NP; k <<= 1) {
+#pragma unroll
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            uint64_t b;
+            if (j < 64) {
+                b = lane_xor64(x, j);
+            } else {
+                L.raw[t] = x;
+                __syncthreads();
+                b = L.raw[t ^ j];
+                __syncthreads();
+            }
+            const bool asc = (t & k) == 0, first = (t & j) == 0;
+            const uint64_t lo = x < b ? x : b, hi = x < b ? b : x;
+            x = first == asc ? lo : hi;
+        }
+    }
+}
+
+__device__ uint32_t sort_cancel(WideShared& L, uint32_t total, uint64_t* out) {
+    static_assert(IPW == 4 && WB == 256 && NW == 1024, "exchange distances assume 4 entries per thread");
+    const uint32_t t = threadIdx.x;
+    if (total <= (uint32_t)WB) {
+        uint64_t x = t < total ? L.raw[t] : PAD;
+        __syncthreads();  // raw is reused below
+        if (total <= 64) bitonic1<64>(L, x);
+        else if (total <= 128) bitonic1<128>(L, x);
+        else bitonic1<256>(L, x);
+        L.raw[t] = x;
+        __syncthreads();
+        uint32_t k = 0;
+        if (t < total && (t == 0 || L.raw[t - 1] != x)) {
+            uint32_t r = 1;
+            while (t + r < total && L.raw[t + r] == x) ++r;
+            k = r & 1;
+        }
+        uint32_t kept;
+        const uint32_t ex = block_excl_scan(L.ws[WS_SORT], k, kept);
+        if (k) out[ex] = x;
+        __syncthreads();
+        return kept;
+    }
+    uint64_t e[IPW];
+#pragma unroll
+    for (int q = 0; q < IPW; ++q) {
+        const uint32_t i = IPW * t + q;
+        e[q] = i < total ? L.raw[i] : PAD;
+    }
+    __syncthreads();  // raw is reused below
+    bitonic<1024>(L, e);
+#pragma unroll
+    for (int q = 0; q < IPW; ++q) L.raw[IPW * t + q] = e[q];
+    __syncthreads();
     uint32_t keep[IPW];
     uint32_t kc = 0;
     for (int q = 0; q < IPW; ++q) {
-        const int j = IPW * t + q;
-        const uint64_t x = j < np ? L.raw[j] : PAD;
+        const uint32_t j = IPW * t + q;
         uint32_t k = 0;
-        if (x != PAD && (j == 0 || L.raw[j - 1] != x)) {
-            int r = 1;
-            while (j + r < np && L.raw[j + r] == x) ++r;
-            k = r & 1;
+        if (j < total) {
+            const uint64_t x = e[q];
+            if (j == 0 || L.raw[j - 1] != x) {
+                uint32_t r = 1;
+                while (j + r < total && L.raw[j + r] == x) ++r;
+                k = r & 1;
+            }
         }
         keep[q] = k;
         kc += k;
     }
-    uint32_t total;
-    const uint32_t ex = block_excl_scan(L, kc, total);
+    uint32_t kept;
+    const uint32_t ex = block_excl_scan(L.ws[WS_SORT], kc, kept);
     uint32_t a = ex;
     for (int q = 0; q < IPW; ++q)
-        if (keep[q]) L.src[a++] = L.raw[IPW * t + q];
+        if (keep[q]) out[a++] = e[q];
     __syncthreads();
-    return total;
+    return kept;
 }
 
-// Save the ascending boundary B[0..n) to the publication heap in the
-// decreasing layout; returns the offset or PAD when the heap is full.
-__device__ uint64_t save_desc(const D1K& P, WideShared& L, const uint64_t* B, uint32_t n) {
-    const int t = threadIdx.x;
+// The boundary of the column being reduced is top ^ low ^ pend: top (LDS
+// buffer cur, nt entries, ascending), low (global, nl entries, ascending,
+// every key below every top key; lmax = its largest key, 0 when empty, keys
+// are never 0) and pend (global, np unsorted keys, each at most lmax when it
+// was added; pend is empty whenever low is).
+struct Col {
+    int cur;
+    uint32_t nt, nl, np;
+    uint64_t lmax;
+    __device__ uint32_t n() const { return nt + nl + np; }
+};
+
+// Merge pend into low: sort and cancel it in LDS, then one low merge.
+__device__ void flush(WideShared& L, Col& C, uint64_t* low, const uint64_t* pend, uint64_t* tmp,
+                      unsigned long long& moved) {
+    if (C.np == 0) return;
+    const uint32_t t = threadIdx.x;
+    __syncthreads();  // pend entries appended by other threads are complete
+    {
+        uint64_t v[IPW];
+#pragma unroll
+        for (int q = 0; q < IPW; ++q) {
+            const uint32_t i = q * WB + t;
+            v[q] = i < C.np ? pend[i] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < IPW; ++q) {
+            const uint32_t i = q * WB + t;
+            if (i < C.np) L.raw[i] = v[q];
+        }
+    }
+    __syncthreads();
+    // sorted in place: the low merge does not use raw
+    const uint32_t m = sort_cancel(L, C.np, L.raw);
+    C.np = 0;
+    if (m == 0) return;
+    C.nl = merge_low(L, low, C.nl, L.raw, m, tmp, L.top[C.cur ^ 1], moved);
+    C.lmax = C.nl ? low[C.nl - 1] : 0;
+    __syncthreads();
+}
+
+// Boundary ^= L.src[0..m) (ascending, unique): keys up to lmax are appended
+// to pend (which is flushed first when they would not fit), the others are
+// merged into the top, which spills its smaller entries to low when it
+// outgrows TOPCAP.
+__device__ void merge_col(WideShared& L, Col& C, uint64_t* low, uint64_t* pend, uint32_t m, uint64_t* tmp,
+                          unsigned long long& moved, uint64_t* ph, uint64_t& tp) {
+    auto lap = [&](int i) {
+        const uint64_t now = __builtin_amdgcn_s_memrealtime();
+        if (ph) ph[i] += now - tp;
+        tp = now;
+    };
+    if (m == 0) return;
+    const uint32_t t = threadIdx.x;
+    uint32_t s0 = C.nl ? count_less<uint64_t>(L.src, m, C.lmax + 1) : 0u;
+    if (s0 > 0) {
+        if (C.np + s0 > (uint32_t)PCAP) {
+            flush(L, C, low, pend, tmp, moved);
+            s0 = C.nl ? count_less<uint64_t>(L.src, m, C.lmax + 1) : 0u;
+        }
+        for (uint32_t i = t; i < s0; i += WB) pend[C.np + i] = L.src[i];
+        C.np += s0;
+        __syncthreads();  // L.src is rewritten by the caller next
+        lap(4);
+    }
+    if (s0 < m) {
+        uint32_t sp;
+        const uint32_t r =
+            merge_seg(L, L.top[C.cur], C.nt, L.src + s0, m - s0, low + C.nl, L.top[C.cur ^ 1], TOPCAP, TOPKEEP, sp);
+        moved += C.nt;
+        __syncthreads();
+        if (sp > 0) {
+            C.nl += sp;
+            C.lmax = L.u64s[0];
+        }
+        C.nt = r - sp;
+        C.cur ^= 1;
+        __syncthreads();  // L.u64s[0] read by all before it is written again
+        lap(5);
+    }
+}
+
+// Load a boundary stored decreasingly at src[0..len): the largest TOPKEEP
+// entries into the top, the rest into low.
+__device__ void load_col(WideShared& L, Col& C, uint64_t* low, const uint64_t* src, uint32_t len) {
+    const uint32_t t = threadIdx.x;
+    C.nt = min(len, (uint32_t)TOPKEEP);
+    C.nl = len - C.nt;
+    C.np = 0;
+    {
+        uint64_t v[TOPKEEP / WB];
+#pragma unroll
+        for (int q = 0; q < TOPKEEP / WB; ++q) {
+            const uint32_t i = q * WB + t;
+            v[q] = i < C.nt ? ld_rlx64(src + (C.nt - 1 - i)) : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < TOPKEEP / WB; ++q) {
+            const uint32_t i = q * WB + t;
+            if (i < C.nt) L.top[C.cur][i] = v[q];
+        }
+    }
+    for (uint32_t base = 0; base < C.nl; base += 8 * WB) {
+        uint64_t v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t i = base + q * WB + t;
+            v[q] = i < C.nl ? ld_rlx64(src + (len - 1 - i)) : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t i = base + q * WB + t;
+            if (i < C.nl) low[i] = v[q];
+        }
+    }
+    C.lmax = C.nl ? ld_rlx64(src + C.nt) : 0;
+    __syncthreads();
+}
+
+// Flush pend, then move the largest low entries below the top until it holds
+// TOPKEEP more entries (or low is empty).
+__device__ void refill(WideShared& L, Col& C, uint64_t* low, const uint64_t* pend, uint64_t* tmp,
+                       unsigned long long& moved) {
+    flush(L, C, low, pend, tmp, moved);
+    if (C.nl == 0) return;
+    const uint32_t t = threadIdx.x;
+    const uint32_t r = min(C.nl, (uint32_t)TOPKEEP);
+    uint64_t* nt = L.top[C.cur ^ 1];
+    const uint64_t* ot = L.top[C.cur];
+    stage(nt, low + (C.nl - r), r);
+    for (uint32_t i = t; i < C.nt; i += WB) nt[r + i] = ot[i];
+    C.nl -= r;
+    C.nt += r;
+    C.cur ^= 1;
+    C.lmax = C.nl ? low[C.nl - 1] : 0;
+    __syncthreads();
+}
+
+// Flush pend and save the boundary (C.n() entries afterwards) to the
+// publication heap in the decreasing layout; returns the offset or PAD when
+// the heap is full.
+__device__ uint64_t save_col(const D1K& P, WideShared& L, Col& C, uint64_t* low, const uint64_t* pend,
+                             uint64_t* tmp, unsigned long long& moved) {
+    flush(L, C, low, pend, tmp, moved);
+    const uint32_t t = threadIdx.x;
+    const uint32_t n = C.n();
     if (t == 0) L.u64s[1] = heap_alloc(P, blockIdx.x, n);
     __syncthreads();
     const uint64_t off = L.u64s[1];
     __syncthreads();
     if (off == NONE) return PAD;
-    for (uint32_t i = t; i < n; i += WB) st_rlx64(P.heap + off + i, B[n - 1 - i]);
+    const uint64_t* T = L.top[C.cur];
+    for (uint32_t i = t; i < C.nt; i += WB) st_rlx64(P.heap + off + i, T[C.nt - 1 - i]);
+    for (uint32_t i = t; i < C.nl; i += WB) st_rlx64(P.heap + off + C.nt + i, low[C.nl - 1 - i]);
     wait_stores();
     __syncthreads();
     return off;
@@ -588,8 +993,10 @@ __device__ uint64_t save_desc(const D1K& P, WideShared& L, const uint64_t* B, ui
 __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
     __shared__ WideShared L;
     const int t = threadIdx.x;
-    uint64_t* B = P.scratch + (int64_t)blockIdx.x * 2 * P.K;
-    uint64_t* tmp = B + P.K;
+    const int lane = t & 63, wv = t >> 6;
+    uint64_t* low = P.scratch + (int64_t)blockIdx.x * (2 * P.K + PCAP);
+    uint64_t* tmp = low + P.K;
+    uint64_t* pend = tmp + P.K;
     const int64_t V = P.g.V;
     unsigned long long steps = 0, evictions = 0, adds = 0, rounds = 0, expanded = 0, moved = 0;
     for (;;) {
@@ -600,18 +1007,30 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
         if ((int64_t)next >= P.nwork) break;
         const uint64_t w = P.work[next];
         uint32_t c = (uint32_t)(w >> 40);
-        uint32_t n;
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();  // 100 MHz clock
+        // time per phase (thread 0): window, sort, round merge, owner rule, additions, claims
+        uint64_t ph[N_PHASE] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        uint64_t tp = t0;
+        auto lap = [&](int i) {
+            const uint64_t now = __builtin_amdgcn_s_memrealtime();
+            ph[i] += now - tp;
+            tp = now;
+        };
+        const unsigned long long rounds0 = rounds, adds0 = adds;
+        uint32_t nmax = 0;
+        Col C;
+        C.cur = 0;
         {
             const uint64_t off = w & ((1ull << 40) - 1);
-            n = P.work_len[next];
-            if ((int64_t)n > P.K) {
+            const uint32_t n0 = P.work_len[next];
+            if ((int64_t)n0 > P.K) {
                 if (t == 0) atomicOr(P.flags, FLAG_WORK);
                 break;
             }
-            for (uint32_t i = t; i < n; i += WB) B[i] = ld_rlx64(P.heap + off + (n - 1 - i));
+            load_col(L, C, low, P.heap + off, n0);
         }
-        __syncthreads();
         bool stop = false;
+        uint32_t retries = 0;
         for (int64_t guard = 0;; ++guard) {
             if (guard > ((int64_t)1 << 24)) {
                 if (t == 0) atomicOr(P.flags, FLAG_GUARD);
@@ -619,8 +1038,21 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
                 break;
             }
             ++steps;
-            if (n == 0) break;  // zero column
-            // scan the top window. Above the first stopping edge, every regular tail
+            if (C.n() == 0) break;  // zero column
+            if (C.nt < (uint32_t)WB && (C.nl > 0 || C.np > 0)) {
+                refill(L, C, low, pend, tmp, moved);
+                lap(9);
+                if (C.n() == 0) break;  // everything cancelled in the flush
+            }
+            // a look-again (an owner that moved on, a lost claim) resolves once the
+            // other column has published; a long run of them means corrupted state
+            if (retries > MAX_RETRIES) {
+                if (t == 0) atomicOr(P.flags, FLAG_GUARD);
+                stop = true;
+                break;
+            }
+            const uint64_t* T = L.top[C.cur];
+            // Scan the top window. Above the first stopping edge, every regular tail
             // (add its partner's boundary) and every critical edge owned by an earlier
             // column with a short cached boundary (add it) is processed this round.
             // Edges that are never a pivot (vertex partners, D0-paired edges) are
@@ -628,36 +1060,39 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
             // edge) stops the round, and so does an earlier-owned one with a long
             // cached boundary, which is added in order when it reaches the top: adding
             // long boundaries out of order inflates the boundaries cached later. The
-            // top must be processable, otherwise the owner rule runs.
-            const uint32_t k = n < (uint32_t)WB ? n : (uint32_t)WB;
-            for (int q = 0; q < IPW; ++q) L.raw[IPW * t + q] = PAD;
-            L.zlen[t] = 0;
-            L.flag[t] = 0;
-            if (t == 0) L.ints[0] = WB;
-            __syncthreads();
-            uint64_t wkey = 0;
-            uint64_t nk0 = PAD, nk1 = PAD;
+            // top must be processable, otherwise the owner rule runs. The window
+            // entries above the stop leave the top; the kept ones come back with the
+            // new keys.
+            const uint32_t k = min(C.nt, (uint32_t)WB);
+            uint64_t wkey = 0, nk0 = PAD, nk1 = PAD, zoff = 0;
+            uint32_t nkeys = 0;  // keys this entry contributes when processed
+            bool batched = false;
             int cls = 0;  // 0 none/stop, 1 processable, 2 kept (never a pivot)
             if ((uint32_t)t < k) {
-                wkey = B[n - 1 - t];
+                wkey = T[C.nt - 1 - t];
                 const EdgeDec e = edecode(P.g, P.order, P.bpr, wkey);
+                // the gradient code and the owner are loaded together
                 const uint8_t code = e.mask ? P.G[(int64_t)e.mask * V + e.lo] : (uint8_t)0xFE;
+                const uint32_t o = e.mask ? ld_rlx(&P.owner1[e.id]) : EMPTY32;
                 if (code < 27) {
                     const uint32_t rw = P.rank[e.lo + lin27(P.g, code)];
                     nk0 = ekey_r(P.bpr, e.ra, rw);
                     nk1 = ekey_r(P.bpr, e.rb, rw);
+                    nkeys = 2;
                     cls = 1;
                 } else if (code == CODE_CRIT) {
-                    const uint32_t o = ld_rlx(&P.owner1[e.id]);
                     if (o == OWN_D0) {
                         cls = 2;
                     } else if (o != EMPTY32 && o < c && t > 0) {
-                        // (a critical top goes through the owner rule below)
+                        // (a critical top goes through the owner rule below). The
+                        // cached boundary's head is checked against wkey when its
+                        // entries are loaded.
                         const uint64_t bo = ld_rlx64(&P.bndptr[o]);
                         const uint32_t zl = (uint32_t)(bo & 0xFFFFFF) - 1;
-                        if (bo != EMPTY64 && zl <= BATCH_ADD_MAX && ld_rlx64(P.heap + (bo >> 24)) == wkey) {
-                            L.zoff[t] = (bo >> 24) + 1;
-                            L.zlen[t] = zl;
+                        if (bo != EMPTY64 && zl <= BATCH_ADD_MAX) {
+                            zoff = bo >> 24;
+                            nkeys = zl;
+                            batched = true;
                             cls = 1;
                         }
                     }
@@ -665,77 +1100,119 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
                     cls = 2;  // vertex partner
                 }
             }
-            if ((uint32_t)t < k && cls == 0) atomicMin(&L.ints[0], t);
-            __syncthreads();
-            uint32_t stop_at = (uint32_t)L.ints[0];
-            // room in the merge list: every window entry reserves one slot (a kept
-            // entry needs exactly that); a processed tail needs one more, a batched
-            // cached boundary its length minus one more. Stop where it would overflow.
-            {
-                uint32_t extra = 0;
-                if ((uint32_t)t < k && cls == 1) extra = (L.zlen[t] ? L.zlen[t] : 2) - 1;
-                uint32_t tot;
-                const uint32_t ex = block_excl_scan(L, extra, tot);
-                if (t == 0) L.ints[1] = WB;
-                __syncthreads();
-                if ((uint32_t)t < k && k + ex + extra > (uint32_t)NW) atomicMin(&L.ints[1], t);
-                __syncthreads();
-                if ((uint32_t)L.ints[1] < stop_at) stop_at = (uint32_t)L.ints[1];
-                __syncthreads();
+            if (cls == 2) nkeys = 1;
+            // first stopping entry (t >= k counts as one) and, per wave, the slots of
+            // the entries before its own first stop
+            const bool stopbit = (uint32_t)t >= k || cls == 0;
+            const uint64_t sm = __ballot(stopbit);
+            const bool stop_in_wave_before = (sm & ((1ull << lane) - 1)) != 0;
+            const uint32_t need = (!stopbit && !stop_in_wave_before) ? nkeys : 0u;
+            const uint32_t inc = wave_incl_scan(need);
+            if (lane == 63) L.ws[WS_ROUND][wv] = inc;
+            if (lane == 0) L.wstop[wv] = sm ? (uint32_t)(wv * 64 + __builtin_ctzll(sm)) : (uint32_t)WB;
+            if (t == 0) {
+                L.ints[0] = cls;
+                L.ints[1] = 0;
+                L.ints[2] = 0;
+                L.ints[3] = 0;
             }
-            uint32_t slot = 0;
-            {
-                uint32_t need = 0;
-                const bool go = (uint32_t)t < k && cls == 1 && (uint32_t)t < stop_at;
-                if ((uint32_t)t < k) need = go ? (L.zlen[t] ? L.zlen[t] : 2) : 1;
-                uint32_t tot;
-                slot = block_excl_scan(L, need, tot);
-                L.ints[7] = (int)tot;  // same value from every thread
-                if ((uint32_t)t < k) {
-                    if (go) {
-                        if (L.zlen[t]) {
-                            const uint64_t zo = L.zoff[t];
-                            for (uint32_t j = 0; j < L.zlen[t]; ++j) L.raw[slot + j] = ld_rlx64(P.heap + zo + j);
-                        } else {
-                            L.raw[slot] = nk0;
-                            L.raw[slot + 1] = nk1;
-                        }
+            __syncthreads();
+            uint32_t stop0 = WB, before = 0;
+#pragma unroll
+            for (int i = 0; i < NWAVE; ++i) {
+                stop0 = min(stop0, L.wstop[i]);
+                before += i < wv ? L.ws[WS_ROUND][i] : 0u;
+            }
+            const bool top_go = L.ints[0] == 1;
+            lap(0);
+            if (top_go) {
+                // entries t < stop0 whose keys fit in the merge list take part; the
+                // slot ends grow with t, so they form a prefix of the window
+                const uint32_t slot = before + inc - need;
+                const bool incl = (uint32_t)t < stop0 && slot + need <= (uint32_t)NW;
+                const bool go = incl && cls == 1;
+                if (incl) {
+                    if (batched) {
+                        for (uint32_t j = 0; j < nkeys; ++j) L.surv[slot + j] = zoff + 1 + j;
+                    } else if (go) {
+                        L.raw[slot] = nk0;
+                        L.raw[slot + 1] = nk1;
+                        L.surv[slot] = NONE;
+                        L.surv[slot + 1] = NONE;
                     } else {
-                        L.raw[slot] = wkey;  // kept: re-inserted below
+                        L.raw[slot] = wkey;  // kept: re-inserted
+                        L.surv[slot] = NONE;
                     }
                 }
-                L.flag[t] = go ? 1u : 0u;
-            }
-            __syncthreads();
-            const bool top_go = L.flag[0] != 0;
-            __syncthreads();
-            if (top_go) {
-                const uint32_t total = (uint32_t)L.ints[7];
-                uint32_t nproc;
-                block_excl_scan(L, L.flag[t], nproc);
-                int np = 2;
-                while (np < (int)total) np <<= 1;
-                const uint32_t m = sort_cancel(L, np);
+                // included entries form a prefix: count them, and the last one of
+                // each wave gives the end of its slots
+                {
+                    const uint64_t im = __ballot(incl);
+                    if (lane == 0) {
+                        L.wcnt[wv] = (uint32_t)__popcll(im);
+                        if (!im) L.wend[wv] = 0;
+                    }
+                    if (incl && (im >> lane) == 1ull) L.wend[wv] = slot + need;
+                }
+                __syncthreads();
+                lap(1);
+                uint32_t stop_at = 0, total = 0;
+#pragma unroll
+                for (int i = 0; i < NWAVE; ++i) {
+                    stop_at += L.wcnt[i];
+                    total = max(total, L.wend[i]);
+                }
+                // entries of the batched cached boundaries, one load per slot, and
+                // the boundaries' heads, all in flight together
+                {
+                    uint64_t v[IPW];
+#pragma unroll
+                    for (int q = 0; q < IPW; ++q) {
+                        const uint32_t j = q * WB + t;
+                        const uint64_t a = j < total ? L.surv[j] : NONE;
+                        v[q] = a != NONE ? ld_rlx64(P.heap + a) : 0;
+                    }
+                    const uint64_t head = (incl && batched) ? ld_rlx64(P.heap + zoff) : wkey;
+#pragma unroll
+                    for (int q = 0; q < IPW; ++q) {
+                        const uint32_t j = q * WB + t;
+                        if (j < total && L.surv[j] != NONE) L.raw[j] = v[q];
+                    }
+                    if (head != wkey) L.ints[3] = 1;  // the owner moved on
+                }
+                __syncthreads();
+                const bool retry = L.ints[3] != 0;
+                __syncthreads();  // L.ints[3] is reset by the next round
+                lap(2);
+                if (retry) {  // nothing changed yet: look again
+                    ++retries;
+                    continue;
+                }
+                retries = 0;
+                expanded += go ? 1 : 0;
+                const uint32_t m = sort_cancel(L, total, L.src);
+                lap(3);
                 ++rounds;
-                expanded += nproc;
-                if ((int64_t)(n - k) + m > P.K) {
+                if ((int64_t)(C.n() - stop_at) + m > P.K) {
                     // no room: save the column unchanged for the next pass
-                    const uint64_t off = save_desc(P, L, B, n);
+                    const uint64_t off = save_col(P, L, C, low, pend, tmp, moved);
                     if (off == PAD) {
                         if (t == 0) atomicOr(P.flags, FLAG_HEAP);
                         stop = true;
                         break;
                     }
-                    if (t == 0) defer_column(P, c, off, n);
+                    if (t == 0) defer_column(P, c, off, C.n());
                     break;
                 }
-                // the window leaves; new keys, batched boundaries and kept entries come in
-                n = merge_xor(L, B, n - k, m, tmp, moved);
+                C.nt -= stop_at;  // the window entries above the stop leave
+                merge_col(L, C, low, pend, m, tmp, moved, ph, tp);
+                nmax = max(nmax, C.n());
                 continue;
             }
             // the top edge is not a regular tail
+            const uint64_t tau = T[C.nt - 1];
             if (t == 0) {
-                const EdgeDec te = edecode(P.g, P.order, P.bpr, B[n - 1]);
+                const EdgeDec te = edecode(P.g, P.order, P.bpr, tau);
                 const uint8_t code = te.mask ? P.G[(int64_t)te.mask * V + te.lo] : (uint8_t)0xFE;
                 int action = 0;
                 uint32_t o = 0;
@@ -747,23 +1224,24 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
                     else if (o == EMPTY32 || o > c) action = 1;  // claim
                     else action = 2;                             // add the owner's boundary
                 }
-                L.ints[2] = action;
-                L.ints[3] = (int)o;
-                L.ints[4] = (int)te.id;
+                L.ints[4] = action;
+                L.ints[5] = (int)o;
+                L.ints[6] = (int)te.id;
             }
             __syncthreads();
-            const int action = L.ints[2];
-            const uint32_t o = (uint32_t)L.ints[3];
-            const uint32_t eid = (uint32_t)L.ints[4];
-            const uint64_t tau = B[n - 1];
+            const int action = L.ints[4];
+            const uint32_t o = (uint32_t)L.ints[5];
+            const uint32_t eid = (uint32_t)L.ints[6];
             __syncthreads();
+            lap(6);
             if (action < 0) {
                 if (t == 0) atomicOr(P.flags, FLAG_GUARD);
                 stop = true;
                 break;
             }
             if (action == 1) {
-                const uint64_t off = save_desc(P, L, B, n);
+                const uint64_t off = save_col(P, L, C, low, pend, tmp, moved);
+                const uint32_t n = C.n();
                 if (off == PAD) {
                     if (t == 0) atomicOr(P.flags, FLAG_HEAP);
                     stop = true;
@@ -772,14 +1250,18 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
                 if (t == 0) {
                     st_rlx64(&P.bndptr[c], (off << 24) | n);
                     wait_stores();
-                    L.ints[5] = cas32(&P.owner1[eid], o, c) ? 1 : 0;
-                    if (L.ints[5] && o != EMPTY32) L.u64s[2] = ld_rlx64(&P.bndptr[o]);
+                    L.ints[7] = cas32(&P.owner1[eid], o, c) ? 1 : 0;
+                    if (L.ints[7] && o != EMPTY32) L.u64s[2] = ld_rlx64(&P.bndptr[o]);
                 }
                 __syncthreads();
-                const int won = L.ints[5];
+                lap(8);
+                const int won = L.ints[7];
                 const uint64_t bo = L.u64s[2];
                 __syncthreads();
-                if (!won) continue;
+                if (!won) {
+                    ++retries;
+                    continue;
+                }
                 if (o == EMPTY32) break;  // settled
                 ++evictions;
                 c = o;
@@ -789,52 +1271,82 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
                     if (t == 0) defer_column(P, c, boff, bl);
                     break;
                 }
-                for (uint32_t i = t; i < bl; i += WB) B[i] = ld_rlx64(P.heap + boff + (bl - 1 - i));
-                __syncthreads();
-                n = bl;
+                load_col(L, C, low, P.heap + boff, bl);
+                lap(8);
                 continue;
             }
-            // action 2: B += Boundary(o), merged in chunks (largest keys first)
+            // action 2: boundary += Boundary(o), merged in chunks (largest keys first)
             if (t == 0) {
                 const uint64_t b = ld_rlx64(&P.bndptr[o]);
                 L.u64s[3] = b;
-                L.ints[6] = (b != EMPTY64 && ld_rlx64(P.heap + (b >> 24)) == tau) ? 1 : 0;
+                L.ints[7] = (b != EMPTY64 && ld_rlx64(P.heap + (b >> 24)) == tau) ? 1 : 0;
             }
             __syncthreads();
             const uint64_t b = L.u64s[3];
-            const int ok = L.ints[6];
+            const int ok = L.ints[7];
             __syncthreads();
-            if (!ok) continue;  // o moved on: look again
+            if (!ok) {  // o moved on: look again
+                ++retries;
+                continue;
+            }
+            retries = 0;
             const uint64_t aoff = b >> 24;
             const uint32_t alen = (uint32_t)(b & 0xFFFFFF);
-            if ((int64_t)n + alen > P.K) {
+            if ((int64_t)C.n() + alen > P.K) {
                 // the sum might not fit: hand the column, unchanged, to the next pass
-                const uint64_t off = save_desc(P, L, B, n);
+                const uint64_t off = save_col(P, L, C, low, pend, tmp, moved);
                 if (off == PAD) {
                     if (t == 0) atomicOr(P.flags, FLAG_HEAP);
                     stop = true;
                     break;
                 }
-                if (t == 0) defer_column(P, c, off, n);
+                if (t == 0) defer_column(P, c, off, C.n());
                 break;
             }
             ++adds;
             for (uint32_t base = 0; base < alen; base += NW) {
                 const uint32_t m = min((uint32_t)NW, alen - base);
-                for (uint32_t j = t; j < m; j += WB) L.src[j] = ld_rlx64(P.heap + aoff + base + (m - 1 - j));
+                uint64_t v[IPW];
+#pragma unroll
+                for (int q = 0; q < IPW; ++q) {
+                    const uint32_t j = q * WB + t;
+                    v[q] = j < m ? ld_rlx64(P.heap + aoff + base + (m - 1 - j)) : 0;
+                }
+#pragma unroll
+                for (int q = 0; q < IPW; ++q) {
+                    const uint32_t j = q * WB + t;
+                    if (j < m) L.src[j] = v[q];
+                }
                 __syncthreads();
-                n = merge_xor(L, B, n, m, tmp, moved);
+                uint64_t tq = 0;
+                merge_col(L, C, low, pend, m, tmp, moved, nullptr, tq);
             }
+            nmax = max(nmax, C.n());
+            lap(7);
         }
         __syncthreads();
+        if (t == 0) {
+            const uint64_t dt = __builtin_amdgcn_s_memrealtime() - t0;
+            atomicMax(&P.ctrs[C_TMAX], (unsigned long long)dt);
+            atomicAdd(&P.ctrs[C_TSUM], (unsigned long long)dt);
+            atomicMax(&P.ctrs[C_RMAX], rounds - rounds0);
+            atomicMax(&P.ctrs[C_AMAX], adds - adds0);
+            atomicMax(&P.ctrs[C_NMAX], (unsigned long long)nmax);
+            if (dt > 100000) {
+                atomicAdd(&P.ctrs[C_SLOW], 1ull);
+                atomicAdd(&P.ctrs[C_PHASE + N_PHASE], rounds - rounds0);
+                atomicAdd(&P.ctrs[C_PHASE + N_PHASE + 1], adds - adds0);
+                for (int i = 0; i < N_PHASE; ++i) atomicAdd(&P.ctrs[C_PHASE + i], (unsigned long long)ph[i]);
+            }
+        }
         if (stop) break;
     }
+    if (expanded) atomicAdd(&P.ctrs[C_EXPANDED], expanded);
     if (t == 0) {
         atomicAdd(&P.ctrs[C_STEPS], steps);
         atomicAdd(&P.ctrs[C_EVICT], evictions);
         atomicAdd(&P.ctrs[C_ADDS], adds);
         atomicAdd(&P.ctrs[C_ROUNDS], rounds);
-        atomicAdd(&P.ctrs[C_EXPANDED], expanded);
         atomicAdd(&P.ctrs[C_MOVED], moved);
     }
 }
@@ -931,6 +1443,8 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
     for (int d = 0; d < 6; ++d) s.stats[d] = 0;
     for (int d = 0; d < 5; ++d) s.pass_work[d] = s.pass_us[d] = 0;
     for (int d = 0; d < 3; ++d) s.wide[d] = 0;
+    for (int d = 0; d < 6; ++d) s.wide_t[d] = 0;
+    for (int d = 0; d < 12; ++d) s.wide_ph[d] = 0;
     // unpaired 2-saddles, ascending
     uint32_t* flag = (uint32_t*)s.colflag;
     uint32_t* cols = (uint32_t*)s.cols;
@@ -980,7 +1494,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         int64_t nwork = ncols;
         int cur = 0;
         bool overflow = false;
-        unsigned long long hc[16] = {0};
+        unsigned long long hc[N_CTRS] = {0};
         // pass plan: thread-per-column with small heaps, then one workgroup per
         // column with boundaries of up to plan_k entries
         int64_t plan_k[MAX_PASSES] = {k0, (int64_t)1 << 15, (int64_t)1 << 20, (int64_t)1 << 24, 0};
@@ -994,7 +1508,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             if (K == 0) break;
             const int64_t T = std::max<int64_t>(1, std::min<int64_t>(nwork, plan_t[pass]));
             const auto t_pass = std::chrono::steady_clock::now();
-            const size_t need = pass == 0 ? (size_t)8 * T * K : (size_t)8 * 2 * T * K;
+            const size_t need = pass == 0 ? (size_t)8 * T * K : (size_t)8 * T * (2 * K + PCAP);
             if (grow(s.scratch, s.scratch_cap, need, s.bytes)) return oom("working boundaries");
             D1K P;
             P.g = in.g;
@@ -1021,14 +1535,15 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             P.ctrs = (unsigned long long*)s.ctrs;
             P.flags = in.flags;
             // fresh work cursor, deferral count and work counters for this pass
-            if (hipMemsetAsync((unsigned long long*)s.ctrs + C_NEXT, 0, 8 * 8, st) != hipSuccess) return -5;
+            if (hipMemsetAsync((unsigned long long*)s.ctrs + C_NEXT, 0, 8 * (N_CTRS - C_NEXT), st) != hipSuccess)
+                return -5;
             if (pass == 0)
                 hipLaunchKernelGGL(k_d1, dim3(nblocks(T)), dim3(DB), 0, st, P);
             else
                 hipLaunchKernelGGL(k_d1_wide, dim3((unsigned)T), dim3(WB), 0, st, P);
             uint32_t f = 0;
             if (hipMemcpyAsync(&f, in.flags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
-                hipMemcpyAsync(hc, s.ctrs, 128, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipMemcpyAsync(hc, s.ctrs, sizeof(hc), hipMemcpyDeviceToHost, st) != hipSuccess ||
                 hipStreamSynchronize(st) != hipSuccess) {
                 err = "D1: kernel failed";
                 return -5;
@@ -1053,6 +1568,15 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             s.wide[0] += hc[C_ROUNDS];
             s.wide[1] += hc[C_EXPANDED];
             s.wide[2] += hc[C_MOVED];
+            s.wide_t[0] = std::max<uint64_t>(s.wide_t[0], hc[C_TMAX] / 100);
+            s.wide_t[1] += hc[C_TSUM] / 100;
+            s.wide_t[2] = std::max<uint64_t>(s.wide_t[2], hc[C_RMAX]);
+            s.wide_t[3] = std::max<uint64_t>(s.wide_t[3], hc[C_AMAX]);
+            s.wide_t[4] = std::max<uint64_t>(s.wide_t[4], hc[C_NMAX]);
+            s.wide_t[5] += hc[C_SLOW];
+            for (int i = 0; i < N_PHASE; ++i) s.wide_ph[i] += hc[C_PHASE + i] / 100;
+            s.wide_ph[10] += hc[C_PHASE + N_PHASE];
+            s.wide_ph[11] += hc[C_PHASE + N_PHASE + 1];
             if (f & (FLAG_HEAP | FLAG_WORK)) {
                 overflow = true;
                 break;

@@ -641,7 +641,7 @@ int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap) {
         case DMS_BUF_ARCS2: bytes = 8 * ctx->ncrit[2]; break;
         case DMS_BUF_STATS: {
             if (ctx->stage < 1) return fail(ctx, DMS_E_STATE, "no gradient computed yet");
-            bytes = 8 * 32;
+            bytes = 8 * 48;
             if (!dst) return bytes;
             if (cap < bytes) return fail(ctx, DMS_E_CAPACITY, "destination too small");
             uint64_t* h = (uint64_t*)dst;
@@ -654,6 +654,8 @@ int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap) {
                 h[11 + 2 * i] = ctx->d1.pass_us[i];
             }
             for (int i = 0; i < 3; ++i) h[20 + i] = ctx->d1.wide[i];
+            for (int i = 0; i < 6; ++i) h[23 + i] = ctx->d1.wide_t[i];
+            for (int i = 0; i < 12; ++i) h[29 + i] = ctx->d1.wide_ph[i];
             return bytes;
         }
         case DMS_BUF_D1LEN: {
