@@ -113,6 +113,18 @@ int dms_pairs_d1(dms_ctx* ctx, dms_pair* d1, int64_t cap1, int64_t* n1);
 /* The whole pipeline: gradient, D0/D2, D1, infinite classes (Sec. 6). */
 int dms_diagram(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t flags, dms_diagram_out* out);
 
+/* Backward of the persistence map (the pair values are f at the highest
+ * vertices of the birth and death simplices, Sec. 2.1 and Sec. 6): writes
+ * d_grad_field[v] = sum of d_grad[i] over the i with d_vertex[i] == v, for
+ * v in [0, nvert), and 0 elsewhere. All pointers are device pointers on the
+ * context's device: d_vertex int64[n], d_grad float[n], d_grad_field
+ * float[nvert] (owned by the caller; fully overwritten). Deterministic: each
+ * vertex's contributions are added in increasing i, in float32, starting
+ * from 0. n may be 0. A vertex outside [0, nvert) is DMS_E_INVAL (its
+ * contribution is dropped). Synchronises the context's stream. */
+int dms_scatter_grad(dms_ctx* ctx, int64_t n, const int64_t* d_vertex, const float* d_grad, int64_t nvert,
+                     float* d_grad_field);
+
 /* Inspection of internal state for tests: copies the device buffer `what`
  * (see DMS_BUF_*) to host memory `dst` of `cap` bytes; returns the byte
  * size of the buffer (or a negative error). */

@@ -46,6 +46,8 @@ struct dms_ctx {
     D1State d1;
     // output staging
     Buf ob, od, okey, ocnt;
+    // gradient scatter
+    Buf gk0, gk1, gv0, gv1, ghist, gpart, gflag;
     hipEvent_t ev[NEV] = {};
     bool ev_ok[NEV] = {};
     float ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -309,7 +311,8 @@ void dms_destroy(dms_ctx* ctx) {
     Buf* all[] = {&ctx->rank, &ctx->keysA, &ctx->keysB, &ctx->valsA, &ctx->valsB, &ctx->G, &ctx->hist,
                   &ctx->part, &ctx->flags, &ctx->counters, &ctx->stats, &ctx->na0, &ctx->nb0, &ctx->owner0, &ctx->bnd0,
                   &ctx->paired1, &ctx->na2, &ctx->nb2, &ctx->owner2, &ctx->bnd2, &ctx->paired2, &ctx->tet2pos,
-                  &ctx->ob, &ctx->od, &ctx->okey, &ctx->ocnt};
+                  &ctx->ob, &ctx->od, &ctx->okey, &ctx->ocnt, &ctx->gk0, &ctx->gk1, &ctx->gv0, &ctx->gv1,
+                  &ctx->ghist, &ctx->gpart, &ctx->gflag};
     for (Buf* b : all)
         if (b->p) (void)hipFree(b->p);
     for (int d = 0; d < 4; ++d) {
@@ -688,6 +691,32 @@ int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap) {
     }
     if (bytes) HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
     return bytes;
+}
+
+int dms_scatter_grad(dms_ctx* ctx, int64_t n, const int64_t* d_vertex, const float* d_grad, int64_t nvert,
+                     float* d_grad_field) {
+    if (!ctx) return DMS_E_INVAL;
+    if (n < 0 || nvert < 1 || nvert > ((int64_t)1 << 32) || !d_grad_field || (n > 0 && (!d_vertex || !d_grad)))
+        return fail(ctx, DMS_E_INVAL, "dms_scatter_grad: bad sizes or null pointers");
+    if (n > ((int64_t)1 << 32) - 1) return fail(ctx, DMS_E_INVAL, "dms_scatter_grad: too many contributions");
+    HIPCHK(hipSetDevice(ctx->device));
+    int r = DMS_OK;
+    const int64_t m = n > 0 ? n : 1;
+    if ((r = ensure(ctx, ctx->gk0, 4 * m)) || (r = ensure(ctx, ctx->gk1, 4 * m)) || (r = ensure(ctx, ctx->gv0, 4 * m)) ||
+        (r = ensure(ctx, ctx->gv1, 4 * m)) || (r = ensure(ctx, ctx->ghist, 4 * 256 * sort_tiles(m))) ||
+        (r = ensure(ctx, ctx->gpart, 4 * scan_part_size(256 * sort_tiles(m)))) || (r = ensure(ctx, ctx->gflag, 64)))
+        return r;
+    uint32_t* flag = P<uint32_t>(ctx->gflag);
+    fill_u32(flag, 0, 1, ctx->st);
+    scatter_grad(d_vertex, d_grad, n, nvert, d_grad_field, P<uint32_t>(ctx->gk0), P<uint32_t>(ctx->gv0),
+                 P<uint32_t>(ctx->gk1), P<uint32_t>(ctx->gv1), P<uint32_t>(ctx->ghist), P<uint32_t>(ctx->gpart), flag,
+                 ctx->st);
+    HIPCHK(hipGetLastError());
+    uint32_t h = 0;
+    HIPCHK(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    if (h) return fail(ctx, DMS_E_INVAL, "dms_scatter_grad: vertex index out of range (gradient left zero there)");
+    return DMS_OK;
 }
 
 int dms_stage_ms(const dms_ctx* ctx, float ms[8]) {

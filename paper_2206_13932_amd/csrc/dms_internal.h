@@ -64,4 +64,9 @@ void reduce_pairs(const uint32_t* na, const uint32_t* nb, int64_t m, uint32_t* o
                   uint32_t* flags, unsigned long long* stats, hipStream_t st);
 void settled_columns(const uint64_t* bnd, const uint32_t* owner, int64_t m, uint8_t* paired, hipStream_t st);
 
+// grad.hip
+void scatter_grad(const int64_t* vertex, const float* grad, int64_t n, int64_t nvert, float* out, uint32_t* k0,
+                  uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t* hist, uint32_t* part, uint32_t* flags,
+                  hipStream_t st);
+
 }  // namespace dms

@@ -75,6 +75,8 @@ def load_library() -> ctypes.CDLL:
     lib.dms_debug_copy.restype = i64
     lib.dms_stage_ms.argtypes = [_p, ctypes.POINTER(ctypes.c_float * 8)]
     lib.dms_stage_ms.restype = ctypes.c_int
+    lib.dms_scatter_grad.argtypes = [_p, i64, _p, _p, i64, _p]
+    lib.dms_scatter_grad.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -205,6 +207,20 @@ class Context:
         if r < 0:
             self._raise(int(r))
         return buf.view(dtype)
+
+    def scatter_grad(self, vertex: torch.Tensor, grad: torch.Tensor, nvert: int) -> torch.Tensor:
+        """Deterministic scatter-add: out[v] = sum of grad[i] with vertex[i] == v
+        (in increasing i), zero elsewhere; a float32 device tensor [nvert]."""
+        vertex = vertex.to(device=self.device, dtype=torch.int64).contiguous()
+        grad = grad.to(device=self.device, dtype=torch.float32).contiguous()
+        if vertex.shape != grad.shape or vertex.dim() != 1:
+            raise ValueError("vertex and grad must be 1-d tensors of the same length")
+        out = torch.empty(nvert, dtype=torch.float32, device=self.device)
+        rc = self.lib.dms_scatter_grad(self.h, vertex.numel(), _p(vertex.data_ptr()), _p(grad.data_ptr()), nvert,
+                                       _p(out.data_ptr()))
+        if rc != DMS_OK:
+            self._raise(rc)
+        return out
 
     def stage_ms(self):
         arr = (ctypes.c_float * 8)()
