@@ -70,6 +70,65 @@ def cpu_baseline(field, crop):
                       f"({sub.size} vertices, {dt:.1f} s)"}
 
 
+def serving_bench(n_requests, rate, plain_sample, calib):
+    """Continuous batching of a Poisson trace of mixed-size requests (grid
+    side log-uniform in [16, 128] per axis, Gaussian mixtures + 1% noise),
+    with the batch tile shapes picked by the autotuner on a calibration
+    sample; the plain pipeline (one request at a time) on a sample beside."""
+    import numpy as np
+    import synthfields as sf
+    from paper_2206_13932_amd import autotune, serving
+    t = time.perf_counter()
+    specs = sf.serving_requests(n_requests, seed=1000, side_range=(16, 128), k=8, noise_frac=0.01, rate=rate)
+    reqs = serving.make_requests(specs, (sf.gaussians(shape, seed, 8, 0.01) for _, shape, seed in specs))
+    real = sum(r.host_field.numel() for r in reqs)
+    print(f"[serve] {n_requests} requests ({real / 1e6:.1f} Mvertices) generated in {time.perf_counter() - t:.1f}s",
+          file=sys.stderr, flush=True)
+    cfg, table = autotune.autotune(reqs[:calib])
+    for c, r in table:
+        print(f"[serve] autotune {c}: {r:.0f} req/s", file=sys.stderr, flush=True)
+    server = serving.Server(cfg)
+    try:
+        stats = server.run_trace(reqs)
+    finally:
+        server.close()
+    plain = serving.run_plain(reqs[:plain_sample])
+    b = np.array([x[1:4] for x in stats.batches], dtype=np.float64)
+    out = {"requests": n_requests, "arrival_rate_per_s": rate, "req_per_s": round(stats.req_per_s, 1),
+           "p50_ms": round(stats.pct(50), 2), "p99_ms": round(stats.pct(99), 2),
+           "Mvertices_per_s": round(real / stats.wall_s / 1e6, 1),
+           "batches": len(stats.batches), "mean_items_per_batch": round(float(b[:, 0].mean()), 1),
+           "packing_efficiency": round(float(b[:, 2].sum() / b[:, 1].sum()), 3),
+           "tuned": {"cross": list(cfg.cross), "budget_vertices": cfg.budget_vertices,
+                     "use_graph": cfg.use_graph, "workers": cfg.workers,
+                     "capacity_req_per_s": round(max(r for _, r in table), 1)},
+           "plain_req_per_s": round(plain, 1), "plain_sample": plain_sample}
+    print(f"[serve] {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def differentiation_bench(n_fields=64, side=96):
+    """Forward + backward of the loss sum over D1, D2 of (death - birth)^2 on a
+    batch of 96^3 fields (16 Gaussians + 2% noise)."""
+    import torch
+    import synthfields as sf
+    from paper_2206_13932_amd import autograd, dms
+    ctx = dms.Context(0)
+    xs = [torch.from_numpy(sf.gaussians((side, side, side), 5000 + i, 16, 0.02)).cuda() for i in range(n_fields)]
+    x = xs[0].clone().requires_grad_(True)
+    autograd.d12_squared_persistence(x, ctx).backward()  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in xs:
+        x = f.requires_grad_(True)
+        autograd.d12_squared_persistence(x, ctx).backward()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.close()
+    return {"fields": n_fields, "side": side, "fields_per_s": round(n_fields / dt, 1),
+            "ms_per_field_fwd_bwd": round(dt * 1e3 / n_fields, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +137,11 @@ def main():
     ap.add_argument("--workload", default="smooth512", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-crop", type=int, default=80)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=4096, help="0 skips the serving run")
+    ap.add_argument("--serve-rate", type=float, default=1000.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-plain-sample", type=int, default=512)
+    ap.add_argument("--serve-calib", type=int, default=256)
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiation run")
     ap.add_argument("--mode", default="diagram", choices=["diagram", "gradient"],
                     help="gradient: time dms_gradient alone and a 1 GiB device copy "
                          "(the reference kernel for hardware byte counters)")
@@ -187,9 +251,17 @@ def main():
                      "traffic": traffic, "algorithmic_bytes": int(gbytes),
                      "avg_kernel_ms": round(g_avg_ms, 4)},
     }
+    ctx.close()
+    del field, out
+    torch.cuda.empty_cache()
+    if args.serve_requests > 0:
+        line["serving"] = serving_bench(args.serve_requests, args.serve_rate, args.serve_plain_sample,
+                                        args.serve_calib)
+    if not args.no_diff:
+        line["differentiation"] = differentiation_bench()
+        print(f"[bench] differentiation {line['differentiation']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(f, args.cpu_crop)
-    ctx.close()
     print(json.dumps(line), flush=True)
 
 

@@ -113,6 +113,57 @@ int dms_pairs_d1(dms_ctx* ctx, dms_pair* d1, int64_t cap1, int64_t* n1);
 /* The whole pipeline: gradient, D0/D2, D1, infinite classes (Sec. 6). */
 int dms_diagram(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t flags, dms_diagram_out* out);
 
+/* ---- Batching: many grids in one pipeline run ----
+ * The grids are placed as disjoint boxes in one super grid of cross-section
+ * cross_x * cross_y, separated by planes of +inf values; one pipeline run
+ * computes all diagrams. In the lower-star filtration the +inf vertices come
+ * after every real one and a real vertex's lower star stays inside its box,
+ * so every pair is the pair the grid has alone, with the same local simplex
+ * ids; around each box the +inf region closes the boundary as the virtual
+ * maximum of D2 does (Sec. 5.2), and a grid's infinite D0 class is reported
+ * as infinite (death = -1). */
+typedef struct {
+    int32_t nx, ny, nz; /* the item's grid, each side >= 2                       */
+    int32_t reserved;
+    int64_t offset;     /* element offset of its field [nz][ny][nx] in d_fields  */
+} dms_item;
+
+typedef struct {
+    int32_t cross_x, cross_y; /* super-grid cross-section (>= every side + 1);
+                                 0 = the smallest multiple of 16 that fits     */
+    int32_t z_quantum;        /* depth rounded up to a multiple (0 = 16) so
+                                 that super grids repeat                       */
+    int32_t use_graph;        /* replay the order + gradient kernels from a
+                                 captured hipGraph per super grid (needs a
+                                 non-default stream)                           */
+} dms_batch_opts;
+
+typedef struct {
+    dms_pair* pairs[3];       /* device, caller-owned: every item's pairs of
+                                 dimension d, item after item, each item's in
+                                 the order of dms_diagram                       */
+    int64_t cap[3];
+    int64_t n[3];             /* pairs written (or needed on DMS_E_CAPACITY)   */
+    int64_t* item_start[3];   /* host, caller-owned, nitems + 1 entries: item
+                                 i's pairs are [item_start[d][i], [i + 1])      */
+} dms_batch_out;
+
+/* Diagrams of nitems grids whose float32 fields lie in d_fields (device).
+ * items and opts are host memory (opts may be NULL). DMS_E_INVAL for an item
+ * wider than the cross-section or a super grid over the size limit. */
+int dms_diagram_batch(dms_ctx* ctx, const float* d_fields, const dms_item* items, int32_t nitems, uint32_t flags,
+                      const dms_batch_opts* opts, dms_batch_out* out);
+
+/* The super grid (X, Y, Z) a batch would use, computed on the host only; its
+ * X*Y*Z vertices set the batch's device footprint. origins (host, 3*nitems,
+ * may be NULL) receives each item's box origin (x, y, z) in the super grid. */
+int dms_batch_layout(const dms_item* items, int32_t nitems, const dms_batch_opts* opts, int32_t dims[3],
+                     int32_t* origins);
+
+/* Last batch: [0..2] super grid X, Y, Z, [3] real vertices, [4] graph
+ * launches, [5] graph captures, [6] runs without a graph, [7] items. */
+int dms_batch_info(const dms_ctx* ctx, int64_t info[8]);
+
 /* Backward of the persistence map (the pair values are f at the highest
  * vertices of the birth and death simplices, Sec. 2.1 and Sec. 6): writes
  * d_grad_field[v] = sum of d_grad[i] over the i with d_vertex[i] == v, for

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/dms.h"
 #include "dms_internal.h"
@@ -48,6 +49,18 @@ struct dms_ctx {
     Buf ob, od, okey, ocnt;
     // gradient scatter
     Buf gk0, gk1, gv0, gv1, ghist, gpart, gflag;
+    // batching: super field, owner map, slot table, super pairs, demux scratch
+    Buf bfield, bowner, bslots, bpairs[3], bkey, bdeath, bitem, bkept;
+    BatchLayout blayout;
+    // captured order + gradient stage per (super grid, buffer generation, caps)
+    struct GraphEntry {
+        int X, Y, Z;
+        std::vector<const void*> sig;  // every buffer the captured kernels touch
+        uint32_t cap[4];
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+    int64_t binfo[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     hipEvent_t ev[NEV] = {};
     bool ev_ok[NEV] = {};
     float ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -312,7 +325,9 @@ void dms_destroy(dms_ctx* ctx) {
                   &ctx->part, &ctx->flags, &ctx->counters, &ctx->stats, &ctx->na0, &ctx->nb0, &ctx->owner0, &ctx->bnd0,
                   &ctx->paired1, &ctx->na2, &ctx->nb2, &ctx->owner2, &ctx->bnd2, &ctx->paired2, &ctx->tet2pos,
                   &ctx->ob, &ctx->od, &ctx->okey, &ctx->ocnt, &ctx->gk0, &ctx->gk1, &ctx->gv0, &ctx->gv1,
-                  &ctx->ghist, &ctx->gpart, &ctx->gflag};
+                  &ctx->ghist, &ctx->gpart, &ctx->gflag, &ctx->bfield, &ctx->bowner, &ctx->bslots, &ctx->bpairs[0],
+                  &ctx->bpairs[1], &ctx->bpairs[2], &ctx->bkey, &ctx->bdeath, &ctx->bitem, &ctx->bkept};
+    for (auto& e : ctx->graphs) (void)hipGraphExecDestroy(e.exec);
     for (Buf* b : all)
         if (b->p) (void)hipFree(b->p);
     for (int d = 0; d < 4; ++d) {
@@ -329,15 +344,12 @@ void dms_destroy(dms_ctx* ctx) {
 
 const char* dms_last_error(const dms_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
 
-int dms_gradient(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t flags, dms_gradient_info* info) {
-    if (!ctx) return DMS_E_INVAL;
-    if (!d_field) return fail(ctx, DMS_E_INVAL, "d_field is NULL");
-    if (grid.nx < 2 || grid.ny < 2 || grid.nz < 2) return fail(ctx, DMS_E_INVAL, "every grid side must be >= 2");
+// ---- a0-a3 in three parts: buffers, the enqueued kernels (no host sync, no
+// allocation, no memset: a hipGraph may capture them), and the count
+// read-back with the critical sort ----
+
+static int gradient_setup(dms_ctx* ctx, dms_grid grid) {
     const int64_t V = (int64_t)grid.nx * grid.ny * grid.nz;
-    if (12 * V >= (int64_t)0xFFFFFFFFll) return fail(ctx, DMS_E_INVAL, "grid too large: 12*V must stay below 2^32");
-    if (!(flags & DMS_VIRTUAL_MAX)) return fail(ctx, DMS_E_INVAL, "DMS_VIRTUAL_MAX is required");
-    HIPCHK(hipSetDevice(ctx->device));
-    hipStream_t st = ctx->st;
     ctx->stage = 0;
     ctx->g.nx = grid.nx;
     ctx->g.ny = grid.ny;
@@ -347,8 +359,6 @@ int dms_gradient(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t fla
     ctx->g.sz = (int64_t)grid.nx * grid.ny;
     ctx->bpr = bits_for((uint64_t)(V - 1));
     for (int i = 0; i < NEV; ++i) ctx->ev_ok[i] = false;
-
-    // ---- a0: vertex order ----
     ENSURE(ctx->rank, 4 * V);
     ENSURE(ctx->keysA, 8 * V);
     ENSURE(ctx->keysB, 8 * V);
@@ -356,77 +366,112 @@ int dms_gradient(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t fla
     ENSURE(ctx->valsB, 4 * V);
     ENSURE(ctx->hist, 4 * 256 * sort_tiles(V));
     ENSURE(ctx->part, 4 * scan_part_size(256 * sort_tiles(V)));
-    HIPCHK(hipMemsetAsync(ctx->flags.p, 0, 64, st));
-    record(ctx, EV_START);
+    ENSURE(ctx->ob, 4 * V);
+    ENSURE(ctx->G, (size_t)PLANES * V);
+    for (int d = 0; d < 4; ++d) {
+        if (ctx->cap[d] == 0)
+            ctx->cap[d] = (uint32_t)std::min<int64_t>(V / (d == 0 || d == 3 ? 4 : 2) + 256, 0xF0000000ll);
+        ENSURE(ctx->cid[d], 4ull * ctx->cap[d]);
+        ENSURE(ctx->ck[d], (d == 0 ? 4ull : 8ull) * ctx->cap[d]);
+        if (d >= 2) ENSURE(ctx->ck2[d], (d == 2 ? 4ull : 8ull) * ctx->cap[d]);
+    }
+    ctx->order = P<uint32_t>(ctx->ob);
+    return DMS_OK;
+}
+
+static void gradient_enqueue(dms_ctx* ctx, const float* d_field, bool events) {
+    hipStream_t st = ctx->st;
+    const int64_t V = ctx->g.V;
+    fill_u32(P<uint32_t>(ctx->flags), 0, 16, st);
+    if (events) record(ctx, EV_START);
     float_keys(d_field, V, P<uint32_t>(ctx->keysA), P<uint32_t>(ctx->flags), st);
     int r = radix_sort_pairs<uint32_t>(P<uint32_t>(ctx->keysA), P<uint32_t>(ctx->valsA), P<uint32_t>(ctx->keysB),
                                        P<uint32_t>(ctx->valsB), V, 0, 32, true, P<uint32_t>(ctx->hist),
                                        P<uint32_t>(ctx->part), st);
     uint32_t* order = r ? P<uint32_t>(ctx->valsB) : P<uint32_t>(ctx->valsA);
     rank_scatter(order, V, P<uint32_t>(ctx->rank), st);
-    record(ctx, EV_ORDER);
+    if (events) record(ctx, EV_ORDER);
     // keep the order (rank -> vertex) in a buffer of its own
-    ENSURE(ctx->ob, 4 * V);
-    HIPCHK(hipMemcpyAsync(ctx->ob.p, order, 4 * V, hipMemcpyDeviceToDevice, st));
-    ctx->order = P<uint32_t>(ctx->ob);
+    (void)hipMemcpyAsync(ctx->ob.p, order, 4 * V, hipMemcpyDeviceToDevice, st);
+    CritLists cl;
+    cl.count = P<uint32_t>(ctx->counters);
+    for (int d = 0; d < 4; ++d) cl.cap[d] = ctx->cap[d];
+    cl.id0 = P<uint32_t>(ctx->cid[0]);
+    cl.key0 = P<uint32_t>(ctx->ck[0]);
+    cl.id1 = P<uint32_t>(ctx->cid[1]);
+    cl.key1 = P<uint64_t>(ctx->ck[1]);
+    cl.id2 = P<uint32_t>(ctx->cid[2]);
+    cl.key2hi = P<uint64_t>(ctx->ck[2]);
+    cl.key2lo = P<uint32_t>(ctx->ck2[2]);
+    cl.id3 = P<uint32_t>(ctx->cid[3]);
+    cl.key3hi = P<uint64_t>(ctx->ck[3]);
+    cl.key3lo = P<uint64_t>(ctx->ck2[3]);
+    fill_u32(P<uint32_t>(ctx->counters), 0, 4, st);
+    if (events) record(ctx, EV_GK);
+    launch_gradient(ctx->g, P<uint32_t>(ctx->rank), P<uint8_t>(ctx->G), ctx->bpr, cl, st);
+    if (events) record(ctx, EV_GRAD);
+}
 
-    // ---- a1 + a2: gradient and critical cells ----
-    ENSURE(ctx->G, (size_t)PLANES * V);
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        for (int d = 0; d < 4; ++d) {
-            if (ctx->cap[d] == 0) ctx->cap[d] = (uint32_t)std::min<int64_t>(V / (d == 0 || d == 3 ? 4 : 2) + 256,
-                                                                           0xF0000000ll);
-            ENSURE(ctx->cid[d], 4ull * ctx->cap[d]);
-            ENSURE(ctx->ck[d], (d == 0 ? 4ull : 8ull) * ctx->cap[d]);
-            if (d >= 2) ENSURE(ctx->ck2[d], (d == 2 ? 4ull : 8ull) * ctx->cap[d]);
+// reads the counts; *over is set when a critical list overflowed (the caps
+// are raised: set up and enqueue again)
+static int gradient_counts(dms_ctx* ctx, bool* over) {
+    hipStream_t st = ctx->st;
+    uint32_t cnt[4];
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(cnt, ctx->counters.p, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *over = false;
+    for (int d = 0; d < 4; ++d) {
+        ctx->ncrit[d] = cnt[d];
+        if (cnt[d] > ctx->cap[d]) {
+            *over = true;
+            ctx->cap[d] = cnt[d] + 256;
         }
-        CritLists cl;
-        cl.count = P<uint32_t>(ctx->counters);
-        for (int d = 0; d < 4; ++d) cl.cap[d] = ctx->cap[d];
-        cl.id0 = P<uint32_t>(ctx->cid[0]);
-        cl.key0 = P<uint32_t>(ctx->ck[0]);
-        cl.id1 = P<uint32_t>(ctx->cid[1]);
-        cl.key1 = P<uint64_t>(ctx->ck[1]);
-        cl.id2 = P<uint32_t>(ctx->cid[2]);
-        cl.key2hi = P<uint64_t>(ctx->ck[2]);
-        cl.key2lo = P<uint32_t>(ctx->ck2[2]);
-        cl.id3 = P<uint32_t>(ctx->cid[3]);
-        cl.key3hi = P<uint64_t>(ctx->ck[3]);
-        cl.key3lo = P<uint64_t>(ctx->ck2[3]);
-        HIPCHK(hipMemsetAsync(ctx->counters.p, 0, 16, st));
-        record(ctx, EV_GK);
-        launch_gradient(ctx->g, P<uint32_t>(ctx->rank), P<uint8_t>(ctx->G), ctx->bpr, cl, st);
-        record(ctx, EV_GRAD);
-        uint32_t cnt[4];
-        HIPCHK(hipMemcpyAsync(cnt, ctx->counters.p, 16, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        HIPCHK(hipGetLastError());
-        bool over = false;
-        for (int d = 0; d < 4; ++d) {
-            ctx->ncrit[d] = cnt[d];
-            if (cnt[d] > ctx->cap[d]) {
-                over = true;
-                ctx->cap[d] = cnt[d] + 256;
-            }
-        }
-        if (!over) break;
-        if (attempt == 1) return fail(ctx, DMS_E_INTERNAL, "critical list capacity");
     }
-    r = check_flags(ctx);
-    if (r != DMS_OK) return r;
+    return DMS_OK;
+}
 
+static int gradient_finish(dms_ctx* ctx, dms_gradient_info* info) {
+    int r = check_flags(ctx);
+    if (r != DMS_OK) return r;
     // ---- a3: sort critical simplices by the lexicographic order ----
     for (int d = 0; d < 4; ++d) {
         r = sort_ids(ctx, d);
         if (r != DMS_OK) return r;
     }
     record(ctx, EV_SORT);
-    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
     HIPCHK(hipGetLastError());
     if (info)
         for (int d = 0; d < 4; ++d) info->n_crit[d] = ctx->ncrit[d];
     ctx->stage = 1;
     return DMS_OK;
+}
+
+static int check_grid(dms_ctx* ctx, dms_grid grid, uint32_t flags) {
+    if (grid.nx < 2 || grid.ny < 2 || grid.nz < 2) return fail(ctx, DMS_E_INVAL, "every grid side must be >= 2");
+    const int64_t V = (int64_t)grid.nx * grid.ny * grid.nz;
+    if (12 * V >= (int64_t)0xFFFFFFFFll) return fail(ctx, DMS_E_INVAL, "grid too large: 12*V must stay below 2^32");
+    if (!(flags & DMS_VIRTUAL_MAX)) return fail(ctx, DMS_E_INVAL, "DMS_VIRTUAL_MAX is required");
+    return DMS_OK;
+}
+
+int dms_gradient(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t flags, dms_gradient_info* info) {
+    if (!ctx) return DMS_E_INVAL;
+    if (!d_field) return fail(ctx, DMS_E_INVAL, "d_field is NULL");
+    int r = check_grid(ctx, grid, flags);
+    if (r != DMS_OK) return r;
+    HIPCHK(hipSetDevice(ctx->device));
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        r = gradient_setup(ctx, grid);
+        if (r != DMS_OK) return r;
+        gradient_enqueue(ctx, d_field, true);
+        bool over = false;
+        r = gradient_counts(ctx, &over);
+        if (r != DMS_OK) return r;
+        if (!over) return gradient_finish(ctx, info);
+    }
+    return fail(ctx, DMS_E_INTERNAL, "critical list capacity");
 }
 
 static int run_d0_d2(dms_ctx* ctx) {
@@ -716,6 +761,208 @@ int dms_scatter_grad(dms_ctx* ctx, int64_t n, const int64_t* d_vertex, const flo
     HIPCHK(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, ctx->st));
     HIPCHK(hipStreamSynchronize(ctx->st));
     if (h) return fail(ctx, DMS_E_INVAL, "dms_scatter_grad: vertex index out of range (gradient left zero there)");
+    return DMS_OK;
+}
+
+static int batch_layout(dms_ctx* ctx, const dms_item* items, int32_t nitems, const dms_batch_opts* opts,
+                        BatchLayout& L) {
+    if (!items || nitems < 1) return fail(ctx, DMS_E_INVAL, "dms batch: no items");
+    std::vector<int32_t> dims(3 * (size_t)nitems);
+    int mx = 0, my = 0;
+    for (int i = 0; i < nitems; ++i) {
+        dims[3 * i] = items[i].nx;
+        dims[3 * i + 1] = items[i].ny;
+        dims[3 * i + 2] = items[i].nz;
+        mx = std::max(mx, items[i].nx);
+        my = std::max(my, items[i].ny);
+    }
+    int X = opts && opts->cross_x > 0 ? opts->cross_x : (mx + 1 + 15) / 16 * 16;
+    int Y = opts && opts->cross_y > 0 ? opts->cross_y : (my + 1 + 15) / 16 * 16;
+    const int zq = opts && opts->z_quantum > 0 ? opts->z_quantum : 16;
+    std::string err;
+    if (pack_layers(dims.data(), nitems, X, Y, zq, L, err)) return fail(ctx, DMS_E_INVAL, "dms batch: " + err);
+    return DMS_OK;
+}
+
+int dms_batch_layout(const dms_item* items, int32_t nitems, const dms_batch_opts* opts, int32_t dims[3],
+                     int32_t* origins) {
+    if (!dims) return DMS_E_INVAL;
+    BatchLayout L;
+    const int r = batch_layout(nullptr, items, nitems, opts, L);
+    if (r != DMS_OK) return r;
+    dims[0] = L.X;
+    dims[1] = L.Y;
+    dims[2] = L.Z;
+    if (origins)
+        for (int i = 0; i < nitems; ++i) {
+            origins[3 * i] = L.slots[i].ox;
+            origins[3 * i + 1] = L.slots[i].oy;
+            origins[3 * i + 2] = L.slots[i].oz;
+        }
+    return DMS_OK;
+}
+
+int dms_diagram_batch(dms_ctx* ctx, const float* d_fields, const dms_item* items, int32_t nitems, uint32_t flags,
+                      const dms_batch_opts* opts, dms_batch_out* out) {
+    if (!ctx) return DMS_E_INVAL;
+    if (!d_fields || !out) return fail(ctx, DMS_E_INVAL, "dms_diagram_batch: NULL fields or output");
+    for (int d = 0; d < 3; ++d)
+        if (!out->item_start[d] || (out->cap[d] > 0 && !out->pairs[d]))
+            return fail(ctx, DMS_E_INVAL, "dms_diagram_batch: NULL output array");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->st;
+    BatchLayout& L = ctx->blayout;
+    int r = batch_layout(ctx, items, nitems, opts, L);
+    if (r != DMS_OK) return r;
+    int64_t real = 0;
+    for (int i = 0; i < nitems; ++i) {
+        if (items[i].offset < 0) return fail(ctx, DMS_E_INVAL, "dms_diagram_batch: negative field offset");
+        L.slots[i].src_off = items[i].offset;
+        real += (int64_t)items[i].nx * items[i].ny * items[i].nz;
+    }
+    const dms_grid sg = {L.X, L.Y, L.Z};
+    r = check_grid(ctx, sg, flags);
+    if (r != DMS_OK) return r;
+    const int64_t V = (int64_t)L.X * L.Y * L.Z;
+    ENSURE(ctx->bfield, 4 * V);
+    ENSURE(ctx->bowner, 4 * V);
+    ENSURE(ctx->bslots, sizeof(BatchSlot) * (size_t)nitems);
+    ENSURE(ctx->bitem, 4 * (size_t)nitems);
+    ENSURE(ctx->bkept, 64);
+    HIPCHK(hipMemcpyAsync(ctx->bslots.p, L.slots.data(), sizeof(BatchSlot) * (size_t)nitems, hipMemcpyHostToDevice,
+                          st));
+    launch_pack(d_fields, P<BatchSlot>(ctx->bslots), nitems, L.nrows, L, P<float>(ctx->bfield),
+                P<uint32_t>(ctx->bowner), st);
+    ctx->binfo[0] = L.X;
+    ctx->binfo[1] = L.Y;
+    ctx->binfo[2] = L.Z;
+    ctx->binfo[3] = real;
+    ctx->binfo[7] = nitems;
+
+    // ---- a0-a3 on the super grid; the kernels before the count read-back are
+    // replayed from a captured graph when the super grid repeats ----
+    const bool use_graph = opts && opts->use_graph && st != nullptr;
+    bool done = false;
+    for (int attempt = 0; attempt < 2 && !done; ++attempt) {
+        r = gradient_setup(ctx, sg);
+        if (r != DMS_OK) return r;
+        if (use_graph) {
+            // the buffers the captured kernels read and write
+            std::vector<const void*> sig = {ctx->bfield.p, ctx->flags.p, ctx->keysA.p, ctx->keysB.p, ctx->valsA.p,
+                                            ctx->valsB.p, ctx->hist.p, ctx->part.p, ctx->rank.p, ctx->ob.p,
+                                            ctx->counters.p, ctx->G.p};
+            for (int d = 0; d < 4; ++d) {
+                sig.push_back(ctx->cid[d].p);
+                sig.push_back(ctx->ck[d].p);
+                sig.push_back(ctx->ck2[d].p);
+            }
+            dms_ctx::GraphEntry* hit = nullptr;
+            for (auto& e : ctx->graphs)
+                if (e.X == L.X && e.Y == L.Y && e.Z == L.Z && e.sig == sig && std::equal(e.cap, e.cap + 4, ctx->cap))
+                    hit = &e;
+            if (!hit) {
+                hipGraph_t graph = nullptr;
+                HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+                gradient_enqueue(ctx, P<float>(ctx->bfield), false);
+                HIPCHK(hipStreamEndCapture(st, &graph));
+                hipGraphExec_t exec = nullptr;
+                const hipError_t ge = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                HIPCHK(ge);
+                if (ctx->graphs.size() >= 8) {
+                    (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+                    ctx->graphs.erase(ctx->graphs.begin());
+                }
+                dms_ctx::GraphEntry e{L.X, L.Y, L.Z, sig, {ctx->cap[0], ctx->cap[1], ctx->cap[2], ctx->cap[3]},
+                                      exec};
+                ctx->graphs.push_back(e);
+                hit = &ctx->graphs.back();
+                ++ctx->binfo[5];
+            }
+            HIPCHK(hipGraphLaunch(hit->exec, st));
+            ++ctx->binfo[4];
+        } else {
+            gradient_enqueue(ctx, P<float>(ctx->bfield), true);
+            ++ctx->binfo[6];
+        }
+        bool over = false;
+        r = gradient_counts(ctx, &over);
+        if (r != DMS_OK) return r;
+        if (!over) done = true;
+    }
+    if (!done) return fail(ctx, DMS_E_INTERNAL, "critical list capacity");
+    r = gradient_finish(ctx, nullptr);
+    if (r != DMS_OK) return r;
+    r = run_d0_d2(ctx);
+    if (r != DMS_OK) return r;
+    record(ctx, EV_D02);
+    r = check_flags(ctx);
+    if (r != DMS_OK) return r;
+    ctx->stage = 2;
+    r = run_d1(ctx);
+    if (r != DMS_OK) return r;
+    record(ctx, EV_D1);
+    r = check_flags(ctx);
+    if (r != DMS_OK) return r;
+    ctx->stage = 3;
+
+    // ---- pairs of the super grid, then per item ----
+    int64_t ns[3] = {0, 0, 0};
+    for (int d = 0; d < 3; ++d) ENSURE(ctx->bpairs[d], sizeof(dms_pair) * (size_t)(ctx->ncrit[d] + 16));
+    r = emit_d0(ctx, P<dms_pair>(ctx->bpairs[0]), ctx->ncrit[0] + 16, &ns[0], nullptr, nullptr, nullptr, nullptr,
+                nullptr);
+    if (r != DMS_OK) return r;
+    r = emit_d1(ctx, P<dms_pair>(ctx->bpairs[1]), ctx->ncrit[1] + 16, &ns[1], nullptr, nullptr, nullptr, nullptr,
+                nullptr);
+    if (r != DMS_OK) return r;
+    r = emit_d2(ctx, P<dms_pair>(ctx->bpairs[2]), ctx->ncrit[2] + 16, &ns[2], nullptr, nullptr, nullptr, nullptr,
+                nullptr, true);
+    if (r != DMS_OK) return r;
+    const int kbits = 33 + bits_for((uint64_t)std::max(1, nitems - 1));
+    bool cap_fail = false;
+    std::vector<uint32_t> cnt(nitems);
+    for (int d = 0; d < 3; ++d) {
+        const int64_t n = ns[d];
+        ENSURE(ctx->bkey, 8 * std::max<int64_t>(n, 1));
+        ENSURE(ctx->bdeath, 8 * std::max<int64_t>(n, 1));
+        ENSURE(ctx->keysB, 8 * std::max<int64_t>(n, 1));
+        ENSURE(ctx->valsA, 4 * std::max<int64_t>(n, 1));
+        ENSURE(ctx->valsB, 4 * std::max<int64_t>(n, 1));
+        ENSURE(ctx->hist, 4 * 256 * sort_tiles(std::max<int64_t>(n, 1)));
+        ENSURE(ctx->part, 4 * scan_part_size(256 * sort_tiles(std::max<int64_t>(n, 1))));
+        fill_u32(P<uint32_t>(ctx->bitem), 0, nitems, st);
+        fill_u32(P<uint32_t>(ctx->bkept), 0, 1, st);
+        launch_demux(P<dms_pair>(ctx->bpairs[d]), n, d, ctx->g, P<uint32_t>(ctx->bowner), P<BatchSlot>(ctx->bslots),
+                     P<uint64_t>(ctx->bkey), P<int64_t>(ctx->bdeath), P<uint32_t>(ctx->bitem),
+                     P<uint32_t>(ctx->bkept), st);
+        const int w = radix_sort_pairs<uint64_t>(P<uint64_t>(ctx->bkey), P<uint32_t>(ctx->valsA),
+                                                 P<uint64_t>(ctx->keysB), P<uint32_t>(ctx->valsB), n, 0, kbits, true,
+                                                 P<uint32_t>(ctx->hist), P<uint32_t>(ctx->part), st);
+        uint32_t kept = 0;
+        HIPCHK(hipMemcpyAsync(&kept, ctx->bkept.p, 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(cnt.data(), ctx->bitem.p, 4 * (size_t)nitems, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        out->n[d] = kept;
+        out->item_start[d][0] = 0;
+        for (int i = 0; i < nitems; ++i) out->item_start[d][i + 1] = out->item_start[d][i] + cnt[i];
+        if ((int64_t)kept > out->cap[d]) {
+            cap_fail = true;
+            continue;
+        }
+        launch_demux_write(w ? P<uint64_t>(ctx->keysB) : P<uint64_t>(ctx->bkey),
+                           w ? P<uint32_t>(ctx->valsB) : P<uint32_t>(ctx->valsA), P<int64_t>(ctx->bdeath), kept,
+                           out->pairs[d], st);
+    }
+    record(ctx, EV_OUT);
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    if (cap_fail) return fail(ctx, DMS_E_CAPACITY, "an output buffer is too small; n[] holds the need");
+    return DMS_OK;
+}
+
+int dms_batch_info(const dms_ctx* ctx, int64_t info[8]) {
+    if (!ctx || !info) return DMS_E_INVAL;
+    for (int i = 0; i < 8; ++i) info[i] = ctx->binfo[i];
     return DMS_OK;
 }
 

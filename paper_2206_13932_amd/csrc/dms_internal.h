@@ -3,6 +3,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+#include <vector>
+
+#include "../../include/dms.h"
 #include "dms_device.h"
 
 namespace dms {
@@ -63,6 +67,28 @@ void trace_d2(const GridDev& g, const uint8_t* G, const uint32_t* tet2pos, const
 void reduce_pairs(const uint32_t* na, const uint32_t* nb, int64_t m, uint32_t* owner, uint64_t* bnd,
                   uint32_t* flags, unsigned long long* stats, hipStream_t st);
 void settled_columns(const uint64_t* bnd, const uint32_t* owner, int64_t m, uint8_t* paired, hipStream_t st);
+
+// batch.hip: one box of the batch layout (origin in the super grid, source
+// offset in the caller's packed fields, first row of the box among all rows)
+struct BatchSlot {
+    int32_t nx, ny, nz;
+    int32_t ox, oy, oz;
+    int64_t src_off;
+    int64_t row0;
+};
+struct BatchLayout {
+    int X = 0, Y = 0, Z = 0;
+    int64_t nrows = 0;
+    std::vector<BatchSlot> slots;
+};
+int pack_layers(const int32_t* dims, int n, int X, int Y, int zq, BatchLayout& L, std::string& err);
+void launch_pack(const float* fields, const BatchSlot* d_slots, int nslots, int64_t nrows, const BatchLayout& L,
+                 float* super, uint32_t* owner, hipStream_t st);
+void launch_demux(const dms_pair* pairs, int64_t n, int dim, const GridDev& g, const uint32_t* owner,
+                  const BatchSlot* d_slots, uint64_t* key, int64_t* death, uint32_t* per_item, uint32_t* kept,
+                  hipStream_t st);
+void launch_demux_write(const uint64_t* key, const uint32_t* idx, const int64_t* death, int64_t n, dms_pair* out,
+                        hipStream_t st);
 
 // grad.hip
 void scatter_grad(const int64_t* vertex, const float* grad, int64_t n, int64_t nvert, float* out, uint32_t* k0,

@@ -46,6 +46,21 @@ class DiagramOut(ctypes.Structure):
                 ("birth_value", _p * 3), ("death_value", _p * 3)]
 
 
+class Item(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("offset", ctypes.c_int64)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("cross_x", ctypes.c_int32), ("cross_y", ctypes.c_int32), ("z_quantum", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
+
+
+class BatchOut(ctypes.Structure):
+    _fields_ = [("pairs", _p * 3), ("cap", ctypes.c_int64 * 3), ("n", ctypes.c_int64 * 3),
+                ("item_start", _p * 3)]
+
+
 _lib = None
 
 
@@ -77,6 +92,14 @@ def load_library() -> ctypes.CDLL:
     lib.dms_stage_ms.restype = ctypes.c_int
     lib.dms_scatter_grad.argtypes = [_p, i64, _p, _p, i64, _p]
     lib.dms_scatter_grad.restype = ctypes.c_int
+    lib.dms_diagram_batch.argtypes = [_p, _p, _p, ctypes.c_int32, u32, ctypes.POINTER(BatchOpts),
+                                      ctypes.POINTER(BatchOut)]
+    lib.dms_diagram_batch.restype = ctypes.c_int
+    lib.dms_batch_layout.argtypes = [_p, ctypes.c_int32, ctypes.POINTER(BatchOpts), ctypes.POINTER(ctypes.c_int32 * 3),
+                                     _p]
+    lib.dms_batch_layout.restype = ctypes.c_int
+    lib.dms_batch_info.argtypes = [_p, ctypes.POINTER(ctypes.c_int64 * 8)]
+    lib.dms_batch_info.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -222,10 +245,68 @@ class Context:
             self._raise(rc)
         return out
 
+    def diagram_batch(self, fields, cross=(0, 0), z_quantum: int = 0, use_graph: bool = False,
+                      flags: int = DMS_VIRTUAL_MAX):
+        """Diagrams of several float32 device fields [nz, ny, nx] in one pipeline
+        run. Returns a list with one {0, 1, 2: pairs} per field, as diagram()."""
+        fields = [_check_field(f) for f in fields]
+        n = len(fields)
+        items = (Item * n)()
+        off = 0
+        for i, f in enumerate(fields):
+            nz, ny, nx = f.shape
+            items[i].nx, items[i].ny, items[i].nz, items[i].offset = nx, ny, nz, off
+            off += f.numel()
+        packed = torch.cat([f.reshape(-1) for f in fields]) if n > 1 else fields[0].reshape(-1)
+        opts = BatchOpts(int(cross[0]), int(cross[1]), int(z_quantum), 1 if use_graph else 0)
+        starts = [np.zeros(n + 1, dtype=np.int64) for _ in range(3)]
+        caps = [max(c, off // 8 + 1024) for c in getattr(self, "_bcaps", [0, 0, 0])]
+        for attempt in range(2):
+            out = BatchOut()
+            bufs = []
+            for d in range(3):
+                t = torch.empty((caps[d], 2), dtype=torch.int64, device=self.device)
+                bufs.append(t)
+                out.pairs[d] = t.data_ptr()
+                out.cap[d] = caps[d]
+                out.item_start[d] = starts[d].ctypes.data
+            rc = self.lib.dms_diagram_batch(self.h, _p(packed.data_ptr()), ctypes.cast(items, _p), n, flags,
+                                            ctypes.byref(opts), ctypes.byref(out))
+            if rc == DMS_E_CAPACITY and attempt == 0:
+                caps = [int(out.n[d] * 1.25) + 16 for d in range(3)]
+                self._bcaps = caps
+                continue
+            if rc != DMS_OK:
+                self._raise(rc)
+            return [{d: bufs[d][int(starts[d][i]): int(starts[d][i + 1])] for d in range(3)} for i in range(n)]
+        raise DmsError(DMS_E_CAPACITY, "output capacity")
+
+    def batch_info(self):
+        arr = (ctypes.c_int64 * 8)()
+        self.lib.dms_batch_info(self.h, ctypes.byref(arr))
+        return list(arr)
+
     def stage_ms(self):
         arr = (ctypes.c_float * 8)()
         self.lib.dms_stage_ms(self.h, ctypes.byref(arr))
         return list(arr)
+
+
+def batch_layout(shapes, cross=(0, 0), z_quantum: int = 0):
+    """Host-only layout of a batch: ((X, Y, Z), origins [n, 3]) for grid shapes
+    [(nz, ny, nx), ...]."""
+    lib = load_library()
+    n = len(shapes)
+    items = (Item * n)()
+    for i, (nz, ny, nx) in enumerate(shapes):
+        items[i].nx, items[i].ny, items[i].nz = nx, ny, nz
+    opts = BatchOpts(int(cross[0]), int(cross[1]), int(z_quantum), 0)
+    dims = (ctypes.c_int32 * 3)()
+    origins = np.zeros((n, 3), dtype=np.int32)
+    rc = lib.dms_batch_layout(ctypes.cast(items, _p), n, ctypes.byref(opts), ctypes.byref(dims), origins.ctypes.data)
+    if rc != DMS_OK:
+        raise DmsError(rc, "dms_batch_layout failed")
+    return (dims[0], dims[1], dims[2]), origins
 
 
 def diagram(field: torch.Tensor, ctx: Context | None = None):

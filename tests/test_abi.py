@@ -1,0 +1,66 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, it
+exports every function include/dms.h declares, the binding refuses to run
+without it, and the batch layout (computed on the host) places disjoint
+boxes with a +inf plane between any two.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "dms.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dms_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    from paper_2206_13932_amd import dms
+    names = _declared_functions()
+    assert "dms_diagram" in names and "dms_diagram_batch" in names and "dms_scatter_grad" in names
+    lib = ctypes.CDLL(dms.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch):
+    from paper_2206_13932_amd import dms
+    monkeypatch.setattr(dms, "_lib", None)
+    monkeypatch.setattr(dms, "LIB_PATH", os.path.join(ROOT, "no_such_libdms.so"))
+    with pytest.raises(ImportError):
+        dms.load_library()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_batch_layout_boxes_are_disjoint_with_gaps(seed):
+    from paper_2206_13932_amd import dms
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 120))
+    lo, hi = (2, 40) if seed % 2 else (16, 129)
+    shapes = [tuple(int(x) for x in rng.integers(lo, hi, size=3)) for _ in range(n)]
+    (X, Y, Z), org = dms.batch_layout(shapes)
+    assert X % 16 == 0 and Y % 16 == 0 and Z % 16 == 0
+    occ = np.zeros((Z, Y, X), dtype=np.int32)
+    for i, (nz, ny, nx) in enumerate(shapes):
+        ox, oy, oz = org[i]
+        assert ox >= 0 and oy >= 0 and oz >= 0
+        assert ox + nx <= X and oy + ny <= Y and oz + nz <= Z
+        # the box and the +inf planes that follow it on each axis are its own
+        sub = occ[oz:oz + nz + 1, oy:oy + ny + 1, ox:ox + nx + 1]
+        assert (sub == 0).all(), i
+        sub += 1
+    real = sum(a * b * c for a, b, c in shapes)
+    assert real <= X * Y * Z
+
+
+def test_batch_layout_rejects_items_wider_than_the_cross_section():
+    from paper_2206_13932_amd import dms
+    with pytest.raises(dms.DmsError):
+        dms.batch_layout([(10, 10, 64)], cross=(48, 48))
+    with pytest.raises(dms.DmsError):
+        dms.batch_layout([(1, 10, 10)])
