@@ -66,10 +66,12 @@ struct D1K {
     const uint32_t* cols;
     int64_t ncols;
     // work of this pass: columns 0..ncols-1 (first pass) or deferred records
-    const uint64_t* work;  // (column << 40 | record offset), or null in the first pass
-    const uint32_t* work_len;
+    const uint64_t* work;  // heap offset of each deferred record, or null in the first pass
+    const uint32_t* work_col;  // its column
+    const uint32_t* work_len;  // its length
     int64_t nwork;
-    uint64_t* defer;  // deferred (column << 40 | offset) of this pass
+    uint64_t* defer;  // records deferred by this pass: heap offset, column, length
+    uint32_t* defer_col;
     uint32_t* defer_len;
     int bpr;
     uint32_t* owner1;
@@ -205,11 +207,17 @@ struct Heap {
     }
 };
 
-// Reserve len entries of the publication heap in segment seg; NONE when full.
+// Reserve len entries of the publication heap, in segment seg or, when it is
+// full, in the following ones; NONE when every segment is full.
 __device__ inline uint64_t heap_alloc(const D1K& P, uint32_t seg, uint64_t len) {
-    const uint64_t off = atomicAdd(&P.ctrs[SEG_BASE + SEG_STRIDE * (seg % NSEG)], (unsigned long long)len);
-    if (off + len > P.seg_cap) return NONE;
-    return (uint64_t)(seg % NSEG) * P.seg_cap + off;
+    for (int k = 0; k < NSEG; ++k) {
+        const uint32_t sg = (seg + k) % NSEG;
+        unsigned long long* ctr = &P.ctrs[SEG_BASE + SEG_STRIDE * sg];
+        if (ld_rlx64((const uint64_t*)ctr) + len > P.seg_cap) continue;  // full: skip without growing it
+        const uint64_t off = atomicAdd(ctr, (unsigned long long)len);
+        if (off + len <= P.seg_cap) return (uint64_t)sg * P.seg_cap + off;
+    }
+    return NONE;
 }
 
 // Copy {top (optional)} + heap (compacted) to the publication heap; returns
@@ -230,7 +238,8 @@ __device__ inline uint64_t publish(const D1K& P, Heap& H, bool with_top, uint64_
 
 __device__ inline void defer_column(const D1K& P, uint32_t c, uint64_t off, uint64_t len) {
     const uint64_t d = atomicAdd(&P.ctrs[C_DEFER], 1ull);
-    P.defer[d] = ((uint64_t)c << 40) | off;
+    P.defer[d] = off;
+    P.defer_col[d] = c;
     P.defer_len[d] = (uint32_t)len;
 }
 
@@ -269,9 +278,8 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
             H.push(ekey_r(P.bpr, r0, r2));
         } else {
             // resume a deferred column from its saved, decreasing boundary
-            const uint64_t w = P.work[next];
-            c = (uint32_t)(w >> 40);
-            const uint64_t off = w & ((1ull << 40) - 1);
+            c = P.work_col[next];
+            const uint64_t off = P.work[next];
             const int64_t len = P.work_len[next];
             if (len > H.K) {
                 atomicOr(P.flags, FLAG_WORK);
@@ -1005,8 +1013,7 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
         const uint64_t next = L.u64s[0];
         __syncthreads();
         if ((int64_t)next >= P.nwork) break;
-        const uint64_t w = P.work[next];
-        uint32_t c = (uint32_t)(w >> 40);
+        uint32_t c = P.work_col[next];
         const uint64_t t0 = __builtin_amdgcn_s_memrealtime();  // 100 MHz clock
         // time per phase (thread 0): window, sort, round merge, owner rule, additions, claims
         uint64_t ph[N_PHASE] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -1021,7 +1028,7 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
         Col C;
         C.cur = 0;
         {
-            const uint64_t off = w & ((1ull << 40) - 1);
+            const uint64_t off = P.work[next];
             const uint32_t n0 = P.work_len[next];
             if ((int64_t)n0 > P.K) {
                 if (t == 0) atomicOr(P.flags, FLAG_WORK);
@@ -1470,7 +1477,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
     s.ncols = ncols;
     if (grow(s.bndptr, s.bndptr_cap, 8 * (ncols + 1), s.bytes)) return oom("boundary pointers");
     // two deferral queues (this pass / next pass): u64 (column, offset) + u32 length
-    if (grow(s.dq, s.dq_cap, 2 * (size_t)(ncols + 1) * 12, s.bytes)) return oom("deferral queues");
+    if (grow(s.dq, s.dq_cap, 2 * (size_t)(ncols + 1) * 16, s.bytes)) return oom("deferral queues");
     if (s.heap_cap < (size_t)8 * 32 * ncols) {
         if (grow(s.heap, s.heap_cap, std::max<size_t>((size_t)8 << 22, (size_t)8 * 32 * ncols), s.bytes))
             return oom("boundary heap");
@@ -1490,6 +1497,8 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
                                (uint32_t*)s.owner1);
         uint64_t* q[2] = {(uint64_t*)s.dq, (uint64_t*)s.dq + (ncols + 1)};
         uint32_t* qlen = (uint32_t*)((uint64_t*)s.dq + 2 * (ncols + 1));
+        uint32_t* qcol = qlen + 2 * (ncols + 1);
+        uint32_t* qc[2] = {qcol, qcol + (ncols + 1)};
         uint32_t* ql[2] = {qlen, qlen + (ncols + 1)};
         int64_t nwork = ncols;
         int cur = 0;
@@ -1497,8 +1506,8 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         unsigned long long hc[N_CTRS] = {0};
         // pass plan: thread-per-column with small heaps, then one workgroup per
         // column with boundaries of up to plan_k entries
-        int64_t plan_k[MAX_PASSES] = {k0, (int64_t)1 << 15, (int64_t)1 << 20, (int64_t)1 << 24, 0};
-        int64_t plan_t[MAX_PASSES] = {lanes, 1024, 32, 2, 0};
+        int64_t plan_k[MAX_PASSES] = {k0, (int64_t)1 << 15, (int64_t)1 << 20, ((int64_t)1 << 24) - 1024, 0};  // lengths stay below 2^24 (24-bit length field)
+        int64_t plan_t[MAX_PASSES] = {lanes, 1024, 256, 2, 0};
         if (std::getenv("DMS_D1_TEST_PLAN")) {  // test hook: tiny capacities, every pass used
             plan_k[0] = 4;
             plan_k[1] = 24;
@@ -1519,9 +1528,11 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             P.ncols = ncols;
             P.work = pass == 0 ? nullptr : q[cur];
             P.work_len = pass == 0 ? nullptr : ql[cur];
+            P.work_col = pass == 0 ? nullptr : qc[cur];
             P.nwork = nwork;
             P.defer = q[cur ^ 1];
             P.defer_len = ql[cur ^ 1];
+            P.defer_col = qc[cur ^ 1];
             P.bpr = in.bpr;
             P.owner1 = (uint32_t*)s.owner1;
             P.bndptr = (uint64_t*)s.bndptr;

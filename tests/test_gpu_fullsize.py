@@ -74,10 +74,6 @@ def test_fullsize_gradient_samples_and_invariants(name):
     del G
     c = ncrit
     assert c[0] - c[1] + c[2] - c[3] == 1
-    if name == "c_noise512":
-        # D1 on 512^3 i.i.d. noise is not yet fast enough for a test run
-        ctx.close()
-        return
     # the whole diagram, as bench.py runs it
     print("[fullsize] samples equal; whole diagram", flush=True)
     out = ctx.diagram(field)
