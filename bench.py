@@ -29,9 +29,13 @@ WORKLOADS = {
 }
 METRIC = "Mvertices/s full D0+D1+D2 (512^3 f32), % HBM peak; served req/s + p99"
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the gradient kernel on smooth512, from FETCH_SIZE and WRITE_SIZE
-# (profiles/gradient_hbm_counters_smooth512.md), valid for the kernel sources with this hash only
-GRADIENT_TRAFFIC = {"sources_sha256_16": "6c4699554efca1ec", "workload": "smooth512", "bytes": 2071644205 + 9124781728}
+# Counters of one gradient-kernel launch on smooth512 (profiles/gradient_hbm_counters_smooth512.md),
+# valid for the kernel sources with this hash only: HBM bytes from FETCH_SIZE (x2 calibration) and
+# WRITE_SIZE, and the VALU wave instructions issued
+GRADIENT_COUNTERS = {"sources_sha256_16": "368182d3a37f9ab9", "workload": "smooth512",
+                     "traffic_bytes": 3302462668 + 9926303027, "valu_wave_insts": 79363277579}
+# VALU issue ceiling: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per 2 cycles per SIMD
+VALU_PEAK_WINST_S = 256 * 4 * 2.4e9 / 2
 
 
 def gradient_sources_hash():
@@ -229,10 +233,13 @@ def main():
         print(f"[bench] D1 cached boundary length p50/p90/p99/p99.9/max: {q}; columns > 1000: "
               f"{int((lens > 1000).sum())}, > 10000: {int((lens > 10000).sum())}", file=sys.stderr, flush=True)
 
-    traffic = None
-    if (GRADIENT_TRAFFIC["workload"] == args.workload
-            and GRADIENT_TRAFFIC["sources_sha256_16"] == gradient_sources_hash()):
-        traffic = GRADIENT_TRAFFIC["bytes"]
+    traffic, valu = None, None
+    if (GRADIENT_COUNTERS["workload"] == args.workload
+            and GRADIENT_COUNTERS["sources_sha256_16"] == gradient_sources_hash()):
+        traffic = GRADIENT_COUNTERS["traffic_bytes"]
+        rate = GRADIENT_COUNTERS["valu_wave_insts"] / (g_avg_ms / 1e3)
+        valu = {"achieved": round(rate / 1e9, 1), "peak": VALU_PEAK_WINST_S / 1e9, "unit": "G wave-instr/s",
+                "frac": round(rate / VALU_PEAK_WINST_S, 4)}
     line = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -254,7 +261,7 @@ def main():
         "roofline": {"kernel": "k_gradient", "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes": int(gbytes),
-                     "avg_kernel_ms": round(g_avg_ms, 4)},
+                     "avg_kernel_ms": round(g_avg_ms, 4), "valu_issue": valu},
     }
     ctx.close()
     del field, out
