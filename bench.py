@@ -147,7 +147,7 @@ def main():
     ap.add_argument("--cpu-crop", type=int, default=80)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=4096, help="0 skips the serving run")
-    ap.add_argument("--serve-rate", type=float, default=1000.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-rate", type=float, default=800.0, help="Poisson arrivals per second")
     ap.add_argument("--serve-plain-sample", type=int, default=512)
     ap.add_argument("--serve-calib", type=int, default=256)
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation run")

@@ -11,13 +11,14 @@ from . import serving
 
 DEFAULT_SPACE = {
     "cross": [(0, 0), (256, 256)],
-    "budget_vertices": [1 << 23, 1 << 25],
+    "budget_vertices": [1 << 23, 1 << 25, 1 << 26],
     "z_quantum": [16],
-    "use_graph": [True, False],
+    # graph replay with one worker, or two overlapping workers without it
+    "workers_graph": [(1, True), (2, False), (3, False)],
 }
 
 
-def autotune(requests, space=None, workers: int = 2, device: int = 0, repeats: int = 1):
+def autotune(requests, space=None, device: int = 0, repeats: int = 1):
     """requests: serving.Request list (their arrival times are ignored).
     Returns (best ServerConfig, [(config dict, requests/s)])."""
     space = space or DEFAULT_SPACE
@@ -25,7 +26,9 @@ def autotune(requests, space=None, workers: int = 2, device: int = 0, repeats: i
     table = []
     best = None
     for values in itertools.product(*(space[k] for k in keys)):
-        cfg = serving.ServerConfig(workers=workers, **dict(zip(keys, values)))
+        kw = dict(zip(keys, values))
+        workers, use_graph = kw.pop("workers_graph")
+        cfg = serving.ServerConfig(workers=workers, use_graph=use_graph, **kw)
         server = serving.Server(cfg, device)
         try:
             rate = 0.0

@@ -1489,8 +1489,10 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
                            (uint32_t*)s.owner1);
     if (ncols == 0) return 0;
     for (int restart = 0; restart < 4; ++restart) {
-        if (hipMemsetAsync(s.ctrs, 0, ctr_bytes, st) != hipSuccess) return -5;
-        if (hipMemsetAsync(in.flags, 0, 4, st) != hipSuccess) return -5;
+        if (hipMemsetAsync(s.ctrs, 0, ctr_bytes, st) != hipSuccess || hipMemsetAsync(in.flags, 0, 4, st) != hipSuccess) {
+            err = "D1: counter reset failed";
+            return -5;
+        }
         fill_u64((uint64_t*)s.bndptr, EMPTY64, ncols, st);
         if (restart > 0 && in.m1 > 0)
             hipLaunchKernelGGL(k_init_owner, dim3(nblocks(in.m1)), dim3(DB), 0, st, in.c1, in.paired1, in.m1,
@@ -1546,8 +1548,10 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             P.ctrs = (unsigned long long*)s.ctrs;
             P.flags = in.flags;
             // fresh work cursor, deferral count and work counters for this pass
-            if (hipMemsetAsync((unsigned long long*)s.ctrs + C_NEXT, 0, 8 * (N_CTRS - C_NEXT), st) != hipSuccess)
+            if (hipMemsetAsync((unsigned long long*)s.ctrs + C_NEXT, 0, 8 * (N_CTRS - C_NEXT), st) != hipSuccess) {
+                err = "D1: counter reset failed";
                 return -5;
+            }
             if (pass == 0)
                 hipLaunchKernelGGL(k_d1, dim3(nblocks(T)), dim3(DB), 0, st, P);
             else
@@ -1597,9 +1601,12 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         }
         {
             uint64_t used = 0, segs[SEG_STRIDE * NSEG];
-            if (hipMemcpy(segs, (unsigned long long*)s.ctrs + SEG_BASE, sizeof(segs), hipMemcpyDeviceToHost) !=
-                hipSuccess)
+            if (hipMemcpyAsync(segs, (unsigned long long*)s.ctrs + SEG_BASE, sizeof(segs), hipMemcpyDeviceToHost,
+                               st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                err = "D1: heap counter read-back failed";
                 return -5;
+            }
             for (int q = 0; q < NSEG; ++q) used += segs[SEG_STRIDE * q];
             hc[C_HEAP] = used;
         }

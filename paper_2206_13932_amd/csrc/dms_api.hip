@@ -695,7 +695,8 @@ int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap) {
             uint64_t* h = (uint64_t*)dst;
             std::memset(h, 0, bytes);
             HIPCHK(hipStreamSynchronize(ctx->st));
-            HIPCHK(hipMemcpy(h, ctx->stats.p, 32, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpyAsync(h, ctx->stats.p, 32, hipMemcpyDeviceToHost, ctx->st));
+            HIPCHK(hipStreamSynchronize(ctx->st));
             for (int i = 0; i < 6; ++i) h[4 + i] = ctx->d1.stats[i];
             for (int i = 0; i < 5; ++i) {
                 h[10 + 2 * i] = ctx->d1.pass_work[i];
@@ -712,7 +713,8 @@ int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap) {
             if (!dst) return bytes;
             if (cap < bytes) return fail(ctx, DMS_E_CAPACITY, "destination too small");
             HIPCHK(hipStreamSynchronize(ctx->st));
-            if (bytes) HIPCHK(hipMemcpy(dst, ctx->d1.bndptr, bytes, hipMemcpyDeviceToHost));
+            if (bytes) HIPCHK(hipMemcpyAsync(dst, ctx->d1.bndptr, bytes, hipMemcpyDeviceToHost, ctx->st));
+            HIPCHK(hipStreamSynchronize(ctx->st));
             return bytes;
         }
         default: return fail(ctx, DMS_E_INVAL, "unknown buffer");
@@ -729,12 +731,14 @@ int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap) {
         Buf& a = what == DMS_BUF_ARCS0 ? ctx->na0 : ctx->na2;
         Buf& b = what == DMS_BUF_ARCS0 ? ctx->nb0 : ctx->nb2;
         if (m) {
-            HIPCHK(hipMemcpy(h, a.p, 4 * m, hipMemcpyDeviceToHost));
-            HIPCHK(hipMemcpy(h + m, b.p, 4 * m, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpyAsync(h, a.p, 4 * m, hipMemcpyDeviceToHost, ctx->st));
+            HIPCHK(hipMemcpyAsync(h + m, b.p, 4 * m, hipMemcpyDeviceToHost, ctx->st));
+            HIPCHK(hipStreamSynchronize(ctx->st));
         }
         return bytes;
     }
-    if (bytes) HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+    if (bytes) HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
     return bytes;
 }
 

@@ -45,7 +45,7 @@ class ServerConfig:
     max_items: int = 512
     cross: tuple = (0, 0)
     z_quantum: int = 16
-    use_graph: bool = True
+    use_graph: bool = False
 
 
 @dataclass
@@ -65,6 +65,10 @@ class TraceStats:
 class Server:
     def __init__(self, cfg: ServerConfig | None = None, device: int = 0):
         self.cfg = cfg or ServerConfig()
+        if self.cfg.use_graph and self.cfg.workers > 1:
+            # a stream capture fails if another thread allocates or synchronises on
+            # the device meanwhile, so graph replay is for a single worker
+            raise ValueError("use_graph needs workers == 1")
         self.device = device
         self.streams = [torch.cuda.Stream(device=device) for _ in range(self.cfg.workers)]
         self.ctxs = [dms.Context(device, stream=s) for s in self.streams]

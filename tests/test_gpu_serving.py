@@ -9,14 +9,14 @@ import synthfields as sf
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("use_graph", [False, True])
-def test_served_results_equal_alone(use_graph):
+@pytest.mark.parametrize("workers,use_graph", [(2, False), (1, True)])
+def test_served_results_equal_alone(workers, use_graph):
     import torch
     from paper_2206_13932_amd import dms, serving
     specs = sf.serving_requests(96, seed=7, side_range=(6, 40), rate=3000.0)
     fields = [sf.gaussians(shape, seed, 4, 0.01) for _, shape, seed in specs]
     reqs = serving.make_requests(specs, fields)
-    cfg = serving.ServerConfig(workers=2, budget_vertices=1 << 18, use_graph=use_graph)
+    cfg = serving.ServerConfig(workers=workers, budget_vertices=1 << 18, use_graph=use_graph)
     server = serving.Server(cfg)
     stats = server.run_trace(reqs)
     server.close()
@@ -24,7 +24,7 @@ def test_served_results_equal_alone(use_graph):
           f"p50 {stats.pct(50):.2f} ms, p99 {stats.pct(99):.2f} ms", flush=True)
     assert len(stats.batches) >= 3
     assert max(b[1] for b in stats.batches) > 1
-    assert {b[0] for b in stats.batches} == {0, 1}
+    assert {b[0] for b in stats.batches} == set(range(workers))
     assert np.isfinite(stats.latencies_ms).all() and (stats.latencies_ms > 0).all()
     ctx = dms.Context(0)
     for r in reqs:
