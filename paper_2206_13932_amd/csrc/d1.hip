@@ -12,8 +12,8 @@
 //   tau critical, free or owned by a later one   -> cache the boundary and
 //       claim tau with compare-and-swap; a later owner is evicted and its
 //       reduction is carried on by this thread (Sec. 7.2).
-// The working boundary is a max-heap in per-thread scratch (interleaved
-// across threads), with mod-2 cancellation of equal keys when they meet at
+// The working boundary is a max-heap in per-thread scratch (contiguous per
+// thread), with mod-2 cancellation of equal keys when they meet at
 // the top. Cached boundaries are immutable arrays (sorted decreasing) bump-
 // allocated from a publication heap and accessed with coherent (agent-scope)
 // loads and stores, so a reader that finds tau at their head has a complete
@@ -252,8 +252,9 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
         H.base = lds_heaps + (int64_t)threadIdx.x * P.K;
         H.stride = 1;
     } else {
-        H.base = P.scratch + tid;
-        H.stride = P.nthreads;
+        // each lane's heap contiguous: its sift paths stay in its own cache lines
+        H.base = P.scratch + tid * P.K;
+        H.stride = 1;
     }
     H.K = P.K;
     const int64_t V = P.g.V;

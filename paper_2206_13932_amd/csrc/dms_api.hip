@@ -39,6 +39,7 @@ struct dms_ctx {
     Buf rank, keysA, keysB, valsA, valsB, G, hist, part, flags, counters, stats;
     Buf cid[4], ck[4], ck2[4];  // unsorted critical ids and keys (hi / lo)
     Buf csorted[4];             // ids sorted by the lexicographic order
+    Buf cpos[4];                // cpos[d][i] = sorted position of cid[d][i] (d = 1, 2)
     uint32_t* order = nullptr;  // rank -> vertex (inside valsA / valsB)
     // D0 / D2
     Buf na0, nb0, owner0, bnd0, paired1, na2, nb2, owner2, bnd2, paired2, tet2pos;
@@ -249,6 +250,10 @@ static int sort_ids(dms_ctx* ctx, int d) {
         perm = r2 ? p1_other : p1;
     }
     gather_u32(P<uint32_t>(ctx->cid[d]), perm, P<uint32_t>(ctx->csorted[d]), m, st);
+    if (d == 1 || d == 2) {
+        ENSURE(ctx->cpos[d], 4 * m);
+        inverse_perm(perm, m, P<uint32_t>(ctx->cpos[d]), st);
+    }
     return DMS_OK;
 }
 
@@ -335,6 +340,7 @@ void dms_destroy(dms_ctx* ctx) {
         if (ctx->ck[d].p) (void)hipFree(ctx->ck[d].p);
         if (ctx->ck2[d].p) (void)hipFree(ctx->ck2[d].p);
         if (ctx->csorted[d].p) (void)hipFree(ctx->csorted[d].p);
+        if (ctx->cpos[d].p) (void)hipFree(ctx->cpos[d].p);
     }
     d1_free(ctx->d1);
     for (int i = 0; i < NEV; ++i)
@@ -486,8 +492,8 @@ static int run_d0_d2(dms_ctx* ctx) {
     ENSURE(ctx->owner0, 4 * V);
     ENSURE(ctx->bnd0, 8 * m1);
     ENSURE(ctx->paired1, m1);
-    trace_d0(ctx->g, P<uint8_t>(ctx->G), P<uint32_t>(ctx->rank), P<uint32_t>(ctx->csorted[1]), m1,
-             P<uint32_t>(ctx->na0), P<uint32_t>(ctx->nb0), P<uint32_t>(ctx->flags), st);
+    trace_d0(ctx->g, P<uint8_t>(ctx->G), P<uint32_t>(ctx->rank), P<uint32_t>(ctx->cid[1]), P<uint32_t>(ctx->cpos[1]),
+             m1, P<uint32_t>(ctx->na0), P<uint32_t>(ctx->nb0), P<uint32_t>(ctx->flags), st);
     fill_u32(P<uint32_t>(ctx->owner0), EMPTY32, V, st);
     fill_u64(P<uint64_t>(ctx->bnd0), EMPTY64, m1, st);
     reduce_pairs(P<uint32_t>(ctx->na0), P<uint32_t>(ctx->nb0), m1, P<uint32_t>(ctx->owner0), P<uint64_t>(ctx->bnd0),
@@ -501,8 +507,8 @@ static int run_d0_d2(dms_ctx* ctx) {
     ENSURE(ctx->bnd2, 8 * m2);
     ENSURE(ctx->paired2, m2);
     tet_positions(P<uint32_t>(ctx->csorted[3]), m3, P<uint32_t>(ctx->tet2pos), st);
-    trace_d2(ctx->g, P<uint8_t>(ctx->G), P<uint32_t>(ctx->tet2pos), P<uint32_t>(ctx->csorted[2]), m2,
-             P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2), P<uint32_t>(ctx->flags), st);
+    trace_d2(ctx->g, P<uint8_t>(ctx->G), P<uint32_t>(ctx->tet2pos), P<uint32_t>(ctx->cid[2]), P<uint32_t>(ctx->cpos[2]),
+             m2, P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2), P<uint32_t>(ctx->flags), st);
     fill_u32(P<uint32_t>(ctx->owner2), EMPTY32, m3 + 1, st);
     fill_u64(P<uint64_t>(ctx->bnd2), EMPTY64, m2, st);
     reduce_pairs(P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2), m2, P<uint32_t>(ctx->owner2), P<uint64_t>(ctx->bnd2),

@@ -57,13 +57,16 @@ void float_keys(const float* f, int64_t n, uint32_t* keys, uint32_t* flags, hipS
 void rank_scatter(const uint32_t* order, int64_t n, uint32_t* rank, hipStream_t st);
 void gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst, int64_t n, hipStream_t st);
 void gather_u64(const uint64_t* src, const uint32_t* idx, uint64_t* dst, int64_t n, hipStream_t st);
+void inverse_perm(const uint32_t* perm, int64_t n, uint32_t* inv, hipStream_t st);  // inv[perm[j]] = j
 
 // pairs.hip -- D0 / D2
-void trace_d0(const GridDev& g, const uint8_t* G, const uint32_t* rank, const uint32_t* c1, int64_t m,
-              uint32_t* na, uint32_t* nb, uint32_t* flags, hipStream_t st);
+// trace_*: c = the critical cells in the gradient kernel's order, pos[i] = the
+// position of c[i] in the sorted order (the arcs are written there)
+void trace_d0(const GridDev& g, const uint8_t* G, const uint32_t* rank, const uint32_t* c1, const uint32_t* pos,
+              int64_t m, uint32_t* na, uint32_t* nb, uint32_t* flags, hipStream_t st);
 void tet_positions(const uint32_t* c3_sorted, int64_t m, uint32_t* tet2pos, hipStream_t st);
-void trace_d2(const GridDev& g, const uint8_t* G, const uint32_t* tet2pos, const uint32_t* c2_sorted, int64_t m,
-              uint32_t* na, uint32_t* nb, uint32_t* flags, hipStream_t st);
+void trace_d2(const GridDev& g, const uint8_t* G, const uint32_t* tet2pos, const uint32_t* c2, const uint32_t* pos,
+              int64_t m, uint32_t* na, uint32_t* nb, uint32_t* flags, hipStream_t st);
 void reduce_pairs(const uint32_t* na, const uint32_t* nb, int64_t m, uint32_t* owner, uint64_t* bnd,
                   uint32_t* flags, unsigned long long* stats, hipStream_t st);
 void settled_columns(const uint64_t* bnd, const uint32_t* owner, int64_t m, uint8_t* paired, hipStream_t st);

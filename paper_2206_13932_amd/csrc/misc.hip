@@ -33,6 +33,11 @@ __global__ void k_float_keys(const float* __restrict__ f, int64_t n, uint32_t* _
     keys[i] = float_key(v);
 }
 
+__global__ void k_inverse(const uint32_t* __restrict__ perm, int64_t n, uint32_t* __restrict__ inv) {
+    const int64_t i = (int64_t)blockIdx.x * MB + threadIdx.x;
+    if (i < n) inv[perm[i]] = (uint32_t)i;
+}
+
 __global__ void k_rank_scatter(const uint32_t* __restrict__ order, int64_t n, uint32_t* __restrict__ rank) {
     const int64_t i = (int64_t)blockIdx.x * MB + threadIdx.x;
     if (i < n) rank[order[i]] = (uint32_t)i;
@@ -58,6 +63,9 @@ void fill_u64(uint64_t* out, uint64_t v, int64_t n, hipStream_t st) {
 }
 void float_keys(const float* f, int64_t n, uint32_t* keys, uint32_t* flags, hipStream_t st) {
     if (n > 0) hipLaunchKernelGGL(k_float_keys, dim3(nblocks(n)), dim3(MB), 0, st, f, n, keys, flags);
+}
+void inverse_perm(const uint32_t* perm, int64_t n, uint32_t* inv, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_inverse, dim3(nblocks(n)), dim3(MB), 0, st, perm, n, inv);
 }
 void rank_scatter(const uint32_t* order, int64_t n, uint32_t* rank, hipStream_t st) {
     if (n > 0) hipLaunchKernelGGL(k_rank_scatter, dim3(nblocks(n)), dim3(MB), 0, st, order, n, rank);

@@ -38,12 +38,16 @@ __device__ inline int64_t descend(const GridDev& g, const uint8_t* __restrict__ 
     return v;
 }
 
+// Critical cells are traced in the order the gradient kernel listed them
+// (neighbouring vertices in neighbouring lanes, so the v-paths of a wave share
+// cache lines); each arc goes to the cell's position in the sorted order.
 __global__ void k_trace_d0(GridDev g, const uint8_t* __restrict__ G, const uint32_t* __restrict__ rank,
-                           const uint32_t* __restrict__ c1, int64_t m, uint32_t* __restrict__ na,
-                           uint32_t* __restrict__ nb, uint32_t* flags) {
-    const int64_t j = (int64_t)blockIdx.x * PB + threadIdx.x;
-    if (j >= m) return;
-    const uint32_t e = c1[j];
+                           const uint32_t* __restrict__ c1, const uint32_t* __restrict__ pos, int64_t m,
+                           uint32_t* __restrict__ na, uint32_t* __restrict__ nb, uint32_t* flags) {
+    const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
+    if (i >= m) return;
+    const uint32_t e = c1[i];
+    const uint32_t j = pos[i];
     const int64_t a = e / 7;
     const int64_t b = a + lin_of_mask(g, e % 7 + 1);
     const int64_t ma = descend(g, G, a, flags), mb = descend(g, G, b, flags);
@@ -126,11 +130,12 @@ __device__ inline uint32_t ascend(const GridDev& g, const uint8_t* __restrict__ 
 }
 
 __global__ void k_trace_d2(GridDev g, const uint8_t* __restrict__ G, const uint32_t* __restrict__ tet2pos,
-                           const uint32_t* __restrict__ c2, int64_t m, uint32_t* __restrict__ na,
-                           uint32_t* __restrict__ nb, uint32_t* flags) {
-    const int64_t j = (int64_t)blockIdx.x * PB + threadIdx.x;
-    if (j >= m) return;
-    const uint32_t t = c2[m - 1 - j];  // decreasing order
+                           const uint32_t* __restrict__ c2, const uint32_t* __restrict__ pos, int64_t m,
+                           uint32_t* __restrict__ na, uint32_t* __restrict__ nb, uint32_t* flags) {
+    const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
+    if (i >= m) return;
+    const uint32_t t = c2[i];
+    const int64_t j = m - 1 - (int64_t)pos[i];  // arcs in decreasing order
     const int64_t anchor = t / 12;
     const int type = t % 12;
     Simp cf[2];
@@ -229,18 +234,18 @@ __global__ void k_settled(const uint64_t* __restrict__ bnd, const uint32_t* __re
 
 }  // namespace
 
-void trace_d0(const GridDev& g, const uint8_t* G, const uint32_t* rank, const uint32_t* c1, int64_t m,
-              uint32_t* na, uint32_t* nb, uint32_t* flags, hipStream_t st) {
-    if (m > 0) hipLaunchKernelGGL(k_trace_d0, dim3(nblocks(m)), dim3(PB), 0, st, g, G, rank, c1, m, na, nb, flags);
+void trace_d0(const GridDev& g, const uint8_t* G, const uint32_t* rank, const uint32_t* c1, const uint32_t* pos,
+              int64_t m, uint32_t* na, uint32_t* nb, uint32_t* flags, hipStream_t st) {
+    if (m > 0)
+        hipLaunchKernelGGL(k_trace_d0, dim3(nblocks(m)), dim3(PB), 0, st, g, G, rank, c1, pos, m, na, nb, flags);
 }
 void tet_positions(const uint32_t* c3_sorted, int64_t m, uint32_t* tet2pos, hipStream_t st) {
     if (m > 0) hipLaunchKernelGGL(k_tet_positions, dim3(nblocks(m)), dim3(PB), 0, st, c3_sorted, m, tet2pos);
 }
-void trace_d2(const GridDev& g, const uint8_t* G, const uint32_t* tet2pos, const uint32_t* c2_sorted, int64_t m,
-              uint32_t* na, uint32_t* nb, uint32_t* flags, hipStream_t st) {
+void trace_d2(const GridDev& g, const uint8_t* G, const uint32_t* tet2pos, const uint32_t* c2, const uint32_t* pos,
+              int64_t m, uint32_t* na, uint32_t* nb, uint32_t* flags, hipStream_t st) {
     if (m > 0)
-        hipLaunchKernelGGL(k_trace_d2, dim3(nblocks(m)), dim3(PB), 0, st, g, G, tet2pos, c2_sorted, m, na, nb,
-                           flags);
+        hipLaunchKernelGGL(k_trace_d2, dim3(nblocks(m)), dim3(PB), 0, st, g, G, tet2pos, c2, pos, m, na, nb, flags);
 }
 void reduce_pairs(const uint32_t* na, const uint32_t* nb, int64_t m, uint32_t* owner, uint64_t* bnd,
                   uint32_t* flags, unsigned long long* stats, hipStream_t st) {
