@@ -44,6 +44,8 @@ constexpr int DB = 256;
 constexpr uint32_t OWN_D0 = 0xFFFFFFFEu;
 constexpr uint64_t NONE = ~0ull;
 constexpr int MAX_PASSES = 5;
+constexpr int LDS_K = 16;   // keys per thread in the first pass (LDS heaps)
+constexpr int LDS_K2 = 64;  // ... and in the second
 constexpr uint32_t MAX_RETRIES = 1u << 16;  // consecutive look-agains before a column is declared corrupt
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + DB - 1) / DB); }
 
@@ -243,167 +245,198 @@ __device__ inline void defer_column(const D1K& P, uint32_t c, uint64_t off, uint
     P.defer_len[d] = (uint32_t)len;
 }
 
+// One lane per column; each iteration of the loop is one reduction step of
+// the lane's column, and a lane whose column is done takes the next one at
+// once (one atomic per wavefront for all lanes that need work), so the lanes
+// of a wavefront do not wait for each other's columns.
 __global__ __launch_bounds__(DB) void k_d1(D1K P) {
     extern __shared__ uint64_t lds_heaps[];
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= P.nthreads) return;  // scratch exists for nthreads lanes only
+    const int lane = threadIdx.x & 63;
+    // scratch exists for nthreads lanes only; the others take no work
+    const bool real = tid < P.nthreads;
     Heap H;
     if (P.lds) {
         H.base = lds_heaps + (int64_t)threadIdx.x * P.K;
         H.stride = 1;
     } else {
         // each lane's heap contiguous: its sift paths stay in its own cache lines
-        H.base = P.scratch + tid * P.K;
+        H.base = P.scratch + (real ? tid : 0) * P.K;
         H.stride = 1;
     }
     H.K = P.K;
+    H.n = 0;
     const int64_t V = P.g.V;
     unsigned long long steps = 0, evictions = 0, adds = 0;
-    for (;;) {
-        // columns are taken in increasing order: the frontier of columns in flight
-        // stays narrow, which keeps evictions rare
-        const int64_t next = (int64_t)atomicAdd(&P.ctrs[C_NEXT], 1ull);
-        if (next >= P.nwork) break;
-        uint32_t c;
-        H.n = 0;
-        if (!P.work) {
-            c = (uint32_t)next;
-            const uint32_t t = P.cols[c];
-            const int64_t a = t / 12;
-            const int ty = t % 12;
-            const int64_t v1 = a + lin_of_mask(P.g, tri_step(ty, 0));
-            const int64_t v2 = v1 + lin_of_mask(P.g, tri_step(ty, 1));
-            const uint32_t r0 = P.rank[a], r1 = P.rank[v1], r2 = P.rank[v2];
-            H.push(ekey_r(P.bpr, r0, r1));
-            H.push(ekey_r(P.bpr, r1, r2));
-            H.push(ekey_r(P.bpr, r0, r2));
-        } else {
-            // resume a deferred column from its saved, decreasing boundary
-            c = P.work_col[next];
-            const uint64_t off = P.work[next];
-            const int64_t len = P.work_len[next];
-            if (len > H.K) {
-                atomicOr(P.flags, FLAG_WORK);
-                break;
-            }
-            for (int64_t i = 0; i < len; ++i) H.at(i) = ld_rlx64(P.heap + off + i);
-            H.n = len;
+    bool active = false, exhausted = !real, stop = false;
+    uint32_t c = 0;
+    bool have = false;
+    uint64_t tau = 0;
+    int64_t guard = 0;
+    uint32_t retries = 0;
+
+    // one step of column c: 0 = go on, 1 = the column is done, 2 = error
+    auto step = [&]() -> int {
+        if (++guard > ((int64_t)1 << 24) || retries > MAX_RETRIES) {
+            atomicOr(P.flags, FLAG_GUARD);
+            return 2;
         }
-        bool have = false;
-        uint64_t tau = 0;
-        bool stop = false;  // leave the thread (error)
-        uint32_t retries = 0;
-        for (int64_t guard = 0;; ++guard) {
-            if (guard > ((int64_t)1 << 24) || retries > MAX_RETRIES) {
+        ++steps;
+        if (!have) {
+            tau = H.extract_max();
+            if (tau == NONE) return 1;  // zero column
+            have = true;
+        }
+        const EdgeDec e = edecode(P.g, P.order, P.bpr, tau);
+        if (e.mask == 0) {  // not an edge: corrupted key
+            atomicOr(P.flags, FLAG_GUARD);
+            return 2;
+        }
+        const uint8_t code = P.G[(int64_t)e.mask * V + e.lo];
+        bool defer = false;
+        if (code != CODE_CRIT) {
+            if (code >= 27) {  // the top of a cycle cannot be a vertex's partner
                 atomicOr(P.flags, FLAG_GUARD);
-                stop = true;
-                break;
+                return 2;
             }
-            ++steps;
-            if (!have) {
-                tau = H.extract_max();
-                if (tau == NONE) break;  // zero column
-                have = true;
+            const int64_t w = e.lo + lin27(P.g, code);
+            if (H.room(2)) {
+                have = false;  // tau cancels against the boundary of its partner
+                const uint32_t rw = P.rank[w];
+                H.push(ekey_r(P.bpr, e.ra, rw));
+                H.push(ekey_r(P.bpr, e.rb, rw));
+                return 0;
             }
-            const EdgeDec e = edecode(P.g, P.order, P.bpr, tau);
-            if (e.mask == 0) {  // not an edge: corrupted key
+            defer = true;
+        } else {
+            const uint32_t o = ld_rlx(&P.owner1[e.id]);
+            if (o == OWN_D0) {
                 atomicOr(P.flags, FLAG_GUARD);
-                stop = true;
-                break;
+                return 2;
             }
-            const uint8_t code = P.G[(int64_t)e.mask * V + e.lo];
-            bool defer = false;
-            if (code != CODE_CRIT) {
-                if (code >= 27) {  // the top of a cycle cannot be a vertex's partner
-                    atomicOr(P.flags, FLAG_GUARD);
-                    stop = true;
-                    break;
-                }
-                const int64_t w = e.lo + lin27(P.g, code);
-                if (H.room(2)) {
-                    have = false;  // tau cancels against the boundary of its partner
-                    const uint32_t rw = P.rank[w];
-                    H.push(ekey_r(P.bpr, e.ra, rw));
-                    H.push(ekey_r(P.bpr, e.rb, rw));
-                    continue;
-                }
-                defer = true;
-            } else {
-                const uint32_t o = ld_rlx(&P.owner1[e.id]);
-                if (o == OWN_D0) {
-                    atomicOr(P.flags, FLAG_GUARD);
-                    stop = true;
-                    break;
-                }
-                if (o == EMPTY32 || o > c) {
-                    // cache Boundary(c) = {tau} + heap, then claim tau
-                    const uint64_t b = publish(P, H, true, tau);
-                    if (b == NONE) {
-                        atomicOr(P.flags, FLAG_HEAP);
-                        stop = true;
-                        break;
-                    }
-                    st_rlx64(&P.bndptr[c], b);
-                    wait_stores();
-                    if (!cas32(&P.owner1[e.id], o, c)) {  // owner changed: look again
-                        ++retries;
-                        continue;
-                    }
-                    if (o == EMPTY32) break;                       // column settled
-                    // evicted o: carry on reducing it from its cached boundary
-                    ++evictions;
-                    const uint64_t bo = ld_rlx64(&P.bndptr[o]);
-                    const uint64_t* B = P.heap + (bo >> 24);
-                    const int64_t bl = (int64_t)(bo & 0xFFFFFF);
-                    if (ld_rlx64(&B[0]) != tau) {
-                        atomicOr(P.flags, FLAG_GUARD);
-                        stop = true;
-                        break;
-                    }
-                    c = o;
-                    if (bl > H.K) {  // too large for this pass: defer it as it stands
-                        defer_column(P, c, bo >> 24, bl);
-                        break;
-                    }
-                    for (int64_t i = 1; i < bl; ++i) H.at(i - 1) = ld_rlx64(&B[i]);
-                    H.n = bl - 1;
-                    have = true;  // tau (= B[0]) is its top
-                    continue;
-                }
-                // o < c: add the cached boundary of the earlier owner
-                const uint64_t b = ld_rlx64(&P.bndptr[o]);
-                if (b == EMPTY64) {
-                    ++retries;
-                    continue;
-                }
-                const uint64_t* B = P.heap + (b >> 24);
-                const int64_t bl = (int64_t)(b & 0xFFFFFF);
-                if (ld_rlx64(&B[0]) != tau) {  // o moved on: look again
-                    ++retries;
-                    continue;
-                }
-                retries = 0;
-                if (H.room(bl - 1)) {
-                    have = false;
-                    ++adds;
-                    for (int64_t i = 1; i < bl; ++i) H.push(ld_rlx64(&B[i]));
-                    continue;
-                }
-                defer = true;
-            }
-            if (defer) {
-                // save {tau} + heap and hand the column to the next pass
-                const uint64_t b = publish(P, H, have, tau);
+            if (o == EMPTY32 || o > c) {
+                // cache Boundary(c) = {tau} + heap, then claim tau
+                const uint64_t b = publish(P, H, true, tau);
                 if (b == NONE) {
                     atomicOr(P.flags, FLAG_HEAP);
-                    stop = true;
-                    break;
+                    return 2;
                 }
-                defer_column(P, c, b >> 24, b & 0xFFFFFF);
-                break;
+                st_rlx64(&P.bndptr[c], b);
+                wait_stores();
+                if (!cas32(&P.owner1[e.id], o, c)) {  // owner changed: look again
+                    ++retries;
+                    return 0;
+                }
+                if (o == EMPTY32) return 1;  // column settled
+                // evicted o: carry on reducing it from its cached boundary
+                ++evictions;
+                const uint64_t bo = ld_rlx64(&P.bndptr[o]);
+                const uint64_t* B = P.heap + (bo >> 24);
+                const int64_t bl = (int64_t)(bo & 0xFFFFFF);
+                if (ld_rlx64(&B[0]) != tau) {
+                    atomicOr(P.flags, FLAG_GUARD);
+                    return 2;
+                }
+                c = o;
+                retries = 0;
+                if (bl > H.K) {  // too large for this pass: defer it as it stands
+                    defer_column(P, c, bo >> 24, bl);
+                    return 1;
+                }
+                for (int64_t i = 1; i < bl; ++i) H.at(i - 1) = ld_rlx64(&B[i]);
+                H.n = bl - 1;
+                have = true;  // tau (= B[0]) is its top
+                return 0;
+            }
+            // o < c: add the cached boundary of the earlier owner
+            const uint64_t b = ld_rlx64(&P.bndptr[o]);
+            if (b == EMPTY64) {
+                ++retries;
+                return 0;
+            }
+            const uint64_t* B = P.heap + (b >> 24);
+            const int64_t bl = (int64_t)(b & 0xFFFFFF);
+            if (ld_rlx64(&B[0]) != tau) {  // o moved on: look again
+                ++retries;
+                return 0;
+            }
+            retries = 0;
+            if (H.room(bl - 1)) {
+                have = false;
+                ++adds;
+                for (int64_t i = 1; i < bl; ++i) H.push(ld_rlx64(&B[i]));
+                return 0;
+            }
+            defer = true;
+        }
+        // save {tau} + heap and hand the column to the next pass
+        (void)defer;
+        const uint64_t b = publish(P, H, have, tau);
+        if (b == NONE) {
+            atomicOr(P.flags, FLAG_HEAP);
+            return 2;
+        }
+        defer_column(P, c, b >> 24, b & 0xFFFFFF);
+        return 1;
+    };
+
+    for (;;) {
+        // lanes without a column take the next ones: one atomic per wavefront.
+        // Columns are taken in increasing order: the frontier of columns in
+        // flight stays narrow, which keeps evictions rare
+        const bool need = !active && !exhausted && !stop;
+        const uint64_t ball = __ballot(need);
+        if (ball) {
+            const int leader = __builtin_ctzll(ball);
+            uint64_t base = 0;
+            if (lane == leader) base = atomicAdd(&P.ctrs[C_NEXT], (unsigned long long)__popcll(ball));
+            const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)base, leader, 64);
+            const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(base >> 32), leader, 64);
+            base = ((uint64_t)hi << 32) | lo;
+            if (need) {
+                const int64_t next = (int64_t)(base + __popcll(ball & ((1ull << lane) - 1)));
+                if (next >= P.nwork) {
+                    exhausted = true;
+                } else {
+                    H.n = 0;
+                    have = false;
+                    guard = 0;
+                    retries = 0;
+                    active = true;
+                    if (!P.work) {
+                        c = (uint32_t)next;
+                        const uint32_t t = P.cols[c];
+                        const int64_t a = t / 12;
+                        const int ty = t % 12;
+                        const int64_t v1 = a + lin_of_mask(P.g, tri_step(ty, 0));
+                        const int64_t v2 = v1 + lin_of_mask(P.g, tri_step(ty, 1));
+                        const uint32_t r0 = P.rank[a], r1 = P.rank[v1], r2 = P.rank[v2];
+                        H.push(ekey_r(P.bpr, r0, r1));
+                        H.push(ekey_r(P.bpr, r1, r2));
+                        H.push(ekey_r(P.bpr, r0, r2));
+                    } else {
+                        // resume a deferred column from its saved, decreasing boundary
+                        c = P.work_col[next];
+                        const uint64_t off = P.work[next];
+                        const int64_t len = P.work_len[next];
+                        if (len > H.K) {
+                            atomicOr(P.flags, FLAG_WORK);
+                            active = false;
+                            stop = true;
+                        } else {
+                            for (int64_t i = 0; i < len; ++i) H.at(i) = ld_rlx64(P.heap + off + i);
+                            H.n = len;
+                        }
+                    }
+                }
             }
         }
-        if (stop) break;
+        if (!__ballot(active)) break;  // every lane is out of work (or stopped)
+        if (active) {
+            const int r = step();
+            if (r != 0) active = false;
+            if (r == 2) stop = true;
+        }
     }
     atomicAdd(&P.ctrs[C_STEPS], steps);
     atomicAdd(&P.ctrs[C_EVICT], evictions);
@@ -433,7 +466,7 @@ constexpr int IPW = NW / WB;
 constexpr int TOPCAP = 2048;  // LDS top capacity; also the staging segment of low merges
 constexpr int TOPKEEP = 1024; // top entries kept after a spill, or loaded by a refill
 constexpr int PCAP = NW;      // pending keys below the top, merged into low in batches
-constexpr uint32_t BATCH_ADD_MAX = 32;  // longest cached boundary added out of order in a round
+constexpr uint32_t BATCH_ADD_MAX = 512;  // longest cached boundary added out of order in a round
 constexpr uint64_t PAD = ~0ull;
 static_assert(TOPKEEP >= WB && TOPKEEP + WB <= TOPCAP, "top refill must fit");
 
@@ -1507,20 +1540,25 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         int cur = 0;
         bool overflow = false;
         unsigned long long hc[N_CTRS] = {0};
-        // pass plan: thread-per-column with small heaps, then one workgroup per
-        // column with boundaries of up to plan_k entries
-        int64_t plan_k[MAX_PASSES] = {k0, (int64_t)1 << 15, (int64_t)1 << 20, ((int64_t)1 << 24) - 1024, 0};  // lengths stay below 2^24 (24-bit length field)
-        int64_t plan_t[MAX_PASSES] = {lanes, 1024, 256, 2, 0};
+        // pass plan: thread-per-column with heaps of plan_k keys (in LDS, then in
+        // global scratch), then one workgroup per column with boundaries of up to
+        // plan_k entries (lengths stay below 2^24: the cached length field)
+        int64_t plan_k[MAX_PASSES] = {LDS_K, LDS_K2, (int64_t)1 << 15, (int64_t)1 << 20, ((int64_t)1 << 24) - 1024};
+        int64_t plan_t[MAX_PASSES] = {lanes, lanes, 1024, 256, 2};
+        const int lane_passes = 2;  // passes 0 and 1 are thread-per-column
         if (std::getenv("DMS_D1_TEST_PLAN")) {  // test hook: tiny capacities, every pass used
-            plan_k[0] = 4;
-            plan_k[1] = 24;
+            plan_k[0] = 3;
+            plan_k[1] = 4;
+            plan_k[2] = 24;
         }
         for (int pass = 0; pass < MAX_PASSES && nwork > 0; ++pass) {
             const int64_t K = plan_k[pass];
             if (K == 0) break;
             const int64_t T = std::max<int64_t>(1, std::min<int64_t>(nwork, plan_t[pass]));
             const auto t_pass = std::chrono::steady_clock::now();
-            const size_t need = pass == 0 ? (size_t)8 * T * K : (size_t)8 * T * (2 * K + PCAP);
+            const bool lane_pass = pass < lane_passes;
+            const bool in_lds = lane_pass;
+            const size_t need = in_lds ? 8 : lane_pass ? (size_t)8 * T * K : (size_t)8 * T * (2 * K + PCAP);
             if (grow(s.scratch, s.scratch_cap, need, s.bytes)) return oom("working boundaries");
             D1K P;
             P.g = in.g;
@@ -1545,7 +1583,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             P.scratch = (uint64_t*)s.scratch;
             P.K = K;
             P.nthreads = T;
-            P.lds = 0;
+            P.lds = in_lds ? 1 : 0;
             P.ctrs = (unsigned long long*)s.ctrs;
             P.flags = in.flags;
             // fresh work cursor, deferral count and work counters for this pass
@@ -1553,8 +1591,8 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
                 err = "D1: counter reset failed";
                 return -5;
             }
-            if (pass == 0)
-                hipLaunchKernelGGL(k_d1, dim3(nblocks(T)), dim3(DB), 0, st, P);
+            if (lane_pass)
+                hipLaunchKernelGGL(k_d1, dim3(nblocks(T)), dim3(DB), in_lds ? (size_t)8 * DB * K : 0, st, P);
             else
                 hipLaunchKernelGGL(k_d1_wide, dim3((unsigned)T), dim3(WB), 0, st, P);
             uint32_t f = 0;
