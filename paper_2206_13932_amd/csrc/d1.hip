@@ -814,6 +814,39 @@ __device__ inline void bitonic1(WideShared& L, uint64_t& x) {
     }
 }
 
+// the same with two entries per thread (entry index = 2 * thread + q), NP <= 2 * WB
+template <uint32_t NP>
+__device__ inline void bitonic2(WideShared& L, uint64_t (&e)[2]) {
+    const uint32_t t = threadIdx.x;
+#pragma unroll
+    for (uint32_t k = 2; k <= NP; k <<= 1) {
+#pragma unroll
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            uint64_t b[2];
+            if (j == 1) {
+                b[0] = e[1], b[1] = e[0];
+            } else if (j < 128) {
+                b[0] = lane_xor64(e[0], j / 2);
+                b[1] = lane_xor64(e[1], j / 2);
+            } else {
+                L.raw[2 * t] = e[0];
+                L.raw[2 * t + 1] = e[1];
+                __syncthreads();
+                b[0] = L.raw[(2 * t) ^ j];
+                b[1] = L.raw[(2 * t + 1) ^ j];
+                __syncthreads();
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const uint32_t i = 2 * t + q;
+                const bool asc = (i & k) == 0, first = (i & j) == 0;
+                const uint64_t lo = e[q] < b[q] ? e[q] : b[q], hi = e[q] < b[q] ? b[q] : e[q];
+                e[q] = first == asc ? lo : hi;
+            }
+        }
+    }
+}
+
 __device__ uint32_t sort_cancel(WideShared& L, uint32_t total, uint64_t* out) {
     static_assert(IPW == 4 && WB == 256 && NW == 1024, "exchange distances assume 4 entries per thread");
     const uint32_t t = threadIdx.x;
@@ -834,6 +867,35 @@ __device__ uint32_t sort_cancel(WideShared& L, uint32_t total, uint64_t* out) {
         uint32_t kept;
         const uint32_t ex = block_excl_scan(L.ws[WS_SORT], k, kept);
         if (k) out[ex] = x;
+        __syncthreads();
+        return kept;
+    }
+    if (total <= 2u * WB) {
+        uint64_t e2[2];
+        e2[0] = 2 * t < total ? L.raw[2 * t] : PAD;
+        e2[1] = 2 * t + 1 < total ? L.raw[2 * t + 1] : PAD;
+        __syncthreads();  // raw is reused below
+        bitonic2<2 * WB>(L, e2);
+        L.raw[2 * t] = e2[0];
+        L.raw[2 * t + 1] = e2[1];
+        __syncthreads();
+        uint32_t keep2[2], kc2 = 0;
+        for (int q = 0; q < 2; ++q) {
+            const uint32_t j = 2 * t + q;
+            uint32_t kk = 0;
+            if (j < total && (j == 0 || L.raw[j - 1] != e2[q])) {
+                uint32_t r = 1;
+                while (j + r < total && L.raw[j + r] == e2[q]) ++r;
+                kk = r & 1;
+            }
+            keep2[q] = kk;
+            kc2 += kk;
+        }
+        uint32_t kept;
+        const uint32_t ex = block_excl_scan(L.ws[WS_SORT], kc2, kept);
+        uint32_t a = ex;
+        for (int q = 0; q < 2; ++q)
+            if (keep2[q]) out[a++] = e2[q];
         __syncthreads();
         return kept;
     }
