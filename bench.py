@@ -225,7 +225,7 @@ def main():
           f"deferrals, published, restarts): {stats[:10]}; D1 passes (columns, us): {stats[10:20]}; wide (rounds, expanded, moved): {stats[20:23]}; "
           f"wide per column (max us, sum us, max rounds, max adds, max len, n over 1 ms): {stats[23:29]}; "
           f"phases of those (window, slots, loads, sort, low merge, top merge, owner, adds, claims, refill) us: "
-          f"{stats[29:39]}, rounds {stats[39]}, adds {stats[40]}",
+          f"{stats[29:39]}, rounds {stats[39]}, adds {stats[40]}; full-merge additions {stats[41]}",
           file=sys.stderr, flush=True)
     lens = (ctx.debug(dms.BUF_D1LEN, np.uint64) & 0xFFFFFF).astype(np.int64)
     if lens.size:

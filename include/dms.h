@@ -200,7 +200,7 @@ enum {
                               scan, slot assignment, batched loads, sort, low
                               merge, top merge, owner rule, additions, claims
                               and reloads, refills), then their rounds and
-                              additions                                         */
+                              additions; additions made by one full merge       */
     DMS_BUF_D1LEN = 9      /* u64 per D1 column: last cached boundary
                               (offset << 24 | length)                             */
 };

@@ -51,7 +51,7 @@ struct D1State {
     uint64_t pass_work[5] = {0, 0, 0, 0, 0};
     uint64_t pass_us[5] = {0, 0, 0, 0, 0};
     // workgroup passes: rounds, edges expanded, boundary entries moved by merges
-    uint64_t wide[3] = {0, 0, 0};
+    uint64_t wide[4] = {0, 0, 0, 0};
     // workgroup passes, per column taken from the queue: longest (us), total (us),
     // most rounds, most cached-boundary additions, longest boundary, columns over 1 ms
     uint64_t wide_t[6] = {0, 0, 0, 0, 0, 0};

@@ -51,7 +51,7 @@ inline unsigned nblocks(int64_t n) { return (unsigned)((n + DB - 1) / DB); }
 
 // counters in D1State::ctrs
 enum { C_HEAP = 0, C_NEXT = 1, C_DEFER = 2, C_STEPS = 3, C_EVICT = 4, C_ADDS = 5, C_ROUNDS = 6, C_EXPANDED = 7,
-       C_MOVED = 8, C_TMAX = 9, C_TSUM = 10, C_RMAX = 11, C_AMAX = 12, C_NMAX = 13, C_SLOW = 14, C_PHASE = 16,
+       C_MOVED = 8, C_TMAX = 9, C_TSUM = 10, C_RMAX = 11, C_AMAX = 12, C_NMAX = 13, C_SLOW = 14, C_LONG = 15, C_PHASE = 16,
        N_PHASE = 10, N_CTRS = 32 };
 // The publication heap is split into NSEG segments with one bump counter each
 // (counters 128 bytes apart, after the N_CTRS counters above), so that
@@ -85,6 +85,7 @@ struct D1K {
     int64_t K;
     int64_t nthreads;
     int lds;  // working heaps in LDS (K entries per thread) instead of global scratch
+    uint32_t long_add;  // cached boundaries longer than this are added by one full merge
     unsigned long long* ctrs;
     uint32_t* flags;
 };
@@ -468,6 +469,7 @@ constexpr int TOPKEEP = 1024; // top entries kept after a spill, or loaded by a 
 constexpr int PCAP = NW;      // pending keys below the top, merged into low in batches
 constexpr uint32_t BATCH_ADD_MAX = 512;  // longest cached boundary added out of order in a round
 constexpr uint64_t PAD = ~0ull;
+constexpr uint32_t LONG_ADD = 2 * PCAP;  // default of D1K::long_add
 static_assert(TOPKEEP >= WB && TOPKEEP + WB <= TOPCAP, "top refill must fit");
 
 // rows of WideShared::ws (wave totals); a row is written again only after
@@ -1094,6 +1096,65 @@ __device__ uint64_t save_col(const D1K& P, WideShared& L, Col& C, uint64_t* low,
     return off;
 }
 
+// Boundary ^= the cached boundary stored decreasingly at P.heap[aoff ..
+// aoff + alen), by one merge of the whole column: pend is flushed, the top
+// is appended to low, and low and the cached boundary are merged into tmp,
+// which becomes low (the two buffers swap). Each step stages TOPCAP low keys
+// and NW cached keys and merges those up to the smaller of the two segments'
+// last keys, so equal keys are always in the same step and every step
+// consumes a full segment of one side. Adding a long boundary in NW-key
+// chunks instead rewrites the low part once per chunk.
+__device__ void add_long(const D1K& P, WideShared& L, Col& C, uint64_t*& low, uint64_t*& tmp, const uint64_t* pend,
+                         uint64_t aoff, uint32_t alen, unsigned long long& moved) {
+    const uint32_t t = threadIdx.x;
+    flush(L, C, low, pend, tmp, moved);
+    {
+        const uint64_t* T = L.top[C.cur];
+        for (uint32_t i = t; i < C.nt; i += WB) low[C.nl + i] = T[i];
+        C.nl += C.nt;
+        C.nt = 0;
+    }
+    __syncthreads();
+    const uint32_t na = C.nl;
+    uint64_t* X = L.top[0];
+    uint32_t i = 0, j = 0, out = 0;
+    while (i < na || j < alen) {
+        const uint32_t la = min((uint32_t)TOPCAP, na - i), lb = min((uint32_t)NW, alen - j);
+        stage(X, low + i, la);
+        {
+            uint64_t v[IPW];
+#pragma unroll
+            for (int q = 0; q < IPW; ++q) {
+                const uint32_t k = q * WB + t;
+                v[q] = k < lb ? ld_rlx64(P.heap + aoff + (alen - 1 - (j + k))) : 0;
+            }
+#pragma unroll
+            for (int q = 0; q < IPW; ++q) {
+                const uint32_t k = q * WB + t;
+                if (k < lb) L.src[k] = v[q];
+            }
+        }
+        __syncthreads();
+        uint64_t bound = PAD;  // keys are below PAD
+        if (i + la < na) bound = X[la - 1];
+        if (j + lb < alen) bound = min(bound, L.src[lb - 1]);
+        const uint32_t ta = bound == PAD ? la : count_less<uint64_t>(X, la, bound + 1);
+        const uint32_t tb = bound == PAD ? lb : count_less<uint64_t>(L.src, lb, bound + 1);
+        uint32_t sp;
+        out += merge_seg(L, X, ta, L.src, tb, tmp + out, nullptr, 0, 0, sp);
+        __syncthreads();
+        i += ta;
+        j += tb;
+    }
+    moved += na + alen;
+    uint64_t* sw = low;
+    low = tmp;
+    tmp = sw;
+    C.nl = out;
+    C.lmax = out ? low[out - 1] : 0;
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
     __shared__ WideShared L;
     const int t = threadIdx.x;
@@ -1102,7 +1163,7 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
     uint64_t* tmp = low + P.K;
     uint64_t* pend = tmp + P.K;
     const int64_t V = P.g.V;
-    unsigned long long steps = 0, evictions = 0, adds = 0, rounds = 0, expanded = 0, moved = 0;
+    unsigned long long steps = 0, evictions = 0, adds = 0, rounds = 0, expanded = 0, moved = 0, longs = 0;
     for (;;) {
         if (t == 0) L.u64s[0] = atomicAdd(&P.ctrs[C_NEXT], 1ull);
         __syncthreads();
@@ -1407,6 +1468,13 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
                 break;
             }
             ++adds;
+            if (alen > P.long_add) {
+                ++longs;
+                add_long(P, L, C, low, tmp, pend, aoff, alen, moved);
+                nmax = max(nmax, C.n());
+                lap(7);
+                continue;
+            }
             for (uint32_t base = 0; base < alen; base += NW) {
                 const uint32_t m = min((uint32_t)NW, alen - base);
                 uint64_t v[IPW];
@@ -1451,6 +1519,7 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
         atomicAdd(&P.ctrs[C_ADDS], adds);
         atomicAdd(&P.ctrs[C_ROUNDS], rounds);
         atomicAdd(&P.ctrs[C_MOVED], moved);
+        atomicAdd(&P.ctrs[C_LONG], longs);
     }
 }
 
@@ -1545,7 +1614,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
     if (grow(s.owner1, s.owner1_cap, 4 * 7 * V, s.bytes)) return oom("owners");
     for (int d = 0; d < 6; ++d) s.stats[d] = 0;
     for (int d = 0; d < 5; ++d) s.pass_work[d] = s.pass_us[d] = 0;
-    for (int d = 0; d < 3; ++d) s.wide[d] = 0;
+    for (int d = 0; d < 4; ++d) s.wide[d] = 0;
     for (int d = 0; d < 6; ++d) s.wide_t[d] = 0;
     for (int d = 0; d < 12; ++d) s.wide_ph[d] = 0;
     // unpaired 2-saddles, ascending
@@ -1606,12 +1675,14 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         // global scratch), then one workgroup per column with boundaries of up to
         // plan_k entries (lengths stay below 2^24: the cached length field)
         int64_t plan_k[MAX_PASSES] = {LDS_K, LDS_K2, (int64_t)1 << 15, (int64_t)1 << 20, ((int64_t)1 << 24) - 1024};
-        int64_t plan_t[MAX_PASSES] = {lanes, lanes, 1024, 256, 2};
+        int64_t plan_t[MAX_PASSES] = {lanes, lanes, 1024, 256, 16};
+        uint32_t long_add = LONG_ADD;
         const int lane_passes = 2;  // passes 0 and 1 are thread-per-column
         if (std::getenv("DMS_D1_TEST_PLAN")) {  // test hook: tiny capacities, every pass used
             plan_k[0] = 3;
             plan_k[1] = 4;
             plan_k[2] = 24;
+            long_add = 2;
         }
         for (int pass = 0; pass < MAX_PASSES && nwork > 0; ++pass) {
             const int64_t K = plan_k[pass];
@@ -1646,6 +1717,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             P.K = K;
             P.nthreads = T;
             P.lds = in_lds ? 1 : 0;
+            P.long_add = long_add;
             P.ctrs = (unsigned long long*)s.ctrs;
             P.flags = in.flags;
             // fresh work cursor, deferral count and work counters for this pass
@@ -1684,6 +1756,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             s.wide[0] += hc[C_ROUNDS];
             s.wide[1] += hc[C_EXPANDED];
             s.wide[2] += hc[C_MOVED];
+            s.wide[3] += hc[C_LONG];
             s.wide_t[0] = std::max<uint64_t>(s.wide_t[0], hc[C_TMAX] / 100);
             s.wide_t[1] += hc[C_TSUM] / 100;
             s.wide_t[2] = std::max<uint64_t>(s.wide_t[2], hc[C_RMAX]);

@@ -711,6 +711,7 @@ int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap) {
             for (int i = 0; i < 3; ++i) h[20 + i] = ctx->d1.wide[i];
             for (int i = 0; i < 6; ++i) h[23 + i] = ctx->d1.wide_t[i];
             for (int i = 0; i < 12; ++i) h[29 + i] = ctx->d1.wide_ph[i];
+            h[41] = ctx->d1.wide[3];
             return bytes;
         }
         case DMS_BUF_D1LEN: {

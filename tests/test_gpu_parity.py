@@ -199,8 +199,9 @@ def test_error_paths():
 
 @pytest.mark.gpu
 def test_parity_d1_every_deferral_pass():
-    """Tiny working heaps force columns through all D1 passes (global heaps,
-    LDS heaps of two sizes, large global heaps); pairs must not change."""
+    """Tiny working heaps force columns through all D1 passes (LDS heaps of
+    two sizes, then workgroup passes), and every cached boundary longer than
+    two entries is added by the full merge; pairs must not change."""
     import os
     import subprocess
     import sys
@@ -208,15 +209,18 @@ def test_parity_d1_every_deferral_pass():
         "import numpy as np, torch, oracle, synthfields as sf\n"
         "from paper_2206_13932_amd import dms\n"
         "ctx = dms.Context(0)\n"
+        "longs = 0\n"
         "for name, f in [('noise24', sf.noise((24, 24, 24), 3)),\n"
         "                ('smooth40', sf.gaussians((40, 36, 32), 4, k=12, noise_frac=0.01))]:\n"
         "    res = oracle.run(f)\n"
         "    out = ctx.diagram(torch.from_numpy(f).cuda())\n"
         "    st = ctx.debug(dms.BUF_STATS, np.uint64).tolist()\n"
-        "    print(name, 'deferrals', st[7], 'passes', st[10:20], flush=True)\n"
+        "    print(name, 'deferrals', st[7], 'passes', st[10:20], 'full-merge additions', st[41], flush=True)\n"
         "    assert st[7] > 0\n"
+        "    longs += st[41]\n"
         "    for d in range(3):\n"
         "        assert np.array_equal(out[d].cpu().numpy(), res.pairs[d]), (name, d)\n"
+        "assert longs > 0\n"
         "print('ok')\n")
     env = dict(os.environ, DMS_D1_TEST_PLAN="1")
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
