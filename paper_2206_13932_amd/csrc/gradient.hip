@@ -22,13 +22,14 @@ namespace dms {
 
 namespace {
 
-constexpr int GB = 256;  // threads per block
+constexpr int GB = 1024;  // threads per block (vertices handed to lanes by lower-star size)
 
 struct LdsTables {
     uint64_t face[NSLOT];
     uint64_t cof_lo[NSLOT];
     uint16_t cof_hi[NSLOT];
     uint16_t cellnb[NSLOT];
+    uint16_t knb[NSLOT];  // the slot's neighbours a | b << 4 | c << 8 (repeated when fewer)
     uint8_t plane[NSLOT];
     int8_t al27[NSLOT];
     int8_t l27[NNB];
@@ -61,10 +62,11 @@ __device__ inline uint32_t wave_reserve(uint32_t cnt, uint32_t* counter) {
     return base + ex;
 }
 
-__global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __restrict__ rank,
+__global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_gradient(GridDev g, const uint32_t* __restrict__ rank,
                                                  uint8_t* __restrict__ G, int bpr, CritLists cl) {
     __shared__ LdsTables T;
-    __shared__ uint8_t scode[NSLOT * GB];  // partner code of each slot, written out coalesced
+    __shared__ uint32_t bins[NSLOT + 1];   // lanes per lower-star size, then bin offsets
+    __shared__ uint16_t perm[GB];          // perm[lane] = the block-local vertex that lane processes
     const int tid = threadIdx.x;
     // cooperative copy of the star tables into LDS
     for (int i = tid; i < NSLOT; i += GB) {
@@ -72,6 +74,11 @@ __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __re
         T.cof_lo[i] = kStar.cof_lo[i];
         T.cof_hi[i] = kStar.cof_hi[i];
         T.cellnb[i] = kStar.cellnb[i];
+        {
+            const uint32_t nb = kStar.cellnb[i], nb2 = nb & (nb - 1), nb3 = nb2 & (nb2 - 1);
+            const uint32_t a = __builtin_ctz(nb), b = nb2 ? __builtin_ctz(nb2) : a, c = nb3 ? __builtin_ctz(nb3) : b;
+            T.knb[i] = (uint16_t)(a | b << 4 | c << 8);
+        }
         T.plane[i] = kStar.plane[i];
         T.al27[i] = kStar.al27[i];
         T.aofflin[i] = (int64_t)kStar.aoff[i][0] + kStar.aoff[i][1] * g.sy + kStar.aoff[i][2] * g.sz;
@@ -81,48 +88,105 @@ __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __re
         T.lessc[i] = kStar.lessc[i];
         T.cpos_pos[i] = kStar.cpos_pos[i];
     }
+    for (int i = tid; i <= NSLOT; i += GB) bins[i] = 0;
     __syncthreads();
 
-    const int64_t x = (int64_t)blockIdx.x * GB + tid;
-    const bool active = x < g.V;
     const int64_t V = g.V;
-#define CODE(s) scode[(s) * GB + tid]
+    const int64_t x0 = (int64_t)blockIdx.x * GB;
 
-    uint64_t crit_lo = 0;
-    uint32_t crit_hi = 0;
-    uint64_t in_lo = 0;
-    uint32_t in_hi = 0;
-    bool crit_vertex = false;
-    uint32_t rx = 0;
-    int cx = 0, cy = 0, cz = 0;
-
-    if (active) {
-        coords_of(g, x, cx, cy, cz);
-        rx = rank[x];
+    // lower neighbours of vertex v (bit n: neighbour n exists and is lower);
+    // r[n] receives the neighbours' ranks
+    auto lower_of = [&](int64_t v, uint32_t& rv, uint32_t (&r)[NNB], int& cx, int& cy, int& cz) {
+        coords_of(g, v, cx, cy, cz);
+        rv = rank[v];
         uint32_t lower = 0;
-        uint32_t r[NNB];
 #pragma unroll
         for (int n = 0; n < NNB; ++n) {
             const int dx = kStar.nbv[n][0], dy = kStar.nbv[n][1], dz = kStar.nbv[n][2];
             const bool in = (unsigned)(cx + dx) < (unsigned)g.nx && (unsigned)(cy + dy) < (unsigned)g.ny &&
                             (unsigned)(cz + dz) < (unsigned)g.nz;
-            uint32_t rv = 0xFFFFFFFFu;
-            if (in) rv = rank[x + dx + dy * g.sy + dz * g.sz];
-            r[n] = rv;
-            if (in && rv < rx) lower |= 1u << n;
+            uint32_t q = 0xFFFFFFFFu;
+            if (in) q = rank[v + dx + dy * g.sy + dz * g.sz];
+            r[n] = q;
+            if (in && q < rv) lower |= 1u << n;
         }
-        // non-existent simplices anchored at x (upper faces of the grid)
-        if (cx == g.nx - 1 || cy == g.ny - 1 || cz == g.nz - 1) {
-            for (int t = 0; t < 7; ++t)
-                if (!fits(g, cx, cy, cz, t + 1)) G[(int64_t)(1 + t) * V + x] = CODE_NONE;
-            for (int t = 0; t < 12; ++t)
-                if (!fits(g, cx, cy, cz, tri_step(t, 0) | tri_step(t, 1))) G[(int64_t)(8 + t) * V + x] = CODE_NONE;
-            for (int t = 0; t < 6; ++t) G[(int64_t)(20 + t) * V + x] = CODE_NONE;
+        return lower;
+    };
+    // cells of L(v): the slots whose neighbour sets are lower
+    auto cells_of = [&](uint32_t lower, uint64_t& in_lo, uint32_t& in_hi) {
+        in_lo = 0;
+        in_hi = 0;
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+            const uint32_t nb = kStar.cellnb[s];
+            if ((nb & ~lower) == 0) {
+                if (s < 64) in_lo |= (uint64_t)1 << s;
+                else in_hi |= 1u << (s - 64);
+            }
         }
+    };
+
+    // ---- 1. own vertex: lower star size, grid-boundary codes, lane assignment ----
+    // Lanes of a wave run the lower-star loop in lockstep, so its cost is the
+    // largest lower star in the wave. The vertices of the block are handed to
+    // lanes in order of lower-star size (a counting sort in LDS), which keeps
+    // the stores of each slot inside the block's span.
+    const int64_t xo = x0 + tid;
+    {
+        uint32_t ncell = 0;
+        if (xo < V) {
+            uint32_t rv, r[NNB];
+            int cx, cy, cz;
+            const uint32_t lower = lower_of(xo, rv, r, cx, cy, cz);
+            // non-existent simplices anchored at x (upper faces of the grid)
+            if (cx == g.nx - 1 || cy == g.ny - 1 || cz == g.nz - 1) {
+                for (int t = 0; t < 7; ++t)
+                    if (!fits(g, cx, cy, cz, t + 1)) G[(int64_t)(1 + t) * V + xo] = CODE_NONE;
+                for (int t = 0; t < 12; ++t)
+                    if (!fits(g, cx, cy, cz, tri_step(t, 0) | tri_step(t, 1))) G[(int64_t)(8 + t) * V + xo] = CODE_NONE;
+                for (int t = 0; t < 6; ++t) G[(int64_t)(20 + t) * V + xo] = CODE_NONE;
+            }
+            if (lower) {
+                uint64_t in_lo;
+                uint32_t in_hi;
+                cells_of(lower, in_lo, in_hi);
+                ncell = (uint32_t)(popc64(in_lo) + __builtin_popcount(in_hi));
+            }
+        }
+        const uint32_t within = atomicAdd(&bins[ncell], 1u);
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t acc = 0;
+            for (int b = 0; b <= NSLOT; ++b) {
+                const uint32_t c = bins[b];
+                bins[b] = acc;
+                acc += c;
+            }
+        }
+        __syncthreads();
+        perm[bins[ncell] + within] = (uint16_t)tid;
+        __syncthreads();
+    }
+
+    // ---- 2. the lower star of vertex perm[tid] (ProcessLowerStars) ----
+    const int64_t x = x0 + perm[tid];
+    const bool active = x < V;
+    uint64_t crit_lo = 0;
+    uint32_t crit_hi = 0;
+    bool crit_vertex = false;
+    uint32_t rx = 0;
+
+    if (active) {
+        uint32_t r[NNB];
+        int cx, cy, cz;
+        const uint32_t lower = lower_of(x, rx, r, cx, cy, cz);
         if (lower == 0) {
             G[x] = CODE_CRIT;  // minimum
             crit_vertex = true;
         } else {
+            uint64_t in_lo;
+            uint32_t in_hi;
+            cells_of(lower, in_lo, in_hi);
             // relabel the lower neighbours by rank: rel[n] = #lower neighbours below n
             uint64_t relpack = 0;
             int n0 = 0;
@@ -135,29 +199,13 @@ __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __re
                 relpack |= (uint64_t)c << (4 * n);
                 if (((lower >> n) & 1) && c == 0) n0 = n;
             }
-            // cells of L(x)
-#pragma unroll
-            for (int s = 0; s < NSLOT; ++s) {
-                const uint32_t nb = kStar.cellnb[s];
-                if ((nb & ~lower) == 0) {
-                    if (s < 64) in_lo |= (uint64_t)1 << s;
-                    else in_hi |= 1u << (s - 64);
-                }
-            }
             // key of a cell of L(x): bitmask of its lower neighbours' rank labels
+            auto label = [&](uint32_t n) { return (uint32_t)(relpack >> (4 * n)) & 15u; };
             auto key_of = [&](int s) {
-                uint32_t nb = T.cellnb[s];
-                uint32_t key = 0;
-                while (nb) {
-                    const int n = __builtin_ctz(nb);
-                    nb &= nb - 1;
-                    key |= 1u << ((uint32_t)(relpack >> (4 * n)) & 15u);
-                }
-                return key;
+                const uint32_t q = T.knb[s];
+                return (1u << label(q & 15u)) | (1u << label((q >> 4) & 15u)) | (1u << label(q >> 8));
             };
-            auto anchor = [&](int s) { return x + T.aofflin[s]; };
-            auto gput = [&](int s, uint8_t code) { CODE(s) = code; };
-            (void)anchor;
+            auto gput = [&](int s, uint8_t code) { G[(int64_t)T.plane[s] * V + x + T.aofflin[s]] = code; };
             auto unpaired = [&](int s, uint64_t cls_lo) { return popc64(T.face[s] & ~cls_lo); };
             // pair (p, a): p is a facet of a; w = the neighbour of a not in p
             auto pair_cells = [&](int p, int a) {
@@ -241,13 +289,7 @@ __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __re
         }
     }
 
-    // ---- gradient codes: one store per slot, consecutive lanes -> consecutive bytes ----
-    for (int s = 0; s < NSLOT; ++s) {
-        const bool w = s < 64 ? ((in_lo >> s) & 1) : ((in_hi >> (s - 64)) & 1);
-        if (w) G[(int64_t)T.plane[s] * V + x + T.aofflin[s]] = CODE(s);
-    }
-
-    // ---- critical-cell lists (all lanes take part in the wave scans) ----
+    // ---- critical-cell lists of vertex x (all lanes take part in the wave scans) ----
     auto nbrank = [&](int n) {
         return rank[x + kStar.nbv[n][0] + kStar.nbv[n][1] * g.sy + kStar.nbv[n][2] * g.sz];
     };
@@ -323,8 +365,6 @@ __global__ __launch_bounds__(GB) void k_gradient(GridDev g, const uint32_t* __re
             ++at;
         }
     }
-#undef KEY
-#undef CODE
 }
 
 }  // namespace
