@@ -486,6 +486,9 @@ static int run_d0_d2(dms_ctx* ctx) {
     const int64_t m0 = ctx->ncrit[0], m1 = ctx->ncrit[1], m2 = ctx->ncrit[2], m3 = ctx->ncrit[3];
     HIPCHK(hipMemsetAsync(ctx->stats.p, 0, 64, st));
     unsigned long long* stats = P<unsigned long long>(ctx->stats);
+    // work counters of the two tracing kernels (bytes 32..47 of the counters)
+    unsigned long long* next = P<unsigned long long>(ctx->counters) + 4;
+    fill_u32(P<uint32_t>(ctx->counters) + 8, 0, 4, st);
     // D0 (Sec. 5.1)
     ENSURE(ctx->na0, 4 * m1);
     ENSURE(ctx->nb0, 4 * m1);
@@ -493,7 +496,7 @@ static int run_d0_d2(dms_ctx* ctx) {
     ENSURE(ctx->bnd0, 8 * m1);
     ENSURE(ctx->paired1, m1);
     trace_d0(ctx->g, P<uint8_t>(ctx->G), P<uint32_t>(ctx->rank), P<uint32_t>(ctx->cid[1]), P<uint32_t>(ctx->cpos[1]),
-             m1, P<uint32_t>(ctx->na0), P<uint32_t>(ctx->nb0), P<uint32_t>(ctx->flags), st);
+             m1, P<uint32_t>(ctx->na0), P<uint32_t>(ctx->nb0), P<uint32_t>(ctx->flags), next, st);
     fill_u32(P<uint32_t>(ctx->owner0), EMPTY32, V, st);
     fill_u64(P<uint64_t>(ctx->bnd0), EMPTY64, m1, st);
     reduce_pairs(P<uint32_t>(ctx->na0), P<uint32_t>(ctx->nb0), m1, P<uint32_t>(ctx->owner0), P<uint64_t>(ctx->bnd0),
@@ -508,7 +511,7 @@ static int run_d0_d2(dms_ctx* ctx) {
     ENSURE(ctx->paired2, m2);
     tet_positions(P<uint32_t>(ctx->csorted[3]), m3, P<uint32_t>(ctx->tet2pos), st);
     trace_d2(ctx->g, P<uint8_t>(ctx->G), P<uint32_t>(ctx->tet2pos), P<uint32_t>(ctx->cid[2]), P<uint32_t>(ctx->cpos[2]),
-             m2, P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2), P<uint32_t>(ctx->flags), st);
+             m2, P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2), P<uint32_t>(ctx->flags), next + 1, st);
     fill_u32(P<uint32_t>(ctx->owner2), EMPTY32, m3 + 1, st);
     fill_u64(P<uint64_t>(ctx->bnd2), EMPTY64, m2, st);
     reduce_pairs(P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2), m2, P<uint32_t>(ctx->owner2), P<uint64_t>(ctx->bnd2),

@@ -62,11 +62,12 @@ void inverse_perm(const uint32_t* perm, int64_t n, uint32_t* inv, hipStream_t st
 // pairs.hip -- D0 / D2
 // trace_*: c = the critical cells in the gradient kernel's order, pos[i] = the
 // position of c[i] in the sorted order (the arcs are written there)
+// next: a zeroed u64 work counter
 void trace_d0(const GridDev& g, const uint8_t* G, const uint32_t* rank, const uint32_t* c1, const uint32_t* pos,
-              int64_t m, uint32_t* na, uint32_t* nb, uint32_t* flags, hipStream_t st);
+              int64_t m, uint32_t* na, uint32_t* nb, uint32_t* flags, unsigned long long* next, hipStream_t st);
 void tet_positions(const uint32_t* c3_sorted, int64_t m, uint32_t* tet2pos, hipStream_t st);
 void trace_d2(const GridDev& g, const uint8_t* G, const uint32_t* tet2pos, const uint32_t* c2, const uint32_t* pos,
-              int64_t m, uint32_t* na, uint32_t* nb, uint32_t* flags, hipStream_t st);
+              int64_t m, uint32_t* na, uint32_t* nb, uint32_t* flags, unsigned long long* next, hipStream_t st);
 void reduce_pairs(const uint32_t* na, const uint32_t* nb, int64_t m, uint32_t* owner, uint64_t* bnd,
                   uint32_t* flags, unsigned long long* stats, hipStream_t st);
 void settled_columns(const uint64_t* bnd, const uint32_t* owner, int64_t m, uint8_t* paired, hipStream_t st);

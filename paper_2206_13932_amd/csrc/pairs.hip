@@ -17,6 +17,8 @@
 // claims its pivot (younger node) if free, adds the published boundary of an
 // earlier owner, or evicts a later owner and carries on reducing the evicted
 // column. Reduced pivots are unique, so the pairs equal the sequential ones.
+#include <algorithm>
+
 #include "dms_internal.h"
 
 namespace dms {
@@ -28,31 +30,68 @@ inline unsigned nblocks(int64_t n) { return (unsigned)((n + PB - 1) / PB); }
 
 constexpr int64_t PATH_GUARD = (int64_t)1 << 22;
 
-__device__ inline int64_t descend(const GridDev& g, const uint8_t* __restrict__ G0, int64_t v, uint32_t* flags) {
-    for (int64_t guard = 0; guard < PATH_GUARD; ++guard) {
-        const uint8_t c = G0[v];
-        if (c >= 27) return v;  // 0xFF: minimum
-        v += lin27(g, c);
+// Paths are handed out one at a time (two per critical cell): a lane whose
+// path has ended takes the next one, so the lanes of a wave stay busy until
+// the work runs out instead of waiting for the wave's longest path. Each wave
+// draws chunks of PCHUNK consecutive path numbers from a global counter (one
+// atomic per chunk) and its lanes take them in order, so neighbouring cells
+// go to neighbouring lanes (the gradient kernel lists them in grid order) and
+// their v-paths share cache lines. [pb, pe) is the wave's remaining chunk
+// (the same in every lane). Returns false when the lane's work is exhausted.
+constexpr int64_t PCHUNK = 256;
+__device__ inline bool take_path(bool idle, unsigned long long* next, int64_t total, int64_t& k, int64_t& pb,
+                                 int64_t& pe) {
+    const uint64_t need = __ballot(idle);
+    if (need == 0) return true;
+    const int lane = threadIdx.x & 63;
+    const int64_t cnt = __popcll(need), avail = pe - pb;
+    const int64_t r = __popcll(need & ((1ull << lane) - 1));
+    if (avail >= cnt) {
+        if (idle) k = pb + r;
+        pb += cnt;
+    } else {
+        const int leader = __builtin_ctzll(need);
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(next, (unsigned long long)PCHUNK);
+        const int64_t nb = (int64_t)__shfl(base, leader, 64);
+        if (idle) k = r < avail ? pb + r : nb + (r - avail);
+        pb = nb + (cnt - avail);
+        pe = nb + PCHUNK;
     }
-    atomicOr(flags, FLAG_GUARD);
-    return v;
+    return !idle || k < total;
 }
 
-// Critical cells are traced in the order the gradient kernel listed them
-// (neighbouring vertices in neighbouring lanes, so the v-paths of a wave share
-// cache lines); each arc goes to the cell's position in the sorted order.
-__global__ void k_trace_d0(GridDev g, const uint8_t* __restrict__ G, const uint32_t* __restrict__ rank,
-                           const uint32_t* __restrict__ c1, const uint32_t* __restrict__ pos, int64_t m,
-                           uint32_t* __restrict__ na, uint32_t* __restrict__ nb, uint32_t* flags) {
-    const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
-    if (i >= m) return;
-    const uint32_t e = c1[i];
-    const uint32_t j = pos[i];
-    const int64_t a = e / 7;
-    const int64_t b = a + lin_of_mask(g, e % 7 + 1);
-    const int64_t ma = descend(g, G, a, flags), mb = descend(g, G, b, flags);
-    na[j] = rank[ma];
-    nb[j] = rank[mb];
+// D0: path 2i + s descends from vertex s of critical edge c1[i] to a minimum;
+// its rank goes to na (s = 0) or nb (s = 1) at the edge's sorted position.
+__global__ __launch_bounds__(PB) void k_trace_d0(GridDev g, const uint8_t* __restrict__ G,
+                                                 const uint32_t* __restrict__ rank, const uint32_t* __restrict__ c1,
+                                                 const uint32_t* __restrict__ pos, int64_t m,
+                                                 uint32_t* __restrict__ na, uint32_t* __restrict__ nb,
+                                                 uint32_t* flags, unsigned long long* next) {
+    bool have = false;
+    int64_t v = 0, steps = 0, k = 0, pb = 0, pe = 0;
+    uint32_t* out = nullptr;
+    for (;;) {
+        if (!take_path(!have, next, 2 * m, k, pb, pe)) break;
+        if (!have) {
+            const int64_t i = k >> 1;
+            const uint32_t e = c1[i];
+            v = e / 7;
+            if (k & 1) v += lin_of_mask(g, e % 7 + 1);
+            out = ((k & 1) ? nb : na) + pos[i];
+            steps = 0;
+            have = true;
+        }
+        const uint8_t c = G[v];
+        if (c >= 27 || steps >= PATH_GUARD) {  // 0xFF: minimum
+            if (c < 27) atomicOr(flags, FLAG_GUARD);
+            *out = rank[v];
+            have = false;
+            continue;
+        }
+        v += lin27(g, c);
+        ++steps;
+    }
 }
 
 // ---- tetrahedra / triangles in anchor+type form ----------------------------
@@ -105,16 +144,55 @@ __device__ inline void tet_facet(const GridDev& g, int64_t anchor, int type, int
     else { A = s0; B = s1; }
 }
 
-__device__ inline uint32_t ascend(const GridDev& g, const uint8_t* __restrict__ G,
-                                  const uint32_t* __restrict__ tet2pos, Simp T, bool ok, uint32_t* flags) {
+// D2: path 2i + s ascends from side s of critical triangle c2[i] through
+// tetrahedra (a regular tet is left through its paired triangle into the tet
+// on the other side) to a maximum, whose age goes to na / nb at the
+// triangle's position in decreasing order; a path that leaves the domain
+// ends at the virtual maximum (age 0).
+__global__ __launch_bounds__(PB) void k_trace_d2(GridDev g, const uint8_t* __restrict__ G,
+                                                 const uint32_t* __restrict__ tet2pos,
+                                                 const uint32_t* __restrict__ c2, const uint32_t* __restrict__ pos,
+                                                 int64_t m, uint32_t* __restrict__ na, uint32_t* __restrict__ nb,
+                                                 uint32_t* flags, unsigned long long* next) {
     const int64_t V = g.V;
-    for (int64_t guard = 0; ok; ++guard) {
-        if (guard >= PATH_GUARD) {
-            atomicOr(flags, FLAG_GUARD);
-            return 0;
+    bool have = false, ok = false;
+    int64_t steps = 0, k = 0, pb = 0, pe = 0;
+    Simp T{0, 0};
+    uint32_t* out = nullptr;
+    for (;;) {
+        if (!take_path(!have, next, 2 * m, k, pb, pe)) break;
+        if (!have) {
+            const int64_t i = k >> 1;
+            const uint32_t t = c2[i];
+            const int type = (int)(t % 12);
+            Simp cf[2];
+            bool cok[2];
+            tri_cofacets(g, t / 12, tri_step(type, 0), tri_step(type, 1), cf, cok);
+            const int side = (int)(k & 1);
+            T = cf[side];
+            ok = cok[side];
+            out = (side ? nb : na) + (m - 1 - (int64_t)pos[i]);
+            steps = 0;
+            have = true;
         }
+        if (!ok) {  // virtual maximum
+            *out = 0;
+            have = false;
+            continue;
+        }
+        if (steps >= PATH_GUARD) {
+            atomicOr(flags, FLAG_GUARD);
+            *out = 0;
+            have = false;
+            continue;
+        }
+        ++steps;
         const uint8_t c = G[(int64_t)(20 + T.type) * V + T.anchor];
-        if (c == CODE_CRIT) return tet2pos[T.anchor * 6 + T.type];
+        if (c == CODE_CRIT) {
+            *out = tet2pos[T.anchor * 6 + T.type];
+            have = false;
+            continue;
+        }
         int64_t ta;
         int A, B;
         tet_facet(g, T.anchor, T.type, c & 3, ta, A, B);
@@ -126,23 +204,6 @@ __device__ inline uint32_t ascend(const GridDev& g, const uint8_t* __restrict__ 
         ok = cok[o];
         T = cf[o];
     }
-    return 0;  // virtual maximum
-}
-
-__global__ void k_trace_d2(GridDev g, const uint8_t* __restrict__ G, const uint32_t* __restrict__ tet2pos,
-                           const uint32_t* __restrict__ c2, const uint32_t* __restrict__ pos, int64_t m,
-                           uint32_t* __restrict__ na, uint32_t* __restrict__ nb, uint32_t* flags) {
-    const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
-    if (i >= m) return;
-    const uint32_t t = c2[i];
-    const int64_t j = m - 1 - (int64_t)pos[i];  // arcs in decreasing order
-    const int64_t anchor = t / 12;
-    const int type = t % 12;
-    Simp cf[2];
-    bool ok[2];
-    tri_cofacets(g, anchor, tri_step(type, 0), tri_step(type, 1), cf, ok);
-    na[j] = ascend(g, G, tet2pos, cf[0], ok[0], flags);
-    nb[j] = ascend(g, G, tet2pos, cf[1], ok[1], flags);
 }
 
 __global__ void k_tet_positions(const uint32_t* __restrict__ c3, int64_t m, uint32_t* __restrict__ tet2pos) {
@@ -234,18 +295,23 @@ __global__ void k_settled(const uint64_t* __restrict__ bnd, const uint32_t* __re
 
 }  // namespace
 
+// persistent launches: enough workgroups to fill every CU, fewer for small inputs
+inline unsigned trace_blocks(int64_t paths) { return std::min(nblocks(paths), 4096u); }
+
 void trace_d0(const GridDev& g, const uint8_t* G, const uint32_t* rank, const uint32_t* c1, const uint32_t* pos,
-              int64_t m, uint32_t* na, uint32_t* nb, uint32_t* flags, hipStream_t st) {
+              int64_t m, uint32_t* na, uint32_t* nb, uint32_t* flags, unsigned long long* next, hipStream_t st) {
     if (m > 0)
-        hipLaunchKernelGGL(k_trace_d0, dim3(nblocks(m)), dim3(PB), 0, st, g, G, rank, c1, pos, m, na, nb, flags);
+        hipLaunchKernelGGL(k_trace_d0, dim3(trace_blocks(2 * m)), dim3(PB), 0, st, g, G, rank, c1, pos, m, na, nb,
+                           flags, next);
 }
 void tet_positions(const uint32_t* c3_sorted, int64_t m, uint32_t* tet2pos, hipStream_t st) {
     if (m > 0) hipLaunchKernelGGL(k_tet_positions, dim3(nblocks(m)), dim3(PB), 0, st, c3_sorted, m, tet2pos);
 }
 void trace_d2(const GridDev& g, const uint8_t* G, const uint32_t* tet2pos, const uint32_t* c2, const uint32_t* pos,
-              int64_t m, uint32_t* na, uint32_t* nb, uint32_t* flags, hipStream_t st) {
+              int64_t m, uint32_t* na, uint32_t* nb, uint32_t* flags, unsigned long long* next, hipStream_t st) {
     if (m > 0)
-        hipLaunchKernelGGL(k_trace_d2, dim3(nblocks(m)), dim3(PB), 0, st, g, G, tet2pos, c2, pos, m, na, nb, flags);
+        hipLaunchKernelGGL(k_trace_d2, dim3(trace_blocks(2 * m)), dim3(PB), 0, st, g, G, tet2pos, c2, pos, m, na, nb,
+                           flags, next);
 }
 void reduce_pairs(const uint32_t* na, const uint32_t* nb, int64_t m, uint32_t* owner, uint64_t* bnd,
                   uint32_t* flags, unsigned long long* stats, hipStream_t st) {
