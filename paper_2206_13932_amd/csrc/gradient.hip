@@ -8,8 +8,15 @@
 // neighbours, and the lexicographic order of Sec. 2.2 restricted to L(x) is
 // the integer order of these masks (the highest differing vertex decides; a
 // face is a mask missing only lower bits). Both priority queues are then
-// 74-bit slot sets whose minimum is found by comparing 14-bit keys held in
-// LDS, so the simulation is exact and needs no per-lane heap.
+// 74-bit slot sets whose minimum is found by comparing 14-bit keys computed
+// from the labels, so the simulation is exact and needs no per-lane heap.
+//
+// A workgroup owns 1024 consecutive vertices and hands them to its lanes in
+// order of lower-star size, so that the lanes of a wave, which run the
+// simulation in lockstep, have stars of similar size. The partner codes are
+// staged in LDS and written out per slot in vertex order (consecutive lanes,
+// consecutive bytes): byte stores scattered over the workgroup's span leave
+// the L2 as partial lines and multiply the write traffic several times.
 //
 // Output: gradient byte planes (see dms_device.h) and the critical cells of
 // each dimension appended, with their packed lexicographic keys, to per-
@@ -65,6 +72,7 @@ __device__ inline uint32_t wave_reserve(uint32_t cnt, uint32_t* counter) {
 __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_gradient(GridDev g, const uint32_t* __restrict__ rank,
                                                  uint8_t* __restrict__ G, int bpr, CritLists cl) {
     __shared__ LdsTables T;
+    __shared__ uint8_t scode[NSLOT * GB];  // partner code of each slot, by processing lane
     __shared__ uint32_t bins[NSLOT + 1];   // lanes per lower-star size, then bin offsets
     __shared__ uint16_t perm[GB];          // perm[lane] = the block-local vertex that lane processes
     const int tid = threadIdx.x;
@@ -92,7 +100,16 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     __syncthreads();
 
     const int64_t V = g.V;
-    const int64_t x0 = (int64_t)blockIdx.x * GB;
+    // Workgroups are dispatched to the 8 XCDs in turn; XCD k takes the k-th
+    // eighth of the grid, in order, so that neighbouring workgroups (which
+    // share cache lines of the gradient planes and of the order) meet in one
+    // L2. The map is a bijection for any grid size.
+    int64_t wg;
+    {
+        const int64_t n = gridDim.x, q = n / 8, r = n % 8, k = blockIdx.x % 8;
+        wg = k * q + (k < r ? k : r) + blockIdx.x / 8;
+    }
+    const int64_t x0 = wg * GB;
 
     // lower neighbours of vertex v (bit n: neighbour n exists and is lower);
     // r[n] receives the neighbours' ranks
@@ -132,6 +149,9 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     // lanes in order of lower-star size (a counting sort in LDS), which keeps
     // the stores of each slot inside the block's span.
     const int64_t xo = x0 + tid;
+    uint64_t own_lo = 0;
+    uint32_t own_hi = 0;
+    uint32_t own_lane;  // the lane that processes the own vertex
     {
         uint32_t ncell = 0;
         if (xo < V) {
@@ -147,10 +167,8 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
                 for (int t = 0; t < 6; ++t) G[(int64_t)(20 + t) * V + xo] = CODE_NONE;
             }
             if (lower) {
-                uint64_t in_lo;
-                uint32_t in_hi;
-                cells_of(lower, in_lo, in_hi);
-                ncell = (uint32_t)(popc64(in_lo) + __builtin_popcount(in_hi));
+                cells_of(lower, own_lo, own_hi);
+                ncell = (uint32_t)(popc64(own_lo) + __builtin_popcount(own_hi));
             }
         }
         const uint32_t within = atomicAdd(&bins[ncell], 1u);
@@ -164,9 +182,12 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
             }
         }
         __syncthreads();
-        perm[bins[ncell] + within] = (uint16_t)tid;
+        own_lane = bins[ncell] + within;
+        perm[own_lane] = (uint16_t)tid;
         __syncthreads();
     }
+
+#define CODE(s) scode[(s) * GB + tid]
 
     // ---- 2. the lower star of vertex perm[tid] (ProcessLowerStars) ----
     const int64_t x = x0 + perm[tid];
@@ -205,7 +226,7 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
                 const uint32_t q = T.knb[s];
                 return (1u << label(q & 15u)) | (1u << label((q >> 4) & 15u)) | (1u << label(q >> 8));
             };
-            auto gput = [&](int s, uint8_t code) { G[(int64_t)T.plane[s] * V + x + T.aofflin[s]] = code; };
+            auto gput = [&](int s, uint8_t code) { CODE(s) = code; };
             auto unpaired = [&](int s, uint64_t cls_lo) { return popc64(T.face[s] & ~cls_lo); };
             // pair (p, a): p is a facet of a; w = the neighbour of a not in p
             auto pair_cells = [&](int p, int a) {
@@ -288,6 +309,17 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
             }
         }
     }
+    __syncthreads();
+
+    // ---- 3. gradient codes of the own vertex's lower star: one store per slot,
+    // consecutive lanes -> consecutive bytes ----
+    {
+        const uint32_t col = own_lane;
+        for (int s = 0; s < NSLOT; ++s) {
+            const bool w = s < 64 ? ((own_lo >> s) & 1) : ((own_hi >> (s - 64)) & 1);
+            if (w) G[(int64_t)T.plane[s] * V + xo + T.aofflin[s]] = scode[s * GB + col];
+        }
+    }
 
     // ---- critical-cell lists of vertex x (all lanes take part in the wave scans) ----
     auto nbrank = [&](int n) {
@@ -365,6 +397,8 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
             ++at;
         }
     }
+#undef KEY
+#undef CODE
 }
 
 }  // namespace
