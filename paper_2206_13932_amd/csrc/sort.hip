@@ -43,12 +43,21 @@ __global__ __launch_bounds__(SB) void k_hist(const K* __restrict__ keys, int64_t
     hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
+// Stable scatter of one tile. Each element's rank among the tile's elements
+// with the same digit comes from ballot matching inside its wavefront and
+// per-wave running counts; the tile is then reordered by digit in LDS and
+// written out from there, so that consecutive lanes write consecutive
+// addresses of a digit's bucket (an element-order scatter writes 64
+// different buckets per store instruction).
 template <typename K>
 __global__ __launch_bounds__(SB) void k_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                K* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n,
                                                int shift, const uint32_t* __restrict__ offs, int64_t nblk) {
-    __shared__ uint32_t wcnt[WAVES][256];
-    __shared__ uint32_t woff[WAVES][256];
+    __shared__ uint32_t wcnt[WAVES][256];  // per-wave digit counts, then per-wave offsets in the digit
+    __shared__ uint32_t dstart[256];       // first tile position of each digit
+    __shared__ uint32_t wsum[WAVES];
+    __shared__ K sk[TILE];
+    __shared__ uint32_t sv[TILE];
     for (int i = threadIdx.x; i < WAVES * 256; i += SB) (&wcnt[0][0])[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * TILE;
@@ -81,12 +90,26 @@ __global__ __launch_bounds__(SB) void k_scatter(const K* __restrict__ kin, const
     }
     __syncthreads();
     {
+        // digit d = thread: offsets of the waves inside the digit, then the
+        // tile-wide exclusive scan over digits
         const int d = threadIdx.x;  // SB == 256 digits
         uint32_t acc = 0;
         for (int ww = 0; ww < WAVES; ++ww) {
-            woff[ww][d] = acc;
-            acc += wcnt[ww][d];
+            const uint32_t c = wcnt[ww][d];
+            wcnt[ww][d] = acc;
+            acc += c;
         }
+        uint32_t inc = acc;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += u;
+        }
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int ww = 0; ww < w; ++ww) before += wsum[ww];
+        dstart[d] = before + inc - acc;
     }
     __syncthreads();
 #pragma unroll
@@ -94,10 +117,19 @@ __global__ __launch_bounds__(SB) void k_scatter(const K* __restrict__ kin, const
         const int64_t i = base + w * WTILE + r * 64 + lane;
         if (i < n) {
             const uint32_t d = digit_of(kk[r], shift);
-            const int64_t dst = (int64_t)offs[(int64_t)d * nblk + blockIdx.x] + woff[w][d] + loc[r];
-            kout[dst] = kk[r];
-            vout[dst] = vv[r];
+            const uint32_t p = dstart[d] + wcnt[w][d] + loc[r];
+            sk[p] = kk[r];
+            sv[p] = vv[r];
         }
+    }
+    __syncthreads();
+    const int64_t cnt = n - base < TILE ? n - base : TILE;
+    for (int j = threadIdx.x; j < cnt; j += SB) {
+        const K k = sk[j];
+        const uint32_t d = digit_of(k, shift);
+        const int64_t dst = (int64_t)offs[(int64_t)d * nblk + blockIdx.x] + (j - dstart[d]);
+        kout[dst] = k;
+        vout[dst] = sv[j];
     }
 }
 
