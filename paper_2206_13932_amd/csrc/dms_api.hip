@@ -486,9 +486,9 @@ static int run_d0_d2(dms_ctx* ctx) {
     const int64_t m0 = ctx->ncrit[0], m1 = ctx->ncrit[1], m2 = ctx->ncrit[2], m3 = ctx->ncrit[3];
     HIPCHK(hipMemsetAsync(ctx->stats.p, 0, 64, st));
     unsigned long long* stats = P<unsigned long long>(ctx->stats);
-    // work counters of the two tracing kernels (bytes 32..47 of the counters)
+    // work counters of the tracing and reduction kernels (bytes 32..63 of the counters)
     unsigned long long* next = P<unsigned long long>(ctx->counters) + 4;
-    fill_u32(P<uint32_t>(ctx->counters) + 8, 0, 4, st);
+    fill_u32(P<uint32_t>(ctx->counters) + 8, 0, 8, st);
     // D0 (Sec. 5.1)
     ENSURE(ctx->na0, 4 * m1);
     ENSURE(ctx->nb0, 4 * m1);
@@ -500,7 +500,7 @@ static int run_d0_d2(dms_ctx* ctx) {
     fill_u32(P<uint32_t>(ctx->owner0), EMPTY32, V, st);
     fill_u64(P<uint64_t>(ctx->bnd0), EMPTY64, m1, st);
     reduce_pairs(P<uint32_t>(ctx->na0), P<uint32_t>(ctx->nb0), m1, P<uint32_t>(ctx->owner0), P<uint64_t>(ctx->bnd0),
-                 P<uint32_t>(ctx->flags), stats, st);
+                 P<uint32_t>(ctx->flags), stats, next + 2, st);
     settled_columns(P<uint64_t>(ctx->bnd0), P<uint32_t>(ctx->owner0), m1, P<uint8_t>(ctx->paired1), st);
     // D2 (Sec. 5.2), virtual maximum = age 0
     ENSURE(ctx->tet2pos, 4 * 6 * V);
@@ -515,7 +515,7 @@ static int run_d0_d2(dms_ctx* ctx) {
     fill_u32(P<uint32_t>(ctx->owner2), EMPTY32, m3 + 1, st);
     fill_u64(P<uint64_t>(ctx->bnd2), EMPTY64, m2, st);
     reduce_pairs(P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2), m2, P<uint32_t>(ctx->owner2), P<uint64_t>(ctx->bnd2),
-                 P<uint32_t>(ctx->flags), stats + 2, st);
+                 P<uint32_t>(ctx->flags), stats + 2, next + 3, st);
     settled_columns(P<uint64_t>(ctx->bnd2), P<uint32_t>(ctx->owner2), m2, P<uint8_t>(ctx->paired2), st);
     (void)m0;
     return DMS_OK;

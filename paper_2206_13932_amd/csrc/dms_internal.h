@@ -69,7 +69,7 @@ void tet_positions(const uint32_t* c3_sorted, int64_t m, uint32_t* tet2pos, hipS
 void trace_d2(const GridDev& g, const uint8_t* G, const uint32_t* tet2pos, const uint32_t* c2, const uint32_t* pos,
               int64_t m, uint32_t* na, uint32_t* nb, uint32_t* flags, unsigned long long* next, hipStream_t st);
 void reduce_pairs(const uint32_t* na, const uint32_t* nb, int64_t m, uint32_t* owner, uint64_t* bnd,
-                  uint32_t* flags, unsigned long long* stats, hipStream_t st);
+                  uint32_t* flags, unsigned long long* stats, unsigned long long* next, hipStream_t st);
 void settled_columns(const uint64_t* bnd, const uint32_t* owner, int64_t m, uint8_t* paired, hipStream_t st);
 
 // batch.hip: one box of the batch layout (origin in the super grid, source

@@ -231,24 +231,46 @@ __device__ inline bool cas32(uint32_t* p, uint32_t expect, uint32_t desired) {
                                                 __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void k_reduce_pairs(const uint32_t* __restrict__ na, const uint32_t* __restrict__ nb, int64_t m,
-                               uint32_t* owner, uint64_t* bnd, uint32_t* flags, unsigned long long* stats) {
-    const int64_t j = (int64_t)blockIdx.x * PB + threadIdx.x;
-    const bool live = j < m;  // every lane reaches the wavefront reduction below
-    uint32_t c = (uint32_t)j;
-    uint32_t p = live ? na[j] : 0, q = live ? nb[j] : 0;
-    if (p < q) { uint32_t t = p; p = q; q = t; }
+// Persistent like the tracing kernels: a lane whose column has settled (or
+// reduced to zero) takes the next column number from its wave's chunk.
+__global__ __launch_bounds__(PB) void k_reduce_pairs(const uint32_t* __restrict__ na,
+                                                     const uint32_t* __restrict__ nb, int64_t m, uint32_t* owner,
+                                                     uint64_t* bnd, uint32_t* flags, unsigned long long* stats,
+                                                     unsigned long long* next) {
     const int64_t limit = (int64_t)1 << 26;
     unsigned long long steps = 0, evictions = 0;
-    for (int64_t guard = 0; live; ++guard) {
-        if (guard > limit) { atomicOr(flags, FLAG_GUARD); break; }
-        if (p == q) break;  // column reduced to zero: a positive arc
+    bool have = false;
+    uint32_t c = 0, p = 0, q = 0;
+    int64_t k = 0, pb = 0, pe = 0, guard = 0;
+    for (;;) {
+        if (!take_path(!have, next, m, k, pb, pe)) break;
+        if (!have) {
+            c = (uint32_t)k;
+            p = na[k];
+            q = nb[k];
+            if (p < q) {
+                const uint32_t t = p;
+                p = q;
+                q = t;
+            }
+            guard = 0;
+            have = true;
+        }
+        if (++guard > limit) {
+            atomicOr(flags, FLAG_GUARD);
+            have = false;
+            continue;
+        }
+        if (p == q) {  // column reduced to zero: a positive arc
+            have = false;
+            continue;
+        }
         ++steps;
         const uint32_t o = ld_rlx(&owner[p]);
         if (o == EMPTY32) {
             st_rlx64(&bnd[c], ((uint64_t)p << 32) | q);
             wait_stores();
-            if (cas32(&owner[p], EMPTY32, c)) break;
+            if (cas32(&owner[p], EMPTY32, c)) have = false;  // settled
             continue;
         }
         if (o < c) {
@@ -261,7 +283,7 @@ __global__ void k_reduce_pairs(const uint32_t* __restrict__ na, const uint32_t* 
             continue;
         }
         // o > c: c is earlier and takes the pivot; the evicted column o is
-        // carried on by this thread.
+        // carried on by this lane.
         st_rlx64(&bnd[c], ((uint64_t)p << 32) | q);
         wait_stores();
         if (cas32(&owner[p], o, c)) {
@@ -314,9 +336,10 @@ void trace_d2(const GridDev& g, const uint8_t* G, const uint32_t* tet2pos, const
                            flags, next);
 }
 void reduce_pairs(const uint32_t* na, const uint32_t* nb, int64_t m, uint32_t* owner, uint64_t* bnd,
-                  uint32_t* flags, unsigned long long* stats, hipStream_t st) {
+                  uint32_t* flags, unsigned long long* stats, unsigned long long* next, hipStream_t st) {
     if (m > 0)
-        hipLaunchKernelGGL(k_reduce_pairs, dim3(nblocks(m)), dim3(PB), 0, st, na, nb, m, owner, bnd, flags, stats);
+        hipLaunchKernelGGL(k_reduce_pairs, dim3(trace_blocks(m)), dim3(PB), 0, st, na, nb, m, owner, bnd, flags,
+                           stats, next);
 }
 void settled_columns(const uint64_t* bnd, const uint32_t* owner, int64_t m, uint8_t* paired, hipStream_t st) {
     if (m > 0) hipLaunchKernelGGL(k_settled, dim3(nblocks(m)), dim3(PB), 0, st, bnd, owner, m, paired);
