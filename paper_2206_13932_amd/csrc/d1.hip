@@ -950,7 +950,7 @@ struct Col {
 };
 
 // Merge pend into low: sort and cancel it in LDS, then one low merge.
-__device__ void flush(WideShared& L, Col& C, uint64_t* low, const uint64_t* pend, uint64_t* tmp,
+__device__ __forceinline__ void flush(WideShared& L, Col& C, uint64_t* low, const uint64_t* pend, uint64_t* tmp,
                       unsigned long long& moved) {
     if (C.np == 0) return;
     const uint32_t t = threadIdx.x;
@@ -982,11 +982,13 @@ __device__ void flush(WideShared& L, Col& C, uint64_t* low, const uint64_t* pend
 // to pend (which is flushed first when they would not fit), the others are
 // merged into the top, which spills its smaller entries to low when it
 // outgrows TOPCAP.
-__device__ void merge_col(WideShared& L, Col& C, uint64_t* low, uint64_t* pend, uint32_t m, uint64_t* tmp,
-                          unsigned long long& moved, uint64_t* ph, uint64_t& tp) {
-    auto lap = [&](int i) {
+// t_low and t_top accumulate the time of the two parts (100 MHz clock ticks
+// since tp, which is advanced).
+__device__ __forceinline__ void merge_col(WideShared& L, Col& C, uint64_t* low, uint64_t* pend, uint32_t m, uint64_t* tmp,
+                          unsigned long long& moved, uint64_t& t_low, uint64_t& t_top, uint64_t& tp) {
+    auto lap = [&](uint64_t& acc) {
         const uint64_t now = __builtin_amdgcn_s_memrealtime();
-        if (ph) ph[i] += now - tp;
+        acc += now - tp;
         tp = now;
     };
     if (m == 0) return;
@@ -1000,7 +1002,7 @@ __device__ void merge_col(WideShared& L, Col& C, uint64_t* low, uint64_t* pend, 
         for (uint32_t i = t; i < s0; i += WB) pend[C.np + i] = L.src[i];
         C.np += s0;
         __syncthreads();  // L.src is rewritten by the caller next
-        lap(4);
+        lap(t_low);
     }
     if (s0 < m) {
         uint32_t sp;
@@ -1015,13 +1017,13 @@ __device__ void merge_col(WideShared& L, Col& C, uint64_t* low, uint64_t* pend, 
         C.nt = r - sp;
         C.cur ^= 1;
         __syncthreads();  // L.u64s[0] read by all before it is written again
-        lap(5);
+        lap(t_top);
     }
 }
 
 // Load a boundary stored decreasingly at src[0..len): the largest TOPKEEP
 // entries into the top, the rest into low.
-__device__ void load_col(WideShared& L, Col& C, uint64_t* low, const uint64_t* src, uint32_t len) {
+__device__ __forceinline__ void load_col(WideShared& L, Col& C, uint64_t* low, const uint64_t* src, uint32_t len) {
     const uint32_t t = threadIdx.x;
     C.nt = min(len, (uint32_t)TOPKEEP);
     C.nl = len - C.nt;
@@ -1058,7 +1060,7 @@ __device__ void load_col(WideShared& L, Col& C, uint64_t* low, const uint64_t* s
 
 // Flush pend, then move the largest low entries below the top until it holds
 // TOPKEEP more entries (or low is empty).
-__device__ void refill(WideShared& L, Col& C, uint64_t* low, const uint64_t* pend, uint64_t* tmp,
+__device__ __forceinline__ void refill(WideShared& L, Col& C, uint64_t* low, const uint64_t* pend, uint64_t* tmp,
                        unsigned long long& moved) {
     flush(L, C, low, pend, tmp, moved);
     if (C.nl == 0) return;
@@ -1078,7 +1080,7 @@ __device__ void refill(WideShared& L, Col& C, uint64_t* low, const uint64_t* pen
 // Flush pend and save the boundary (C.n() entries afterwards) to the
 // publication heap in the decreasing layout; returns the offset or PAD when
 // the heap is full.
-__device__ uint64_t save_col(const D1K& P, WideShared& L, Col& C, uint64_t* low, const uint64_t* pend,
+__device__ __forceinline__ uint64_t save_col(const D1K& P, WideShared& L, Col& C, uint64_t* low, const uint64_t* pend,
                              uint64_t* tmp, unsigned long long& moved) {
     flush(L, C, low, pend, tmp, moved);
     const uint32_t t = threadIdx.x;
@@ -1104,7 +1106,7 @@ __device__ uint64_t save_col(const D1K& P, WideShared& L, Col& C, uint64_t* low,
 // last keys, so equal keys are always in the same step and every step
 // consumes a full segment of one side. Adding a long boundary in NW-key
 // chunks instead rewrites the low part once per chunk.
-__device__ void add_long(const D1K& P, WideShared& L, Col& C, uint64_t*& low, uint64_t*& tmp, const uint64_t* pend,
+__device__ __forceinline__ void add_long(const D1K& P, WideShared& L, Col& C, uint64_t*& low, uint64_t*& tmp, const uint64_t* pend,
                          uint64_t aoff, uint32_t alen, unsigned long long& moved) {
     const uint32_t t = threadIdx.x;
     flush(L, C, low, pend, tmp, moved);
@@ -1369,7 +1371,7 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
                     break;
                 }
                 C.nt -= stop_at;  // the window entries above the stop leave
-                merge_col(L, C, low, pend, m, tmp, moved, ph, tp);
+                merge_col(L, C, low, pend, m, tmp, moved, ph[4], ph[5], tp);
                 nmax = max(nmax, C.n());
                 continue;
             }
@@ -1490,7 +1492,8 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
                 }
                 __syncthreads();
                 uint64_t tq = 0;
-                merge_col(L, C, low, pend, m, tmp, moved, nullptr, tq);
+                uint64_t u0 = 0, u1 = 0;
+                merge_col(L, C, low, pend, m, tmp, moved, u0, u1, tq);
             }
             nmax = max(nmax, C.n());
             lap(7);
