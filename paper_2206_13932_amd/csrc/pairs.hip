@@ -107,10 +107,11 @@ __device__ inline bool in_grid(const GridDev& g, int64_t anchor, int mask_total,
     return fits(g, x, y, z, mask_total);
 }
 
-// The two tetrahedra containing triangle (anchor; A, B); ok[i] false if outside.
-__device__ inline void tri_cofacets(const GridDev& g, int64_t anchor, int A, int B, Simp out[2], bool ok[2]) {
-    int x, y, z;
-    coords_of(g, anchor, x, y, z);
+// The two tetrahedra containing triangle (anchor; A, B), whose anchor has
+// coordinates (x, y, z); ok[i] false if outside. out[0] is anchored at
+// anchor - lin_of_mask(C) when the triangle spans two steps, else at anchor.
+__device__ inline void tri_cofacets_at(const GridDev& g, int64_t anchor, int x, int y, int z, int A, int B,
+                                       Simp out[2], bool ok[2]) {
     const int pa = __builtin_popcount(A), pb = __builtin_popcount(B);
     if (pa + pb == 3) {
         if (pa == 2) {
@@ -132,6 +133,12 @@ __device__ inline void tri_cofacets(const GridDev& g, int64_t anchor, int A, int
     out[0] = {anchor - lin_of_mask(g, C), tet_type(C, A, B)};
     ok[1] = fits(g, x, y, z, 7);
     out[1] = {anchor, tet_type(A, B, C)};
+}
+
+__device__ inline void tri_cofacets(const GridDev& g, int64_t anchor, int A, int B, Simp out[2], bool ok[2]) {
+    int x, y, z;
+    coords_of(g, anchor, x, y, z);
+    tri_cofacets_at(g, anchor, x, y, z, A, B, out, ok);
 }
 
 // Triangle of tet (anchor; s0, s1, s2) opposite chain vertex i.
@@ -158,6 +165,7 @@ __global__ __launch_bounds__(PB) void k_trace_d2(GridDev g, const uint8_t* __res
     bool have = false, ok = false;
     int64_t steps = 0, k = 0, pb = 0, pe = 0;
     Simp T{0, 0};
+    int tx = 0, ty = 0, tz = 0;  // coordinates of T.anchor, followed step by step
     uint32_t* out = nullptr;
     for (;;) {
         if (!take_path(!have, next, 2 * m, k, pb, pe)) break;
@@ -171,6 +179,7 @@ __global__ __launch_bounds__(PB) void k_trace_d2(GridDev g, const uint8_t* __res
             const int side = (int)(k & 1);
             T = cf[side];
             ok = cok[side];
+            coords_of(g, T.anchor, tx, ty, tz);
             out = (side ? nb : na) + (m - 1 - (int64_t)pos[i]);
             steps = 0;
             have = true;
@@ -196,12 +205,24 @@ __global__ __launch_bounds__(PB) void k_trace_d2(GridDev g, const uint8_t* __res
         int64_t ta;
         int A, B;
         tet_facet(g, T.anchor, T.type, c & 3, ta, A, B);
+        if (ta != T.anchor) {  // the facet without chain vertex 0 starts one step further
+            const int s0 = tet_step(T.type, 0);
+            tx += s0 & 1;
+            ty += (s0 >> 1) & 1;
+            tz += (s0 >> 2) & 1;
+        }
         Simp cf[2];
         bool cok[2];
-        tri_cofacets(g, ta, A, B, cf, cok);
+        tri_cofacets_at(g, ta, tx, ty, tz, A, B, cf, cok);
         const bool first_is_T = cf[0].anchor == T.anchor && cf[0].type == T.type;
         const int o = first_is_T ? 1 : 0;
         ok = cok[o];
+        if (cf[o].anchor != ta) {  // anchored one step below: anchor - lin_of_mask(C)
+            const int C = 7 ^ (A | B);
+            tx -= C & 1;
+            ty -= (C >> 1) & 1;
+            tz -= (C >> 2) & 1;
+        }
         T = cf[o];
     }
 }
