@@ -275,6 +275,7 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
     uint64_t tau = 0;
     int64_t guard = 0;
     uint32_t retries = 0;
+    int64_t pb = 0, pe = 0;  // the wavefront's chunk of column numbers
 
     // one step of column c: 0 = go on, 1 = the column is done, 2 = error
     auto step = [&]() -> int {
@@ -382,53 +383,43 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
     };
 
     for (;;) {
-        // lanes without a column take the next ones: one atomic per wavefront.
-        // Columns are taken in increasing order: the frontier of columns in
-        // flight stays narrow, which keeps evictions rare
+        // lanes without a column take the next ones, from chunks of 128
+        // consecutive columns per wavefront. Columns are taken in increasing
+        // order: the frontier of columns in flight stays narrow, which keeps
+        // evictions rare
         const bool need = !active && !exhausted && !stop;
-        const uint64_t ball = __ballot(need);
-        if (ball) {
-            const int leader = __builtin_ctzll(ball);
-            uint64_t base = 0;
-            if (lane == leader) base = atomicAdd(&P.ctrs[C_NEXT], (unsigned long long)__popcll(ball));
-            const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)base, leader, 64);
-            const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(base >> 32), leader, 64);
-            base = ((uint64_t)hi << 32) | lo;
-            if (need) {
-                const int64_t next = (int64_t)(base + __popcll(ball & ((1ull << lane) - 1)));
-                if (next >= P.nwork) {
-                    exhausted = true;
+        int64_t next = 0;
+        if (!wave_take<128>(need, &P.ctrs[C_NEXT], P.nwork, next, pb, pe)) {
+            exhausted = true;
+        } else if (need) {
+            H.n = 0;
+            have = false;
+            guard = 0;
+            retries = 0;
+            active = true;
+            if (!P.work) {
+                c = (uint32_t)next;
+                const uint32_t t = P.cols[c];
+                const int64_t a = t / 12;
+                const int ty = t % 12;
+                const int64_t v1 = a + lin_of_mask(P.g, tri_step(ty, 0));
+                const int64_t v2 = v1 + lin_of_mask(P.g, tri_step(ty, 1));
+                const uint32_t r0 = P.rank[a], r1 = P.rank[v1], r2 = P.rank[v2];
+                H.push(ekey_r(P.bpr, r0, r1));
+                H.push(ekey_r(P.bpr, r1, r2));
+                H.push(ekey_r(P.bpr, r0, r2));
+            } else {
+                // resume a deferred column from its saved, decreasing boundary
+                c = P.work_col[next];
+                const uint64_t off = P.work[next];
+                const int64_t len = P.work_len[next];
+                if (len > H.K) {
+                    atomicOr(P.flags, FLAG_WORK);
+                    active = false;
+                    stop = true;
                 } else {
-                    H.n = 0;
-                    have = false;
-                    guard = 0;
-                    retries = 0;
-                    active = true;
-                    if (!P.work) {
-                        c = (uint32_t)next;
-                        const uint32_t t = P.cols[c];
-                        const int64_t a = t / 12;
-                        const int ty = t % 12;
-                        const int64_t v1 = a + lin_of_mask(P.g, tri_step(ty, 0));
-                        const int64_t v2 = v1 + lin_of_mask(P.g, tri_step(ty, 1));
-                        const uint32_t r0 = P.rank[a], r1 = P.rank[v1], r2 = P.rank[v2];
-                        H.push(ekey_r(P.bpr, r0, r1));
-                        H.push(ekey_r(P.bpr, r1, r2));
-                        H.push(ekey_r(P.bpr, r0, r2));
-                    } else {
-                        // resume a deferred column from its saved, decreasing boundary
-                        c = P.work_col[next];
-                        const uint64_t off = P.work[next];
-                        const int64_t len = P.work_len[next];
-                        if (len > H.K) {
-                            atomicOr(P.flags, FLAG_WORK);
-                            active = false;
-                            stop = true;
-                        } else {
-                            for (int64_t i = 0; i < len; ++i) H.at(i) = ld_rlx64(P.heap + off + i);
-                            H.n = len;
-                        }
-                    }
+                    for (int64_t i = 0; i < len; ++i) H.at(i) = ld_rlx64(P.heap + off + i);
+                    H.n = len;
                 }
             }
         }

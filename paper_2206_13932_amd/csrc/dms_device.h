@@ -114,4 +114,35 @@ struct StarTables {
     uint8_t type[NSLOT];
 };
 
+// Persistent work distribution: lanes that are idle take the next work item
+// numbers in order. Each wave draws chunks of CHUNK consecutive numbers from
+// the global counter *next (one atomic per chunk, not per step: a counter
+// hit by every wave at every step serialises the kernel); [pb, pe) is the
+// wave's remaining chunk, identical in all its lanes (pass zeros at the
+// start). Idle lanes get k; returns false for a lane whose number is past
+// total (its work is exhausted). Every active lane of the wave must call it.
+template <int64_t CHUNK>
+__device__ inline bool wave_take(bool idle, unsigned long long* next, int64_t total, int64_t& k, int64_t& pb,
+                                 int64_t& pe) {
+    static_assert(CHUNK >= 64, "one refill must serve a whole wave");
+    const uint64_t need = __ballot(idle);
+    if (need == 0) return true;
+    const int lane = threadIdx.x & 63;
+    const int64_t cnt = __popcll(need), avail = pe - pb;
+    const int64_t r = __popcll(need & ((1ull << lane) - 1));
+    if (avail >= cnt) {
+        if (idle) k = pb + r;
+        pb += cnt;
+    } else {
+        const int leader = __builtin_ctzll(need);
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(next, (unsigned long long)CHUNK);
+        const int64_t nb = (int64_t)__shfl(base, leader, 64);
+        if (idle) k = r < avail ? pb + r : nb + (r - avail);
+        pb = nb + (cnt - avail);
+        pe = nb + CHUNK;
+    }
+    return !idle || k < total;
+}
+
 }  // namespace dms

@@ -30,35 +30,15 @@ inline unsigned nblocks(int64_t n) { return (unsigned)((n + PB - 1) / PB); }
 
 constexpr int64_t PATH_GUARD = (int64_t)1 << 22;
 
-// Paths are handed out one at a time (two per critical cell): a lane whose
-// path has ended takes the next one, so the lanes of a wave stay busy until
-// the work runs out instead of waiting for the wave's longest path. Each wave
-// draws chunks of PCHUNK consecutive path numbers from a global counter (one
-// atomic per chunk) and its lanes take them in order, so neighbouring cells
-// go to neighbouring lanes (the gradient kernel lists them in grid order) and
-// their v-paths share cache lines. [pb, pe) is the wave's remaining chunk
-// (the same in every lane). Returns false when the lane's work is exhausted.
-constexpr int64_t PCHUNK = 256;
+// Paths are handed out one at a time (two per critical cell) by wave_take
+// (dms_device.h): a lane whose path has ended takes the next one, so the
+// lanes of a wave stay busy until the work runs out instead of waiting for
+// the wave's longest path; neighbouring cells still go to neighbouring lanes
+// (the gradient kernel lists them in grid order), so their v-paths share
+// cache lines.
 __device__ inline bool take_path(bool idle, unsigned long long* next, int64_t total, int64_t& k, int64_t& pb,
                                  int64_t& pe) {
-    const uint64_t need = __ballot(idle);
-    if (need == 0) return true;
-    const int lane = threadIdx.x & 63;
-    const int64_t cnt = __popcll(need), avail = pe - pb;
-    const int64_t r = __popcll(need & ((1ull << lane) - 1));
-    if (avail >= cnt) {
-        if (idle) k = pb + r;
-        pb += cnt;
-    } else {
-        const int leader = __builtin_ctzll(need);
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(next, (unsigned long long)PCHUNK);
-        const int64_t nb = (int64_t)__shfl(base, leader, 64);
-        if (idle) k = r < avail ? pb + r : nb + (r - avail);
-        pb = nb + (cnt - avail);
-        pe = nb + PCHUNK;
-    }
-    return !idle || k < total;
+    return wave_take<256>(idle, next, total, k, pb, pe);
 }
 
 // D0: path 2i + s descends from vertex s of critical edge c1[i] to a minimum;
