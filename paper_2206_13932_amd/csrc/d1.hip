@@ -1641,8 +1641,6 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         if (grow(s.heap, s.heap_cap, std::max<size_t>((size_t)8 << 22, (size_t)8 * 32 * ncols), s.bytes))
             return oom("boundary heap");
     }
-    const int64_t lanes = (int64_t)1 << 18;  // first pass: 262144 threads x 256 entries
-    const int64_t k0 = 256;
     if (in.m1 > 0)
         hipLaunchKernelGGL(k_init_owner, dim3(nblocks(in.m1)), dim3(DB), 0, st, in.c1, in.paired1, in.m1,
                            (uint32_t*)s.owner1);
@@ -1669,7 +1667,11 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         // global scratch), then one workgroup per column with boundaries of up to
         // plan_k entries (lengths stay below 2^24: the cached length field)
         int64_t plan_k[MAX_PASSES] = {LDS_K, LDS_K2, (int64_t)1 << 15, (int64_t)1 << 20, ((int64_t)1 << 24) - 1024};
-        int64_t plan_t[MAX_PASSES] = {lanes, lanes, 1024, 256, 16};
+        // lane passes: as many lanes as the LDS heaps leave resident (160 KB
+        // per CU: 5 workgroups of 256 lanes x 16 keys, or 5 of 64 lanes x 64
+        // keys); workgroup passes: workgroups
+        int64_t plan_t[MAX_PASSES] = {256 * 5 * 256, 256 * 5 * 64, 1024, 256, 16};
+        const int plan_db[MAX_PASSES] = {256, 64, WB, WB, WB};
         uint32_t long_add = LONG_ADD;
         const int lane_passes = 2;  // passes 0 and 1 are thread-per-column
         if (std::getenv("DMS_D1_TEST_PLAN")) {  // test hook: tiny capacities, every pass used
@@ -1720,7 +1722,8 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
                 return -5;
             }
             if (lane_pass)
-                hipLaunchKernelGGL(k_d1, dim3(nblocks(T)), dim3(DB), in_lds ? (size_t)8 * DB * K : 0, st, P);
+                hipLaunchKernelGGL(k_d1, dim3((unsigned)((T + plan_db[pass] - 1) / plan_db[pass])),
+                                   dim3(plan_db[pass]), in_lds ? (size_t)8 * plan_db[pass] * K : 0, st, P);
             else
                 hipLaunchKernelGGL(k_d1_wide, dim3((unsigned)T), dim3(WB), 0, st, P);
             uint32_t f = 0;
