@@ -122,10 +122,11 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
             const int dx = kStar.nbv[n][0], dy = kStar.nbv[n][1], dz = kStar.nbv[n][2];
             const bool in = (unsigned)(cx + dx) < (unsigned)g.nx && (unsigned)(cy + dy) < (unsigned)g.ny &&
                             (unsigned)(cz + dz) < (unsigned)g.nz;
-            uint32_t q = 0xFFFFFFFFu;
-            if (in) q = rank[v + dx + dy * g.sy + dz * g.sz];
-            r[n] = q;
-            if (in && q < rv) lower |= 1u << n;
+            // an outside neighbour reads the vertex itself, so that the 14 loads
+            // are unconditional and in flight together
+            const uint32_t q = rank[in ? v + dx + dy * g.sy + dz * g.sz : v];
+            r[n] = in ? q : 0xFFFFFFFFu;
+            lower |= ((uint32_t)in & (uint32_t)(q < rv)) << n;  // no branch: no load is sunk into one
         }
         return lower;
     };
