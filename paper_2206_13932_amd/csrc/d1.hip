@@ -45,6 +45,7 @@ constexpr uint32_t OWN_D0 = 0xFFFFFFFEu;
 constexpr uint64_t NONE = ~0ull;
 constexpr int MAX_PASSES = 5;
 constexpr int LDS_K = 16;   // keys per thread in the first pass (LDS heaps)
+constexpr int SMALL_K = LDS_K;  // heaps up to this size are compacted by a sorting network
 constexpr int LDS_K2 = 64;  // ... and in the second
 constexpr uint32_t MAX_RETRIES = 1u << 16;  // consecutive look-agains before a column is declared corrupt
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + DB - 1) / DB); }
@@ -203,6 +204,45 @@ struct Heap {
         for (int64_t i = 0; i < out; ++i) at(i) = at(n0 - out + i);
         n = out;
     }
+    // The same for heaps of at most SMALL_K keys, without branches: the keys
+    // are sorted in registers by a bitonic network (every index is a
+    // compile-time constant), equal keys are adjacent and cancel in pairs.
+    // A wavefront runs this when any of its lanes publishes a boundary, which
+    // on the first pass is nearly every step, so its cost must not depend on
+    // the lane's heap.
+    __device__ void compact_small() {
+        uint64_t a[SMALL_K];
+#pragma unroll
+        for (int i = 0; i < SMALL_K; ++i) a[i] = i < n ? at(i) : 0;  // keys are never 0
+#pragma unroll
+        for (int k = 2; k <= SMALL_K; k <<= 1) {
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+                for (int i = 0; i < SMALL_K; ++i) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        // descending where (i & k) == 0, ascending elsewhere: the
+                        // last merge (k = SMALL_K) leaves the whole array descending
+                        const bool desc = (i & k) == 0;
+                        const uint64_t x = a[i], y = a[l];
+                        const bool sw = desc ? x < y : x > y;
+                        a[i] = sw ? y : x;
+                        a[l] = sw ? x : y;
+                    }
+                }
+            }
+        }
+        int64_t out = 0;
+        int start = 0;
+#pragma unroll
+        for (int i = 0; i < SMALL_K; ++i) {
+            if (i > 0 && a[i] != a[i - 1]) start = i;
+            const bool last = i == SMALL_K - 1 || a[i + 1 < SMALL_K ? i + 1 : i] != a[i];
+            if (a[i] != 0 && last && ((i - start) & 1) == 0) at(out++) = a[i];  // odd run: keep one
+        }
+        n = out;
+    }
     __device__ bool room(int64_t extra) {
         if (n + extra <= K) return true;
         compact();
@@ -226,7 +266,8 @@ __device__ inline uint64_t heap_alloc(const D1K& P, uint32_t seg, uint64_t len) 
 // Copy {top (optional)} + heap (compacted) to the publication heap; returns
 // the packed (offset << 24 | length) or NONE when the heap is full.
 __device__ inline uint64_t publish(const D1K& P, Heap& H, bool with_top, uint64_t top) {
-    H.compact();
+    if (H.K <= SMALL_K) H.compact_small();
+    else H.compact();
     const uint64_t len = (uint64_t)H.n + (with_top ? 1 : 0);
     if (len >= (1ull << 24)) return NONE;
     const uint64_t off = heap_alloc(P, (uint32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), len);
@@ -1542,7 +1583,7 @@ __global__ void k_emit_pairs(GridDev g, const uint32_t* order, int bpr, const ui
     if (b == EMPTY64) return;
     const EdgeDec e = edecode(g, order, bpr, heap[b >> 24]);
     if (owner1[e.id] != (uint32_t)c) return;
-    const uint32_t at = atomicAdd(cnt, 1u);
+    const uint32_t at = wave_append(true, cnt);
     key[at] = e.id;
     death[at] = cols[c];
 }
@@ -1552,7 +1593,7 @@ __global__ void k_emit_ess1(const uint32_t* c1, const uint8_t* paired1, int64_t 
     const int64_t i = (int64_t)blockIdx.x * DB + threadIdx.x;
     if (i >= m1 || paired1[i]) return;
     if (owner1[c1[i]] != EMPTY32) return;
-    const uint32_t at = atomicAdd(cnt, 1u);
+    const uint32_t at = wave_append(true, cnt);
     key[at] = (1ull << 32) | c1[i];
     death[at] = EMPTY32;
 }
@@ -1567,7 +1608,7 @@ __global__ void k_emit_ess2(GridDev g, const uint32_t* order, int bpr, const uin
         const EdgeDec e = edecode(g, order, bpr, heap[b >> 24]);
         if (owner1[e.id] == (uint32_t)c) return;
     }
-    const uint32_t at = atomicAdd(cnt, 1u);
+    const uint32_t at = wave_append(true, cnt);
     key[at] = (1ull << 32) | cols[c];
     death[at] = EMPTY32;
 }

@@ -138,18 +138,18 @@ __global__ void k_emit_d0(const uint64_t* bnd, const uint8_t* paired, const uint
                           int64_t m1, const uint32_t* c0, const uint32_t* rank, const uint32_t* owner0, int64_t m0,
                           uint64_t* key, uint32_t* death, uint32_t* cnt) {
     const int64_t i = (int64_t)blockIdx.x * OB + threadIdx.x;
-    if (i < m1 && paired[i]) {
-        const uint32_t at = atomicAdd(cnt, 1u);
+    const bool pair = i < m1 && paired[i];
+    const uint32_t at = wave_append(pair, cnt);
+    if (pair) {
         key[at] = order[(uint32_t)(bnd[i] >> 32)];
         death[at] = c1[i];
     }
-    if (i < m0) {
-        const uint32_t v = c0[i];
-        if (owner0[rank[v]] == EMPTY32) {
-            const uint32_t at = atomicAdd(cnt, 1u);
-            key[at] = (1ull << 32) | v;
-            death[at] = EMPTY32;
-        }
+    const uint32_t v = i < m0 ? c0[i] : 0u;
+    const bool ess = i < m0 && owner0[rank[v]] == EMPTY32;
+    const uint32_t at2 = wave_append(ess, cnt);
+    if (ess) {
+        key[at2] = (1ull << 32) | v;
+        death[at2] = EMPTY32;
     }
 }
 
@@ -159,7 +159,7 @@ __global__ void k_emit_d2(const uint64_t* bnd, const uint8_t* paired, const uint
     const int64_t j = (int64_t)blockIdx.x * OB + threadIdx.x;
     if (j >= m2 || !paired[j]) return;
     const uint32_t pos = (uint32_t)(bnd[j] >> 32);  // 1 = highest maximum
-    const uint32_t at = atomicAdd(cnt, 1u);
+    const uint32_t at = wave_append(true, cnt);
     key[at] = c2[m2 - 1 - j];
     death[at] = c3[m3 - pos];
 }

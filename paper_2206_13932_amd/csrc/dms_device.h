@@ -145,4 +145,19 @@ __device__ inline bool wave_take(bool idle, unsigned long long* next, int64_t to
     return !idle || k < total;
 }
 
+// Reserve one entry of the list counted by *cnt for every lane that calls
+// this with pred set: one atomic per wavefront instead of one per lane (a
+// single counter hit by every lane serialises the kernel). The lanes that
+// call it together must be converged; lanes that have returned take no part.
+__device__ inline uint32_t wave_append(bool pred, uint32_t* cnt) {
+    const uint64_t b = __ballot(pred);
+    if (b == 0) return 0;
+    const int lane = threadIdx.x & 63;
+    const int leader = __builtin_ctzll(b);
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(cnt, (uint32_t)__popcll(b));
+    base = __shfl(base, leader, 64);
+    return base + (uint32_t)__popcll(b & ((1ull << lane) - 1));
+}
+
 }  // namespace dms
