@@ -45,7 +45,6 @@ constexpr uint32_t OWN_D0 = 0xFFFFFFFEu;
 constexpr uint64_t NONE = ~0ull;
 constexpr int MAX_PASSES = 5;
 constexpr int LDS_K = 16;   // keys per thread in the first pass (LDS heaps)
-constexpr int SMALL_K = LDS_K;  // heaps up to this size are compacted by a sorting network
 constexpr int LDS_K2 = 64;  // ... and in the second
 constexpr uint32_t MAX_RETRIES = 1u << 16;  // consecutive look-agains before a column is declared corrupt
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + DB - 1) / DB); }
@@ -204,45 +203,6 @@ struct Heap {
         for (int64_t i = 0; i < out; ++i) at(i) = at(n0 - out + i);
         n = out;
     }
-    // The same for heaps of at most SMALL_K keys, without branches: the keys
-    // are sorted in registers by a bitonic network (every index is a
-    // compile-time constant), equal keys are adjacent and cancel in pairs.
-    // A wavefront runs this when any of its lanes publishes a boundary, which
-    // on the first pass is nearly every step, so its cost must not depend on
-    // the lane's heap.
-    __device__ void compact_small() {
-        uint64_t a[SMALL_K];
-#pragma unroll
-        for (int i = 0; i < SMALL_K; ++i) a[i] = i < n ? at(i) : 0;  // keys are never 0
-#pragma unroll
-        for (int k = 2; k <= SMALL_K; k <<= 1) {
-#pragma unroll
-            for (int j = k >> 1; j > 0; j >>= 1) {
-#pragma unroll
-                for (int i = 0; i < SMALL_K; ++i) {
-                    const int l = i ^ j;
-                    if (l > i) {
-                        // descending where (i & k) == 0, ascending elsewhere: the
-                        // last merge (k = SMALL_K) leaves the whole array descending
-                        const bool desc = (i & k) == 0;
-                        const uint64_t x = a[i], y = a[l];
-                        const bool sw = desc ? x < y : x > y;
-                        a[i] = sw ? y : x;
-                        a[l] = sw ? x : y;
-                    }
-                }
-            }
-        }
-        int64_t out = 0;
-        int start = 0;
-#pragma unroll
-        for (int i = 0; i < SMALL_K; ++i) {
-            if (i > 0 && a[i] != a[i - 1]) start = i;
-            const bool last = i == SMALL_K - 1 || a[i + 1 < SMALL_K ? i + 1 : i] != a[i];
-            if (a[i] != 0 && last && ((i - start) & 1) == 0) at(out++) = a[i];  // odd run: keep one
-        }
-        n = out;
-    }
     __device__ bool room(int64_t extra) {
         if (n + extra <= K) return true;
         compact();
@@ -263,11 +223,15 @@ __device__ inline uint64_t heap_alloc(const D1K& P, uint32_t seg, uint64_t len) 
     return NONE;
 }
 
-// Copy {top (optional)} + heap (compacted) to the publication heap; returns
-// the packed (offset << 24 | length) or NONE when the heap is full.
+// Copy {top (optional)} + the heap array as it stands to the publication
+// heap; returns the packed (offset << 24 | length) or NONE when the heap is
+// full. The copy is neither sorted nor cancelled (the lane's wavefront runs
+// this whenever any of its lanes claims, so it must be short): entries after
+// the head form a valid max-heap and count mod 2. Lane passes read such
+// boundaries as heaps; the workgroup passes sort and cancel every boundary of
+// up to NW entries they load (longer ones come only from workgroup passes,
+// which publish them sorted and cancelled).
 __device__ inline uint64_t publish(const D1K& P, Heap& H, bool with_top, uint64_t top) {
-    if (H.K <= SMALL_K) H.compact_small();
-    else H.compact();
     const uint64_t len = (uint64_t)H.n + (with_top ? 1 : 0);
     if (len >= (1ull << 24)) return NONE;
     const uint64_t off = heap_alloc(P, (uint32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), len);
@@ -450,7 +414,7 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
                 H.push(ekey_r(P.bpr, r1, r2));
                 H.push(ekey_r(P.bpr, r0, r2));
             } else {
-                // resume a deferred column from its saved, decreasing boundary
+                // resume a deferred column from its saved boundary
                 c = P.work_col[next];
                 const uint64_t off = P.work[next];
                 const int64_t len = P.work_len[next];
@@ -459,8 +423,8 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
                     active = false;
                     stop = true;
                 } else {
-                    for (int64_t i = 0; i < len; ++i) H.at(i) = ld_rlx64(P.heap + off + i);
-                    H.n = len;
+                    // a saved boundary is {tau} + a heap array: pushed entry by entry
+                    for (int64_t i = 0; i < len; ++i) H.push(ld_rlx64(P.heap + off + i));
                 }
             }
         }
@@ -1053,10 +1017,20 @@ __device__ __forceinline__ void merge_col(WideShared& L, Col& C, uint64_t* low, 
     }
 }
 
-// Load a boundary stored decreasingly at src[0..len): the largest TOPKEEP
-// entries into the top, the rest into low.
+// Load a boundary stored at src[0..len): the largest TOPKEEP entries into the
+// top, the rest into low. One of more than NW entries is stored decreasing
+// and cancelled; a shorter one is sorted and cancelled here.
 __device__ __forceinline__ void load_col(WideShared& L, Col& C, uint64_t* low, const uint64_t* src, uint32_t len) {
     const uint32_t t = threadIdx.x;
+    if (len <= (uint32_t)NW) {  // possibly a lane pass's unsorted copy: sort and cancel it
+        for (uint32_t i = t; i < len; i += WB) L.raw[i] = ld_rlx64(src + i);
+        __syncthreads();
+        C.nt = sort_cancel(L, len, L.top[C.cur]);
+        C.nl = 0;
+        C.np = 0;
+        C.lmax = 0;
+        return;
+    }
     C.nt = min(len, (uint32_t)TOPKEEP);
     C.nl = len - C.nt;
     C.np = 0;
@@ -1149,13 +1123,22 @@ __device__ __forceinline__ void add_long(const D1K& P, WideShared& L, Col& C, ui
         C.nt = 0;
     }
     __syncthreads();
+    // a boundary of up to NW entries may be a lane pass's unsorted copy: it is
+    // sorted and cancelled into L.src once; a longer one is stored decreasing
+    const bool small = alen <= (uint32_t)NW;
+    uint32_t nb = alen;
+    if (small) {
+        for (uint32_t k = t; k < alen; k += WB) L.raw[k] = ld_rlx64(P.heap + aoff + k);
+        __syncthreads();
+        nb = sort_cancel(L, alen, L.src);
+    }
     const uint32_t na = C.nl;
     uint64_t* X = L.top[0];
     uint32_t i = 0, j = 0, out = 0;
-    while (i < na || j < alen) {
-        const uint32_t la = min((uint32_t)TOPCAP, na - i), lb = min((uint32_t)NW, alen - j);
+    while (i < na || j < nb) {
+        const uint32_t la = min((uint32_t)TOPCAP, na - i), lb = min((uint32_t)NW, nb - j);
         stage(X, low + i, la);
-        {
+        if (!small) {
             uint64_t v[IPW];
 #pragma unroll
             for (int q = 0; q < IPW; ++q) {
@@ -1169,13 +1152,14 @@ __device__ __forceinline__ void add_long(const D1K& P, WideShared& L, Col& C, ui
             }
         }
         __syncthreads();
+        const uint64_t* S = small ? L.src + j : L.src;  // this step's segment of the boundary
         uint64_t bound = PAD;  // keys are below PAD
         if (i + la < na) bound = X[la - 1];
-        if (j + lb < alen) bound = min(bound, L.src[lb - 1]);
+        if (j + lb < nb) bound = min(bound, S[lb - 1]);
         const uint32_t ta = bound == PAD ? la : count_less<uint64_t>(X, la, bound + 1);
-        const uint32_t tb = bound == PAD ? lb : count_less<uint64_t>(L.src, lb, bound + 1);
+        const uint32_t tb = bound == PAD ? lb : count_less<uint64_t>(S, lb, bound + 1);
         uint32_t sp;
-        out += merge_seg(L, X, ta, L.src, tb, tmp + out, nullptr, 0, 0, sp);
+        out += merge_seg(L, X, ta, S, tb, tmp + out, nullptr, 0, 0, sp);
         __syncthreads();
         i += ta;
         j += tb;
@@ -1505,6 +1489,16 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
             if (alen > P.long_add) {
                 ++longs;
                 add_long(P, L, C, low, tmp, pend, aoff, alen, moved);
+                nmax = max(nmax, C.n());
+                lap(7);
+                continue;
+            }
+            if (alen <= (uint32_t)NW) {  // possibly unsorted: sort and cancel, then merge
+                for (uint32_t k = t; k < alen; k += WB) L.raw[k] = ld_rlx64(P.heap + aoff + k);
+                __syncthreads();
+                const uint32_t m = sort_cancel(L, alen, L.src);
+                uint64_t tq = 0, u0 = 0, u1 = 0;
+                merge_col(L, C, low, pend, m, tmp, moved, u0, u1, tq);
                 nmax = max(nmax, C.n());
                 lap(7);
                 continue;
