@@ -18,26 +18,36 @@ DEFAULT_SPACE = {
 }
 
 
-def autotune(requests, space=None, device: int = 0, repeats: int = 1):
+def autotune(requests, space=None, device: int = 0, repeats: int = 1, rate: float | None = None,
+             headroom: float = 1.5):
     """requests: serving.Request list (their arrival times are ignored).
-    Returns (best ServerConfig, [(config dict, requests/s)])."""
+    Without a rate, picks the configuration of highest capacity. With the
+    expected arrival rate (requests/s), picks the smallest per-batch vertex
+    budget -- the shortest batches, hence the lowest latency -- among the
+    configurations whose capacity is at least headroom x rate (the highest
+    capacity if none is), ties broken by capacity.
+    Returns (chosen ServerConfig, [(config dict, requests/s)])."""
     space = space or DEFAULT_SPACE
     keys = list(space)
     table = []
-    best = None
+    configs = []
     for values in itertools.product(*(space[k] for k in keys)):
         kw = dict(zip(keys, values))
         workers, use_graph = kw.pop("workers_graph")
         cfg = serving.ServerConfig(workers=workers, use_graph=use_graph, **kw)
         server = serving.Server(cfg, device)
         try:
-            rate = 0.0
+            server_rate = 0.0
             for _ in range(repeats + 1):  # the first run warms the context up
                 reqs = [serving.Request(r.rid, 0.0, r.host_field) for r in requests]
-                rate = server.run_trace(reqs).req_per_s
+                server_rate = server.run_trace(reqs).req_per_s
         finally:
             server.close()
-        table.append((dict(zip(keys, values)), rate))
-        if best is None or rate > best[1]:
-            best = (cfg, rate)
+        table.append((dict(zip(keys, values)), server_rate))
+        configs.append((cfg, server_rate))
+    best = max(configs, key=lambda cc: cc[1])
+    if rate is not None:
+        ok = [cc for cc in configs if cc[1] >= headroom * rate]
+        if ok:
+            best = min(ok, key=lambda cc: (cc[0].budget_vertices, -cc[1]))
     return best[0], table

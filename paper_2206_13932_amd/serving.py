@@ -81,6 +81,22 @@ class Server:
         for c in self.ctxs:
             c.close()
 
+    def warmup(self, requests: list[Request]):
+        """Run the given requests (arrival times ignored) through every
+        worker's context once before serving, so that the device buffers a
+        batch needs are allocated before the first real request arrives."""
+        for w, (ctx, stream) in enumerate(zip(self.ctxs, self.streams)):
+            with torch.cuda.stream(stream):
+                batch = [Request(r.rid, 0.0, r.host_field) for r in requests]
+                self.queue.extend(batch)
+                while self.queue:
+                    with self.lock:
+                        take = self._take_batch()
+                    dev = [r.host_field.to(f"cuda:{self.device}", non_blocking=True) for r in take]
+                    ctx.diagram_batch(dev, cross=self.cfg.cross, z_quantum=self.cfg.z_quantum,
+                                      use_graph=self.cfg.use_graph)
+            stream.synchronize()
+
     # ---- admission ----
     def _take_batch(self) -> list[Request]:
         """Called with the lock held and the queue non-empty: FIFO requests
