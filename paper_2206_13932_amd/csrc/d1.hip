@@ -1188,7 +1188,12 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
         const uint64_t next = L.u64s[0];
         __syncthreads();
         if ((int64_t)next >= P.nwork) break;
-        uint32_t c = P.work_col[next];
+        // Deferred columns are taken last-deferred first: the column that ran
+        // longest in the previous pass before outgrowing it tends to be the
+        // longest here too, and its chain of rounds then starts with the pass
+        // instead of after thousands of short columns (smooth512: 43 -> 35 ms).
+        const uint64_t wi = (uint64_t)P.nwork - 1 - next;
+        uint32_t c = P.work_col[wi];
         const uint64_t t0 = __builtin_amdgcn_s_memrealtime();  // 100 MHz clock
         // time per phase (thread 0): window, sort, round merge, owner rule, additions, claims
         uint64_t ph[N_PHASE] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -1203,8 +1208,8 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
         Col C;
         C.cur = 0;
         {
-            const uint64_t off = P.work[next];
-            const uint32_t n0 = P.work_len[next];
+            const uint64_t off = P.work[wi];
+            const uint32_t n0 = P.work_len[wi];
             if ((int64_t)n0 > P.K) {
                 if (t == 0) atomicOr(P.flags, FLAG_WORK);
                 break;
