@@ -695,9 +695,12 @@ __device__ uint32_t merge_seg(WideShared& L, const uint64_t* X, uint32_t len, co
 // TOPCAP entries of low are staged in LDS (in stg); when the suffix lies
 // inside them it is merged straight back. A longer suffix is found by a block
 // search and merged segment by segment (TOPCAP entries each, with the keys
-// below the next segment's first key) into tmp, then copied back.
-__device__ uint32_t merge_low(WideShared& L, uint64_t* low, uint32_t n, const uint64_t* S, uint32_t m,
-                              uint64_t* tmp, uint64_t* stg, unsigned long long& moved) {
+// below the next segment's first key) into tmp. Then either the merged
+// suffix is copied back, or, when the unchanged prefix is shorter, the prefix
+// is copied in front of it and the two buffers swap roles.
+__device__ __forceinline__ uint32_t merge_low(WideShared& L, uint64_t*& low, uint32_t n, const uint64_t* S,
+                                              uint32_t m, uint64_t*& tmp, uint64_t* stg,
+                                              unsigned long long& moved) {
     const uint32_t t = threadIdx.x;
     if (m == 0) return n;
     uint32_t sp;
@@ -714,6 +717,8 @@ __device__ uint32_t merge_low(WideShared& L, uint64_t* low, uint32_t n, const ui
     const uint32_t p = count_less_block(L, low, n, S[0]);
     uint64_t* Bp = low + p;
     const uint32_t len = n - p;
+    const bool swap = p < len;
+    uint64_t* dst = swap ? tmp + p : tmp;
     moved += len;
     uint32_t out = 0, j0 = 0;
     for (uint32_t sb = 0; sb < len; sb += TOPCAP) {
@@ -722,9 +727,29 @@ __device__ uint32_t merge_low(WideShared& L, uint64_t* low, uint32_t n, const ui
         uint32_t ja = m;
         if (sb + sl < len) ja = j0 + count_less<uint64_t>(S + j0, m - j0, Bp[sb + sl]);
         __syncthreads();
-        out += merge_seg(L, stg, sl, S + j0, ja - j0, tmp + out, nullptr, 0, 0, sp);
+        out += merge_seg(L, stg, sl, S + j0, ja - j0, dst + out, nullptr, 0, 0, sp);
         __syncthreads();
         j0 = ja;
+    }
+    if (swap) {
+        for (uint32_t base = 0; base < p; base += 8 * WB) {
+            uint64_t v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t i = base + q * WB + t;
+                v[q] = i < p ? low[i] : 0;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t i = base + q * WB + t;
+                if (i < p) tmp[i] = v[q];
+            }
+        }
+        __syncthreads();
+        uint64_t* w = low;
+        low = tmp;
+        tmp = w;
+        return p + out;
     }
     for (uint32_t base = 0; base < out; base += 8 * WB) {
         uint64_t v[8];
@@ -946,7 +971,7 @@ struct Col {
 };
 
 // Merge pend into low: sort and cancel it in LDS, then one low merge.
-__device__ __forceinline__ void flush(WideShared& L, Col& C, uint64_t* low, const uint64_t* pend, uint64_t* tmp,
+__device__ __forceinline__ void flush(WideShared& L, Col& C, uint64_t*& low, const uint64_t* pend, uint64_t*& tmp,
                       unsigned long long& moved) {
     if (C.np == 0) return;
     const uint32_t t = threadIdx.x;
@@ -980,7 +1005,7 @@ __device__ __forceinline__ void flush(WideShared& L, Col& C, uint64_t* low, cons
 // outgrows TOPCAP.
 // t_low and t_top accumulate the time of the two parts (100 MHz clock ticks
 // since tp, which is advanced).
-__device__ __forceinline__ void merge_col(WideShared& L, Col& C, uint64_t* low, uint64_t* pend, uint32_t m, uint64_t* tmp,
+__device__ __forceinline__ void merge_col(WideShared& L, Col& C, uint64_t*& low, uint64_t* pend, uint32_t m, uint64_t*& tmp,
                           unsigned long long& moved, uint64_t& t_low, uint64_t& t_top, uint64_t& tp) {
     auto lap = [&](uint64_t& acc) {
         const uint64_t now = __builtin_amdgcn_s_memrealtime();
@@ -1066,7 +1091,7 @@ __device__ __forceinline__ void load_col(WideShared& L, Col& C, uint64_t* low, c
 
 // Flush pend, then move the largest low entries below the top until it holds
 // TOPKEEP more entries (or low is empty).
-__device__ __forceinline__ void refill(WideShared& L, Col& C, uint64_t* low, const uint64_t* pend, uint64_t* tmp,
+__device__ __forceinline__ void refill(WideShared& L, Col& C, uint64_t*& low, const uint64_t* pend, uint64_t*& tmp,
                        unsigned long long& moved) {
     flush(L, C, low, pend, tmp, moved);
     if (C.nl == 0) return;
@@ -1086,8 +1111,8 @@ __device__ __forceinline__ void refill(WideShared& L, Col& C, uint64_t* low, con
 // Flush pend and save the boundary (C.n() entries afterwards) to the
 // publication heap in the decreasing layout; returns the offset or PAD when
 // the heap is full.
-__device__ __forceinline__ uint64_t save_col(const D1K& P, WideShared& L, Col& C, uint64_t* low, const uint64_t* pend,
-                             uint64_t* tmp, unsigned long long& moved) {
+__device__ __forceinline__ uint64_t save_col(const D1K& P, WideShared& L, Col& C, uint64_t*& low, const uint64_t* pend,
+                             uint64_t*& tmp, unsigned long long& moved) {
     flush(L, C, low, pend, tmp, moved);
     const uint32_t t = threadIdx.x;
     const uint32_t n = C.n();
