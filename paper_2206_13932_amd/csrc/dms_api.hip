@@ -680,6 +680,14 @@ int dms_diagram(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t flag
     return DMS_OK;
 }
 
+// the tetrahedra of the gradient storage (by id) -> 6 planes indexed by anchor
+__global__ void k_tet_planes(const uint8_t* __restrict__ by_id, int64_t V, uint8_t* __restrict__ planes) {
+    const int64_t i = (int64_t)blockIdx.x * OB + threadIdx.x;
+    if (i >= 6 * V) return;
+    const int64_t type = i / V, anchor = i - type * V;
+    planes[i] = by_id[anchor * 6 + type];
+}
+
 int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap) {
     if (!ctx) return DMS_E_INVAL;
     const int64_t V = ctx->g.V;
@@ -745,6 +753,15 @@ int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap) {
             HIPCHK(hipMemcpyAsync(h + m, b.p, 4 * m, hipMemcpyDeviceToHost, ctx->st));
             HIPCHK(hipStreamSynchronize(ctx->st));
         }
+        return bytes;
+    }
+    if (what == DMS_BUF_GRADIENT && V > 0) {  // the tetrahedra go out as planes, like the rest
+        ENSURE(ctx->keysB, 6 * V);
+        hipLaunchKernelGGL(k_tet_planes, dim3(nb_of(6 * V)), dim3(OB), 0, ctx->st, P<uint8_t>(ctx->G) + 20 * V, V,
+                           P<uint8_t>(ctx->keysB));
+        HIPCHK(hipMemcpyAsync(dst, src, 20 * V, hipMemcpyDeviceToHost, ctx->st));
+        HIPCHK(hipMemcpyAsync((uint8_t*)dst + 20 * V, ctx->keysB.p, 6 * V, hipMemcpyDeviceToHost, ctx->st));
+        HIPCHK(hipStreamSynchronize(ctx->st));
         return bytes;
     }
     if (bytes) HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->st));

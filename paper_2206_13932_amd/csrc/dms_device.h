@@ -7,9 +7,11 @@
 // pairwise disjoint axis sets (3-bit masks: bit0 = x, bit1 = y, bit2 = z).
 // Simplex id = anchor * T_k + type with anchor = w0 and T = {1, 7, 12, 6}.
 //
-// Discrete gradient storage: 26 byte planes of V bytes each, indexed by the
-// anchor vertex: plane 0 = vertices, 1..7 = edge types, 8..19 = triangle
-// types, 20..25 = tetrahedron types. A byte holds the partner of the simplex:
+// Discrete gradient storage, 26 V bytes: 20 byte planes of V bytes each,
+// indexed by the anchor vertex (plane 0 = vertices, 1..7 = edge types, 8..19 =
+// triangle types), then one byte per tetrahedron id (anchor * 6 + type): the
+// tetrahedra of a cube, which a D2 v-path visits in turn, share a cache line
+// (tet_code_at). A byte holds the partner of the simplex:
 //   c < 27      partner = cofacet obtained by adding vertex anchor + off27(c),
 //               off27(c) = (c%3-1, c/3%3-1, c/9-1)
 //   0x80 | i    partner = facet obtained by removing the chain vertex i
@@ -25,7 +27,12 @@ constexpr int NSLOT = 74;   // cells of the open star of a vertex: 14 + 36 + 24
 constexpr int NNB = 14;     // Freudenthal neighbours
 constexpr uint8_t CODE_CRIT = 0xFF;
 constexpr uint8_t CODE_NONE = 0xFE;
-constexpr int PLANES = 26;
+constexpr int PLANES = 26;  // V bytes each; the last 6 are the tetrahedra by id
+
+// byte of tetrahedron (anchor, type) in the gradient storage
+__host__ __device__ constexpr int64_t tet_code_at(int64_t V, int64_t anchor, int type) {
+    return 20 * V + anchor * 6 + type;
+}
 
 __host__ __device__ constexpr int ntypes(int dim) { return dim == 0 ? 1 : dim == 1 ? 7 : dim == 2 ? 12 : 6; }
 __host__ __device__ constexpr int plane_base(int dim) { return dim == 0 ? 0 : dim == 1 ? 1 : dim == 2 ? 8 : 20; }

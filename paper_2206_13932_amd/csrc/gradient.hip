@@ -165,7 +165,7 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
                     if (!fits(g, cx, cy, cz, t + 1)) G[(int64_t)(1 + t) * V + xo] = CODE_NONE;
                 for (int t = 0; t < 12; ++t)
                     if (!fits(g, cx, cy, cz, tri_step(t, 0) | tri_step(t, 1))) G[(int64_t)(8 + t) * V + xo] = CODE_NONE;
-                for (int t = 0; t < 6; ++t) G[(int64_t)(20 + t) * V + xo] = CODE_NONE;
+                for (int t = 0; t < 6; ++t) G[tet_code_at(V, xo, t)] = CODE_NONE;
             }
             if (lower) {
                 cells_of(lower, own_lo, own_hi);
@@ -318,7 +318,11 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         const uint32_t col = own_lane;
         for (int s = 0; s < NSLOT; ++s) {
             const bool w = s < 64 ? ((own_lo >> s) & 1) : ((own_hi >> (s - 64)) & 1);
-            if (w) G[(int64_t)T.plane[s] * V + xo + T.aofflin[s]] = scode[s * GB + col];
+            if (w) {
+                const int pl = T.plane[s];  // the same in every lane
+                const int64_t a = xo + T.aofflin[s];
+                G[pl < 20 ? (int64_t)pl * V + a : tet_code_at(V, a, pl - 20)] = scode[s * GB + col];
+            }
         }
     }
 

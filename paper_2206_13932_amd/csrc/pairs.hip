@@ -176,7 +176,7 @@ __global__ __launch_bounds__(PB) void k_trace_d2(GridDev g, const uint8_t* __res
             continue;
         }
         ++steps;
-        const uint8_t c = G[(int64_t)(20 + T.type) * V + T.anchor];
+        const uint8_t c = G[tet_code_at(V, T.anchor, T.type)];
         if (c == CODE_CRIT) {
             *out = tet2pos[T.anchor * 6 + T.type];
             have = false;
