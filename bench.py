@@ -32,8 +32,8 @@ HBM_PEAK_GBS = 8000.0
 # Counters of one gradient-kernel launch on smooth512 (profiles/gradient_hbm_counters_smooth512.md),
 # valid for the kernel sources with this hash only: HBM bytes from FETCH_SIZE (x2 calibration) and
 # WRITE_SIZE, and the VALU wave instructions issued
-GRADIENT_COUNTERS = {"sources_sha256_16": "779f3bb3e031e9f7", "workload": "smooth512",
-                     "traffic_bytes": 2430708981 + 6838408755, "valu_wave_insts": 28233932215}
+GRADIENT_COUNTERS = {"sources_sha256_16": "d1c889b7ec20c5db", "workload": "smooth512",
+                     "traffic_bytes": 2488373489 + 6853847040, "valu_wave_insts": 29239834601}
 # VALU issue ceiling: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per 2 cycles per SIMD
 VALU_PEAK_WINST_S = 256 * 4 * 2.4e9 / 2
 
