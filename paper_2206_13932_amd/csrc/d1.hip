@@ -116,6 +116,23 @@ struct EdgeDec {
     int mask;
     uint32_t id;
 };
+// the same when the endpoints' vertex ids are known (va of rank ra, vb of rb)
+__device__ inline EdgeDec edecode_ids(const GridDev& g, int bpr, uint64_t key, int64_t va, int64_t vb) {
+    EdgeDec e;
+    e.ra = (uint32_t)(key >> bpr);
+    e.rb = (uint32_t)(key & ((1ull << bpr) - 1));
+    e.va = va;
+    e.vb = vb;
+    e.lo = e.va < e.vb ? e.va : e.vb;
+    int64_t d = (e.va < e.vb ? e.vb : e.va) - e.lo;
+    int m = 0;
+    if (d >= g.sz) { m |= 4; d -= g.sz; }
+    if (d >= g.sy) { m |= 2; d -= g.sy; }
+    if (d >= 1) { m |= 1; }
+    e.mask = m;
+    e.id = (uint32_t)(e.lo * 7 + (m - 1));
+    return e;
+}
 __device__ inline EdgeDec edecode(const GridDev& g, const uint32_t* order, int bpr, uint64_t key) {
     EdgeDec e;
     e.ra = (uint32_t)(key >> bpr);
@@ -281,6 +298,10 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
     int64_t guard = 0;
     uint32_t retries = 0;
     int64_t pb = 0, pe = 0;  // the wavefront's chunk of column numbers
+    // keys of the last two edges pushed by an expansion, with their endpoints
+    // (va: the endpoint of the higher rank)
+    uint64_t hint_key[2] = {NONE, NONE};
+    int64_t hint_va[2] = {0, 0}, hint_vb[2] = {0, 0};
 
     // one step of column c: 0 = go on, 1 = the column is done, 2 = error
     auto step = [&]() -> int {
@@ -294,7 +315,12 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
             if (tau == NONE) return 1;  // zero column
             have = true;
         }
-        const EdgeDec e = edecode(P.g, P.order, P.bpr, tau);
+        // The two edges an expansion pushes are often the next top (the v-path
+        // goes on): their vertex ids are kept, which saves the order lookups,
+        // one dependent global load, on the lane's chain of loads.
+        const EdgeDec e = tau == hint_key[0]   ? edecode_ids(P.g, P.bpr, tau, hint_va[0], hint_vb[0])
+                          : tau == hint_key[1] ? edecode_ids(P.g, P.bpr, tau, hint_va[1], hint_vb[1])
+                                               : edecode(P.g, P.order, P.bpr, tau);
         if (e.mask == 0) {  // not an edge: corrupted key
             atomicOr(P.flags, FLAG_GUARD);
             return 2;
@@ -310,8 +336,14 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
             if (H.room(2)) {
                 have = false;  // tau cancels against the boundary of its partner
                 const uint32_t rw = P.rank[w];
-                H.push(ekey_r(P.bpr, e.ra, rw));
-                H.push(ekey_r(P.bpr, e.rb, rw));
+                hint_key[0] = ekey_r(P.bpr, e.ra, rw);
+                hint_key[1] = ekey_r(P.bpr, e.rb, rw);
+                hint_va[0] = e.ra > rw ? e.va : w;
+                hint_vb[0] = e.ra > rw ? w : e.va;
+                hint_va[1] = e.rb > rw ? e.vb : w;
+                hint_vb[1] = e.rb > rw ? w : e.vb;
+                H.push(hint_key[0]);
+                H.push(hint_key[1]);
                 return 0;
             }
             defer = true;
