@@ -37,14 +37,17 @@ __host__ __device__ constexpr int64_t tet_code_at(int64_t V, int64_t anchor, int
 __host__ __device__ constexpr int ntypes(int dim) { return dim == 0 ? 1 : dim == 1 ? 7 : dim == 2 ? 12 : 6; }
 __host__ __device__ constexpr int plane_base(int dim) { return dim == 0 ? 0 : dim == 1 ? 1 : dim == 2 ? 8 : 20; }
 
-// Step tables (axis masks) of each simplex type.
+// Step tables (axis masks) of each simplex type, packed 3 bits per step so
+// that a lookup is a shift; per type (s0 | s1 << 4 | s2 << 8):
+//   triangles  0x21 0x41 0x61 0x12 0x42 0x52 0x43 0x14 0x24 0x34 0x25 0x16
+//   tetrahedra 0x421 0x241 0x412 0x142 0x214 0x124
 __host__ __device__ inline int tri_step(int type, int s) {
-    const uint8_t t[12] = {0x21, 0x41, 0x61, 0x12, 0x42, 0x52, 0x43, 0x14, 0x24, 0x34, 0x25, 0x16};
-    return s == 0 ? (t[type] & 15) : (t[type] >> 4);
+    const uint64_t lo = 0x714323aa22b1851ull, hi = 0x395ull;  // types 0..9, 10..11: 6 bits each
+    const uint64_t w = type < 10 ? lo >> (6 * type) : hi >> (6 * (type - 10));
+    return (int)((w >> (3 * s)) & 7);
 }
 __host__ __device__ inline int tet_step(int type, int s) {
-    const uint16_t t[6] = {0x421, 0x241, 0x412, 0x142, 0x214, 0x124};
-    return (t[type] >> (4 * s)) & 15;
+    return (int)((0xa88c314294311ull >> (9 * type + 3 * s)) & 7);  // 9 bits per type
 }
 __host__ __device__ inline int tri_type(int a, int b) {
     // inverse of tri_step: (A, B) -> type, -1 if not a triangle step pair
@@ -52,10 +55,11 @@ __host__ __device__ inline int tri_type(int a, int b) {
         if (tri_step(t, 0) == a && tri_step(t, 1) == b) return t;
     return -1;
 }
+// inverse of tet_step for a chain of single-axis steps (a, b, c), a
+// permutation of 1, 2, 4: two types per first step, the second of them when
+// the second step is the larger of the two left
 __host__ __device__ inline int tet_type(int a, int b, int c) {
-    for (int t = 0; t < 6; ++t)
-        if (tet_step(t, 0) == a && tet_step(t, 1) == b && tet_step(t, 2) == c) return t;
-    return -1;
+    return 2 * (a == 1 ? 0 : a == 2 ? 1 : 2) + (b > c ? 1 : 0);
 }
 
 struct GridDev {
