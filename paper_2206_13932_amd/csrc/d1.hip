@@ -1767,7 +1767,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         // lane passes: as many lanes as the LDS heaps leave resident (160 KB
         // per CU: 5 workgroups of 256 lanes x 16 keys, or 5 of 64 lanes x 64
         // keys); workgroup passes: workgroups
-        int64_t plan_t[MAX_PASSES] = {256 * 5 * 256, 256 * 5 * 64, 1024, 256, 16};
+        int64_t plan_t[MAX_PASSES] = {256 * 5 * 256, 256 * 5 * 64, 1024, 512, 64};
         const int plan_db[MAX_PASSES] = {256, 64, WB, WB, WB};
         uint32_t long_add = LONG_ADD;
         const int lane_passes = 2;  // passes 0 and 1 are thread-per-column
