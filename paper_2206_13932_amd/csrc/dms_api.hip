@@ -37,7 +37,7 @@ struct dms_ctx {
     int64_t ncrit[4] = {0, 0, 0, 0};
     uint32_t cap[4] = {0, 0, 0, 0};
     Buf rank, keysA, keysB, valsA, valsB, G, hist, part, flags, counters, stats;
-    Buf cid[4], ck[4], ck2[4];  // unsorted critical ids and keys (hi / lo)
+    Buf cid[4], ck[4];          // unsorted critical ids and their keys (CritLists)
     Buf csorted[4];             // ids sorted by the lexicographic order
     Buf cpos[4];                // cpos[d][i] = sorted position of cid[d][i] (d = 1, 2)
     uint32_t* order = nullptr;  // rank -> vertex (inside valsA / valsB)
@@ -227,27 +227,11 @@ static int sort_ids(dms_ctx* ctx, int d) {
         int r = radix_sort_pairs<uint32_t>(P<uint32_t>(ctx->ck[0]), P<uint32_t>(ctx->valsA), P<uint32_t>(ctx->keysA),
                                            P<uint32_t>(ctx->valsB), m, 0, bpr, true, hist, part, st);
         perm = r ? P<uint32_t>(ctx->valsB) : P<uint32_t>(ctx->valsA);
-    } else if (d == 1) {
-        int r = radix_sort_pairs<uint64_t>(P<uint64_t>(ctx->ck[1]), P<uint32_t>(ctx->valsA), P<uint64_t>(ctx->keysA),
-                                           P<uint32_t>(ctx->valsB), m, 0, 2 * bpr, true, hist, part, st);
-        perm = r ? P<uint32_t>(ctx->valsB) : P<uint32_t>(ctx->valsA);
     } else {
-        // two stable passes: low part first, then high part
-        const bool tri = d == 2;
-        int r;
-        if (tri)
-            r = radix_sort_pairs<uint32_t>(P<uint32_t>(ctx->ck2[2]), P<uint32_t>(ctx->valsA), P<uint32_t>(ctx->keysA),
-                                           P<uint32_t>(ctx->valsB), m, 0, bpr, true, hist, part, st);
-        else
-            r = radix_sort_pairs<uint64_t>(P<uint64_t>(ctx->ck2[3]), P<uint32_t>(ctx->valsA), P<uint64_t>(ctx->keysA),
-                                           P<uint32_t>(ctx->valsB), m, 0, 2 * bpr, true, hist, part, st);
-        uint32_t* p1 = r ? P<uint32_t>(ctx->valsB) : P<uint32_t>(ctx->valsA);
-        uint32_t* p1_other = r ? P<uint32_t>(ctx->valsA) : P<uint32_t>(ctx->valsB);
-        // hi keys in permuted order -> keysB (as u64)
-        gather_u64(P<uint64_t>(ctx->ck[d]), p1, P<uint64_t>(ctx->keysB), m, st);
-        int r2 = radix_sort_pairs<uint64_t>(P<uint64_t>(ctx->keysB), p1, P<uint64_t>(ctx->keysA), p1_other, m, 0,
-                                            2 * bpr, false, hist, part, st);
-        perm = r2 ? p1_other : p1;
+        // rank of the highest vertex, then 4-bit labels of the others (CritLists)
+        int r = radix_sort_pairs<uint64_t>(P<uint64_t>(ctx->ck[d]), P<uint32_t>(ctx->valsA), P<uint64_t>(ctx->keysA),
+                                           P<uint32_t>(ctx->valsB), m, 0, bpr + 4 * d, true, hist, part, st);
+        perm = r ? P<uint32_t>(ctx->valsB) : P<uint32_t>(ctx->valsA);
     }
     gather_u32(P<uint32_t>(ctx->cid[d]), perm, P<uint32_t>(ctx->csorted[d]), m, st);
     if (d == 1 || d == 2) {
@@ -338,7 +322,6 @@ void dms_destroy(dms_ctx* ctx) {
     for (int d = 0; d < 4; ++d) {
         if (ctx->cid[d].p) (void)hipFree(ctx->cid[d].p);
         if (ctx->ck[d].p) (void)hipFree(ctx->ck[d].p);
-        if (ctx->ck2[d].p) (void)hipFree(ctx->ck2[d].p);
         if (ctx->csorted[d].p) (void)hipFree(ctx->csorted[d].p);
         if (ctx->cpos[d].p) (void)hipFree(ctx->cpos[d].p);
     }
@@ -379,7 +362,6 @@ static int gradient_setup(dms_ctx* ctx, dms_grid grid) {
             ctx->cap[d] = (uint32_t)std::min<int64_t>(V / (d == 0 || d == 3 ? 4 : 2) + 256, 0xF0000000ll);
         ENSURE(ctx->cid[d], 4ull * ctx->cap[d]);
         ENSURE(ctx->ck[d], (d == 0 ? 4ull : 8ull) * ctx->cap[d]);
-        if (d >= 2) ENSURE(ctx->ck2[d], (d == 2 ? 4ull : 8ull) * ctx->cap[d]);
     }
     ctx->order = P<uint32_t>(ctx->ob);
     return DMS_OK;
@@ -407,11 +389,9 @@ static void gradient_enqueue(dms_ctx* ctx, const float* d_field, bool events) {
     cl.id1 = P<uint32_t>(ctx->cid[1]);
     cl.key1 = P<uint64_t>(ctx->ck[1]);
     cl.id2 = P<uint32_t>(ctx->cid[2]);
-    cl.key2hi = P<uint64_t>(ctx->ck[2]);
-    cl.key2lo = P<uint32_t>(ctx->ck2[2]);
+    cl.key2 = P<uint64_t>(ctx->ck[2]);
     cl.id3 = P<uint32_t>(ctx->cid[3]);
-    cl.key3hi = P<uint64_t>(ctx->ck[3]);
-    cl.key3lo = P<uint64_t>(ctx->ck2[3]);
+    cl.key3 = P<uint64_t>(ctx->ck[3]);
     fill_u32(P<uint32_t>(ctx->counters), 0, 4, st);
     if (events) record(ctx, EV_GK);
     launch_gradient(ctx->g, P<uint32_t>(ctx->rank), P<uint8_t>(ctx->G), ctx->bpr, cl, st);
@@ -885,7 +865,6 @@ int dms_diagram_batch(dms_ctx* ctx, const float* d_fields, const dms_item* items
             for (int d = 0; d < 4; ++d) {
                 sig.push_back(ctx->cid[d].p);
                 sig.push_back(ctx->ck[d].p);
-                sig.push_back(ctx->ck2[d].p);
             }
             dms_ctx::GraphEntry* hit = nullptr;
             for (auto& e : ctx->graphs)

@@ -16,6 +16,11 @@ namespace dms {
 //   C0 key = rank; C1 key = (r0 << bpr) | r1;
 //   C2 key = hi (r0 << bpr) | r1, lo r2; C3 key = hi (r0 << bpr) | r1, lo (r2 << bpr) | r3
 // with r0 > r1 > r2 > r3 the vertex ranks in decreasing order.
+// Critical cells with their keys in the lexicographic order. A cell's key is
+// the rank of its highest vertex x, then the labels (rank order among the
+// lower neighbours of x, 4 bits each) of its other vertices, highest first:
+// a vertex key has bpr bits, an edge key bpr + 4, a triangle key bpr + 8 and
+// a tetrahedron key bpr + 12.
 struct CritLists {
     uint32_t* count;  // 4 device counters
     uint32_t cap[4];
@@ -24,11 +29,9 @@ struct CritLists {
     uint32_t* id1;
     uint64_t* key1;
     uint32_t* id2;
-    uint64_t* key2hi;
-    uint32_t* key2lo;
+    uint64_t* key2;
     uint32_t* id3;
-    uint64_t* key3hi;
-    uint64_t* key3lo;
+    uint64_t* key3;
 };
 
 constexpr uint32_t EMPTY32 = 0xFFFFFFFFu;

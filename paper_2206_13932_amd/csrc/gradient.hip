@@ -197,6 +197,7 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     uint32_t crit_hi = 0;
     bool crit_vertex = false;
     uint32_t rx = 0;
+    uint64_t relpack = 0;  // 4-bit label of each lower neighbour: its rank order among them
 
     if (active) {
         uint32_t r[NNB];
@@ -210,7 +211,6 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
             uint32_t in_hi;
             cells_of(lower, in_lo, in_hi);
             // relabel the lower neighbours by rank: rel[n] = #lower neighbours below n
-            uint64_t relpack = 0;
             int n0 = 0;
 #pragma unroll
             for (int n = 0; n < NNB; ++n) {
@@ -327,9 +327,9 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     }
 
     // ---- critical-cell lists of vertex x (all lanes take part in the wave scans) ----
-    auto nbrank = [&](int n) {
-        return rank[x + kStar.nbv[n][0] + kStar.nbv[n][1] * g.sy + kStar.nbv[n][2] * g.sz];
-    };
+    // keys in the lexicographic order: the rank of x, then the labels of the
+    // other vertices, highest first, 4 bits each (see CritLists)
+    auto lab = [&](int n) { return (uint32_t)(relpack >> (4 * n)) & 15u; };
     const uint64_t E_MASK = 0x3FFFull, T_MASK = ((1ull << 50) - 1) & ~0x3FFFull;
     const uint64_t Q_LO = ~((1ull << 50) - 1);
     uint32_t c0 = crit_vertex ? 1 : 0;
@@ -344,12 +344,12 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         uint32_t at = wave_reserve(c1, &cl.count[1]);
         uint64_t m = crit_lo & E_MASK;
         while (m) {
-            const int s = __builtin_ctzll(m);
+            const int s = __builtin_ctzll(m);  // edge slot s joins x to neighbour s
             m &= m - 1;
             if (at < cl.cap[1]) {
                 const int64_t a = x + T.aofflin[s];
                 cl.id1[at] = (uint32_t)(a * 7 + (T.plane[s] - 1));
-                cl.key1[at] = ((uint64_t)rx << bpr) | nbrank(s);
+                cl.key1[at] = ((uint64_t)rx << 4) | lab(s);
             }
             ++at;
         }
@@ -364,11 +364,9 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
                 const int64_t a = x + T.aofflin[s];
                 cl.id2[at] = (uint32_t)(a * 12 + (T.plane[s] - 8));
                 const uint32_t nb = T.cellnb[s];
-                const int na = __builtin_ctz(nb), nbb = 31 - __builtin_clz(nb);
-                const uint32_t ra = nbrank(na), rb = nbrank(nbb);
-                const uint32_t hi = ra > rb ? ra : rb, lo = ra > rb ? rb : ra;
-                cl.key2hi[at] = ((uint64_t)rx << bpr) | hi;
-                cl.key2lo[at] = lo;
+                const uint32_t la = lab(__builtin_ctz(nb)), lb = lab(31 - __builtin_clz(nb));
+                const uint32_t hi = la > lb ? la : lb, lo = la > lb ? lb : la;
+                cl.key2[at] = ((uint64_t)rx << 8) | (hi << 4) | lo;
             }
             ++at;
         }
@@ -385,19 +383,18 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
                 const int64_t a = x + T.aofflin[s];
                 cl.id3[at] = (uint32_t)(a * 6 + (T.plane[s] - 20));
                 uint32_t nb = T.cellnb[s];
-                uint32_t rr[3];
+                uint32_t ll[3];
                 for (int i = 0; i < 3; ++i) {
                     const int n = __builtin_ctz(nb);
                     nb &= nb - 1;
-                    rr[i] = nbrank(n);
+                    ll[i] = lab(n);
                 }
-                // sort three ranks descending
-                uint32_t t0 = rr[0], t1 = rr[1], t2 = rr[2], t;
+                // sort the three labels descending
+                uint32_t t0 = ll[0], t1 = ll[1], t2 = ll[2], t;
                 if (t0 < t1) { t = t0; t0 = t1; t1 = t; }
                 if (t1 < t2) { t = t1; t1 = t2; t2 = t; }
                 if (t0 < t1) { t = t0; t0 = t1; t1 = t; }
-                cl.key3hi[at] = ((uint64_t)rx << bpr) | t0;
-                cl.key3lo[at] = ((uint64_t)t1 << bpr) | t2;
+                cl.key3[at] = ((uint64_t)rx << 12) | (t0 << 8) | (t1 << 4) | t2;
             }
             ++at;
         }
