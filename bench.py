@@ -32,8 +32,8 @@ HBM_PEAK_GBS = 8000.0
 # Counters of one gradient-kernel launch on smooth512 (profiles/gradient_hbm_counters_smooth512.md),
 # valid for the kernel sources with this hash only: HBM bytes from FETCH_SIZE (x2 calibration) and
 # WRITE_SIZE, and the VALU wave instructions issued
-GRADIENT_COUNTERS = {"sources_sha256_16": "d1c889b7ec20c5db", "workload": "smooth512",
-                     "traffic_bytes": 2488373489 + 6853847040, "valu_wave_insts": 29239834601}
+GRADIENT_COUNTERS = {"sources_sha256_16": "c7fbc8f802bd1bce", "workload": "smooth512",
+                     "traffic_bytes": 1609884197 + 6740072294, "valu_wave_insts": 29058432461}
 # VALU issue ceiling: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per 2 cycles per SIMD
 VALU_PEAK_WINST_S = 256 * 4 * 2.4e9 / 2
 
@@ -59,8 +59,8 @@ def make_field(name):
 def gradient_algorithmic_bytes(V, ncrit):
     """Bytes the gradient kernel must move: read the order (4 B/vertex; the
     neighbours come from cache), write the 26 gradient byte planes, append
-    critical ids + packed keys (C0: 4+4, C1: 4+8, C2: 4+8+4, C3: 4+8+8)."""
-    return 4 * V + 26 * V + 8 * ncrit[0] + 12 * ncrit[1] + 16 * ncrit[2] + 20 * ncrit[3]
+    critical ids + packed keys (C0: 4+4, C1, C2, C3: 4+8)."""
+    return 4 * V + 26 * V + 8 * ncrit[0] + 12 * (ncrit[1] + ncrit[2] + ncrit[3])
 
 
 def cpu_baseline(field, crop):
