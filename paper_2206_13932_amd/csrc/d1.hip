@@ -1630,18 +1630,25 @@ __global__ void k_compact(const uint32_t* c2, const uint8_t* paired2_desc, const
     if (k < m2 && !paired2_desc[m2 - 1 - k]) cols[pos[k]] = c2[k];
 }
 
-__global__ void k_emit_pairs(GridDev g, const uint32_t* order, int bpr, const uint32_t* cols, int64_t ncols,
-                             const uint64_t* bndptr, const uint64_t* heap, const uint32_t* owner1, uint64_t* key,
-                             uint32_t* death, uint32_t* cnt) {
-    const int64_t c = (int64_t)blockIdx.x * DB + threadIdx.x;
-    if (c >= ncols) return;
-    const uint64_t b = bndptr[c];
-    if (b == EMPTY64) return;
-    const EdgeDec e = edecode(g, order, bpr, heap[b >> 24]);
-    if (owner1[e.id] != (uint32_t)c) return;
-    const uint32_t at = wave_append(true, cnt);
-    key[at] = e.id;
-    death[at] = cols[c];
+constexpr int EMIT_ITEMS = 16;  // columns per lane of k_emit_pairs: one list atomic per 4096 columns
+
+__global__ __launch_bounds__(DB) void k_emit_pairs(GridDev g, const uint32_t* order, int bpr, const uint32_t* cols,
+                                                   int64_t ncols, const uint64_t* bndptr, const uint64_t* heap,
+                                                   const uint32_t* owner1, uint64_t* key, uint32_t* death,
+                                                   uint32_t* cnt) {
+    block_append<DB, EMIT_ITEMS>(
+        cnt, (int64_t)blockIdx.x * DB * EMIT_ITEMS, ncols,
+        [&](int64_t c, uint64_t& p) {
+            const uint64_t b = bndptr[c];
+            if (b == EMPTY64) return false;
+            const EdgeDec e = edecode(g, order, bpr, heap[b >> 24]);
+            p = e.id;
+            return owner1[e.id] == (uint32_t)c;
+        },
+        [&](int64_t c, uint64_t p, uint32_t at) {
+            key[at] = p;
+            death[at] = cols[c];
+        });
 }
 
 __global__ void k_emit_ess1(const uint32_t* c1, const uint8_t* paired1, int64_t m1, const uint32_t* owner1,
@@ -1898,7 +1905,8 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
 void d1_emit(D1State& s, int64_t m1, const uint8_t* paired1, const uint32_t* c1, uint64_t* key, uint32_t* death,
              uint32_t* cnt, hipStream_t st) {
     if (s.ncols > 0)
-        hipLaunchKernelGGL(k_emit_pairs, dim3(nblocks(s.ncols)), dim3(DB), 0, st, s.g, s.order, s.bpr,
+        hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)((s.ncols + DB * EMIT_ITEMS - 1) / (DB * EMIT_ITEMS))),
+                           dim3(DB), 0, st, s.g, s.order, s.bpr,
                            (const uint32_t*)s.cols, s.ncols, (const uint64_t*)s.bndptr, (const uint64_t*)s.heap,
                            (const uint32_t*)s.owner1, key, death, cnt);
     if (m1 > 0)

@@ -134,34 +134,47 @@ inline unsigned nb_of(int64_t n) { return (unsigned)((n + OB - 1) / OB); }
 
 // D0: paired column j -> (vertex of dying minimum, edge); unowned minima ->
 // infinite classes (key bit 32 set so that they sort last).
-__global__ void k_emit_d0(const uint64_t* bnd, const uint8_t* paired, const uint32_t* order, const uint32_t* c1,
-                          int64_t m1, const uint32_t* c0, const uint32_t* rank, const uint32_t* owner0, int64_t m0,
-                          uint64_t* key, uint32_t* death, uint32_t* cnt) {
-    const int64_t i = (int64_t)blockIdx.x * OB + threadIdx.x;
-    const bool pair = i < m1 && paired[i];
-    const uint32_t at = wave_append(pair, cnt);
-    if (pair) {
-        key[at] = order[(uint32_t)(bnd[i] >> 32)];
-        death[at] = c1[i];
-    }
-    const uint32_t v = i < m0 ? c0[i] : 0u;
-    const bool ess = i < m0 && owner0[rank[v]] == EMPTY32;
-    const uint32_t at2 = wave_append(ess, cnt);
-    if (ess) {
-        key[at2] = (1ull << 32) | v;
-        death[at2] = EMPTY32;
-    }
+constexpr int EMIT_ITEMS = 16;  // items per lane of the emit kernels: one list atomic per 4096 items
+inline unsigned nb_emit(int64_t n) { return (unsigned)((n + OB * EMIT_ITEMS - 1) / (OB * EMIT_ITEMS)); }
+
+__global__ __launch_bounds__(OB) void k_emit_d0(const uint64_t* bnd, const uint8_t* paired, const uint32_t* order,
+                                                const uint32_t* c1, int64_t m1, const uint32_t* c0,
+                                                const uint32_t* rank, const uint32_t* owner0, int64_t m0,
+                                                uint64_t* key, uint32_t* death, uint32_t* cnt) {
+    const int64_t first = (int64_t)blockIdx.x * OB * EMIT_ITEMS;
+    block_append<OB, EMIT_ITEMS>(
+        cnt, first, m1, [&](int64_t i, uint64_t& p) {
+            if (!paired[i]) return false;
+            p = bnd[i] >> 32;
+            return true;
+        },
+        [&](int64_t i, uint64_t p, uint32_t at) {
+            key[at] = order[(uint32_t)p];
+            death[at] = c1[i];
+        });
+    block_append<OB, EMIT_ITEMS>(
+        cnt, first, m0,
+        [&](int64_t i, uint64_t& p) {
+            p = c0[i];
+            return owner0[rank[p]] == EMPTY32;
+        },
+        [&](int64_t, uint64_t p, uint32_t at) {
+            key[at] = (1ull << 32) | p;
+            death[at] = EMPTY32;
+        });
 }
 
 // D2: paired column j (decreasing triangles) -> (triangle, tet of the pivot age).
-__global__ void k_emit_d2(const uint64_t* bnd, const uint8_t* paired, const uint32_t* c2, int64_t m2,
-                          const uint32_t* c3, int64_t m3, uint64_t* key, uint32_t* death, uint32_t* cnt) {
-    const int64_t j = (int64_t)blockIdx.x * OB + threadIdx.x;
-    if (j >= m2 || !paired[j]) return;
-    const uint32_t pos = (uint32_t)(bnd[j] >> 32);  // 1 = highest maximum
-    const uint32_t at = wave_append(true, cnt);
-    key[at] = c2[m2 - 1 - j];
-    death[at] = c3[m3 - pos];
+__global__ __launch_bounds__(OB) void k_emit_d2(const uint64_t* bnd, const uint8_t* paired, const uint32_t* c2,
+                                                int64_t m2, const uint32_t* c3, int64_t m3, uint64_t* key,
+                                                uint32_t* death, uint32_t* cnt) {
+    block_append<OB, EMIT_ITEMS>(
+        cnt, (int64_t)blockIdx.x * OB * EMIT_ITEMS, m2, [&](int64_t j, uint64_t&) { return paired[j] != 0; },
+        [&](int64_t j, uint64_t, uint32_t at) {
+            const uint32_t pos = (uint32_t)(bnd[j] >> 32);  // 1 = highest maximum
+            key[at] = c2[m2 - 1 - j];
+            death[at] = c3[m3 - pos];
+        });
 }
 
 __device__ inline int64_t max_vertex_of(const GridDev& g, const uint32_t* rank, int dim, int64_t id) {
@@ -511,7 +524,7 @@ static int emit_d0(dms_ctx* ctx, dms_pair* d0, int64_t cap0, int64_t* n0, int64_
     HIPCHK(hipMemsetAsync(ctx->ocnt.p, 0, 4, st));
     const int64_t n = std::max(m0, m1);
     if (n > 0)
-        hipLaunchKernelGGL(k_emit_d0, dim3(nb_of(n)), dim3(OB), 0, st, P<uint64_t>(ctx->bnd0),
+        hipLaunchKernelGGL(k_emit_d0, dim3(nb_emit(n)), dim3(OB), 0, st, P<uint64_t>(ctx->bnd0),
                            P<uint8_t>(ctx->paired1), ctx->order, P<uint32_t>(ctx->csorted[1]), m1,
                            P<uint32_t>(ctx->csorted[0]), P<uint32_t>(ctx->rank), P<uint32_t>(ctx->owner0), m0,
                            P<uint64_t>(ctx->okey), P<uint32_t>(ctx->od), P<uint32_t>(ctx->ocnt));
@@ -532,7 +545,7 @@ static int emit_d2(dms_ctx* ctx, dms_pair* d2, int64_t cap2, int64_t* n2, int64_
     ENSURE(ctx->od, 4 * cap);
     HIPCHK(hipMemsetAsync(ctx->ocnt.p, 0, 4, st));
     if (m2 > 0)
-        hipLaunchKernelGGL(k_emit_d2, dim3(nb_of(m2)), dim3(OB), 0, st, P<uint64_t>(ctx->bnd2),
+        hipLaunchKernelGGL(k_emit_d2, dim3(nb_emit(m2)), dim3(OB), 0, st, P<uint64_t>(ctx->bnd2),
                            P<uint8_t>(ctx->paired2), P<uint32_t>(ctx->csorted[2]), m2, P<uint32_t>(ctx->csorted[3]),
                            m3, P<uint64_t>(ctx->okey), P<uint32_t>(ctx->od), P<uint32_t>(ctx->ocnt));
     if (with_essential) d1_emit_essential2(ctx->d1, m2, P<uint8_t>(ctx->paired2), P<uint32_t>(ctx->csorted[2]),

@@ -171,4 +171,51 @@ __device__ inline uint32_t wave_append(bool pred, uint32_t* cnt) {
     return base + (uint32_t)__popcll(b & ((1ull << lane) - 1));
 }
 
+// Block-wide list append for kernels over long item ranges. Lane l of the
+// block tests items first + it * NT + l (it < ITEMS, reads coalesced); the
+// block reserves the places of all its hits with ONE atomicAdd on *cnt, then
+// each hit is written by emit. Atomics on one counter from the whole grid
+// are executed one after another (about 11 ns each on MI355X), so one per
+// wavefront already costs ~3 ms over 17M items; one per NT * ITEMS items
+// does not. test(i, payload) -> bool may leave a 64-bit payload for
+// emit(i, payload, slot). Every lane of the block must call it (it holds
+// two barriers); the order of the hits in the list is unspecified.
+template <int NT, int ITEMS, class Test, class Emit>
+__device__ inline void block_append(uint32_t* cnt, int64_t first, int64_t n, Test test, Emit emit) {
+    static_assert(NT % 64 == 0 && NT <= 1024 && ITEMS <= 32, "block shape");
+    __shared__ uint32_t wsum[NT / 64 + 1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t pay[ITEMS];
+    uint32_t hits = 0;  // bit it: item it of this lane is appended
+    uint32_t wcount = 0;
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int64_t i = first + (int64_t)it * NT + threadIdx.x;
+        pay[it] = 0;
+        const bool h = i < n && test(i, pay[it]);
+        hits |= (uint32_t)h << it;
+        wcount += (uint32_t)__popcll(__ballot(h));
+    }
+    if (lane == 0) wsum[w] = wcount;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int k = 0; k < NT / 64; ++k) {
+            const uint32_t c = wsum[k];
+            wsum[k] = s;
+            s += c;
+        }
+        wsum[NT / 64] = s ? atomicAdd(cnt, s) : 0u;
+    }
+    __syncthreads();
+    uint32_t at = wsum[NT / 64] + wsum[w];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const bool h = (hits >> it) & 1u;
+        const uint64_t b = __ballot(h);
+        if (h) emit(first + (int64_t)it * NT + threadIdx.x, pay[it], at + (uint32_t)__popcll(b & ((1ull << lane) - 1)));
+        at += (uint32_t)__popcll(b);
+    }
+}
+
 }  // namespace dms

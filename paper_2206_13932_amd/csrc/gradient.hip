@@ -59,15 +59,6 @@ __device__ inline uint32_t wave_exclusive(uint32_t v, uint32_t& total) {
     return incl - v;
 }
 
-// Reserve `cnt` entries of a list: one atomicAdd per wavefront.
-__device__ inline uint32_t wave_reserve(uint32_t cnt, uint32_t* counter) {
-    uint32_t total;
-    uint32_t ex = wave_exclusive(cnt, total);
-    uint32_t base = 0;
-    if ((threadIdx.x & 63) == 63 && total) base = atomicAdd(counter, total);
-    base = __shfl(base, 63, 64);
-    return base + ex;
-}
 
 __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_gradient(GridDev g, const uint32_t* __restrict__ rank,
                                                  uint8_t* __restrict__ G, int bpr, CritLists cl) {
@@ -326,7 +317,7 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         }
     }
 
-    // ---- critical-cell lists of vertex x (all lanes take part in the wave scans) ----
+    // ---- critical-cell lists of vertex x (every lane of the block takes part) ----
     // keys in the lexicographic order: the rank of x, then the labels of the
     // other vertices, highest first, 4 bits each (see CritLists)
     auto lab = [&](int n) { return (uint32_t)(relpack >> (4 * n)) & 15u; };
@@ -336,12 +327,43 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     uint32_t c1 = popc64(crit_lo & E_MASK);
     uint32_t c2 = popc64(crit_lo & T_MASK);
     uint32_t c3 = popc64(crit_lo & Q_LO) + __builtin_popcount(crit_hi);
+    // places in the four lists: one atomicAdd per list and workgroup (a list
+    // counter hit by every wavefront of the grid serialises the kernel at
+    // about 11 ns per atomic); bins is free again after the counting sort
+    constexpr int NWV = GB / 64;
+    static_assert(4 * (NWV + 1) <= NSLOT + 1, "list sums must fit in bins");
+    uint32_t base[4];
     {
-        uint32_t at = wave_reserve(c0, &cl.count[0]);
+        const int lane = tid & 63, w = tid >> 6;
+        const uint32_t cc[4] = {c0, c1, c2, c3};
+        uint32_t ex[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            uint32_t tot;
+            ex[d] = wave_exclusive(cc[d], tot);
+            if (lane == 63) bins[d * (NWV + 1) + w] = tot;
+        }
+        __syncthreads();
+        if (tid < 4) {
+            uint32_t* b = bins + tid * (NWV + 1);
+            uint32_t sum = 0;
+            for (int k = 0; k < NWV; ++k) {
+                const uint32_t c = b[k];
+                b[k] = sum;
+                sum += c;
+            }
+            b[NWV] = sum ? atomicAdd(&cl.count[tid], sum) : 0u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int d = 0; d < 4; ++d) base[d] = bins[d * (NWV + 1) + NWV] + bins[d * (NWV + 1) + w] + ex[d];
+    }
+    {
+        uint32_t at = base[0];
         if (c0 && at < cl.cap[0]) { cl.id0[at] = (uint32_t)x; cl.key0[at] = rx; }
     }
     {
-        uint32_t at = wave_reserve(c1, &cl.count[1]);
+        uint32_t at = base[1];
         uint64_t m = crit_lo & E_MASK;
         while (m) {
             const int s = __builtin_ctzll(m);  // edge slot s joins x to neighbour s
@@ -355,7 +377,7 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         }
     }
     {
-        uint32_t at = wave_reserve(c2, &cl.count[2]);
+        uint32_t at = base[2];
         uint64_t m = crit_lo & T_MASK;
         while (m) {
             const int s = __builtin_ctzll(m);
@@ -372,7 +394,7 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         }
     }
     {
-        uint32_t at = wave_reserve(c3, &cl.count[3]);
+        uint32_t at = base[3];
         uint64_t m = crit_lo & Q_LO;
         uint32_t h = crit_hi;
         while (m | h) {
