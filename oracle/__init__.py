@@ -28,6 +28,7 @@ _loaded = {}
 
 ORC_RANK, ORC_PARTNER0, ORC_CRIT0 = 0, 1, 5
 ORC_D0, ORC_D1, ORC_D2, ORC_ARCS0, ORC_ARCS2, ORC_TIMES = 9, 10, 11, 12, 13, 14
+ORC_GEN1_OFF, ORC_GEN1_EDGES = 15, 16
 NTYPES = (1, 7, 12, 6)
 
 
@@ -101,6 +102,10 @@ class OracleResult:
         self.arcs0 = get(ORC_ARCS0, np.int64, 3)
         self.arcs2 = get(ORC_ARCS2, np.int64, 3)
         self.times = get(ORC_TIMES, np.float64)
+        # persistent 1-cycle generators (Sec. 8): for the i-th finite D1 pair,
+        # gen1_edges[gen1_off[i]:gen1_off[i + 1]] (edge ids, ascending)
+        self.gen1_off = get(ORC_GEN1_OFF, np.int64)
+        self.gen1_edges = get(ORC_GEN1_EDGES, np.int64)
 
 
 def run(field: np.ndarray) -> OracleResult:
@@ -176,6 +181,26 @@ def bf_d0_kruskal(shape, rank: np.ndarray) -> np.ndarray:
     out = np.empty((cap, 2), dtype=np.int64)
     m = _lib("bruteforce").bf_d0_kruskal(nx, ny, nz, _ptr(r), _ptr(out), cap)
     return out[:m].copy()
+
+
+def bf_check_cycles(shape, rank: np.ndarray, pairs1: np.ndarray, off: np.ndarray, edges: np.ndarray) -> np.ndarray:
+    """Check persistent 1-cycle generators against their definition over the
+    whole filtration: pairs1 (n, 2) finite D1 pairs (edge id, triangle id),
+    generator i = edges[off[i]:off[i + 1]] (edge ids). Returns a status per
+    pair (0 = valid; see bf_check_cycles in bruteforce.cpp)."""
+    nz, ny, nx = shape
+    pairs1 = np.asarray(pairs1, dtype=np.int64).reshape(-1, 2)
+    n = len(pairs1)
+    tv = np.ascontiguousarray(simplex_vertices(shape, 1, pairs1[:, 0]), dtype=np.int64)
+    sv = np.ascontiguousarray(simplex_vertices(shape, 2, pairs1[:, 1]), dtype=np.int64)
+    ev = np.ascontiguousarray(simplex_vertices(shape, 1, np.asarray(edges, dtype=np.int64)), dtype=np.int64)
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    r = np.ascontiguousarray(rank, dtype=np.uint32)
+    status = np.zeros(n, dtype=np.int32)
+    if n:
+        _lib("bruteforce").bf_check_cycles(nx, ny, nz, _ptr(r), n, _ptr(tv), _ptr(sv), _ptr(off), _ptr(ev),
+                                           _ptr(status))
+    return status
 
 
 def bf_lower_link_betti(shape, rank: np.ndarray) -> np.ndarray:

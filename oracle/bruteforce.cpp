@@ -296,3 +296,116 @@ int64_t bf_d0_kruskal(int64_t nx, int64_t ny, int64_t nz, const uint32_t* rank, 
 }
 
 }  // extern "C"
+
+extern "C" {
+
+/* Persistent 1-cycle generators against their definition (Sec. 8): for a
+ * D1 pair (tau, sigma), a representative is a 1-cycle z, homologous to the
+ * boundary of sigma, that is born at tau. Over the lexicographic filtration
+ * (simplices enumerated from the tetrahedra as above) that means:
+ *   - z is a cycle: every vertex lies on an even number of its edges;
+ *   - the highest edge of z is tau;
+ *   - z + boundary(sigma) is a sum of boundaries of triangles that come
+ *     before sigma (Z2 elimination over the triangles in filtration order).
+ * Pairs and edges are given by vertex ids: pair i has birth edge
+ * (tv[2i], tv[2i+1]) and death triangle (sv[3i..3i+2]); its cycle is the
+ * edges ev[2k], ev[2k+1] for off[i] <= k < off[i+1]. status[i] = 0 when all
+ * holds, 1 not a cycle, 2 an edge or simplex not in the complex, 3 highest
+ * edge is not tau, 4 not homologous to boundary(sigma) before sigma. */
+void bf_check_cycles(int64_t nx, int64_t ny, int64_t nz, const uint32_t* rank, int64_t n, const int64_t* tv,
+                     const int64_t* sv, const int64_t* off, const int64_t* ev, int32_t* status) {
+    Complex K;
+    all_simplices(nx, ny, nz, K);
+    const size_t ns = K.simp.size();
+    std::map<Verts, int> index;
+    for (size_t i = 0; i < ns; ++i) index[K.simp[i]] = (int)i;
+    std::vector<int> tri;  /* triangles in filtration order */
+    for (size_t i = 0; i < ns; ++i)
+        if (K.dim[i] == 2) tri.push_back((int)i);
+    std::vector<std::array<i64, 4>> key(ns);
+    for (size_t i = 0; i < ns; ++i) key[i] = lex_key(K.simp[i], rank);
+    std::sort(tri.begin(), tri.end(), [&](int a, int b) { return key[a] < key[b]; });
+    /* rows: edges by filtration position */
+    std::vector<int> edges;
+    for (size_t i = 0; i < ns; ++i)
+        if (K.dim[i] == 1) edges.push_back((int)i);
+    std::sort(edges.begin(), edges.end(), [&](int a, int b) { return key[a] < key[b]; });
+    std::vector<int> row(ns, -1);
+    for (size_t r = 0; r < edges.size(); ++r) row[edges[r]] = (int)r;
+    auto find = [&](std::initializer_list<i64> vs) {
+        Verts v = {-1, -1, -1, -1};
+        int k = 0;
+        for (i64 x : vs) v[k++] = x;
+        std::sort(v.begin(), v.begin() + k);
+        auto it = index.find(v);
+        return it == index.end() ? -1 : it->second;
+    };
+    auto boundary = [&](int t) {
+        std::vector<int> b;
+        const Verts& v = K.simp[t];
+        b.push_back(row[find({v[0], v[1]})]);
+        b.push_back(row[find({v[0], v[2]})]);
+        b.push_back(row[find({v[1], v[2]})]);
+        std::sort(b.begin(), b.end());
+        return b;
+    };
+    /* pairs by death triangle */
+    std::map<int, std::vector<int64_t>> at;
+    for (int64_t i = 0; i < n; ++i) {
+        status[i] = 0;
+        const int s = find({sv[3 * i], sv[3 * i + 1], sv[3 * i + 2]});
+        const int t = find({tv[2 * i], tv[2 * i + 1]});
+        if (s < 0 || t < 0 || K.dim[s] != 2 || K.dim[t] != 1) { status[i] = 2; continue; }
+        std::vector<int> deg;
+        std::vector<int> z;
+        for (int64_t k = off[i]; k < off[i + 1]; ++k) {
+            const int e = find({ev[2 * k], ev[2 * k + 1]});
+            if (e < 0 || K.dim[e] != 1) { status[i] = 2; break; }
+            z.push_back(row[e]);
+            deg.push_back((int)ev[2 * k]);
+            deg.push_back((int)ev[2 * k + 1]);
+        }
+        if (status[i]) continue;
+        std::sort(deg.begin(), deg.end());
+        for (size_t a = 0; a < deg.size();) {
+            size_t b = a;
+            while (b < deg.size() && deg[b] == deg[a]) ++b;
+            if ((b - a) & 1) status[i] = 1;
+            a = b;
+        }
+        if (status[i]) continue;
+        std::sort(z.begin(), z.end());
+        if (std::adjacent_find(z.begin(), z.end()) != z.end()) { status[i] = 1; continue; }
+        if (z.empty() || z.back() != row[t]) { status[i] = 3; continue; }
+        at[s].push_back(i);
+        (void)z;
+    }
+    /* eliminate in filtration order; test each pair just before its sigma */
+    std::vector<std::vector<int>> basis;
+    std::vector<int> owner(edges.size(), -1);
+    std::vector<int> tmp;
+    auto reduce = [&](std::vector<int>& c) {
+        while (!c.empty() && owner[c.back()] >= 0) sym_diff(c, basis[owner[c.back()]], tmp);
+    };
+    for (int s : tri) {
+        std::vector<int> bs = boundary(s);
+        auto it = at.find(s);
+        if (it != at.end()) {
+            for (int64_t i : it->second) {
+                std::vector<int> z;
+                for (int64_t k = off[i]; k < off[i + 1]; ++k) z.push_back(row[find({ev[2 * k], ev[2 * k + 1]})]);
+                std::sort(z.begin(), z.end());
+                sym_diff(z, bs, tmp);
+                reduce(z);
+                if (!z.empty()) status[i] = 4;
+            }
+        }
+        reduce(bs);
+        if (!bs.empty()) {
+            owner[bs.back()] = (int)basis.size();
+            basis.push_back(bs);
+        }
+    }
+}
+
+}  // extern "C"

@@ -205,6 +205,10 @@ struct Ctx {
     std::vector<i64> crit[4];              /* sorted ascending by Key */
     std::vector<i64> d0, d1, d2;           /* flattened (birth, death) */
     std::vector<i64> arcs0, arcs2;         /* flattened (node_a, node_b, saddle) */
+    /* Sec. 8: the boundary cached when a 2-saddle was paired (its
+     * persistent 1-cycle generator), by 2-saddle id */
+    std::map<i64, std::vector<i64>> gen1;
+    std::vector<i64> gen1_off, gen1_edges; /* per finite D1 pair, in output order */
     double times[6] = {0, 0, 0, 0, 0, 0};  /* order, gradient, sort, D0+D2, D1, total */
     std::string err;
 
@@ -552,6 +556,7 @@ void diagram1(Ctx& C, const std::vector<char>& edge_paired0, const std::vector<c
                     edge_owner[tau] = sigma;
                     std::vector<i64>& cb = cached[sigma];
                     for (auto& k : B) cb.push_back(k.second);
+                    C.gen1[sigma] = cb;
                     C.d1.push_back(tau);
                     C.d1.push_back(sigma);
                     break;
@@ -613,6 +618,15 @@ void run(Ctx& C, const float* f) {
     sort_pairs(C.d0);
     sort_pairs(C.d1);
     sort_pairs(C.d2);
+    /* generators in the order of the finite D1 pairs, edge ids ascending */
+    C.gen1_off.push_back(0);
+    for (size_t k = 0; k < C.d1.size(); k += 2) {
+        if (C.d1[k + 1] < 0) continue;
+        std::vector<i64> z = C.gen1.at(C.d1[k + 1]);
+        std::sort(z.begin(), z.end());
+        C.gen1_edges.insert(C.gen1_edges.end(), z.begin(), z.end());
+        C.gen1_off.push_back((i64)C.gen1_edges.size());
+    }
     C.times[0] = t1 - t0;
     C.times[1] = t2 - t1;
     C.times[2] = t3 - t2;
@@ -633,7 +647,9 @@ enum {
     ORC_CRIT0 = 5,         /* i64 sorted critical ids, d = 0..3 (5..8) */
     ORC_D0 = 9, ORC_D1 = 10, ORC_D2 = 11, /* i64 (birth, death) pairs  */
     ORC_ARCS0 = 12, ORC_ARCS2 = 13,       /* i64 (a, b, saddle)        */
-    ORC_TIMES = 14         /* f64[6]                                   */
+    ORC_TIMES = 14,        /* f64[6]                                   */
+    ORC_GEN1_OFF = 15,     /* i64 offsets of the D1 generators (n1 + 1) */
+    ORC_GEN1_EDGES = 16    /* i64 edge ids of the D1 generators         */
 };
 
 int orc_run(int64_t nx, int64_t ny, int64_t nz, const float* f, void** out, char* err, int errlen) {
@@ -664,6 +680,8 @@ int64_t orc_size(void* h, int what) {
         case ORC_ARCS0: return (int64_t)C->arcs0.size() / 3;
         case ORC_ARCS2: return (int64_t)C->arcs2.size() / 3;
         case ORC_TIMES: return 6;
+        case ORC_GEN1_OFF: return (int64_t)C->gen1_off.size();
+        case ORC_GEN1_EDGES: return (int64_t)C->gen1_edges.size();
     }
     return -1;
 }
@@ -681,6 +699,8 @@ void orc_copy(void* h, int what, void* dst) {
         case ORC_ARCS0: cp(C->arcs0); break;
         case ORC_ARCS2: cp(C->arcs2); break;
         case ORC_TIMES: std::memcpy(dst, C->times, sizeof(C->times)); break;
+        case ORC_GEN1_OFF: cp(C->gen1_off); break;
+        case ORC_GEN1_EDGES: cp(C->gen1_edges); break;
     }
 }
 
