@@ -158,6 +158,7 @@ def main():
     ap.add_argument("--serve-plain-sample", type=int, default=512)
     ap.add_argument("--serve-calib", type=int, default=256)
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation run")
+    ap.add_argument("--no-generators", action="store_true", help="skip the 1-cycle generator export")
     ap.add_argument("--mode", default="diagram", choices=["diagram", "gradient"],
                     help="gradient: time dms_gradient alone and a 1 GiB device copy "
                          "(the reference kernel for hardware byte counters)")
@@ -240,6 +241,22 @@ def main():
         print(f"[bench] D1 cached boundary length p50/p90/p99/p99.9/max: {q}; columns > 1000: "
               f"{int((lens > 1000).sum())}, > 10000: {int((lens > 10000).sum())}", file=sys.stderr, flush=True)
 
+    generators = None
+    if not args.no_generators:
+        # persistent 1-cycle generators of the same diagram: the first export
+        # sizes the context's working buffers, the second (after a fresh
+        # diagram) is timed, from the call to the cycles in HBM
+        ctx.d1_generators()
+        ctx.diagram(field)
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        goff, gedges = ctx.d1_generators()
+        torch.cuda.synchronize()
+        gms = (time.perf_counter() - tg) * 1e3
+        generators = {"cycles": int(goff.numel() - 1), "edges": int(gedges.numel()), "ms": round(gms, 3)}
+        del goff, gedges
+        print(f"[bench] generators {generators}", file=sys.stderr, flush=True)
+
     traffic, valu = None, None
     if (GRADIENT_COUNTERS["workload"] == args.workload
             and GRADIENT_COUNTERS["sources_sha256_16"] == gradient_sources_hash()):
@@ -270,6 +287,8 @@ def main():
                      "traffic": traffic, "algorithmic_bytes": int(gbytes),
                      "avg_kernel_ms": round(g_avg_ms, 4), "valu_issue": valu},
     }
+    if generators is not None:
+        line["generators"] = generators
     ctx.close()
     del field, out
     torch.cuda.empty_cache()

@@ -113,6 +113,27 @@ int dms_pairs_d1(dms_ctx* ctx, dms_pair* d1, int64_t cap1, int64_t* n1);
 /* The whole pipeline: gradient, D0/D2, D1, infinite classes (Sec. 6). */
 int dms_diagram(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t flags, dms_diagram_out* out);
 
+/* Persistent 1-cycle generators (Sec. 8): for a D1 pair (tau, sigma), the
+ * boundary of sigma as it stood when sigma was paired with tau. It is a
+ * 1-cycle whose highest edge is tau, and it differs from the boundary of
+ * sigma by boundaries of triangles that precede sigma in the filtration.
+ * Which such cycle is returned depends on the order in which concurrent
+ * columns were reduced; the birth edge, the death triangle and the three
+ * properties above do not.
+ *
+ * Needs dms_pairs_d1 or dms_diagram on one field (not a batch) first:
+ * DMS_E_STATE otherwise. Cycle i belongs to the i-th finite pair of the D1
+ * list those calls write (finite pairs come first, in increasing birth-edge
+ * id). Output, device memory owned by the caller:
+ *   d_offsets[0..n_pairs]  int64, cycle i = d_edges[d_offsets[i] .. d_offsets[i+1])
+ *   d_edges[0..n_edges)    int64 edge ids (anchor * 7 + type), ascending per cycle
+ * *n_pairs and *n_edges are always set. If cap_offsets < n_pairs + 1 or
+ * cap_edges < n_edges, nothing is written and DMS_E_CAPACITY is returned
+ * (NULL buffers with zero capacities ask for the sizes). Working memory grows
+ * with the total length of the cycles and stays with the context. */
+int dms_d1_generators(dms_ctx* ctx, int64_t* d_offsets, int64_t cap_offsets, int64_t* d_edges, int64_t cap_edges,
+                      int64_t* n_pairs, int64_t* n_edges);
+
 /* ---- Batching: many grids in one pipeline run ----
  * The grids are placed as disjoint boxes in one super grid of cross-section
  * cross_x * cross_y, separated by planes of +inf values; one pipeline run

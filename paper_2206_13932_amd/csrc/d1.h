@@ -64,6 +64,12 @@ struct D1State {
     GridDev g{};
     const uint32_t* order = nullptr;
     int bpr = 1;
+    // working buffers of the generator export, and what they hold: the
+    // cancelled (pair, edge) keys of the last run once gen_n >= 0
+    void* gbuf[12] = {nullptr};
+    size_t gcap[12] = {0};
+    int64_t gen_n = -1, gen_ne = 0, gen_total = 0;
+    int gen_sorted = 0;  // which key buffer holds the sorted keys
 };
 
 int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, std::string& err);
@@ -71,6 +77,14 @@ void d1_emit(D1State& s, int64_t m1, const uint8_t* paired1, const uint32_t* c1,
              uint32_t* cnt, hipStream_t st);
 void d1_emit_essential2(D1State& s, int64_t m2, const uint8_t* paired2_desc, const uint32_t* c2, uint64_t* key,
                         uint32_t* death, uint32_t* cnt, hipStream_t st);
+// Persistent 1-cycle generators of the finite D1 pairs (Sec. 8): for the
+// i-th finite pair in increasing birth-edge order, the edge ids (ascending)
+// of the boundary cached when its 2-saddle claimed the birth edge, mod-2
+// cancelled. Writes offsets[0..n] and edges[0..E) only when cap_off >= n + 1
+// and cap_edges >= E; always sets *n_pairs and *n_edges. Returns 0, 1 when
+// a buffer is too small, or a negative DMS error code (message in err).
+int d1_generators(D1State& s, int64_t* offsets, int64_t cap_off, int64_t* edges, int64_t cap_edges,
+                  int64_t* n_pairs, int64_t* n_edges, uint32_t* flags, hipStream_t st, std::string& err);
 void d1_free(D1State& s);
 
 }  // namespace dms

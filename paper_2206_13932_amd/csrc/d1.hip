@@ -1676,6 +1676,95 @@ __global__ void k_emit_ess2(GridDev g, const uint32_t* order, int bpr, const uin
     death[at] = EMPTY32;
 }
 
+// ---- persistent 1-cycle generators (Sec. 8) -------------------------------
+// The cycle of a finite D1 pair is the boundary its 2-saddle published when
+// it claimed the birth edge: a lane pass publishes {pivot} + its working heap
+// as it stood (entries may repeat and count mod 2), a workgroup pass a
+// sorted, cancelled list. The export gathers those entries per pair, sorts
+// them by (pair, edge id) and keeps the keys that occur an odd number of times.
+
+// (birth edge id, column) of every column that owns its pivot
+__global__ __launch_bounds__(DB) void k_gen_pairs(GridDev g, const uint32_t* order, int bpr, int64_t ncols,
+                                                  const uint64_t* bndptr, const uint64_t* heap,
+                                                  const uint32_t* owner1, uint32_t* edge, uint32_t* col,
+                                                  uint32_t* cnt) {
+    block_append<DB, EMIT_ITEMS>(
+        cnt, (int64_t)blockIdx.x * DB * EMIT_ITEMS, ncols,
+        [&](int64_t c, uint64_t& p) {
+            const uint64_t b = bndptr[c];
+            if (b == EMPTY64) return false;
+            const EdgeDec e = edecode(g, order, bpr, heap[b >> 24]);
+            p = e.id;
+            return owner1[e.id] == (uint32_t)c;
+        },
+        [&](int64_t c, uint64_t p, uint32_t at) {
+            edge[at] = (uint32_t)p;
+            col[at] = (uint32_t)c;
+        });
+}
+
+// published length of the boundary of pair i
+__global__ void k_gen_len(const uint32_t* col, int64_t n, const uint64_t* bndptr, uint32_t* len) {
+    const int64_t i = (int64_t)blockIdx.x * DB + threadIdx.x;
+    if (i < n) len[i] = (uint32_t)(bndptr[col[i]] & 0xFFFFFFull);
+}
+
+// entry j of the concatenated boundaries -> pair << 32 | edge id; off is the
+// exclusive scan of the lengths, every one of which is at least 1
+__global__ void k_gen_gather(GridDev g, const uint32_t* order, int bpr, const uint32_t* col, const uint32_t* off,
+                             int64_t n, int64_t total, const uint64_t* bndptr, const uint64_t* heap,
+                             uint64_t* key) {
+    const int64_t j = (int64_t)blockIdx.x * DB + threadIdx.x;
+    if (j >= total) return;
+    int64_t lo = 0, hi = n - 1;  // the last pair whose offset is <= j
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if ((int64_t)off[mid] <= j) lo = mid;
+        else hi = mid - 1;
+    }
+    const uint64_t b = bndptr[col[lo]];
+    const EdgeDec e = edecode(g, order, bpr, heap[(b >> 24) + (uint64_t)(j - (int64_t)off[lo])]);
+    key[j] = ((uint64_t)lo << 32) | e.id;
+}
+
+// sorted keys: one copy of every key that occurs an odd number of times
+__global__ void k_gen_keep(const uint64_t* key, int64_t total, uint32_t* keep) {
+    const int64_t j = (int64_t)blockIdx.x * DB + threadIdx.x;
+    if (j >= total) return;
+    const uint64_t k = key[j];
+    uint32_t odd = 0;
+    if (j == 0 || key[j - 1] != k) {
+        int64_t r = j + 1;
+        while (r < total && key[r] == k) ++r;
+        odd = (uint32_t)((r - j) & 1);
+    }
+    keep[j] = odd;
+}
+
+__global__ void k_gen_write(const uint64_t* key, const uint32_t* keep, const uint32_t* pos, int64_t total,
+                            int64_t* edges, uint32_t* pair_of) {
+    const int64_t j = (int64_t)blockIdx.x * DB + threadIdx.x;
+    if (j >= total || !keep[j]) return;
+    const uint32_t p = pos[j];
+    edges[p] = (int64_t)(key[j] & 0xFFFFFFFFull);
+    pair_of[p] = (uint32_t)(key[j] >> 32);
+}
+
+// offsets[i] = the first output position of pair i; offsets[n] = ne
+__global__ void k_gen_offsets(const uint32_t* pair_of, int64_t ne, int64_t n, int64_t* offsets) {
+    const int64_t p = (int64_t)blockIdx.x * DB + threadIdx.x;
+    if (p == 0) offsets[n] = ne;
+    if (p >= ne) return;
+    const uint32_t i = pair_of[p];
+    if (p == 0 || pair_of[p - 1] != i) offsets[i] = p;
+}
+
+// every cycle holds at least its birth edge: an offset left at -1 is a fault
+__global__ void k_gen_check(const int64_t* offsets, int64_t n, uint32_t* flags) {
+    const int64_t i = (int64_t)blockIdx.x * DB + threadIdx.x;
+    if (i < n && offsets[i] < 0) atomicOr(flags, FLAG_GUARD);
+}
+
 int grow(void*& p, size_t& cap, size_t bytes, size_t& total) {
     if (cap >= bytes) return 0;
     if (p) (void)hipFree(p);
@@ -1694,6 +1783,7 @@ int grow(void*& p, size_t& cap, size_t bytes, size_t& total) {
 }  // namespace
 
 int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, std::string& err) {
+    s.gen_n = -1;  // generators of an earlier run are stale
     (void)budget_left;
     const int64_t V = in.g.V;
     const int64_t m2 = in.m2;
@@ -1925,9 +2015,123 @@ void d1_emit_essential2(D1State& s, int64_t m2, const uint8_t* paired2_desc, con
                            (const uint32_t*)s.owner1, key, death, cnt);
 }
 
+int d1_generators(D1State& s, int64_t* offsets, int64_t cap_off, int64_t* edges, int64_t cap_edges,
+                  int64_t* n_pairs, int64_t* n_edges, uint32_t* flags, hipStream_t st, std::string& err) {
+    enum { G_EDGE, G_COL, G_EDGE2, G_COL2, G_LEN, G_OFF, G_KEY0, G_KEY1, G_VAL0, G_VAL1, G_HIST, G_PART };
+    static_assert(G_PART < (int)(sizeof(s.gbuf) / sizeof(s.gbuf[0])), "generator buffers");
+    auto buf = [&](int k, size_t bytes) -> void* {
+        if (grow(s.gbuf[k], s.gcap[k], std::max<size_t>(bytes, 64), s.bytes)) return nullptr;
+        return s.gbuf[k];
+    };
+    auto hip_fail = [&](const char* what) {
+        err = std::string("generators: ") + what;
+        return -5;  // DMS_E_HIP
+    };
+    auto oom = [&]() {
+        err = "generators: cannot allocate working buffers";
+        return -3;  // DMS_E_NOMEM
+    };
+    *n_pairs = 0;
+    *n_edges = 0;
+    if (s.gen_n < 0) {  // build the cycles of the last D1 run once; later calls only copy them out
+        const int64_t nc = s.ncols;
+        if (s.stats[4] >= (1ull << 32)) {
+            err = "generators: more than 2^32 published boundary entries";
+            return -7;  // DMS_E_INTERNAL
+        }
+        // 1. finite pairs: (birth edge, column)
+        uint32_t* ecol[4];
+        for (int k = 0; k < 4; ++k)
+            if (!(ecol[k] = (uint32_t*)buf(G_EDGE + k, 4 * (size_t)(nc + 1)))) return oom();
+        uint32_t* len = (uint32_t*)buf(G_LEN, 4 * (size_t)(nc + 1));
+        uint32_t* off = (uint32_t*)buf(G_OFF, 4 * (size_t)(nc + 1));
+        if (!len || !off) return oom();
+        if (hipMemsetAsync(len, 0, 4, st) != hipSuccess) return hip_fail("counter reset");
+        if (nc > 0)
+            hipLaunchKernelGGL(k_gen_pairs, dim3((unsigned)((nc + DB * EMIT_ITEMS - 1) / (DB * EMIT_ITEMS))),
+                               dim3(DB), 0, st, s.g, s.order, s.bpr, nc, (const uint64_t*)s.bndptr,
+                               (const uint64_t*)s.heap, (const uint32_t*)s.owner1, ecol[0], ecol[1], len);
+        uint32_t n32 = 0;
+        if (hipMemcpyAsync(&n32, len, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return hip_fail("pair count");
+        const int64_t n = n32;
+        int64_t total = 0, ne = 0;
+        int r2 = 0;
+        if (n > 0) {
+            // 2. pairs in increasing birth-edge order (the order of the D1 output)
+            const int ebits = 64 - __builtin_clzll((unsigned long long)(7 * s.g.V));
+            const int pbits = 64 - __builtin_clzll((unsigned long long)n);
+            uint32_t *hist = nullptr, *part = nullptr;
+            auto scratch_for = [&](int64_t m) {
+                const int64_t hn = 256 * sort_tiles(m);
+                hist = (uint32_t*)buf(G_HIST, 4 * (size_t)hn);
+                part = (uint32_t*)buf(G_PART, 4 * (size_t)std::max(scan_part_size(hn), scan_part_size(m)));
+                return hist && part;
+            };
+            if (!scratch_for(n)) return oom();
+            const int r1 = radix_sort_pairs<uint32_t>(ecol[0], ecol[1], ecol[2], ecol[3], n, 0, ebits, false, hist,
+                                                      part, st);
+            const uint32_t* col = r1 ? ecol[3] : ecol[1];
+            // 3. published lengths and their offsets
+            hipLaunchKernelGGL(k_gen_len, dim3(nblocks(n)), dim3(DB), 0, st, col, n, (const uint64_t*)s.bndptr, len);
+            exclusive_scan_u32(len, off, n, part, st);
+            uint32_t tail[2] = {0, 0};
+            if (hipMemcpyAsync(&tail[0], off + n - 1, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipMemcpyAsync(&tail[1], len + n - 1, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return hip_fail("boundary sizes");
+            total = (int64_t)tail[0] + tail[1];
+            // 4. (pair, edge) keys of every published entry, sorted
+            uint64_t* k0 = (uint64_t*)buf(G_KEY0, 8 * (size_t)total);
+            uint64_t* k1 = (uint64_t*)buf(G_KEY1, 8 * (size_t)total);
+            uint32_t* v0 = (uint32_t*)buf(G_VAL0, 4 * (size_t)total);
+            uint32_t* v1 = (uint32_t*)buf(G_VAL1, 4 * (size_t)total);
+            if (!k0 || !k1 || !v0 || !v1 || !scratch_for(std::max(n, total))) return oom();
+            hipLaunchKernelGGL(k_gen_gather, dim3(nblocks(total)), dim3(DB), 0, st, s.g, s.order, s.bpr, col,
+                               (const uint32_t*)off, n, total, (const uint64_t*)s.bndptr, (const uint64_t*)s.heap,
+                               k0);
+            r2 = radix_sort_pairs<uint64_t>(k0, v0, k1, v1, total, 0, 32 + pbits, true, hist, part, st);
+            // 5. mod-2 cancellation: keep flags (v0), output positions (v1)
+            hipLaunchKernelGGL(k_gen_keep, dim3(nblocks(total)), dim3(DB), 0, st, r2 ? k1 : k0, total, v0);
+            exclusive_scan_u32(v0, v1, total, part, st);
+            if (hipMemcpyAsync(&tail[0], v1 + total - 1, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipMemcpyAsync(&tail[1], v0 + total - 1, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return hip_fail("cycle sizes");
+            ne = (int64_t)tail[0] + tail[1];
+        }
+        s.gen_n = n;
+        s.gen_ne = ne;
+        s.gen_total = total;
+        s.gen_sorted = r2;
+    }
+    const int64_t n = s.gen_n, ne = s.gen_ne, total = s.gen_total;
+    *n_pairs = n;
+    *n_edges = ne;
+    if (cap_off < n + 1 || cap_edges < ne) return 1;
+    if (n == 0) {
+        fill_u64((uint64_t*)offsets, 0, 1, st);
+        return 0;
+    }
+    // 6. edges and offsets (pair_of: the key buffer that does not hold the keys)
+    const uint64_t* key = (const uint64_t*)s.gbuf[s.gen_sorted ? G_KEY1 : G_KEY0];
+    uint32_t* pair_of = (uint32_t*)s.gbuf[s.gen_sorted ? G_KEY0 : G_KEY1];
+    fill_u64((uint64_t*)offsets, ~0ull, n, st);
+    hipLaunchKernelGGL(k_gen_write, dim3(nblocks(total)), dim3(DB), 0, st, key, (const uint32_t*)s.gbuf[G_VAL0],
+                       (const uint32_t*)s.gbuf[G_VAL1], total, edges, pair_of);
+    hipLaunchKernelGGL(k_gen_offsets, dim3(nblocks(std::max<int64_t>(ne, 1))), dim3(DB), 0, st,
+                       (const uint32_t*)pair_of, ne, n, offsets);
+    hipLaunchKernelGGL(k_gen_check, dim3(nblocks(n)), dim3(DB), 0, st, (const int64_t*)offsets, n, flags);
+    if (hipGetLastError() != hipSuccess) return hip_fail("kernel launch");
+    return 0;
+}
+
 void d1_free(D1State& s) {
     void* ps[] = {s.cols, s.colflag, s.scanpart, s.owner1, s.bndptr, s.heap, s.scratch, s.ctrs, s.dq};
     for (void* p : ps)
+        if (p) (void)hipFree(p);
+    for (void* p : s.gbuf)
         if (p) (void)hipFree(p);
     s = D1State();
 }

@@ -34,6 +34,7 @@ struct dms_ctx {
     GridDev g{};
     int bpr = 1;
     int stage = 0;  // 0: nothing, 1: gradient, 2: D0/D2, 3: D1
+    bool batched = false;  // the last run was a batch (super-grid ids)
     int64_t ncrit[4] = {0, 0, 0, 0};
     uint32_t cap[4] = {0, 0, 0, 0};
     Buf rank, keysA, keysB, valsA, valsB, G, hist, part, flags, counters, stats;
@@ -461,6 +462,7 @@ int dms_gradient(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t fla
     int r = check_grid(ctx, grid, flags);
     if (r != DMS_OK) return r;
     HIPCHK(hipSetDevice(ctx->device));
+    ctx->batched = false;
     for (int attempt = 0; attempt < 2; ++attempt) {
         r = gradient_setup(ctx, grid);
         if (r != DMS_OK) return r;
@@ -634,6 +636,26 @@ int dms_pairs_d1(dms_ctx* ctx, dms_pair* d1, int64_t cap1, int64_t* n1) {
     r = emit_d1(ctx, d1, cap1, n1, nullptr, nullptr, nullptr, nullptr, nullptr);
     HIPCHK(hipStreamSynchronize(ctx->st));
     return r;
+}
+
+int dms_d1_generators(dms_ctx* ctx, int64_t* d_offsets, int64_t cap_offsets, int64_t* d_edges, int64_t cap_edges,
+                      int64_t* n_pairs, int64_t* n_edges) {
+    if (!ctx) return DMS_E_INVAL;
+    if (!n_pairs || !n_edges) return fail(ctx, DMS_E_INVAL, "n_pairs or n_edges is NULL");
+    if (cap_offsets < 0 || cap_edges < 0 || (cap_offsets > 0 && !d_offsets) || (cap_edges > 0 && !d_edges))
+        return fail(ctx, DMS_E_INVAL, "an output buffer is NULL or a capacity is negative");
+    if (ctx->stage < 3 || ctx->batched)
+        return fail(ctx, DMS_E_STATE, "dms_d1_generators needs dms_pairs_d1 or dms_diagram on one field first");
+    HIPCHK(hipSetDevice(ctx->device));
+    std::string err;
+    int r = d1_generators(ctx->d1, d_offsets, cap_offsets, d_edges, cap_edges, n_pairs, n_edges,
+                          P<uint32_t>(ctx->flags), ctx->st, err);
+    if (r < 0) return fail(ctx, r, err);
+    if (r == 1) return fail(ctx, DMS_E_CAPACITY, "generator output buffers too small");
+    r = check_flags(ctx);
+    if (r != DMS_OK) return r;
+    HIPCHK(hipGetLastError());
+    return DMS_OK;
 }
 
 int dms_diagram(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t flags, dms_diagram_out* out) {
@@ -928,6 +950,7 @@ int dms_diagram_batch(dms_ctx* ctx, const float* d_fields, const dms_item* items
     r = check_flags(ctx);
     if (r != DMS_OK) return r;
     ctx->stage = 3;
+    ctx->batched = true;
 
     // ---- pairs of the super grid, then per item ----
     int64_t ns[3] = {0, 0, 0};

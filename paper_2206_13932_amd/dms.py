@@ -86,6 +86,8 @@ def load_library() -> ctypes.CDLL:
     lib.dms_pairs_d1.restype = ctypes.c_int
     lib.dms_diagram.argtypes = [_p, _p, Grid, u32, ctypes.POINTER(DiagramOut)]
     lib.dms_diagram.restype = ctypes.c_int
+    lib.dms_d1_generators.argtypes = [_p, _p, i64, _p, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.dms_d1_generators.restype = ctypes.c_int
     lib.dms_debug_copy.argtypes = [_p, ctypes.c_int, _p, i64]
     lib.dms_debug_copy.restype = i64
     lib.dms_stage_ms.argtypes = [_p, ctypes.POINTER(ctypes.c_float * 8)]
@@ -177,6 +179,23 @@ class Context:
         if rc != DMS_OK:
             self._raise(rc)
         return d1[: n1.value]
+
+    def d1_generators(self):
+        """Persistent 1-cycle generators of the finite D1 pairs of the last
+        single-field run: (offsets [n + 1], edges [E]) LongTensors on the
+        device; cycle i = edges[offsets[i]:offsets[i + 1]] (edge ids,
+        ascending) belongs to the i-th finite pair of pairs_d1 / diagram."""
+        n, e = ctypes.c_int64(), ctypes.c_int64()
+        rc = self.lib.dms_d1_generators(self.h, None, 0, None, 0, ctypes.byref(n), ctypes.byref(e))
+        if rc not in (DMS_OK, DMS_E_CAPACITY):
+            self._raise(rc)
+        offsets = torch.empty(n.value + 1, dtype=torch.int64, device=self.device)
+        edges = torch.empty(max(e.value, 1), dtype=torch.int64, device=self.device)
+        rc = self.lib.dms_d1_generators(self.h, _p(offsets.data_ptr()), offsets.numel(), _p(edges.data_ptr()),
+                                        edges.numel(), ctypes.byref(n), ctypes.byref(e))
+        if rc != DMS_OK:
+            self._raise(rc)
+        return offsets, edges[: e.value]
 
     def diagram(self, field: torch.Tensor, flags: int = DMS_VIRTUAL_MAX, with_values: bool = False):
         """Whole pipeline in one call. Returns {0: pairs, 1: pairs, 2: pairs}

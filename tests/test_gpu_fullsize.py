@@ -10,7 +10,9 @@ whole field):
   infinite class at the global minimum, |D0| = c0, |D2| = c3,
   |D1| = c1 - c0 + 1 = c2 - c3);
 * at 256^3, D0 in vertex-order space against Kruskal's union-find over every
-  edge of the triangulation (an independent computation of the definition).
+  edge of the triangulation (an independent computation of the definition);
+* on the smooth fields, sampled persistent 1-cycle generators: cycles whose
+  highest edge is the birth edge.
 """
 import numpy as np
 import pytest
@@ -44,6 +46,32 @@ def _sample_vertices(shape, rank, rng, n=1500):
     # the 300 highest vertices (local maxima are likely there)
     v += list(np.argsort(rank)[-300:])
     return np.unique(np.array(v, dtype=np.int64))
+
+
+def _check_generators_sampled(shape, rank, d1, ctx):
+    """Persistent 1-cycle generators (Sec. 8) at full size: one cycle per
+    finite D1 pair; on sampled cycles (random and the longest), edge ids
+    ascending, every vertex on an even number of edges, and the highest edge
+    in the lexicographic order is the birth edge."""
+    print("[fullsize] generators", flush=True)
+    off, edges = ctx.d1_generators()
+    off, edges = off.cpu().numpy(), edges.cpu().numpy()
+    assert len(off) == len(d1) + 1 and off[0] == 0 and off[-1] == len(edges)
+    lens = np.diff(off)
+    assert (lens >= 3).all()
+    rng = np.random.default_rng(11)
+    pick = np.unique(np.concatenate([rng.choice(len(d1), size=min(1500, len(d1)), replace=False),
+                                     np.argsort(lens)[-20:]]))
+    for i in pick:
+        z = edges[off[i]:off[i + 1]]
+        assert (np.diff(z) > 0).all(), i
+        ev = oracle.simplex_vertices(shape, 1, z)
+        _, deg = np.unique(ev.ravel(), return_counts=True)
+        assert (deg % 2 == 0).all(), i
+        r = np.sort(rank[ev].astype(np.int64), axis=1)[:, ::-1]
+        top = np.lexsort((r[:, 1], r[:, 0]))[-1]
+        assert z[top] == d1[i, 0], i
+    print(f"[fullsize] generators: {len(d1)} cycles, {len(edges)} edges, longest {lens.max()}", flush=True)
 
 
 @pytest.mark.gpu
@@ -86,6 +114,8 @@ def test_fullsize_gradient_samples_and_invariants(name):
     # canonical order: births strictly increasing within the finite part
     for p in (d0[:-1], d1, d2):
         assert (np.diff(p[:, 0]) > 0).all()
+    if name != "c_noise512":
+        _check_generators_sampled(shape, rank, d1, ctx)
     if name == "a_smooth256":
         b = rank[d0[:-1, 0]].astype(np.int64)
         ev = oracle.simplex_vertices(shape, 1, d0[:-1, 1])

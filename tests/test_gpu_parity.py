@@ -201,7 +201,8 @@ def test_error_paths():
 def test_parity_d1_every_deferral_pass():
     """Tiny working heaps force columns through all D1 passes (LDS heaps of
     two sizes, then workgroup passes), and every cached boundary longer than
-    two entries is added by the full merge; pairs must not change."""
+    two entries is added by the full merge; pairs must not change, and the
+    cycles published by every kind of pass must be valid generators."""
     import os
     import subprocess
     import sys
@@ -220,6 +221,11 @@ def test_parity_d1_every_deferral_pass():
         "    longs += st[41]\n"
         "    for d in range(3):\n"
         "        assert np.array_equal(out[d].cpu().numpy(), res.pairs[d]), (name, d)\n"
+        "    off, edges = ctx.d1_generators()\n"
+        "    d1 = out[1].cpu().numpy()\n"
+        "    fin = d1[d1[:, 1] >= 0]\n"
+        "    st = oracle.bf_check_cycles(res.shape, res.rank, fin, off.cpu().numpy(), edges.cpu().numpy())\n"
+        "    assert (st == 0).all(), (name, np.bincount(st))\n"
         "assert longs > 0\n"
         "print('ok')\n")
     env = dict(os.environ, DMS_D1_TEST_PLAN="1")
