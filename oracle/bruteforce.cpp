@@ -16,6 +16,8 @@
  *    vertex; the expansion-based gradient has exactly that many critical
  *    cells per dimension in each lower star (Sec. 1.1, Sec. 2.6).
  *  - bf_counts: numbers of vertices, edges, triangles and tetrahedra.
+ * A grid with nz = 1 is the 2D grid of the plane z = 0, built from its
+ * triangles (bf_lower_link_betti is for 3D grids only).
  */
 #include <algorithm>
 #include <array>
@@ -57,16 +59,32 @@ void tetrahedra(i64 nx, i64 ny, i64 nz, std::vector<std::array<i64, 4>>& tets) {
                 }
 }
 
+/* A 2D grid (nz = 1): each unit square is cut into the 2 monotone lattice
+ * paths from its lowest to its highest corner (the same triangulation the
+ * plane z = 0 receives from the 3D one). Padded with -1. */
+void triangles2d(i64 nx, i64 ny, std::vector<std::array<i64, 4>>& tris) {
+    tris.clear();
+    for (i64 y = 0; y + 1 < ny; ++y)
+        for (i64 x = 0; x + 1 < nx; ++x) {
+            const i64 a = x + nx * y, b = a + 1, c = a + nx, d = a + nx + 1;
+            tris.push_back({a, b, d, -1});
+            tris.push_back({a, c, d, -1});
+        }
+}
+
 void all_simplices(i64 nx, i64 ny, i64 nz, Complex& K) {
-    std::vector<std::array<i64, 4>> tets;
-    tetrahedra(nx, ny, nz, tets);
+    std::vector<std::array<i64, 4>> tops;
+    if (nz == 1) triangles2d(nx, ny, tops);
+    else tetrahedra(nx, ny, nz, tops);
+    const int nv = nz == 1 ? 3 : 4;
     std::set<Verts> seen;
-    for (auto& t : tets)
-        for (int m = 1; m < 16; ++m) {
+    for (auto& t : tops)
+        for (int m = 1; m < (1 << nv); ++m) {
             Verts v = {-1, -1, -1, -1};
             int k = 0;
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < nv; ++i)
                 if (m & (1 << i)) v[k++] = t[i];
+            std::sort(v.begin(), v.begin() + k);
             seen.insert(v);
         }
     K.simp.assign(seen.begin(), seen.end());

@@ -18,6 +18,10 @@
  *      with the virtual maximum for the domain boundary       (Sec. 5.2)
  *   7. D1 by PairCriticalSimplices on the unpaired 2-saddles  (Sec. 4, Alg. "PairCriticalSimplices")
  *   8. classes of infinite persistence                        (Sec. 6)
+ * A grid with nz = 1 is a 2D grid (the plane z = 0 of the same
+ * triangulation): there D1 comes from the dual union-find of step 6 applied
+ * to the 1-saddles and triangles, and steps 6 (in 3D form) and 7 are skipped
+ * (Sec. 3: the sandwich is needed for 3D data only).
  *
  * Readings where the paper is silent (each listed in the design notes):
  *   - vertex id v = x + nx*(y + ny*z); ties of f broken by the lower vertex id;
@@ -460,36 +464,39 @@ void diagram0(Ctx& C, std::vector<char>& edge_paired, std::vector<char>& min_pai
 
 /* ------------------------------------------------------------------ D2 -- */
 
-/* Sec. 5.2: by duality the stable set of a critical triangle is followed
- * through tetrahedra: enter a cofacet tet; while it is regular, leave through
- * its paired triangle into the tet on the other side. Leaving the domain
- * reaches the virtual maximum (value +infinity, the outside). Arcs are merged
- * in decreasing order; the younger root is the lower tet. */
+/* Sec. 5.2: by duality the stable set of a critical (n-1)-saddle, n the
+ * dimension of the grid's top simplices, is followed through n-simplices:
+ * enter a cofacet; while it is regular, leave through its paired facet into
+ * the n-simplex on the other side. Leaving the domain reaches the virtual
+ * maximum (value +infinity, the outside). Arcs are merged in decreasing
+ * order; the younger root is the lower n-simplex. On a 3D grid this is D2
+ * over the 2-saddles (triangles into tetrahedra); on a 2D grid it is D1 over
+ * the 1-saddles (edges into triangles), where no sandwich is needed (Sec. 3). */
 const i64 VIRTUAL = -1;
 
-void diagram2(Ctx& C, std::vector<char>& tri_paired) {
+void diagram_dual(Ctx& C, int d, std::vector<char>& saddle_paired, std::vector<i64>& pairs) {
+    const int top = d + 1;
     std::vector<i64> cof;
-    auto other_side = [&](i64 tri, i64 tet) {
-        C.cofacets(2, tri, cof);
+    auto other_side = [&](i64 facet, i64 cell) {
+        C.cofacets(d, facet, cof);
         for (i64 t : cof)
-            if (t != tet) return t;
+            if (t != cell) return t;
         return VIRTUAL;
     };
-    auto ascend = [&](i64 tet) {
-        while (tet != VIRTUAL) {
-            i64 p = C.partner[3][tet];
-            if (p == -1) return tet;
-            tet = other_side(p / 4, tet);
+    auto ascend = [&](i64 cell) {
+        while (cell != VIRTUAL) {
+            i64 p = C.partner[top][cell];
+            if (p == -1) return cell;
+            cell = other_side(p / 4, cell);
         }
         return VIRTUAL;
     };
     UF uf;
-    const std::vector<i64>& C2 = C.crit[2];
-    tri_paired.assign(C2.size(), 0);
-    std::map<i64, Key> tet_key;
-    for (size_t kk = C2.size(); kk-- > 0;) {
-        i64 t = C2[kk];
-        C.cofacets(2, t, cof);
+    const std::vector<i64>& S = C.crit[d];
+    saddle_paired.assign(S.size(), 0);
+    for (size_t kk = S.size(); kk-- > 0;) {
+        i64 t = S[kk];
+        C.cofacets(d, t, cof);
         i64 side[2] = {VIRTUAL, VIRTUAL};
         for (size_t s = 0; s < cof.size() && s < 2; ++s) side[s] = cof[s];
         i64 ma = ascend(side[0]), mb = ascend(side[1]);
@@ -501,12 +508,12 @@ void diagram2(Ctx& C, std::vector<char>& tri_paired) {
         i64 young;
         if (ra == VIRTUAL) young = rb;
         else if (rb == VIRTUAL) young = ra;
-        else young = C.key(3, ra) < C.key(3, rb) ? ra : rb;
+        else young = C.key(top, ra) < C.key(top, rb) ? ra : rb;
         i64 old = young == ra ? rb : ra;
-        C.d2.push_back(t);
-        C.d2.push_back(young);
+        pairs.push_back(t);
+        pairs.push_back(young);
         uf.parent[young] = old;
-        tri_paired[kk] = 1;
+        saddle_paired[kk] = 1;
     }
 }
 
@@ -600,11 +607,13 @@ void run(Ctx& C, const float* f) {
     double t2 = now();
     critical_sets(C);
     double t3 = now();
-    std::vector<char> e0, m0, t2p;
+    std::vector<char> e0, m0, t2p, e1p;
+    const bool flat = C.g.n[2] == 1;  /* a 2D grid: the plane z = 0 */
     diagram0(C, e0, m0);
-    diagram2(C, t2p);
+    if (flat) diagram_dual(C, 1, e1p, C.d1);
+    else diagram_dual(C, 2, t2p, C.d2);
     double t4 = now();
-    diagram1(C, e0, t2p);
+    if (!flat) diagram1(C, e0, t2p);
     double t5 = now();
     /* Sec. 6: what stays unpaired is a class of infinite persistence */
     for (size_t k = 0; k < C.crit[0].size(); ++k)
@@ -618,9 +627,10 @@ void run(Ctx& C, const float* f) {
     sort_pairs(C.d0);
     sort_pairs(C.d1);
     sort_pairs(C.d2);
-    /* generators in the order of the finite D1 pairs, edge ids ascending */
+    /* generators in the order of the finite D1 pairs, edge ids ascending
+     * (3D only: on a 2D grid D1 comes from the dual union-find) */
     C.gen1_off.push_back(0);
-    for (size_t k = 0; k < C.d1.size(); k += 2) {
+    for (size_t k = 0; k < C.d1.size() && !flat; k += 2) {
         if (C.d1[k + 1] < 0) continue;
         std::vector<i64> z = C.gen1.at(C.d1[k + 1]);
         std::sort(z.begin(), z.end());
@@ -656,7 +666,8 @@ int orc_run(int64_t nx, int64_t ny, int64_t nz, const float* f, void** out, char
     Ctx* C = new Ctx();
     C->g.n[0] = nx; C->g.n[1] = ny; C->g.n[2] = nz;
     try {
-        if (nx < 2 || ny < 2 || nz < 2) throw std::invalid_argument("every grid side must be >= 2");
+        if (nx < 2 || ny < 2 || nz < 1)
+            throw std::invalid_argument("nx and ny must be >= 2, nz >= 1 (nz = 1: a 2D grid)");
         run(*C, f);
     } catch (const std::exception& e) {
         if (err && errlen > 0) { std::strncpy(err, e.what(), errlen - 1); err[errlen - 1] = 0; }
