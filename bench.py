@@ -26,6 +26,11 @@ WORKLOADS = {
                       text="256^3 float32, 32 Gaussians + 1% uniform noise, seed 0"),
     "noise256": dict(shape=(256, 256, 256), kind="noise", seed=0,
                      text="256^3 float32 i.i.d. uniform noise, seed 0"),
+    # 2D grids (nz = 1) at the paper's 2D resolution, 4096^2
+    "smooth4096_2d": dict(shape=(1, 4096, 4096), kind="gaussians", k=64, r=0.005, seed=0,
+                          text="4096^2 float32 (2D), 64 Gaussians + 0.5% uniform noise, seed 0"),
+    "noise4096_2d": dict(shape=(1, 4096, 4096), kind="noise", seed=0,
+                         text="4096^2 float32 (2D) i.i.d. uniform noise, seed 0"),
 }
 METRIC = "Mvertices/s full D0+D1+D2 (512^3 f32), % HBM peak; served req/s + p99"
 HBM_PEAK_GBS = 8000.0
@@ -65,13 +70,17 @@ def gradient_algorithmic_bytes(V, ncrit):
 
 def cpu_baseline(field, crop):
     import oracle
-    sub = field[:crop, :crop, :crop].copy()
+    if field.shape[0] == 1:  # 2D grid: a square corner crop with as many vertices
+        side = int(round(crop ** 1.5))
+        sub = field[:, :side, :side].copy()
+    else:
+        sub = field[:crop, :crop, :crop].copy()
     t0 = time.perf_counter()
     oracle.run(sub)
     dt = time.perf_counter() - t0
     return {"value": round(sub.size / dt / 1e6, 4), "unit": "Mvertices/s", "cores": 1, "kind": "oracle",
-            "sample": f"sequential oracle, whole pipeline on the {crop}^3 corner crop of the same field "
-                      f"({sub.size} vertices, {dt:.1f} s)"}
+            "sample": f"sequential oracle, whole pipeline on the {'x'.join(map(str, sub.shape[::-1]))} corner "
+                      f"crop of the same field ({sub.size} vertices, {dt:.1f} s)"}
 
 
 def serving_bench(n_requests, rate, plain_sample, calib):
@@ -242,7 +251,7 @@ def main():
               f"{int((lens > 1000).sum())}, > 10000: {int((lens > 10000).sum())}", file=sys.stderr, flush=True)
 
     generators = None
-    if not args.no_generators:
+    if not args.no_generators and field.shape[0] > 1:  # 3D only: 2D grids have no sandwich
         # persistent 1-cycle generators of the same diagram: the first export
         # sizes the context's working buffers, the second (after a fresh
         # diagram) is timed, from the call to the cycles in HBM

@@ -24,6 +24,10 @@
  *      tetrahedra types 0..5:  (1,2,4) (1,4,2) (2,1,4) (2,4,1) (4,1,2) (4,2,1)
  *  - Pairs are sorted by (birth, death) as int64, classes of infinite
  *    persistence (death = -1) last.
+ *  - A grid with nz = 1 is a 2D grid: the plane z = 0 of the same
+ *    triangulation (edges of types 0, 1, 2; triangles of types 0 and 3).
+ *    There the method computes D0 and, from the stable sets of the
+ *    1-saddles, D1 (Sec. 3: the sandwich is for 3D data only); D2 is empty.
  *  - All pointers named d_* are device pointers on the context's device.
  *    The caller owns them; the library only borrows them for the duration of
  *    the call's work on the context's stream.
@@ -44,7 +48,8 @@ extern "C" {
 typedef struct dms_ctx dms_ctx;
 
 typedef struct {
-    int32_t nx, ny, nz; /* vertex counts per axis, each >= 2, 12*nx*ny*nz < 2^32 */
+    int32_t nx, ny, nz; /* vertex counts per axis: nx, ny >= 2; nz >= 2, or 1 for a
+                           2D grid; 12*nx*ny*nz < 2^32 */
 } dms_grid;
 
 typedef struct {
@@ -99,6 +104,8 @@ const char* dms_last_error(const dms_ctx* ctx);
 int dms_gradient(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t flags, dms_gradient_info* info);
 
 /* D0 (Sec. 5.1) and D2 (Sec. 5.2) from the gradient left by dms_gradient.
+ * On a 2D grid the stable sets of the 1-saddles are traced here as well and
+ * D2 holds only maxima no saddle kills (none with DMS_VIRTUAL_MAX).
  * Writes the pairs (sorted, infinite classes last) to d0 / d2 (device).
  * On DMS_E_CAPACITY the required counts are in *n0 / *n2 and nothing is
  * written. Returns DMS_E_STATE without a prior dms_gradient. */
@@ -106,7 +113,9 @@ int dms_pairs_d0_d2(dms_ctx* ctx, dms_pair* d0, int64_t cap0, int64_t* n0, dms_p
                     int64_t* n2);
 
 /* D1 by PairCriticalSimplices on the 2-saddles left unpaired by D2 (Sec. 3
- * and 4, Alg. "PairCriticalSimplices"), with boundary caching and clearing.
+ * and 4, Alg. "PairCriticalSimplices"), with boundary caching and clearing;
+ * on a 2D grid, the (1-saddle, maximum) pairs of the dual union-find over
+ * the stable sets (Sec. 5.2 one dimension down).
  * Requires dms_pairs_d0_d2 first (DMS_E_STATE otherwise). */
 int dms_pairs_d1(dms_ctx* ctx, dms_pair* d1, int64_t cap1, int64_t* n1);
 
@@ -121,8 +130,9 @@ int dms_diagram(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t flag
  * columns were reduced; the birth edge, the death triangle and the three
  * properties above do not.
  *
- * Needs dms_pairs_d1 or dms_diagram on one field (not a batch) first:
- * DMS_E_STATE otherwise. Cycle i belongs to the i-th finite pair of the D1
+ * Needs dms_pairs_d1 or dms_diagram on one 3D field (not a batch, not a 2D
+ * grid, where D1 comes from the dual union-find) first: DMS_E_STATE
+ * otherwise. Cycle i belongs to the i-th finite pair of the D1
  * list those calls write (finite pairs come first, in increasing birth-edge
  * id). Output, device memory owned by the caller:
  *   d_offsets[0..n_pairs]  int64, cycle i = d_edges[d_offsets[i] .. d_offsets[i+1])

@@ -35,6 +35,7 @@ struct dms_ctx {
     int bpr = 1;
     int stage = 0;  // 0: nothing, 1: gradient, 2: D0/D2, 3: D1
     bool batched = false;  // the last run was a batch (super-grid ids)
+    bool flat = false;     // the last grid was 2D (nz = 1)
     int64_t ncrit[4] = {0, 0, 0, 0};
     uint32_t cap[4] = {0, 0, 0, 0};
     Buf rank, keysA, keysB, valsA, valsB, G, hist, part, flags, counters, stats;
@@ -175,6 +176,40 @@ __global__ __launch_bounds__(OB) void k_emit_d2(const uint64_t* bnd, const uint8
             const uint32_t pos = (uint32_t)(bnd[j] >> 32);  // 1 = highest maximum
             key[at] = c2[m2 - 1 - j];
             death[at] = c3[m3 - pos];
+        });
+}
+
+// 2D, D1: paired column j (decreasing edges) -> (edge, triangle of the pivot
+// age); then the edges paired neither here nor in D0 (infinite classes)
+__global__ __launch_bounds__(OB) void k_emit_flat1(const uint64_t* bnd, const uint8_t* paired, const uint32_t* c1,
+                                                   int64_t m1, const uint32_t* c2, int64_t m2,
+                                                   const uint8_t* paired0, uint64_t* key, uint32_t* death,
+                                                   uint32_t* cnt) {
+    const int64_t first = (int64_t)blockIdx.x * OB * EMIT_ITEMS;
+    block_append<OB, EMIT_ITEMS>(
+        cnt, first, m1, [&](int64_t j, uint64_t&) { return paired[j] != 0; },
+        [&](int64_t j, uint64_t, uint32_t at) {
+            const uint32_t pos = (uint32_t)(bnd[j] >> 32);  // 1 = highest maximum
+            key[at] = c1[m1 - 1 - j];
+            death[at] = c2[m2 - pos];
+        });
+    block_append<OB, EMIT_ITEMS>(
+        cnt, first, m1, [&](int64_t i, uint64_t&) { return !paired0[i] && !paired[m1 - 1 - i]; },
+        [&](int64_t i, uint64_t, uint32_t at) {
+            key[at] = (1ull << 32) | c1[i];
+            death[at] = EMPTY32;
+        });
+}
+
+// 2D, D2: maxima no saddle killed (none with the virtual maximum on)
+__global__ __launch_bounds__(OB) void k_emit_flat2(const uint32_t* owner, const uint32_t* c2, int64_t m2,
+                                                   uint64_t* key, uint32_t* death, uint32_t* cnt) {
+    block_append<OB, EMIT_ITEMS>(
+        cnt, (int64_t)blockIdx.x * OB * EMIT_ITEMS, m2,
+        [&](int64_t i, uint64_t&) { return owner[m2 - i] == EMPTY32; },  // position m2 - i is c2[i]
+        [&](int64_t i, uint64_t, uint32_t at) {
+            key[at] = (1ull << 32) | c2[i];
+            death[at] = EMPTY32;
         });
 }
 
@@ -449,7 +484,8 @@ static int gradient_finish(dms_ctx* ctx, dms_gradient_info* info) {
 }
 
 static int check_grid(dms_ctx* ctx, dms_grid grid, uint32_t flags) {
-    if (grid.nx < 2 || grid.ny < 2 || grid.nz < 2) return fail(ctx, DMS_E_INVAL, "every grid side must be >= 2");
+    if (grid.nx < 2 || grid.ny < 2 || grid.nz < 1)
+        return fail(ctx, DMS_E_INVAL, "nx and ny must be >= 2 and nz >= 1 (nz = 1: a 2D grid)");
     const int64_t V = (int64_t)grid.nx * grid.ny * grid.nz;
     if (12 * V >= (int64_t)0xFFFFFFFFll) return fail(ctx, DMS_E_INVAL, "grid too large: 12*V must stay below 2^32");
     if (!(flags & DMS_VIRTUAL_MAX)) return fail(ctx, DMS_E_INVAL, "DMS_VIRTUAL_MAX is required");
@@ -463,6 +499,7 @@ int dms_gradient(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t fla
     if (r != DMS_OK) return r;
     HIPCHK(hipSetDevice(ctx->device));
     ctx->batched = false;
+    ctx->flat = grid.nz == 1;
     for (int attempt = 0; attempt < 2; ++attempt) {
         r = gradient_setup(ctx, grid);
         if (r != DMS_OK) return r;
@@ -497,6 +534,27 @@ static int run_d0_d2(dms_ctx* ctx) {
     reduce_pairs(P<uint32_t>(ctx->na0), P<uint32_t>(ctx->nb0), m1, P<uint32_t>(ctx->owner0), P<uint64_t>(ctx->bnd0),
                  P<uint32_t>(ctx->flags), stats, next + 2, st);
     settled_columns(P<uint64_t>(ctx->bnd0), P<uint32_t>(ctx->owner0), m1, P<uint8_t>(ctx->paired1), st);
+    if (ctx->flat) {
+        // 2D: the maxima's diagram is D1, from the stable sets of the 1-saddles
+        // (Sec. 5.2 one dimension down; no sandwich, Sec. 3); virtual maximum = age 0
+        ENSURE(ctx->tet2pos, 4 * 2 * V);
+        ENSURE(ctx->na2, 4 * m1);
+        ENSURE(ctx->nb2, 4 * m1);
+        ENSURE(ctx->owner2, 4 * (m2 + 1));
+        ENSURE(ctx->bnd2, 8 * m1);
+        ENSURE(ctx->paired2, m1);
+        tri_positions_flat(P<uint32_t>(ctx->csorted[2]), m2, P<uint32_t>(ctx->tet2pos), st);
+        trace_flat(ctx->g, P<uint8_t>(ctx->G), P<uint32_t>(ctx->tet2pos), P<uint32_t>(ctx->cid[1]),
+                   P<uint32_t>(ctx->cpos[1]), m1, P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2),
+                   P<uint32_t>(ctx->flags), next + 1, st);
+        fill_u32(P<uint32_t>(ctx->owner2), EMPTY32, m2 + 1, st);
+        fill_u64(P<uint64_t>(ctx->bnd2), EMPTY64, m1, st);
+        reduce_pairs(P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2), m1, P<uint32_t>(ctx->owner2),
+                     P<uint64_t>(ctx->bnd2), P<uint32_t>(ctx->flags), stats + 2, next + 3, st);
+        settled_columns(P<uint64_t>(ctx->bnd2), P<uint32_t>(ctx->owner2), m1, P<uint8_t>(ctx->paired2), st);
+        (void)m3;
+        return DMS_OK;
+    }
     // D2 (Sec. 5.2), virtual maximum = age 0
     ENSURE(ctx->tet2pos, 4 * 6 * V);
     ENSURE(ctx->na2, 4 * m2);
@@ -546,7 +604,13 @@ static int emit_d2(dms_ctx* ctx, dms_pair* d2, int64_t cap2, int64_t* n2, int64_
     ENSURE(ctx->okey, 8 * cap);
     ENSURE(ctx->od, 4 * cap);
     HIPCHK(hipMemsetAsync(ctx->ocnt.p, 0, 4, st));
-    if (m2 > 0)
+    if (ctx->flat) {
+        if (m2 > 0)
+            hipLaunchKernelGGL(k_emit_flat2, dim3(nb_emit(m2)), dim3(OB), 0, st, P<uint32_t>(ctx->owner2),
+                               P<uint32_t>(ctx->csorted[2]), m2, P<uint64_t>(ctx->okey), P<uint32_t>(ctx->od),
+                               P<uint32_t>(ctx->ocnt));
+        with_essential = false;
+    } else if (m2 > 0)
         hipLaunchKernelGGL(k_emit_d2, dim3(nb_emit(m2)), dim3(OB), 0, st, P<uint64_t>(ctx->bnd2),
                            P<uint8_t>(ctx->paired2), P<uint32_t>(ctx->csorted[2]), m2, P<uint32_t>(ctx->csorted[3]),
                            m3, P<uint64_t>(ctx->okey), P<uint32_t>(ctx->od), P<uint32_t>(ctx->ocnt));
@@ -585,6 +649,11 @@ int dms_pairs_d0_d2(dms_ctx* ctx, dms_pair* d0, int64_t cap0, int64_t* n0, dms_p
 }
 
 static int run_d1(dms_ctx* ctx) {
+    if (ctx->flat) {  // 2D: D1 came from the dual tracing with D0 (no sandwich)
+        ctx->d1.ncols = 0;
+        ctx->d1.gen_n = -1;
+        return DMS_OK;
+    }
     D1Inputs in;
     in.g = ctx->g;
     in.G = P<uint8_t>(ctx->G);
@@ -612,8 +681,16 @@ static int emit_d1(dms_ctx* ctx, dms_pair* d1, int64_t cap1, int64_t* n1, int64_
     ENSURE(ctx->okey, 8 * cap);
     ENSURE(ctx->od, 4 * cap);
     HIPCHK(hipMemsetAsync(ctx->ocnt.p, 0, 4, st));
-    d1_emit(ctx->d1, m1, P<uint8_t>(ctx->paired1), P<uint32_t>(ctx->csorted[1]), P<uint64_t>(ctx->okey),
-            P<uint32_t>(ctx->od), P<uint32_t>(ctx->ocnt), st);
+    if (ctx->flat) {
+        if (m1 > 0)
+            hipLaunchKernelGGL(k_emit_flat1, dim3(nb_emit(m1)), dim3(OB), 0, st, P<uint64_t>(ctx->bnd2),
+                               P<uint8_t>(ctx->paired2), P<uint32_t>(ctx->csorted[1]), m1,
+                               P<uint32_t>(ctx->csorted[2]), ctx->ncrit[2], P<uint8_t>(ctx->paired1),
+                               P<uint64_t>(ctx->okey), P<uint32_t>(ctx->od), P<uint32_t>(ctx->ocnt));
+    } else {
+        d1_emit(ctx->d1, m1, P<uint8_t>(ctx->paired1), P<uint32_t>(ctx->csorted[1]), P<uint64_t>(ctx->okey),
+                P<uint32_t>(ctx->od), P<uint32_t>(ctx->ocnt), st);
+    }
     uint32_t cnt = 0;
     int r = read_counter(ctx, &cnt);
     if (r != DMS_OK) return r;
@@ -646,6 +723,8 @@ int dms_d1_generators(dms_ctx* ctx, int64_t* d_offsets, int64_t cap_offsets, int
         return fail(ctx, DMS_E_INVAL, "an output buffer is NULL or a capacity is negative");
     if (ctx->stage < 3 || ctx->batched)
         return fail(ctx, DMS_E_STATE, "dms_d1_generators needs dms_pairs_d1 or dms_diagram on one field first");
+    if (ctx->flat)
+        return fail(ctx, DMS_E_STATE, "generators come from the sandwich of 3D grids; on a 2D grid D1 is dual");
     HIPCHK(hipSetDevice(ctx->device));
     std::string err;
     int r = d1_generators(ctx->d1, d_offsets, cap_offsets, d_edges, cap_edges, n_pairs, n_edges,

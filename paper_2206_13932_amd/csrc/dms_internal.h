@@ -71,6 +71,12 @@ void trace_d0(const GridDev& g, const uint8_t* G, const uint32_t* rank, const ui
 void tet_positions(const uint32_t* c3_sorted, int64_t m, uint32_t* tet2pos, hipStream_t st);
 void trace_d2(const GridDev& g, const uint8_t* G, const uint32_t* tet2pos, const uint32_t* c2, const uint32_t* pos,
               int64_t m, uint32_t* na, uint32_t* nb, uint32_t* flags, unsigned long long* next, hipStream_t st);
+// 2D grids (nz = 1): positions of the plane's critical triangles (index
+// anchor * 2 + (type == 3), 1 = highest) and the dual tracing of the
+// critical edges into triangles, arcs at the edges' decreasing positions
+void tri_positions_flat(const uint32_t* c2_sorted, int64_t m, uint32_t* tri2pos, hipStream_t st);
+void trace_flat(const GridDev& g, const uint8_t* G, const uint32_t* tri2pos, const uint32_t* c1, const uint32_t* pos,
+                int64_t m, uint32_t* na, uint32_t* nb, uint32_t* flags, unsigned long long* next, hipStream_t st);
 void reduce_pairs(const uint32_t* na, const uint32_t* nb, int64_t m, uint32_t* owner, uint64_t* bnd,
                   uint32_t* flags, unsigned long long* stats, unsigned long long* next, hipStream_t st);
 void settled_columns(const uint64_t* bnd, const uint32_t* owner, int64_t m, uint8_t* paired, hipStream_t st);

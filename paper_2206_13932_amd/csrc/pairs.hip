@@ -1,4 +1,5 @@
-// Extremum-saddle pairs: D0 (Sec. 5.1) and D2 (Sec. 5.2).
+// Extremum-saddle pairs: D0 (Sec. 5.1) and D2 (Sec. 5.2); on 2D grids the
+// maxima's diagram D1 by the same dual tracing one dimension down.
 //
 // Tracing. D0: each critical edge follows its two descending v-paths (a
 // regular vertex continues through its paired edge) to minima. D2: each
@@ -207,6 +208,118 @@ __global__ __launch_bounds__(PB) void k_trace_d2(GridDev g, const uint8_t* __res
     }
 }
 
+// ---- 2D grids (nz = 1) ---------------------------------------------------
+// On a 2D grid the diagram of the maxima is D1, taken from the stable sets
+// of the 1-saddles exactly as D2 is in 3D, one dimension down (Sec. 3, 5.2):
+// each critical edge follows, on both sides, the dual v-path through
+// triangles (a regular triangle is left through its paired edge into the
+// triangle on the other side) to a maximum or, across the boundary of the
+// square, to the virtual maximum. The plane's triangles are types 0 (steps
+// x then y) and 3 (y then x) of the 3D id scheme.
+
+// in-plane cofacet triangles of the edge with anchor a at (x, y) and step mask m
+__device__ inline void edge_cofacets_flat(const GridDev& g, int64_t a, int x, int y, int m, Simp cf[2], bool ok[2]) {
+    if (m == 1) {  // x edge: type 0 at a (above), type 3 at a - y (below)
+        cf[0] = Simp{a, 0};
+        ok[0] = y + 1 < g.ny;
+        cf[1] = Simp{a - g.sy, 3};
+        ok[1] = y > 0;
+    } else if (m == 2) {  // y edge: type 3 at a (right), type 0 at a - x (left)
+        cf[0] = Simp{a, 3};
+        ok[0] = x + 1 < g.nx;
+        cf[1] = Simp{a - 1, 0};
+        ok[1] = x > 0;
+    } else {  // diagonal: the two triangles of the square at a
+        cf[0] = Simp{a, 0};
+        cf[1] = Simp{a, 3};
+        ok[0] = ok[1] = true;
+    }
+}
+
+// position of a plane triangle in the decreasing list of maxima (1 = highest)
+__device__ inline int64_t tri_slot_flat(const Simp& t) { return t.anchor * 2 + (t.type == 3 ? 1 : 0); }
+
+// path 2i + s of critical edge c1[i]: side s to a maximum's position (0 =
+// virtual maximum), written at the edge's position in the decreasing order
+__global__ __launch_bounds__(PB) void k_trace_flat(GridDev g, const uint8_t* __restrict__ G,
+                                                   const uint32_t* __restrict__ tri2pos,
+                                                   const uint32_t* __restrict__ c1, const uint32_t* __restrict__ pos,
+                                                   int64_t m, uint32_t* __restrict__ na, uint32_t* __restrict__ nb,
+                                                   uint32_t* flags, unsigned long long* next) {
+    const int64_t V = g.V;
+    bool have = false, ok = false;
+    int64_t steps = 0, k = 0, pb = 0, pe = 0;
+    Simp T{0, 0};
+    uint32_t* out = nullptr;
+    for (;;) {
+        if (!take_path(!have, next, 2 * m, k, pb, pe)) break;
+        if (!have) {
+            const int64_t i = k >> 1;
+            const uint32_t e = c1[i];
+            const int64_t a = e / 7;
+            int x, y, z;
+            coords_of(g, a, x, y, z);
+            Simp cf[2];
+            bool cok[2];
+            edge_cofacets_flat(g, a, x, y, (int)(e % 7) + 1, cf, cok);
+            const int side = (int)(k & 1);
+            T = cf[side];
+            ok = cok[side];
+            out = (side ? nb : na) + (m - 1 - (int64_t)pos[i]);
+            steps = 0;
+            have = true;
+        }
+        if (!ok) {  // virtual maximum
+            *out = 0;
+            have = false;
+            continue;
+        }
+        const uint8_t c = G[(int64_t)(8 + T.type) * V + T.anchor];
+        if (c == CODE_CRIT) {
+            *out = tri2pos[tri_slot_flat(T)];
+            have = false;
+            continue;
+        }
+        // a plane triangle can only be paired with one of its edges (0x80 |
+        // the chain position of the vertex the edge leaves out)
+        if (steps >= PATH_GUARD || (c & 0xFC) != 0x80 || (c & 3) == 3) {
+            atomicOr(flags, FLAG_GUARD);
+            *out = 0;
+            have = false;
+            continue;
+        }
+        ++steps;
+        const int p = c & 3;
+        const int s0 = T.type == 0 ? 1 : 2, s1 = 3 - s0;  // chain steps: x then y, or y then x
+        int64_t ea = T.anchor;
+        int em;
+        if (p == 0) {  // edge (v1, v2): one step s1 from v1
+            ea += lin_of_mask(g, s0);
+            em = s1;
+        } else if (p == 1) {  // edge (v0, v2): the diagonal
+            em = 3;
+        } else {  // edge (v0, v1)
+            em = s0;
+        }
+        int x, y, z;
+        coords_of(g, ea, x, y, z);
+        Simp cf[2];
+        bool cok[2];
+        edge_cofacets_flat(g, ea, x, y, em, cf, cok);
+        const int o = (cf[0].anchor == T.anchor && cf[0].type == T.type) ? 1 : 0;
+        ok = cok[o];
+        T = cf[o];
+    }
+}
+
+__global__ void k_tri_positions_flat(const uint32_t* __restrict__ c2, int64_t m, uint32_t* __restrict__ tri2pos) {
+    const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
+    if (i < m) {
+        const uint32_t t = c2[i];
+        tri2pos[(int64_t)(t / 12) * 2 + (t % 12 == 3 ? 1 : 0)] = (uint32_t)(m - i);  // highest -> 1
+    }
+}
+
 __global__ void k_tet_positions(const uint32_t* __restrict__ c3, int64_t m, uint32_t* __restrict__ tet2pos) {
     const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
     if (i < m) tet2pos[c3[i]] = (uint32_t)(m - i);  // highest tet -> 1
@@ -335,6 +448,15 @@ void trace_d2(const GridDev& g, const uint8_t* G, const uint32_t* tet2pos, const
     if (m > 0)
         hipLaunchKernelGGL(k_trace_d2, dim3(trace_blocks(2 * m)), dim3(PB), 0, st, g, G, tet2pos, c2, pos, m, na, nb,
                            flags, next);
+}
+void tri_positions_flat(const uint32_t* c2_sorted, int64_t m, uint32_t* tri2pos, hipStream_t st) {
+    if (m > 0) hipLaunchKernelGGL(k_tri_positions_flat, dim3(nblocks(m)), dim3(PB), 0, st, c2_sorted, m, tri2pos);
+}
+void trace_flat(const GridDev& g, const uint8_t* G, const uint32_t* tri2pos, const uint32_t* c1, const uint32_t* pos,
+                int64_t m, uint32_t* na, uint32_t* nb, uint32_t* flags, unsigned long long* next, hipStream_t st) {
+    if (m > 0)
+        hipLaunchKernelGGL(k_trace_flat, dim3(trace_blocks(2 * m)), dim3(PB), 0, st, g, G, tri2pos, c1, pos, m, na,
+                           nb, flags, next);
 }
 void reduce_pairs(const uint32_t* na, const uint32_t* nb, int64_t m, uint32_t* owner, uint64_t* bnd,
                   uint32_t* flags, unsigned long long* stats, unsigned long long* next, hipStream_t st) {

@@ -178,7 +178,7 @@ def test_error_paths():
         ctx.gradient(g)
     assert e.value.code == dms.DMS_E_NAN
     with pytest.raises(dms.DmsError) as e:
-        ctx.gradient(torch.zeros((1, 5, 5), device="cuda"))
+        ctx.gradient(torch.zeros((2, 1, 5), device="cuda"))
     assert e.value.code == dms.DMS_E_INVAL
     ctx.gradient(f)
     n1 = ctypes.c_int64()
