@@ -44,7 +44,7 @@ struct dms_ctx {
     Buf cpos[4];                // cpos[d][i] = sorted position of cid[d][i] (d = 1, 2)
     uint32_t* order = nullptr;  // rank -> vertex (inside valsA / valsB)
     // D0 / D2
-    Buf na0, nb0, owner0, bnd0, paired1, na2, nb2, owner2, bnd2, paired2, tet2pos;
+    Buf na0, nb0, owner0, bnd0, paired1, na2, nb2, owner2, bnd2, paired2, tet2pos, jump0, jump2;
     int64_t n_d0_pairs = 0, n_d2_pairs = 0;
     // D1
     D1State d1;
@@ -362,7 +362,7 @@ void dms_destroy(dms_ctx* ctx) {
     Buf* all[] = {&ctx->rank, &ctx->keysA, &ctx->keysB, &ctx->valsA, &ctx->valsB, &ctx->G, &ctx->hist,
                   &ctx->part, &ctx->flags, &ctx->counters, &ctx->stats, &ctx->na0, &ctx->nb0, &ctx->owner0, &ctx->bnd0,
                   &ctx->paired1, &ctx->na2, &ctx->nb2, &ctx->owner2, &ctx->bnd2, &ctx->paired2, &ctx->tet2pos,
-                  &ctx->ob, &ctx->od, &ctx->okey, &ctx->ocnt, &ctx->gk0, &ctx->gk1, &ctx->gv0, &ctx->gv1,
+                  &ctx->jump0, &ctx->jump2, &ctx->ob, &ctx->od, &ctx->okey, &ctx->ocnt, &ctx->gk0, &ctx->gk1, &ctx->gv0, &ctx->gv1,
                   &ctx->ghist, &ctx->gpart, &ctx->gflag, &ctx->bfield, &ctx->bowner, &ctx->bslots, &ctx->bpairs[0],
                   &ctx->bpairs[1], &ctx->bpairs[2], &ctx->bkey, &ctx->bdeath, &ctx->bitem, &ctx->bkept};
     for (auto& e : ctx->graphs) (void)hipGraphExecDestroy(e.exec);
@@ -529,10 +529,12 @@ static int run_d0_d2(dms_ctx* ctx) {
     ENSURE(ctx->paired1, m1);
     trace_d0(ctx->g, P<uint8_t>(ctx->G), P<uint32_t>(ctx->rank), P<uint32_t>(ctx->cid[1]), P<uint32_t>(ctx->cpos[1]),
              m1, P<uint32_t>(ctx->na0), P<uint32_t>(ctx->nb0), P<uint32_t>(ctx->flags), next, st);
+    ENSURE(ctx->jump0, 8 * V);
     fill_u32(P<uint32_t>(ctx->owner0), EMPTY32, V, st);
     fill_u64(P<uint64_t>(ctx->bnd0), EMPTY64, m1, st);
+    fill_u64(P<uint64_t>(ctx->jump0), EMPTY64, V, st);
     reduce_pairs(P<uint32_t>(ctx->na0), P<uint32_t>(ctx->nb0), m1, P<uint32_t>(ctx->owner0), P<uint64_t>(ctx->bnd0),
-                 P<uint32_t>(ctx->flags), stats, next + 2, st);
+                 P<uint64_t>(ctx->jump0), P<uint32_t>(ctx->flags), stats, next + 2, st);
     settled_columns(P<uint64_t>(ctx->bnd0), P<uint32_t>(ctx->owner0), m1, P<uint8_t>(ctx->paired1), st);
     if (ctx->flat) {
         // 2D: the maxima's diagram is D1, from the stable sets of the 1-saddles
@@ -547,10 +549,13 @@ static int run_d0_d2(dms_ctx* ctx) {
         trace_flat(ctx->g, P<uint8_t>(ctx->G), P<uint32_t>(ctx->tet2pos), P<uint32_t>(ctx->cid[1]),
                    P<uint32_t>(ctx->cpos[1]), m1, P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2),
                    P<uint32_t>(ctx->flags), next + 1, st);
+        ENSURE(ctx->jump2, 8 * (m2 + 1));
         fill_u32(P<uint32_t>(ctx->owner2), EMPTY32, m2 + 1, st);
         fill_u64(P<uint64_t>(ctx->bnd2), EMPTY64, m1, st);
+        fill_u64(P<uint64_t>(ctx->jump2), EMPTY64, m2 + 1, st);
         reduce_pairs(P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2), m1, P<uint32_t>(ctx->owner2),
-                     P<uint64_t>(ctx->bnd2), P<uint32_t>(ctx->flags), stats + 2, next + 3, st);
+                     P<uint64_t>(ctx->bnd2), P<uint64_t>(ctx->jump2), P<uint32_t>(ctx->flags), stats + 2, next + 3,
+                     st);
         settled_columns(P<uint64_t>(ctx->bnd2), P<uint32_t>(ctx->owner2), m1, P<uint8_t>(ctx->paired2), st);
         (void)m3;
         return DMS_OK;
@@ -565,10 +570,12 @@ static int run_d0_d2(dms_ctx* ctx) {
     tet_positions(P<uint32_t>(ctx->csorted[3]), m3, P<uint32_t>(ctx->tet2pos), st);
     trace_d2(ctx->g, P<uint8_t>(ctx->G), P<uint32_t>(ctx->tet2pos), P<uint32_t>(ctx->cid[2]), P<uint32_t>(ctx->cpos[2]),
              m2, P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2), P<uint32_t>(ctx->flags), next + 1, st);
+    ENSURE(ctx->jump2, 8 * (m3 + 1));
     fill_u32(P<uint32_t>(ctx->owner2), EMPTY32, m3 + 1, st);
     fill_u64(P<uint64_t>(ctx->bnd2), EMPTY64, m2, st);
+    fill_u64(P<uint64_t>(ctx->jump2), EMPTY64, m3 + 1, st);
     reduce_pairs(P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2), m2, P<uint32_t>(ctx->owner2), P<uint64_t>(ctx->bnd2),
-                 P<uint32_t>(ctx->flags), stats + 2, next + 3, st);
+                 P<uint64_t>(ctx->jump2), P<uint32_t>(ctx->flags), stats + 2, next + 3, st);
     settled_columns(P<uint64_t>(ctx->bnd2), P<uint32_t>(ctx->owner2), m2, P<uint8_t>(ctx->paired2), st);
     (void)m0;
     return DMS_OK;

@@ -77,8 +77,10 @@ void trace_d2(const GridDev& g, const uint8_t* G, const uint32_t* tet2pos, const
 void tri_positions_flat(const uint32_t* c2_sorted, int64_t m, uint32_t* tri2pos, hipStream_t st);
 void trace_flat(const GridDev& g, const uint8_t* G, const uint32_t* tri2pos, const uint32_t* c1, const uint32_t* pos,
                 int64_t m, uint32_t* na, uint32_t* nb, uint32_t* flags, unsigned long long* next, hipStream_t st);
+// jump: one u64 per node, all EMPTY64 (path-halving shortcuts, written by the kernel)
 void reduce_pairs(const uint32_t* na, const uint32_t* nb, int64_t m, uint32_t* owner, uint64_t* bnd,
-                  uint32_t* flags, unsigned long long* stats, unsigned long long* next, hipStream_t st);
+                  uint64_t* jump, uint32_t* flags, unsigned long long* stats, unsigned long long* next,
+                  hipStream_t st);
 void settled_columns(const uint64_t* bnd, const uint32_t* owner, int64_t m, uint8_t* paired, hipStream_t st);
 
 // batch.hip: one box of the batch layout (origin in the super grid, source

@@ -347,14 +347,24 @@ __device__ inline bool cas32(uint32_t* p, uint32_t expect, uint32_t desired) {
 
 // Persistent like the tracing kernels: a lane whose column has settled (or
 // reduced to zero) takes the next column number from its wave's chunk.
+//
+// Path halving. Adding any sum of columns to the left of c is a valid step
+// for c (it is how the lock-free rule already uses the published, possibly
+// unfinished, boundaries of earlier owners); only the reduced pivots are
+// unique. So when c goes p0 -> p1 -> p2 through two such sums, {p0, p2} is a
+// sum of columns up to the larger of the two highest columns involved, M,
+// and jump[p0] = (p2, M) lets any column after M go from p0 to p2 in one
+// step: the union-find's path halving, with the column bound that keeps
+// each use a left-to-right operation.
 __global__ __launch_bounds__(PB) void k_reduce_pairs(const uint32_t* __restrict__ na,
                                                      const uint32_t* __restrict__ nb, int64_t m, uint32_t* owner,
-                                                     uint64_t* bnd, uint32_t* flags, unsigned long long* stats,
-                                                     unsigned long long* next) {
+                                                     uint64_t* bnd, uint64_t* jump, uint32_t* flags,
+                                                     unsigned long long* stats, unsigned long long* next) {
     const int64_t limit = (int64_t)1 << 26;
     unsigned long long steps = 0, evictions = 0;
     bool have = false;
     uint32_t c = 0, p = 0, q = 0;
+    uint32_t pp = EMPTY32, pm = 0;  // the pivot before p and the highest column of the sum that led to p
     int64_t k = 0, pb = 0, pe = 0, guard = 0;
     for (;;) {
         if (!take_path(!have, next, m, k, pb, pe)) break;
@@ -368,6 +378,7 @@ __global__ __launch_bounds__(PB) void k_reduce_pairs(const uint32_t* __restrict_
                 q = t;
             }
             guard = 0;
+            pp = EMPTY32;
             have = true;
         }
         if (++guard > limit) {
@@ -388,12 +399,28 @@ __global__ __launch_bounds__(PB) void k_reduce_pairs(const uint32_t* __restrict_
             continue;
         }
         if (o < c) {
-            const uint64_t b = ld_rlx64(&bnd[o]);
-            if ((uint32_t)(b >> 32) != p) continue;  // owner moved on; look again
-            const uint32_t r = (uint32_t)b;
+            uint32_t r, M;
+            const uint64_t sc = ld_rlx64(&jump[p]);
+            if (sc != EMPTY64 && (uint32_t)sc < c) {  // {p, r}: a sum of columns up to M < c
+                r = (uint32_t)(sc >> 32);
+                M = (uint32_t)sc;
+            } else {
+                const uint64_t b = ld_rlx64(&bnd[o]);
+                if ((uint32_t)(b >> 32) != p) continue;  // owner moved on; look again
+                r = (uint32_t)b;
+                M = o;
+            }
+            if (pp != EMPTY32) st_rlx64(&jump[pp], ((uint64_t)r << 32) | (pm > M ? pm : M));
             // {p, q} + {p, r} = {q, r}
-            if (q > r) { p = q; q = r; }
-            else { p = r; }
+            if (q > r) {
+                p = q;
+                q = r;
+                pp = EMPTY32;
+            } else {
+                pp = p;
+                pm = M;
+                p = r;
+            }
             continue;
         }
         // o > c: c is earlier and takes the pivot; the evicted column o is
@@ -406,6 +433,7 @@ __global__ __launch_bounds__(PB) void k_reduce_pairs(const uint32_t* __restrict_
             c = o;
             p = (uint32_t)(b >> 32);
             q = (uint32_t)b;
+            pp = EMPTY32;
         }
     }
     if (stats) {  // one atomic per wavefront
@@ -459,10 +487,11 @@ void trace_flat(const GridDev& g, const uint8_t* G, const uint32_t* tri2pos, con
                            nb, flags, next);
 }
 void reduce_pairs(const uint32_t* na, const uint32_t* nb, int64_t m, uint32_t* owner, uint64_t* bnd,
-                  uint32_t* flags, unsigned long long* stats, unsigned long long* next, hipStream_t st) {
+                  uint64_t* jump, uint32_t* flags, unsigned long long* stats, unsigned long long* next,
+                  hipStream_t st) {
     if (m > 0)
-        hipLaunchKernelGGL(k_reduce_pairs, dim3(trace_blocks(m)), dim3(PB), 0, st, na, nb, m, owner, bnd, flags,
-                           stats, next);
+        hipLaunchKernelGGL(k_reduce_pairs, dim3(trace_blocks(m)), dim3(PB), 0, st, na, nb, m, owner, bnd, jump,
+                           flags, stats, next);
 }
 void settled_columns(const uint64_t* bnd, const uint32_t* owner, int64_t m, uint8_t* paired, hipStream_t st) {
     if (m > 0) hipLaunchKernelGGL(k_settled, dim3(nblocks(m)), dim3(PB), 0, st, bnd, owner, m, paired);
