@@ -37,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # Counters of one gradient-kernel launch on smooth512 (profiles/gradient_hbm_counters_smooth512.md),
 # valid for the kernel sources with this hash only: HBM bytes from FETCH_SIZE (x2 calibration) and
 # WRITE_SIZE, and the VALU wave instructions issued
-GRADIENT_COUNTERS = {"sources_sha256_16": "c7fbc8f802bd1bce", "workload": "smooth512",
-                     "traffic_bytes": 1609884197 + 6740072294, "valu_wave_insts": 29058432461}
+GRADIENT_COUNTERS = {"sources_sha256_16": "8c5e16c82ab5aae1", "workload": "smooth512",
+                     "traffic_bytes": 1608969989 + 6572305152, "valu_wave_insts": 29029037958}
 # VALU issue ceiling: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per 2 cycles per SIMD
 VALU_PEAK_WINST_S = 256 * 4 * 2.4e9 / 2
 
