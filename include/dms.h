@@ -90,7 +90,10 @@ enum {
 };
 
 /* Create a context on `device`, enqueuing on `hip_stream` (NULL = the null
- * stream). hbm_budget_bytes = 0 means no limit. The context owns all internal
+ * stream). hbm_budget_bytes = 0 means no limit; otherwise it bounds all the
+ * device memory the context holds (D1's boundary storage and the generator
+ * export's working buffers included), and a call that would pass it fails
+ * with DMS_E_NOMEM. The context owns all internal
  * device state (order, gradient, critical sets, union-find owners, boundary
  * heap), which persists from dms_gradient() to the next dms_gradient() /
  * dms_diagram() or dms_destroy(). */

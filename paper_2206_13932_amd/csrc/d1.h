@@ -43,7 +43,8 @@ struct D1State {
     size_t dq_cap = 0;
     void* ctrs = nullptr;     // u64 counters (heap top, work cursor, deferrals, work counts)
     int64_t ncols = 0;
-    size_t bytes = 0;
+    size_t bytes = 0;         // device bytes held by D1 (ctrs aside)
+    size_t limit = 0;         // most bytes D1 may hold (0 = no limit)
     // last run: [0] loop steps, [1] evictions, [2] cached-boundary additions,
     // [3] deferrals, [4] published entries, [5] restarts
     uint64_t stats[6] = {0, 0, 0, 0, 0, 0};
@@ -72,6 +73,7 @@ struct D1State {
     int gen_sorted = 0;  // which key buffer holds the sorted keys
 };
 
+// budget_left: most device bytes D1 may hold (0 = no limit); more is DMS_E_NOMEM
 int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, std::string& err);
 void d1_emit(D1State& s, int64_t m1, const uint8_t* paired1, const uint32_t* c1, uint64_t* key, uint32_t* death,
              uint32_t* cnt, hipStream_t st);

@@ -1765,8 +1765,11 @@ __global__ void k_gen_check(const int64_t* offsets, int64_t n, uint32_t* flags) 
     if (i < n && offsets[i] < 0) atomicOr(flags, FLAG_GUARD);
 }
 
-int grow(void*& p, size_t& cap, size_t bytes, size_t& total) {
+// (re)allocate p to at least `bytes`; total counts the bytes D1 holds and may
+// not pass limit (0 = no limit): the context's HBM budget left for D1
+int grow(void*& p, size_t& cap, size_t bytes, size_t& total, size_t limit) {
     if (cap >= bytes) return 0;
+    if (limit && total - cap + bytes > limit) return -1;
     if (p) (void)hipFree(p);
     total -= cap;
     p = nullptr;
@@ -1784,7 +1787,7 @@ int grow(void*& p, size_t& cap, size_t bytes, size_t& total) {
 
 int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, std::string& err) {
     s.gen_n = -1;  // generators of an earlier run are stale
-    (void)budget_left;
+    s.limit = budget_left;
     const int64_t V = in.g.V;
     const int64_t m2 = in.m2;
     s.g = in.g;
@@ -1796,10 +1799,10 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
     };
     const size_t ctr_bytes = 8 * (SEG_BASE + SEG_STRIDE * NSEG);
     if (!s.ctrs && hipMalloc(&s.ctrs, ctr_bytes) != hipSuccess) return oom("counters");
-    if (grow(s.colflag, s.colflag_cap, 4 * (m2 + 1), s.bytes)) return oom("column flags");
-    if (grow(s.cols, s.cols_cap, 4 * (m2 + 1), s.bytes)) return oom("columns");
-    if (grow(s.scanpart, s.scanpart_cap, 4 * scan_part_size(m2 + 1), s.bytes)) return oom("scan");
-    if (grow(s.owner1, s.owner1_cap, 4 * 7 * V, s.bytes)) return oom("owners");
+    if (grow(s.colflag, s.colflag_cap, 4 * (m2 + 1), s.bytes, s.limit)) return oom("column flags");
+    if (grow(s.cols, s.cols_cap, 4 * (m2 + 1), s.bytes, s.limit)) return oom("columns");
+    if (grow(s.scanpart, s.scanpart_cap, 4 * scan_part_size(m2 + 1), s.bytes, s.limit)) return oom("scan");
+    if (grow(s.owner1, s.owner1_cap, 4 * 7 * V, s.bytes, s.limit)) return oom("owners");
     for (int d = 0; d < 6; ++d) s.stats[d] = 0;
     for (int d = 0; d < 5; ++d) s.pass_work[d] = s.pass_us[d] = 0;
     for (int d = 0; d < 4; ++d) s.wide[d] = 0;
@@ -1828,11 +1831,11 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         }
     }
     s.ncols = ncols;
-    if (grow(s.bndptr, s.bndptr_cap, 8 * (ncols + 1), s.bytes)) return oom("boundary pointers");
+    if (grow(s.bndptr, s.bndptr_cap, 8 * (ncols + 1), s.bytes, s.limit)) return oom("boundary pointers");
     // two deferral queues (this pass / next pass): u64 (column, offset) + u32 length
-    if (grow(s.dq, s.dq_cap, 2 * (size_t)(ncols + 1) * 16, s.bytes)) return oom("deferral queues");
+    if (grow(s.dq, s.dq_cap, 2 * (size_t)(ncols + 1) * 16, s.bytes, s.limit)) return oom("deferral queues");
     if (s.heap_cap < (size_t)8 * 32 * ncols) {
-        if (grow(s.heap, s.heap_cap, std::max<size_t>((size_t)8 << 22, (size_t)8 * 32 * ncols), s.bytes))
+        if (grow(s.heap, s.heap_cap, std::max<size_t>((size_t)8 << 22, (size_t)8 * 32 * ncols), s.bytes, s.limit))
             return oom("boundary heap");
     }
     if (in.m1 > 0)
@@ -1882,7 +1885,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             const bool lane_pass = pass < lane_passes;
             const bool in_lds = lane_pass;
             const size_t need = in_lds ? 8 : lane_pass ? (size_t)8 * T * K : (size_t)8 * T * (2 * K + PCAP);
-            if (grow(s.scratch, s.scratch_cap, need, s.bytes)) return oom("working boundaries");
+            if (grow(s.scratch, s.scratch_cap, need, s.bytes, s.limit)) return oom("working boundaries");
             D1K P;
             P.g = in.g;
             P.G = in.G;
@@ -1986,7 +1989,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         }
         // publication heap exhausted: grow it and redo D1 from the start
         const size_t want = std::max<size_t>(2 * s.heap_cap, (size_t)16 * hc[C_HEAP]);  // segments fill unevenly
-        if (grow(s.heap, s.heap_cap, want, s.bytes)) return oom("boundary heap");
+        if (grow(s.heap, s.heap_cap, want, s.bytes, s.limit)) return oom("boundary heap");
     }
     err = "D1: boundary storage kept overflowing";
     return -3;
@@ -2020,7 +2023,7 @@ int d1_generators(D1State& s, int64_t* offsets, int64_t cap_off, int64_t* edges,
     enum { G_EDGE, G_COL, G_EDGE2, G_COL2, G_LEN, G_OFF, G_KEY0, G_KEY1, G_VAL0, G_VAL1, G_HIST, G_PART };
     static_assert(G_PART < (int)(sizeof(s.gbuf) / sizeof(s.gbuf[0])), "generator buffers");
     auto buf = [&](int k, size_t bytes) -> void* {
-        if (grow(s.gbuf[k], s.gcap[k], std::max<size_t>(bytes, 64), s.bytes)) return nullptr;
+        if (grow(s.gbuf[k], s.gcap[k], std::max<size_t>(bytes, 64), s.bytes, s.limit)) return nullptr;
         return s.gbuf[k];
     };
     auto hip_fail = [&](const char* what) {

@@ -86,10 +86,11 @@ int ensure(dms_ctx* ctx, Buf& b, size_t bytes) {
     if (bytes == 0) bytes = 256;
     if (b.cap >= bytes) return DMS_OK;
     size_t want = bytes + bytes / 8;
-    if (ctx->budget && ctx->used - b.cap + want > ctx->budget) {
+    const size_t held = ctx->used + ctx->d1.bytes;  // the context's buffers and D1's
+    if (ctx->budget && held - b.cap + want > ctx->budget) {
         want = bytes;
-        if (ctx->used - b.cap + want > ctx->budget)
-            return fail(ctx, DMS_E_NOMEM, "HBM budget exceeded (" + std::to_string(ctx->used - b.cap + want) +
+        if (held - b.cap + want > ctx->budget)
+            return fail(ctx, DMS_E_NOMEM, "HBM budget exceeded (" + std::to_string(held - b.cap + want) +
                                               " > " + std::to_string(ctx->budget) + " bytes)");
     }
     if (b.p) {
@@ -655,6 +656,13 @@ int dms_pairs_d0_d2(dms_ctx* ctx, dms_pair* d0, int64_t cap0, int64_t* n0, dms_p
     return DMS_OK;
 }
 
+// device bytes D1 may hold under the context's budget (0 = no budget; at
+// least 1, so that an exhausted budget still limits)
+static size_t d1_limit(const dms_ctx* ctx) {
+    if (!ctx->budget) return 0;
+    return std::max<size_t>(1, ctx->budget - std::min(ctx->budget, ctx->used));
+}
+
 static int run_d1(dms_ctx* ctx) {
     if (ctx->flat) {  // 2D: D1 came from the dual tracing with D0 (no sandwich)
         ctx->d1.ncols = 0;
@@ -675,7 +683,7 @@ static int run_d1(dms_ctx* ctx) {
     in.bpr = ctx->bpr;
     in.flags = P<uint32_t>(ctx->flags);
     std::string err;
-    int r = d1_run(ctx->d1, in, ctx->st, ctx->budget ? ctx->budget - std::min(ctx->budget, ctx->used) : 0, err);
+    int r = d1_run(ctx->d1, in, ctx->st, d1_limit(ctx), err);
     if (r != DMS_OK) return fail(ctx, r, err);
     return DMS_OK;
 }
@@ -734,6 +742,7 @@ int dms_d1_generators(dms_ctx* ctx, int64_t* d_offsets, int64_t cap_offsets, int
         return fail(ctx, DMS_E_STATE, "generators come from the sandwich of 3D grids; on a 2D grid D1 is dual");
     HIPCHK(hipSetDevice(ctx->device));
     std::string err;
+    ctx->d1.limit = d1_limit(ctx);
     int r = d1_generators(ctx->d1, d_offsets, cap_offsets, d_edges, cap_edges, n_pairs, n_edges,
                           P<uint32_t>(ctx->flags), ctx->st, err);
     if (r < 0) return fail(ctx, r, err);

@@ -198,6 +198,36 @@ def test_error_paths():
 
 
 @pytest.mark.gpu
+def test_hbm_budget_bounds_every_stage():
+    """Budgets doubling from 64 KiB: each diagram either equals the oracle's or
+    fails with DMS_E_NOMEM; D1's storage and the generator export count
+    against the budget too (some budget runs out inside D1)."""
+    import torch
+    from paper_2206_13932_amd import dms
+    f = sf.noise((32, 32, 32), 12)
+    res = oracle.run(f)
+    ft = torch.from_numpy(f).cuda()
+    messages, ok = [], 0
+    for k in range(16, 32):
+        print(f"[parity] budget 2^{k}", flush=True)
+        ctx = dms.Context(0, hbm_budget=1 << k)
+        try:
+            out = ctx.diagram(ft)
+            for d in range(3):
+                assert np.array_equal(out[d].cpu().numpy(), res.pairs[d]), (k, d)
+            off, edges = ctx.d1_generators()
+            assert off.numel() == int((res.pairs[1][:, 1] >= 0).sum()) + 1
+            ok += 1
+        except dms.DmsError as e:
+            assert e.code == dms.DMS_E_NOMEM, (k, e.code, str(e))
+            messages.append(str(e))
+        finally:
+            ctx.close()
+    assert ok > 0 and messages
+    assert any("D1" in m or "generators" in m for m in messages), messages
+
+
+@pytest.mark.gpu
 def test_parity_d1_every_deferral_pass():
     """Tiny working heaps force columns through all D1 passes (LDS heaps of
     two sizes, then workgroup passes), and every cached boundary longer than
