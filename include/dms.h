@@ -221,7 +221,8 @@ enum {
     DMS_BUF_CRIT2 = 4,
     DMS_BUF_CRIT3 = 5,
     DMS_BUF_ARCS0 = 6,     /* u32[2*n] D0 arcs (rank of minimum a, b) per C1      */
-    DMS_BUF_ARCS2 = 7,     /* u32[2*n] D2 arcs (age of maximum a, b), C2 reversed */
+    DMS_BUF_ARCS2 = 7,     /* u32[2*n] D2 arcs (age of maximum a, b), C2 reversed
+                              (2D grids: the dual arcs of the 1-saddles, C1 reversed) */
     DMS_BUF_STATS = 8,     /* u64[48] work counters of the last call: D0 steps,
                               evictions; D2 steps, evictions; D1 steps, evictions,
                               boundary additions, deferrals, published entries,

@@ -44,8 +44,8 @@ constexpr int DB = 256;
 constexpr uint32_t OWN_D0 = 0xFFFFFFFEu;
 constexpr uint64_t NONE = ~0ull;
 constexpr int MAX_PASSES = 5;
-constexpr int LDS_K = 16;   // keys per thread in the first pass (LDS heaps)
-constexpr int LDS_K2 = 64;  // ... and in the second
+constexpr int LDS_K = 20;   // keys per thread in the first pass (LDS heaps)
+constexpr int LDS_K2 = 48;  // ... and in the second
 constexpr uint32_t MAX_RETRIES = 1u << 16;  // consecutive look-agains before a column is declared corrupt
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + DB - 1) / DB); }
 
@@ -1865,9 +1865,9 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         // plan_k entries (lengths stay below 2^24: the cached length field)
         int64_t plan_k[MAX_PASSES] = {LDS_K, LDS_K2, (int64_t)1 << 15, (int64_t)1 << 20, ((int64_t)1 << 24) - 1024};
         // lane passes: as many lanes as the LDS heaps leave resident (160 KB
-        // per CU: 5 workgroups of 256 lanes x 16 keys, or 5 of 64 lanes x 64
+        // per CU: 4 workgroups of 256 lanes x 20 keys, or 6 of 64 lanes x 48
         // keys); workgroup passes: workgroups
-        int64_t plan_t[MAX_PASSES] = {256 * 5 * 256, 256 * 5 * 64, 1024, 512, 64};
+        int64_t plan_t[MAX_PASSES] = {256 * 4 * 256, 256 * 6 * 64, 1024, 512, 64};
         const int plan_db[MAX_PASSES] = {256, 64, WB, WB, WB};
         uint32_t long_add = LONG_ADD;
         const int lane_passes = 2;  // passes 0 and 1 are thread-per-column

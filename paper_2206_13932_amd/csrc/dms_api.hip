@@ -813,7 +813,7 @@ int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap) {
             break;
         }
         case DMS_BUF_ARCS0: bytes = 8 * ctx->ncrit[1]; break;
-        case DMS_BUF_ARCS2: bytes = 8 * ctx->ncrit[2]; break;
+        case DMS_BUF_ARCS2: bytes = 8 * ctx->ncrit[ctx->flat ? 1 : 2]; break;  // 2D: the 1-saddles' dual arcs
         case DMS_BUF_STATS: {
             if (ctx->stage < 1) return fail(ctx, DMS_E_STATE, "no gradient computed yet");
             bytes = 8 * 48;

@@ -100,6 +100,15 @@ def _check_all(name, f, ctx, torch, dms):
     assert np.array_equal(d0.cpu().numpy(), res.pairs[0]), (name, "D0")
     exp2 = res.pairs[2][res.pairs[2][:, 1] >= 0]
     assert np.array_equal(d2.cpu().numpy(), exp2), (name, "D2")
+    # dual arcs (D2 in 3D, D1 on 2D grids): the ages of the two maxima each
+    # saddle reaches, saddles in decreasing order; 0 = virtual maximum, 1 = the
+    # highest maximum; the two sides as an unordered pair
+    top = res.crit[2 if res.shape[0] == 1 else 3]
+    age = {int(t): len(top) - i for i, t in enumerate(top)}
+    exp_arcs = np.array([[0 if a < 0 else age[int(a)], 0 if b < 0 else age[int(b)]] for a, b, _ in res.arcs2],
+                        dtype=np.int64).reshape(-1, 2)
+    got_arcs = ctx.debug(dms.BUF_ARCS2).reshape(2, -1).T.astype(np.int64)
+    assert np.array_equal(np.sort(got_arcs, axis=1), np.sort(exp_arcs, axis=1)), (name, "dual arcs")
     d1 = ctx.pairs_d1()
     assert np.array_equal(d1.cpu().numpy(), res.pairs[1]), (name, "D1")
     out = ctx.diagram(ft)
