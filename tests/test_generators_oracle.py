@@ -103,3 +103,28 @@ def test_checker_catches_planted_mistakes():
     good[a] = np.setxor1d(gens[a], gens[b])
     st = oracle.bf_check_cycles(res.shape, res.rank, fin, *_pack(good))
     assert (st == 0).all()
+
+
+def test_generators_every_order_of_one_cube():
+    """Every vertex order of one cube: each D1 pair's cycle passes the check."""
+    import itertools
+    n_pairs = 0
+    for perm in itertools.permutations(range(8)):
+        res = oracle.run(np.array(perm, dtype=np.float32).reshape(2, 2, 2))
+        fin = _finite(res)
+        if len(fin):
+            st = oracle.bf_check_cycles(res.shape, res.rank, fin, res.gen1_off, res.gen1_edges)
+            assert (st == 0).all(), (perm, st)
+            n_pairs += len(fin)
+    assert n_pairs > 0
+
+
+@pytest.mark.parametrize("shape", [(3, 3, 3), (4, 4, 4), (2, 3, 5)])
+def test_generators_random_orders(shape):
+    rng = np.random.default_rng(100 + sum(shape))
+    n = int(np.prod(shape))
+    for _ in range(60):
+        res = oracle.run(rng.permutation(n).astype(np.float32).reshape(shape))
+        fin = _finite(res)
+        st = oracle.bf_check_cycles(res.shape, res.rank, fin, res.gen1_off, res.gen1_edges)
+        assert (st == 0).all()
