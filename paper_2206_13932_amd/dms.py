@@ -107,8 +107,13 @@ def load_library() -> ctypes.CDLL:
 
 
 def _grid_of(field: torch.Tensor) -> Grid:
+    """[nz, ny, nx] is a 3D grid (nz = 1: the 2D grid of the plane z = 0);
+    [ny, nx] is a 2D grid too."""
+    if field.dim() == 2:
+        ny, nx = field.shape
+        return Grid(nx, ny, 1)
     if field.dim() != 3:
-        raise ValueError("field must be shaped [nz, ny, nx]")
+        raise ValueError("field must be shaped [nz, ny, nx] (or [ny, nx] for a 2D grid)")
     nz, ny, nx = field.shape
     return Grid(nx, ny, nz)
 

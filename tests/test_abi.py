@@ -64,3 +64,16 @@ def test_batch_layout_rejects_items_wider_than_the_cross_section():
         dms.batch_layout([(10, 10, 64)], cross=(48, 48))
     with pytest.raises(dms.DmsError):
         dms.batch_layout([(1, 10, 10)])
+
+
+def test_grid_marshalling_of_2d_and_3d_fields():
+    import torch
+    from paper_2206_13932_amd import dms
+    g = dms._grid_of(torch.zeros((4, 5, 6)))
+    assert (g.nx, g.ny, g.nz) == (6, 5, 4)
+    g = dms._grid_of(torch.zeros((5, 6)))  # [ny, nx]: a 2D grid
+    assert (g.nx, g.ny, g.nz) == (6, 5, 1)
+    g = dms._grid_of(torch.zeros((1, 5, 6)))
+    assert (g.nx, g.ny, g.nz) == (6, 5, 1)
+    with pytest.raises(ValueError):
+        dms._grid_of(torch.zeros(7))

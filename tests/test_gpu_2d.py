@@ -35,6 +35,18 @@ def test_parity_2d(name):
 
 
 @pytest.mark.gpu
+def test_2d_field_given_as_a_matrix():
+    """A [ny, nx] tensor is the same 2D grid as [1, ny, nx]."""
+    torch, dms, ctx = _gpu_ctx()
+    f = sf.noise((1, 18, 23), 11)
+    a = ctx.diagram(torch.from_numpy(f).cuda())
+    b = ctx.diagram(torch.from_numpy(f[0].copy()).cuda())
+    for d in range(3):
+        assert np.array_equal(a[d].cpu().numpy(), b[d].cpu().numpy())
+    ctx.close()
+
+
+@pytest.mark.gpu
 def test_2d_then_3d_in_one_context():
     torch, dms, ctx = _gpu_ctx()
     _check_all("noise_2d", sf.noise((1, 20, 24), 7), ctx, torch, dms)
