@@ -17,7 +17,7 @@
  *    cells per dimension in each lower star (Sec. 1.1, Sec. 2.6).
  *  - bf_counts: numbers of vertices, edges, triangles and tetrahedra.
  * A grid with nz = 1 is the 2D grid of the plane z = 0, built from its
- * triangles (bf_lower_link_betti is for 3D grids only).
+ * triangles (there the lower link of a vertex is a graph).
  */
 #include <algorithm>
 #include <array>
@@ -204,7 +204,53 @@ int64_t bf_diagram(int64_t nx, int64_t ny, int64_t nz, const uint32_t* rank, int
  * every vertex: the link of x is the set of faces, opposite to x, of the
  * tetrahedra around x; the lower link keeps those whose vertices are all
  * lower than x. */
+/* 2D grid: the link of x is the cycle of edges opposite x in its
+ * triangles; the lower link is a graph, so b~_1 = E - V + components. */
+static void lower_link_betti_2d(int64_t nx, int64_t ny, const uint32_t* rank, int32_t* out) {
+    std::vector<std::array<i64, 4>> tris;
+    triangles2d(nx, ny, tris);
+    const i64 V = nx * ny;
+    std::vector<std::vector<int>> around(V);
+    for (size_t t = 0; t < tris.size(); ++t)
+        for (int i = 0; i < 3; ++i) around[tris[t][i]].push_back((int)t);
+    for (i64 x = 0; x < V; ++x) {
+        std::set<i64> lv;
+        std::set<std::pair<i64, i64>> le;
+        for (int t : around[x]) {
+            i64 o[2];
+            int k = 0;
+            for (int i = 0; i < 3; ++i)
+                if (tris[t][i] != x) o[k++] = tris[t][i];
+            const bool l0 = rank[o[0]] < rank[x], l1 = rank[o[1]] < rank[x];
+            if (l0) lv.insert(o[0]);
+            if (l1) lv.insert(o[1]);
+            if (l0 && l1) le.insert({std::min(o[0], o[1]), std::max(o[0], o[1])});
+        }
+        int32_t* b = out + 4 * x;
+        b[3] = 0;
+        b[0] = lv.empty() ? 1 : 0;
+        if (lv.empty()) { b[1] = b[2] = 0; continue; }
+        std::map<i64, i64> par;
+        for (i64 v : lv) par[v] = v;
+        auto find = [&](i64 v) {
+            while (par[v] != v) v = par[v] = par[par[v]];
+            return v;
+        };
+        i64 comps = (i64)lv.size();
+        for (auto& e : le) {
+            i64 a = find(e.first), bb = find(e.second);
+            if (a != bb) { par[a] = bb; --comps; }
+        }
+        b[1] = (int32_t)(comps - 1);
+        b[2] = (int32_t)((i64)le.size() - (i64)lv.size() + comps);
+    }
+}
+
 void bf_lower_link_betti(int64_t nx, int64_t ny, int64_t nz, const uint32_t* rank, int32_t* out) {
+    if (nz == 1) {
+        lower_link_betti_2d(nx, ny, rank, out);
+        return;
+    }
     std::vector<std::array<i64, 4>> tets;
     tetrahedra(nx, ny, nz, tets);
     const i64 V = nx * ny * nz;

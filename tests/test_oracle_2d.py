@@ -101,3 +101,25 @@ def test_2d_gradient_pairs_are_lower_star_facet_pairs():
             assert max(res.rank[small]) == max(res.rank[big])
     # no tetrahedra, and every existing triangle lies in the plane
     assert (res.partner[3] == -2).all()
+
+
+@pytest.mark.parametrize("field", ["noise", "smooth", "ties", "thin"])
+def test_2d_critical_cells_equal_lower_link_betti(field):
+    """The expansion-based gradient puts exactly b~_{k-1}(lower link) critical
+    k-cells in each lower star (Sec. 1.1, 2.6); on a 2D grid the link of a
+    vertex is the cycle of its (up to) six neighbours."""
+    f = {
+        "noise": lambda: sf.noise((1, 21, 19), 12),
+        "smooth": lambda: sf.gaussians((1, 40, 36), 13, k=6, noise_frac=0.01),
+        "ties": lambda: np.random.default_rng(14).integers(0, 3, size=(1, 15, 16)).astype(np.float32),
+        "thin": lambda: sf.noise((1, 2, 30), 15),
+    }[field]()
+    res = oracle.run(f)
+    betti = oracle.bf_lower_link_betti(res.shape, res.rank)
+    counts = np.zeros_like(betti)
+    for d in range(3):
+        if len(res.crit[d]):
+            mv = H.vertices(res.shape, d, res.crit[d])
+            top = mv[np.arange(len(mv)), res.rank[mv].argmax(axis=1)]
+            np.add.at(counts[:, d], top, 1)
+    assert np.array_equal(counts, betti)
