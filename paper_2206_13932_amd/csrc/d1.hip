@@ -275,7 +275,6 @@ __device__ inline void defer_column(const D1K& P, uint32_t c, uint64_t off, uint
 __global__ __launch_bounds__(DB) void k_d1(D1K P) {
     extern __shared__ uint64_t lds_heaps[];
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
     // scratch exists for nthreads lanes only; the others take no work
     const bool real = tid < P.nthreads;
     Heap H;

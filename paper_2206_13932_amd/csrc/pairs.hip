@@ -81,13 +81,6 @@ struct Simp {
     int type;
 };
 
-__device__ inline bool in_grid(const GridDev& g, int64_t anchor, int mask_total, int neg_mask) {
-    int x, y, z;
-    coords_of(g, anchor, x, y, z);
-    (void)neg_mask;
-    return fits(g, x, y, z, mask_total);
-}
-
 // The two tetrahedra containing triangle (anchor; A, B), whose anchor has
 // coordinates (x, y, z); ok[i] false if outside. out[0] is anchored at
 // anchor - lin_of_mask(C) when the triangle spans two steps, else at anchor.
