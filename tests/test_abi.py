@@ -1,7 +1,8 @@
 """Host-side checks of the C-ABI library (no GPU needed): it loads, it
 exports every function include/dms.h declares, the binding refuses to run
-without it, and the batch layout (computed on the host) places disjoint
-boxes with a +inf plane between any two.
+without it, the batch layout (computed on the host) places disjoint boxes
+with a +inf plane between any two, grids are marshalled from 2D and 3D
+tensors, and the server admits requests in arrival order within its budget.
 """
 import ctypes
 import os
@@ -77,3 +78,34 @@ def test_grid_marshalling_of_2d_and_3d_fields():
     assert (g.nx, g.ny, g.nz) == (6, 5, 1)
     with pytest.raises(ValueError):
         dms._grid_of(torch.zeros(7))
+
+
+@pytest.mark.parametrize("budget", [1 << 16, 1 << 18, 1 << 21])
+def test_serving_admission_is_fifo_and_fits_the_budget(budget):
+    """Host-side admission of the server (no GPU): batches take requests in
+    arrival order, and a batch of more than one request has a super grid
+    within the vertex budget."""
+    import collections
+    import threading
+
+    import torch
+    from paper_2206_13932_amd import dms, serving
+    rng = np.random.default_rng(budget % 97)
+    srv = object.__new__(serving.Server)
+    srv.cfg = serving.ServerConfig(workers=1, budget_vertices=budget, max_items=32)
+    srv.lock = threading.Condition()
+    srv.queue = collections.deque()
+    shapes = [tuple(int(s) for s in rng.integers(2, 40, size=3)) for _ in range(200)]
+    for i, sh in enumerate(shapes):
+        srv.queue.append(serving.Request(i, 0.0, torch.zeros(sh)))
+    taken = []
+    while srv.queue:
+        with srv.lock:
+            batch = srv._take_batch()
+        assert 1 <= len(batch) <= 32
+        if len(batch) > 1:
+            (X, Y, Z), _ = dms.batch_layout([tuple(r.host_field.shape) for r in batch], srv.cfg.cross,
+                                            srv.cfg.z_quantum)
+            assert X * Y * Z <= budget
+        taken += [r.rid for r in batch]
+    assert taken == list(range(len(shapes)))
