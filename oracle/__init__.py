@@ -55,6 +55,8 @@ def _lib(name: str) -> ctypes.CDLL:
     if name == "oracle":
         lib.orc_run.argtypes = [i64, i64, i64, p, ctypes.POINTER(p), ctypes.c_char_p, ctypes.c_int]
         lib.orc_run.restype = ctypes.c_int
+        lib.orc_run_opts.argtypes = [i64, i64, i64, p, ctypes.c_int, ctypes.POINTER(p), ctypes.c_char_p, ctypes.c_int]
+        lib.orc_run_opts.restype = ctypes.c_int
         lib.orc_size.argtypes = [p, ctypes.c_int]
         lib.orc_size.restype = i64
         lib.orc_copy.argtypes = [p, ctypes.c_int, p]
@@ -108,14 +110,16 @@ class OracleResult:
         self.gen1_edges = get(ORC_GEN1_EDGES, np.int64)
 
 
-def run(field: np.ndarray) -> OracleResult:
-    """Run the whole oracle pipeline on a float32 field shaped [nz, ny, nx]."""
+def run(field: np.ndarray, sandwich: bool = True) -> OracleResult:
+    """Run the whole oracle pipeline on a float32 field shaped [nz, ny, nx].
+    sandwich=False: the ablation of Sec. 3, D1 over every critical triangle
+    instead of those D2 left unpaired (the diagrams must not change)."""
     f = np.ascontiguousarray(field, dtype=np.float32)
     nz, ny, nx = f.shape
     lib = _lib("oracle")
     h = ctypes.c_void_p()
     err = ctypes.create_string_buffer(512)
-    rc = lib.orc_run(nx, ny, nz, _ptr(f), ctypes.byref(h), err, 512)
+    rc = lib.orc_run_opts(nx, ny, nz, _ptr(f), 0 if sandwich else 1, ctypes.byref(h), err, 512)
     if rc != 0:
         raise ValueError(err.value.decode())
     try:

@@ -525,7 +525,11 @@ void diagram_dual(Ctx& C, int d, std::vector<char>& saddle_paired, std::vector<i
  * a critical edge with no partner yet pairs with the triangle; a critical
  * edge already paired with an earlier triangle adds that triangle's cached
  * boundary; a regular edge adds the boundary of its gradient partner. */
-void diagram1(Ctx& C, const std::vector<char>& edge_paired0, const std::vector<char>& tri_paired2) {
+/* sandwich = false: the ablation without the sandwich (Sec. 3): every
+ * critical triangle is processed, and one whose boundary reduces to zero
+ * (a triangle D2 pairs with a tetrahedron) is skipped. */
+void diagram1(Ctx& C, const std::vector<char>& edge_paired0, const std::vector<char>& tri_paired2,
+              bool sandwich = true) {
     typedef std::pair<std::pair<i64, i64>, i64> EK;  /* ((rank max, rank min), edge id) */
     auto ekey = [&](i64 e) {
         Key k = C.key(1, e);
@@ -538,7 +542,7 @@ void diagram1(Ctx& C, const std::vector<char>& edge_paired0, const std::vector<c
     std::vector<i64> fs;
     const std::vector<i64>& C2 = C.crit[2];
     for (size_t kk = 0; kk < C2.size(); ++kk) {
-        if (tri_paired2[kk]) continue;
+        if (sandwich && tri_paired2[kk]) continue;
         i64 sigma = C2[kk];
         std::set<EK> B;
         auto toggle = [&](i64 e) {
@@ -551,7 +555,10 @@ void diagram1(Ctx& C, const std::vector<char>& edge_paired0, const std::vector<c
         for (i64 e : fs) toggle(e);
         i64 guard = 0;
         for (;;) {
-            if (B.empty()) throw std::runtime_error("D1: boundary vanished on an unpaired 2-saddle");
+            if (B.empty()) {
+                if (sandwich) throw std::runtime_error("D1: boundary vanished on an unpaired 2-saddle");
+                break;  /* a positive triangle: no D1 pair */
+            }
             if (++guard > (i64)4e9) throw std::runtime_error("D1: no progress");
             i64 tau = B.rbegin()->second;
             i64 p = C.partner[1][tau];
@@ -599,7 +606,7 @@ void sort_pairs(std::vector<i64>& p) {
     }
 }
 
-void run(Ctx& C, const float* f) {
+void run(Ctx& C, const float* f, bool sandwich = true) {
     double t0 = now();
     if (!vertex_order(f, C.g.V(), C.rank)) throw std::invalid_argument("NaN in the scalar field");
     double t1 = now();
@@ -613,7 +620,7 @@ void run(Ctx& C, const float* f) {
     if (flat) diagram_dual(C, 1, e1p, C.d1);
     else diagram_dual(C, 2, t2p, C.d2);
     double t4 = now();
-    if (!flat) diagram1(C, e0, t2p);
+    if (!flat) diagram1(C, e0, t2p, sandwich);
     double t5 = now();
     /* Sec. 6: what stays unpaired is a class of infinite persistence */
     for (size_t k = 0; k < C.crit[0].size(); ++k)
@@ -662,13 +669,15 @@ enum {
     ORC_GEN1_EDGES = 16    /* i64 edge ids of the D1 generators         */
 };
 
-int orc_run(int64_t nx, int64_t ny, int64_t nz, const float* f, void** out, char* err, int errlen) {
+/* flags bit 0: D1 without the sandwich (the ablation of Sec. 3) */
+int orc_run_opts(int64_t nx, int64_t ny, int64_t nz, const float* f, int flags, void** out, char* err,
+                 int errlen) {
     Ctx* C = new Ctx();
     C->g.n[0] = nx; C->g.n[1] = ny; C->g.n[2] = nz;
     try {
         if (nx < 2 || ny < 2 || nz < 1)
             throw std::invalid_argument("nx and ny must be >= 2, nz >= 1 (nz = 1: a 2D grid)");
-        run(*C, f);
+        run(*C, f, !(flags & 1));
     } catch (const std::exception& e) {
         if (err && errlen > 0) { std::strncpy(err, e.what(), errlen - 1); err[errlen - 1] = 0; }
         delete C;
@@ -677,6 +686,10 @@ int orc_run(int64_t nx, int64_t ny, int64_t nz, const float* f, void** out, char
     }
     *out = C;
     return 0;
+}
+
+int orc_run(int64_t nx, int64_t ny, int64_t nz, const float* f, void** out, char* err, int errlen) {
+    return orc_run_opts(nx, ny, nz, f, 0, out, err, errlen);
 }
 
 int64_t orc_size(void* h, int what) {

@@ -309,3 +309,18 @@ def test_kruskal_d0_matches_oracle(field):
     fin, _ = oracle.order_space(res)
     d0 = sorted((b, d) for (dim, b, d) in fin if dim == 0)
     assert d0 == [tuple(x) for x in oracle.bf_d0_kruskal(res.shape, res.rank).tolist()]
+
+
+@pytest.mark.parametrize("field", [sf.noise((16, 16, 16), 0), sf.noise((24, 24, 24), 3),
+                                   sf.gaussians((20, 22, 18), 7, k=8, noise_frac=0.01),
+                                   np.random.default_rng(6).integers(0, 4, size=(9, 8, 7)).astype(np.float32)])
+def test_sandwich_does_not_change_d1(field):
+    """Sec. 3: restricting PairCriticalSimplices to the 2-saddles D2 left
+    unpaired gives the D1 of running it on every critical triangle (where the
+    triangles D2 pairs reduce to an empty boundary)."""
+    a = oracle.run(field)
+    b = oracle.run(field, sandwich=False)
+    for d in range(3):
+        assert np.array_equal(a.pairs[d], b.pairs[d])
+    st = oracle.bf_check_cycles(a.shape, a.rank, b.pairs[1][b.pairs[1][:, 1] >= 0], b.gen1_off, b.gen1_edges)
+    assert (st == 0).all()
