@@ -39,8 +39,12 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE, and the VALU wave instructions issued
 GRADIENT_COUNTERS = {"sources_sha256_16": "8c5e16c82ab5aae1", "workload": "smooth512",
                      "traffic_bytes": 1608969989 + 6572305152, "valu_wave_insts": 29029037958}
-# VALU issue ceiling: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per 2 cycles per SIMD
-VALU_PEAK_WINST_S = 256 * 4 * 2.4e9 / 2
+# VALU issue ceiling for the plain (non-packed) 32-bit integer and bit operations the gradient
+# kernel runs: the fp64 vector peak, 78.6 TFLOP/s = 2 FLOP x 64 lanes per CU per clock at 256 CUs
+# x 2.4 GHz, i.e. 16-lane SIMDs taking 4 cycles per wave64 instruction: one wave64 instruction
+# per CU per clock. (The 157.3 TFLOP/s fp32 figure counts packed dual-lane FP32, which this
+# build turns off and which integer work cannot use.)
+VALU_PEAK_WINST_S = 256 * 2.4e9
 
 
 def gradient_sources_hash():
