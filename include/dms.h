@@ -149,12 +149,14 @@ int dms_d1_generators(dms_ctx* ctx, int64_t* d_offsets, int64_t cap_offsets, int
 
 /* ---- Batching: many grids in one pipeline run ----
  * The grids are placed as disjoint boxes in one super grid of cross-section
- * cross_x * cross_y, separated by planes of +inf values; one pipeline run
- * computes all diagrams. In the lower-star filtration the +inf vertices come
- * after every real one and a real vertex's lower star stays inside its box,
- * so every pair is the pair the grid has alone, with the same local simplex
- * ids; around each box the +inf region closes the boundary as the virtual
- * maximum of D2 does (Sec. 5.2), and a grid's infinite D0 class is reported
+ * cross_x * cross_y, separated by planes of separator vertices; one pipeline
+ * run computes all diagrams. Separators are ordered above every real value,
+ * +inf included (items may hold +-inf), so in the lower-star filtration they
+ * come after every real vertex and a real vertex's lower star stays inside
+ * its box: every pair is the pair the grid has alone, with the same local
+ * simplex ids; around each box the separator region closes the boundary as
+ * the virtual maximum of D2 does (Sec. 5.2), and a grid's infinite D0 class
+ * is reported
  * as infinite (death = -1). */
 typedef struct {
     int32_t nx, ny, nz; /* the item's grid, each side >= 2                       */

@@ -1,17 +1,20 @@
 // Batching: many small grids in one pipeline run. The grids are placed in
-// one "super grid" as disjoint boxes separated by planes of +inf values.
+// one "super grid" as disjoint boxes separated by separator planes: vertices
+// that belong to no grid, filled with +inf and keyed above every float by the
+// order kernel (key 0xFFFFFFFF from the owner map; +inf itself keys lower).
 //
-// Why the pairs are unchanged: in the lower-star filtration the +inf
-// vertices (ordered among themselves by index, like any tie) enter after
-// every real vertex, and a real vertex's lower star holds only vertices of
-// its own box. Up to the largest real value the filtration is the disjoint
+// Why the pairs are unchanged: in the lower-star filtration the separator
+// vertices (ordered among themselves by index) enter after every real vertex,
+// +inf ones included, and a real vertex's lower star holds only vertices of
+// its own box. Up to the last real vertex the filtration is the disjoint
 // union of the grids' filtrations, so every pair whose birth and death are
 // real is a pair of its grid, with the same simplices (the id scheme and the
 // Freudenthal split are translation invariant, and the order of equal values
-// by index is preserved inside a box). Around each box, the +inf region is
-// connected and older than every real maximum: it plays the role of the
+// by index is preserved inside a box). Around each box, the separator region
+// is connected and older than every real maximum: it plays the role of the
 // virtual maximum that closes the domain boundary in D2 (Sec. 5.2). A grid's
-// one infinite D0 class dies in the +inf region; it is reported as infinite.
+// one infinite D0 class dies in the separator region; it is reported as
+// infinite.
 #include <algorithm>
 #include <numeric>
 #include <string>

@@ -417,12 +417,12 @@ static int gradient_setup(dms_ctx* ctx, dms_grid grid) {
     return DMS_OK;
 }
 
-static void gradient_enqueue(dms_ctx* ctx, const float* d_field, bool events) {
+static void gradient_enqueue(dms_ctx* ctx, const float* d_field, const uint32_t* owner, bool events) {
     hipStream_t st = ctx->st;
     const int64_t V = ctx->g.V;
     fill_u32(P<uint32_t>(ctx->flags), 0, 16, st);
     if (events) record(ctx, EV_START);
-    float_keys(d_field, V, P<uint32_t>(ctx->keysA), P<uint32_t>(ctx->flags), st);
+    float_keys(d_field, owner, V, P<uint32_t>(ctx->keysA), P<uint32_t>(ctx->flags), st);
     int r = radix_sort_pairs<uint32_t>(P<uint32_t>(ctx->keysA), P<uint32_t>(ctx->valsA), P<uint32_t>(ctx->keysB),
                                        P<uint32_t>(ctx->valsB), V, 0, 32, true, P<uint32_t>(ctx->hist),
                                        P<uint32_t>(ctx->part), st);
@@ -504,7 +504,7 @@ int dms_gradient(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t fla
     for (int attempt = 0; attempt < 2; ++attempt) {
         r = gradient_setup(ctx, grid);
         if (r != DMS_OK) return r;
-        gradient_enqueue(ctx, d_field, true);
+        gradient_enqueue(ctx, d_field, nullptr, true);
         bool over = false;
         r = gradient_counts(ctx, &over);
         if (r != DMS_OK) return r;
@@ -989,7 +989,7 @@ int dms_diagram_batch(dms_ctx* ctx, const float* d_fields, const dms_item* items
         if (r != DMS_OK) return r;
         if (use_graph) {
             // the buffers the captured kernels read and write
-            std::vector<const void*> sig = {ctx->bfield.p, ctx->flags.p, ctx->keysA.p, ctx->keysB.p, ctx->valsA.p,
+            std::vector<const void*> sig = {ctx->bfield.p, ctx->bowner.p, ctx->flags.p, ctx->keysA.p, ctx->keysB.p, ctx->valsA.p,
                                             ctx->valsB.p, ctx->hist.p, ctx->part.p, ctx->rank.p, ctx->ob.p,
                                             ctx->counters.p, ctx->G.p};
             for (int d = 0; d < 4; ++d) {
@@ -1003,7 +1003,7 @@ int dms_diagram_batch(dms_ctx* ctx, const float* d_fields, const dms_item* items
             if (!hit) {
                 hipGraph_t graph = nullptr;
                 HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
-                gradient_enqueue(ctx, P<float>(ctx->bfield), false);
+                gradient_enqueue(ctx, P<float>(ctx->bfield), P<uint32_t>(ctx->bowner), false);
                 HIPCHK(hipStreamEndCapture(st, &graph));
                 hipGraphExec_t exec = nullptr;
                 const hipError_t ge = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -1022,7 +1022,7 @@ int dms_diagram_batch(dms_ctx* ctx, const float* d_fields, const dms_item* items
             HIPCHK(hipGraphLaunch(hit->exec, st));
             ++ctx->binfo[4];
         } else {
-            gradient_enqueue(ctx, P<float>(ctx->bfield), true);
+            gradient_enqueue(ctx, P<float>(ctx->bfield), P<uint32_t>(ctx->bowner), true);
             ++ctx->binfo[6];
         }
         bool over = false;

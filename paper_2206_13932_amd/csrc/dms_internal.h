@@ -56,7 +56,8 @@ int radix_sort_pairs(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t n, int bi
 void iota_u32(uint32_t* out, int64_t n, hipStream_t st);
 void fill_u32(uint32_t* out, uint32_t v, int64_t n, hipStream_t st);
 void fill_u64(uint64_t* out, uint64_t v, int64_t n, hipStream_t st);
-void float_keys(const float* f, int64_t n, uint32_t* keys, uint32_t* flags, hipStream_t st);
+// owner: optional map of batched grids (EMPTY32 = separator vertex, keyed above every float)
+void float_keys(const float* f, const uint32_t* owner, int64_t n, uint32_t* keys, uint32_t* flags, hipStream_t st);
 void rank_scatter(const uint32_t* order, int64_t n, uint32_t* rank, hipStream_t st);
 void gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst, int64_t n, hipStream_t st);
 void gather_u64(const uint64_t* src, const uint32_t* idx, uint64_t* dst, int64_t n, hipStream_t st);

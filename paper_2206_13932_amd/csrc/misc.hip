@@ -24,10 +24,18 @@ __global__ void k_fill64(uint64_t* out, uint64_t v, int64_t n) {
 
 // Sec. 2.1: the symbolic perturbation orders equal values by vertex id; the
 // stable sort over (key, implicit index) realises it. -0 == +0; NaN flagged.
-__global__ void k_float_keys(const float* __restrict__ f, int64_t n, uint32_t* __restrict__ keys,
-                             uint32_t* flags) {
+// With an owner map (batched grids), a vertex that belongs to no grid gets
+// the key 0xFFFFFFFF, above float_key(+inf) = 0xFF800000 (NaN keys, the only
+// ones above that, are rejected): separator vertices come after every real
+// vertex, +inf included.
+__global__ void k_float_keys(const float* __restrict__ f, const uint32_t* __restrict__ owner, int64_t n,
+                             uint32_t* __restrict__ keys, uint32_t* flags) {
     const int64_t i = (int64_t)blockIdx.x * MB + threadIdx.x;
     if (i >= n) return;
+    if (owner && owner[i] == EMPTY32) {
+        keys[i] = 0xFFFFFFFFu;
+        return;
+    }
     const float v = f[i];
     if (is_nan_bits(v)) atomicOr(flags, FLAG_NAN);
     keys[i] = float_key(v);
@@ -61,8 +69,8 @@ void fill_u32(uint32_t* out, uint32_t v, int64_t n, hipStream_t st) {
 void fill_u64(uint64_t* out, uint64_t v, int64_t n, hipStream_t st) {
     if (n > 0) hipLaunchKernelGGL(k_fill64, dim3(nblocks(n)), dim3(MB), 0, st, out, v, n);
 }
-void float_keys(const float* f, int64_t n, uint32_t* keys, uint32_t* flags, hipStream_t st) {
-    if (n > 0) hipLaunchKernelGGL(k_float_keys, dim3(nblocks(n)), dim3(MB), 0, st, f, n, keys, flags);
+void float_keys(const float* f, const uint32_t* owner, int64_t n, uint32_t* keys, uint32_t* flags, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_float_keys, dim3(nblocks(n)), dim3(MB), 0, st, f, owner, n, keys, flags);
 }
 void inverse_perm(const uint32_t* perm, int64_t n, uint32_t* inv, hipStream_t st) {
     if (n > 0) hipLaunchKernelGGL(k_inverse, dim3(nblocks(n)), dim3(MB), 0, st, perm, n, inv);

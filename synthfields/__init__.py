@@ -97,6 +97,20 @@ CONFIGS = {
 }
 
 
+def with_infinities(field: np.ndarray, seed: int, frac_pos: float = 0.1, frac_neg: float = 0.05) -> np.ndarray:
+    """A copy of field with random vertices set to +inf / -inf, plus the whole
+    x = 0 face at +inf and the last vertex at -inf (infinities on the grid
+    boundary, where batched grids meet their separators)."""
+    rng = _rng(seed)
+    f = np.array(field, dtype=np.float32, copy=True)
+    u = rng.random(f.shape)
+    f[u < frac_pos] = np.inf
+    f[u > 1.0 - frac_neg] = -np.inf
+    f[..., 0] = np.inf
+    f.reshape(-1)[-1] = -np.inf
+    return f
+
+
 def field_from_config(name: str, seed: int = 0, shape=None) -> np.ndarray:
     cfg = CONFIGS[name]
     shp = tuple(shape) if shape is not None else cfg["shape"]

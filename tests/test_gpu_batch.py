@@ -45,6 +45,27 @@ def test_batch_equals_alone_and_oracle():
 
 
 @pytest.mark.gpu
+def test_batch_with_infinities():
+    """Items holding +inf (a whole box face, so real +inf vertices touch the
+    separators) and -inf: batched = alone = oracle. Separators are ordered
+    above every real value, +inf included."""
+    import torch
+    from paper_2206_13932_amd import dms
+    ctx = dms.Context(0)
+    rng = np.random.default_rng(11)
+    fs = [sf.with_infinities(f, 100 + i, 0.05 + 0.05 * (i % 4), 0.05) for i, f in enumerate(_fields(rng, 12, 3, 20))]
+    dev = [torch.from_numpy(f).cuda() for f in fs]
+    got = ctx.diagram_batch(dev)
+    for i, f in enumerate(fs):
+        print(f"[batch-inf] item={i} shape={f.shape}", flush=True)
+        res = oracle.run(f)
+        for d in range(3):
+            assert np.array_equal(got[i][d].cpu().numpy(), res.pairs[d]), (i, f.shape, d)
+        assert _same(got[i], ctx.diagram(dev[i])), i
+    ctx.close()
+
+
+@pytest.mark.gpu
 def test_batch_of_one_and_mixed_sizes():
     import torch
     from paper_2206_13932_amd import dms

@@ -23,6 +23,8 @@ SMALL_FIELDS = {
     "elevation": lambda: sf.elevation((7, 6, 5)),
     "radial": lambda: sf.radial((17, 17, 17)),
     "neg_zero": lambda: np.where(sf.noise((6, 6, 6), 8) < 0.5, np.float32(-0.0), np.float32(0.0)),
+    "infinities": lambda: sf.with_infinities(sf.noise((7, 8, 9), 9), 9),
+    "infinities_smooth": lambda: sf.with_infinities(sf.gaussians((12, 10, 11), 10, k=4, noise_frac=0.01), 10, 0.3, 0.1),
 }
 
 

@@ -73,6 +73,18 @@ def test_vertex_order_matches_stable_argsort_with_ties():
     assert np.array_equal(r, expect)
 
 
+@pytest.mark.parametrize("field", [sf.with_infinities(sf.noise((6, 5, 7), 40), 40),
+                                   sf.with_infinities(sf.gaussians((8, 7, 6), 41, 3, 0.01), 41, 0.3, 0.1)])
+def test_infinities_match_bruteforce(field):
+    # +-inf are ordinary, ordered values (ties by index); the whole pipeline
+    # on such a field equals the full-filtration reduction
+    g = field.ravel()
+    expect = np.empty(g.size, dtype=np.int64)
+    expect[np.argsort(g, kind="stable")] = np.arange(g.size)
+    assert np.array_equal(oracle.vertex_order(field), expect)
+    _bf_equal(field)
+
+
 def test_vertex_order_rejects_nan():
     f = sf.noise((3, 3, 3), 0)
     f[1, 1, 1] = np.nan
