@@ -243,6 +243,17 @@ enum {
 };
 int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap);
 
+/* Debug options of a context (inspection and tests; a new context has all
+ * of them 0). They change no result, only how the work is split or logged:
+ *   DMS_OPT_D1_SMALL_PASSES  value != 0: the D1 passes get tiny capacities
+ *       (lane heaps of 3 and 4 keys, first workgroup pass 24 keys, cached
+ *       boundaries of more than 2 keys added by full merges), so that small
+ *       grids go through every pass of PairCriticalSimplices;
+ *   DMS_OPT_LOG_PASSES       value != 0: one line per D1 pass on stderr.
+ * Returns DMS_OK, or DMS_E_INVAL for an unknown option or a NULL ctx. */
+enum { DMS_OPT_D1_SMALL_PASSES = 1, DMS_OPT_LOG_PASSES = 2 };
+int dms_set_option(dms_ctx* ctx, int32_t option, int64_t value);
+
 /* Milliseconds of the last call's stages, measured with HIP events on the
  * context's stream: [0] order, [1] gradient+critical (with the count
  * read-back), [2] critical sort, [3] D0+D2, [4] D1, [5] output assembly,

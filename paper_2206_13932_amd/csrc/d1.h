@@ -22,6 +22,8 @@ struct D1Inputs {
     const uint8_t* paired2_desc;  // per decreasing C2 position: paired in D2
     int bpr;
     uint32_t* flags;
+    bool small_passes = false;  // debug: tiny pass capacities, every pass used
+    bool log_passes = false;    // debug: one stderr line per pass
 };
 
 struct D1State {

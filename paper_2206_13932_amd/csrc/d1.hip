@@ -1870,7 +1870,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         const int plan_db[MAX_PASSES] = {256, 64, WB, WB, WB};
         uint32_t long_add = LONG_ADD;
         const int lane_passes = 2;  // passes 0 and 1 are thread-per-column
-        if (std::getenv("DMS_D1_TEST_PLAN")) {  // test hook: tiny capacities, every pass used
+        if (in.small_passes) {  // debug option: tiny capacities, every pass used
             plan_k[0] = 3;
             plan_k[1] = 4;
             plan_k[2] = 24;
@@ -1933,7 +1933,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
                 err = "D1: consistency check failed";
                 return -7;
             }
-            if (std::getenv("DMS_LOG"))
+            if (in.log_passes)
                 std::fprintf(stderr, "[dms] D1 pass %d: %lld columns, heap %lld entries/thread, %.1f ms\n", pass,
                              (long long)nwork, (long long)K,
                              std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_pass)

@@ -48,6 +48,7 @@ struct dms_ctx {
     int64_t n_d0_pairs = 0, n_d2_pairs = 0;
     // D1
     D1State d1;
+    bool opt_d1_small = false, opt_log = false;  // debug options (dms_set_option)
     // output staging
     Buf ob, od, okey, ocnt;
     // gradient scatter
@@ -682,6 +683,8 @@ static int run_d1(dms_ctx* ctx) {
     in.paired2_desc = P<uint8_t>(ctx->paired2);
     in.bpr = ctx->bpr;
     in.flags = P<uint32_t>(ctx->flags);
+    in.small_passes = ctx->opt_d1_small;
+    in.log_passes = ctx->opt_log;
     std::string err;
     int r = d1_run(ctx->d1, in, ctx->st, d1_limit(ctx), err);
     if (r != DMS_OK) return fail(ctx, r, err);
@@ -1105,6 +1108,15 @@ int dms_batch_info(const dms_ctx* ctx, int64_t info[8]) {
     if (!ctx || !info) return DMS_E_INVAL;
     for (int i = 0; i < 8; ++i) info[i] = ctx->binfo[i];
     return DMS_OK;
+}
+
+int dms_set_option(dms_ctx* ctx, int32_t option, int64_t value) {
+    if (!ctx) return DMS_E_INVAL;
+    switch (option) {
+        case DMS_OPT_D1_SMALL_PASSES: ctx->opt_d1_small = value != 0; return DMS_OK;
+        case DMS_OPT_LOG_PASSES: ctx->opt_log = value != 0; return DMS_OK;
+        default: return fail(ctx, DMS_E_INVAL, "dms_set_option: unknown option");
+    }
 }
 
 int dms_stage_ms(const dms_ctx* ctx, float ms[8]) {

@@ -19,6 +19,8 @@ DMS_OK, DMS_E_INVAL, DMS_E_NAN, DMS_E_NOMEM, DMS_E_CAPACITY, DMS_E_HIP, DMS_E_ST
     0, -1, -2, -3, -4, -5, -6, -7
 DMS_VIRTUAL_MAX = 1
 BUF_RANK, BUF_GRADIENT, BUF_CRIT0, BUF_ARCS0, BUF_ARCS2, BUF_STATS, BUF_D1LEN = 0, 1, 2, 6, 7, 8, 9
+# debug options of a context (dms_set_option)
+OPT_D1_SMALL_PASSES, OPT_LOG_PASSES = 1, 2
 _ERRNAMES = {-1: "DMS_E_INVAL", -2: "DMS_E_NAN", -3: "DMS_E_NOMEM", -4: "DMS_E_CAPACITY", -5: "DMS_E_HIP",
              -6: "DMS_E_STATE", -7: "DMS_E_INTERNAL"}
 
@@ -90,6 +92,8 @@ def load_library() -> ctypes.CDLL:
     lib.dms_d1_generators.restype = ctypes.c_int
     lib.dms_debug_copy.argtypes = [_p, ctypes.c_int, _p, i64]
     lib.dms_debug_copy.restype = i64
+    lib.dms_set_option.argtypes = [_p, ctypes.c_int32, i64]
+    lib.dms_set_option.restype = ctypes.c_int
     lib.dms_stage_ms.argtypes = [_p, ctypes.POINTER(ctypes.c_float * 8)]
     lib.dms_stage_ms.restype = ctypes.c_int
     lib.dms_scatter_grad.argtypes = [_p, i64, _p, _p, i64, _p]
@@ -309,6 +313,13 @@ class Context:
         arr = (ctypes.c_int64 * 8)()
         self.lib.dms_batch_info(self.h, ctypes.byref(arr))
         return list(arr)
+
+    def set_option(self, option: int, value: int = 1):
+        """Debug options (OPT_D1_SMALL_PASSES, OPT_LOG_PASSES); they change
+        how D1 splits or logs its work, never a result."""
+        rc = self.lib.dms_set_option(self.h, int(option), int(value))
+        if rc != DMS_OK:
+            self._raise(rc)
 
     def stage_ms(self):
         arr = (ctypes.c_float * 8)()

@@ -240,38 +240,40 @@ def test_hbm_budget_bounds_every_stage():
 
 @pytest.mark.gpu
 def test_parity_d1_every_deferral_pass():
-    """Tiny working heaps force columns through all D1 passes (LDS heaps of
-    two sizes, then workgroup passes), and every cached boundary longer than
-    two entries is added by the full merge; pairs must not change, and the
-    cycles published by every kind of pass must be valid generators."""
-    import os
-    import subprocess
-    import sys
-    code = (
-        "import numpy as np, torch, oracle, synthfields as sf\n"
-        "from paper_2206_13932_amd import dms\n"
-        "ctx = dms.Context(0)\n"
-        "longs = 0\n"
-        "for name, f in [('noise24', sf.noise((24, 24, 24), 3)),\n"
-        "                ('smooth40', sf.gaussians((40, 36, 32), 4, k=12, noise_frac=0.01))]:\n"
-        "    res = oracle.run(f)\n"
-        "    out = ctx.diagram(torch.from_numpy(f).cuda())\n"
-        "    st = ctx.debug(dms.BUF_STATS, np.uint64).tolist()\n"
-        "    print(name, 'deferrals', st[7], 'passes', st[10:20], 'full-merge additions', st[41], flush=True)\n"
-        "    assert st[7] > 0\n"
-        "    longs += st[41]\n"
-        "    for d in range(3):\n"
-        "        assert np.array_equal(out[d].cpu().numpy(), res.pairs[d]), (name, d)\n"
-        "    off, edges = ctx.d1_generators()\n"
-        "    d1 = out[1].cpu().numpy()\n"
-        "    fin = d1[d1[:, 1] >= 0]\n"
-        "    st = oracle.bf_check_cycles(res.shape, res.rank, fin, off.cpu().numpy(), edges.cpu().numpy())\n"
-        "    assert (st == 0).all(), (name, np.bincount(st))\n"
-        "assert longs > 0\n"
-        "print('ok')\n")
-    env = dict(os.environ, DMS_D1_TEST_PLAN="1")
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    r = subprocess.run([sys.executable, "-c", code], env=env, cwd=root, capture_output=True, text=True,
-                       timeout=240)
-    print(r.stdout[-2000:], r.stderr[-2000:])
-    assert r.returncode == 0 and "ok" in r.stdout
+    """Tiny working heaps (the context's debug option) force columns through
+    all D1 passes (LDS heaps of two sizes, then workgroup passes), and every
+    cached boundary longer than two entries is added by the full merge; pairs
+    must not change, and the cycles published by every kind of pass must be
+    valid generators. A second context without the option, used in between,
+    keeps the production plan."""
+    torch, dms, ctx = _gpu_ctx()
+    ctx.set_option(dms.OPT_D1_SMALL_PASSES, 1)
+    plain = dms.Context(0)
+    longs = 0
+    for name, f in [("noise24", sf.noise((24, 24, 24), 3)),
+                    ("smooth40", sf.gaussians((40, 36, 32), 4, k=12, noise_frac=0.01))]:
+        print(f"[parity] case=d1_small_passes/{name}", flush=True)
+        res = oracle.run(f)
+        ft = torch.from_numpy(f).cuda()
+        out = ctx.diagram(ft)
+        st = ctx.debug(dms.BUF_STATS, np.uint64).tolist()
+        print(name, "deferrals", st[7], "passes", st[10:20], "full-merge additions", st[41], flush=True)
+        assert st[7] > 0
+        longs += st[41]
+        for d in range(3):
+            assert np.array_equal(out[d].cpu().numpy(), res.pairs[d]), (name, d)
+        off, edges = ctx.d1_generators()
+        d1 = out[1].cpu().numpy()
+        fin = d1[d1[:, 1] >= 0]
+        status = oracle.bf_check_cycles(res.shape, res.rank, fin, off.cpu().numpy(), edges.cpu().numpy())
+        assert (status == 0).all(), (name, np.bincount(status))
+        ref = plain.diagram(ft)
+        pst = plain.debug(dms.BUF_STATS, np.uint64).tolist()
+        assert pst[7] < st[7], (name, pst[7], st[7])  # the option stays with its context
+        for d in range(3):
+            assert np.array_equal(ref[d].cpu().numpy(), res.pairs[d]), (name, "plain", d)
+    assert longs > 0
+    with pytest.raises(dms.DmsError):
+        ctx.set_option(99, 1)
+    ctx.close()
+    plain.close()
