@@ -99,7 +99,17 @@ __device__ inline uint64_t ld_rlx64(const uint64_t* p) {
 __device__ inline void st_rlx64(uint64_t* p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); /* vmcnt(0) */ }
+// Publish order: the data a claim makes visible is written with agent-scope
+// atomic stores (sc1, coherent across the XCDs' L2s); vmcnt(0) makes the
+// hardware finish them before the claiming atomic is issued, and the two
+// signal fences (compiler-only barriers) keep the compiler from moving any
+// memory operation across the wait. A release CAS at agent scope would also
+// order them, but it adds an L2 writeback (buffer_wbl2) per claim.
+__device__ inline void wait_stores() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0x0F70); /* vmcnt(0) */
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 __device__ inline bool cas32(uint32_t* p, uint32_t expect, uint32_t desired) {
     return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
