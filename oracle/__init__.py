@@ -75,6 +75,8 @@ def _lib(name: str) -> ctypes.CDLL:
         lib.bf_lower_link_betti.argtypes = [i64, i64, i64, p, p]
         lib.bf_d0_kruskal.argtypes = [i64, i64, i64, p, p, i64]
         lib.bf_d0_kruskal.restype = i64
+        lib.bf_d2_dual.argtypes = [i64, i64, i64, p, p, i64]
+        lib.bf_d2_dual.restype = i64
     _loaded[name] = lib
     return lib
 
@@ -184,6 +186,18 @@ def bf_d0_kruskal(shape, rank: np.ndarray) -> np.ndarray:
     cap = nx * ny * nz
     out = np.empty((cap, 2), dtype=np.int64)
     m = _lib("bruteforce").bf_d0_kruskal(nx, ny, nz, _ptr(r), _ptr(out), cap)
+    return out[:m].copy()
+
+
+def bf_d2_dual(shape, rank: np.ndarray) -> np.ndarray:
+    """D2 of the lexicographic filtration from the dual union-find over every
+    triangle and tetrahedron, with the outside as the oldest node:
+    (birth rank, death rank) pairs with positive persistence, sorted."""
+    nz, ny, nx = shape
+    r = np.ascontiguousarray(rank, dtype=np.uint32)
+    cap = nx * ny * nz + 16  # at most one maximum per lower star
+    out = np.empty((cap, 2), dtype=np.int64)
+    m = _lib("bruteforce").bf_d2_dual(nx, ny, nz, _ptr(r), _ptr(out), cap)
     return out[:m].copy()
 
 

@@ -16,6 +16,11 @@
  *    vertex; the expansion-based gradient has exactly that many critical
  *    cells per dimension in each lower star (Sec. 1.1, Sec. 2.6).
  *  - bf_counts: numbers of vertices, edges, triangles and tetrahedra.
+ *  - bf_d0_kruskal / bf_d2_dual: D0 and D2 of the whole filtration from
+ *    union-finds over every edge, or over every triangle and tetrahedron
+ *    with the outside (Sec. 5.1, 5.2), cheap enough for 512^3 grids.
+ *  - bf_check_cycles: persistent 1-cycle generators against their
+ *    definition (Sec. 8).
  * A grid with nz = 1 is the 2D grid of the plane z = 0, built from its
  * triangles (there the lower link of a vertex is a graph).
  */
@@ -470,6 +475,154 @@ void bf_check_cycles(int64_t nx, int64_t ny, int64_t nz, const uint32_t* rank, i
             basis.push_back(bs);
         }
     }
+}
+
+}  // extern "C"
+
+extern "C" {
+
+/* D2 in vertex-order space from the dual union-find over the whole
+ * triangulation (Sec. 5.2, the dual of the Sec. 5.1 argument; PairSimplices
+ * restricted to the top dimension, Sec. 2.5): every triangle, in decreasing
+ * lexicographic order, joins the components of its two cofacet tetrahedra,
+ * or of its one tetrahedron and the outside when it lies on the boundary of
+ * the grid. A component is as old as its highest tetrahedron; the outside is
+ * older than all. When two components meet, the younger one is filled: the
+ * pair is (triangle, that component's highest tetrahedron). Triangles and
+ * their cofacets are found from vertex coordinates (two vertices are joined
+ * when their coordinates differ by a non-zero vector whose non-zero
+ * components are all +1 or all -1; any 3 or 4 pairwise joined vertices span
+ * a simplex), not from any id table. Output: (birth rank, death rank) of
+ * every pair with positive persistence, sorted; returns their number. */
+int64_t bf_d2_dual(int64_t nx, int64_t ny, int64_t nz, const uint32_t* rank, int64_t* out, int64_t cap) {
+    const int64_t V = nx * ny * nz;
+    std::vector<uint32_t> order((size_t)V);
+    for (int64_t v = 0; v < V; ++v) order[rank[v]] = (uint32_t)v;
+    int nb[14][3];
+    int nn = 0;
+    for (int m = 1; m < 8; ++m)
+        for (int sg = 1; sg >= -1; sg -= 2) {
+            nb[nn][0] = sg * (m & 1);
+            nb[nn][1] = sg * ((m >> 1) & 1);
+            nb[nn][2] = sg * ((m >> 2) & 1);
+            ++nn;
+        }
+    auto joined = [](const int* p, const int* q) {
+        bool pos = true, neg = true, nzero = false;
+        for (int a = 0; a < 3; ++a) {
+            const int d = q[a] - p[a];
+            if (d != 0 && d != 1) pos = false;
+            if (d != 0 && d != -1) neg = false;
+            if (d != 0) nzero = true;
+        }
+        return nzero && (pos || neg);
+    };
+    /* a tetrahedron = (lowest corner, order in which its chain takes the
+     * three axes): node anchor * 6 + one of the 6 axis orders */
+    const int64_t OUT = 6 * V;
+    std::vector<uint32_t> parent((size_t)(OUT + 1));
+    for (int64_t i = 0; i <= OUT; ++i) parent[(size_t)i] = (uint32_t)i;
+    auto find = [&](uint32_t a) {
+        while (parent[a] != a) {
+            parent[a] = parent[parent[a]];
+            a = parent[a];
+        }
+        return a;
+    };
+    auto tet_node = [&](int pts[4][3]) {
+        int idx[4] = {0, 1, 2, 3};
+        std::sort(idx, idx + 4, [&](int i, int j) {
+            return pts[i][0] + pts[i][1] + pts[i][2] < pts[j][0] + pts[j][1] + pts[j][2];
+        });
+        int axis[3];
+        for (int s = 0; s < 3; ++s)
+            for (int a = 0; a < 3; ++a)
+                if (pts[idx[s + 1]][a] != pts[idx[s]][a]) axis[s] = a;
+        const int code = axis[0] * 2 + (axis[1] < axis[2] ? 0 : 1);
+        const int* p = pts[idx[0]];
+        return (uint32_t)((p[0] + nx * (p[1] + ny * (int64_t)p[2])) * 6 + code);
+    };
+    /* age of a node: the ranks of its vertices, decreasing (outside: above all) */
+    auto age = [&](uint32_t node, std::array<i64, 4>& k) {
+        if (node == (uint32_t)OUT) {
+            k = {V, V, V, V};
+            return;
+        }
+        const int64_t anchor = node / 6;
+        const int code = (int)(node % 6);
+        const int a0 = code / 2;
+        const int r1 = (a0 + 1) % 3, r2 = (a0 + 2) % 3;
+        const int lo = r1 < r2 ? r1 : r2, hi = r1 < r2 ? r2 : r1;
+        const int axes[3] = {a0, code % 2 ? hi : lo, code % 2 ? lo : hi};
+        int c[3] = {(int)(anchor % nx), (int)((anchor / nx) % ny), (int)(anchor / (nx * ny))};
+        k[0] = rank[anchor];
+        for (int s = 0; s < 3; ++s) {
+            c[axes[s]] += 1;
+            k[s + 1] = rank[c[0] + nx * (c[1] + ny * (int64_t)c[2])];
+        }
+        std::sort(k.begin(), k.end(), [](i64 a, i64 b) { return a > b; });
+    };
+    std::vector<std::pair<int64_t, int64_t>> pairs;
+    struct Tri { i64 k1, k2; int a, b; };
+    std::vector<Tri> tris;
+    for (int64_t r = V - 1; r >= 0; --r) {
+        const int64_t x = order[(size_t)r];
+        const int cx[3] = {(int)(x % nx), (int)((x / nx) % ny), (int)(x / (nx * ny))};
+        int pts[14][3];
+        int64_t ids[14];
+        bool lower[14];
+        int np = 0;
+        for (int n = 0; n < 14; ++n) {
+            int q[3] = {cx[0] + nb[n][0], cx[1] + nb[n][1], cx[2] + nb[n][2]};
+            if (q[0] < 0 || q[1] < 0 || q[2] < 0 || q[0] >= nx || q[1] >= ny || q[2] >= nz) continue;
+            for (int a = 0; a < 3; ++a) pts[np][a] = q[a];
+            ids[np] = q[0] + nx * (q[1] + ny * (int64_t)q[2]);
+            lower[np] = rank[ids[np]] < (uint32_t)r;
+            ++np;
+        }
+        tris.clear();
+        for (int i = 0; i < np; ++i)
+            for (int j = i + 1; j < np; ++j)
+                if (lower[i] && lower[j] && joined(pts[i], pts[j])) {
+                    const i64 ri = rank[ids[i]], rj = rank[ids[j]];
+                    tris.push_back({ri > rj ? ri : rj, ri > rj ? rj : ri, i, j});
+                }
+        std::sort(tris.begin(), tris.end(), [](const Tri& u, const Tri& w) {
+            return u.k1 != w.k1 ? u.k1 > w.k1 : u.k2 > w.k2;
+        });
+        for (const Tri& t : tris) {
+            uint32_t side[2] = {(uint32_t)OUT, (uint32_t)OUT};
+            int ns = 0;
+            for (int c = 0; c < np && ns < 2; ++c) {
+                if (c == t.a || c == t.b) continue;
+                if (!joined(pts[c], pts[t.a]) || !joined(pts[c], pts[t.b])) continue;
+                int tp[4][3];
+                for (int a = 0; a < 3; ++a) {
+                    tp[0][a] = cx[a];
+                    tp[1][a] = pts[t.a][a];
+                    tp[2][a] = pts[t.b][a];
+                    tp[3][a] = pts[c][a];
+                }
+                side[ns++] = tet_node(tp);
+            }
+            const uint32_t ra = find(side[0]), rb = find(side[1]);
+            if (ra == rb) continue;
+            std::array<i64, 4> ka, kb;
+            age(ra, ka);
+            age(rb, kb);
+            const bool a_young = ka < kb;
+            const uint32_t young = a_young ? ra : rb, old = a_young ? rb : ra;
+            const i64 death = a_young ? ka[0] : kb[0];
+            parent[young] = old;
+            if (death != r) pairs.push_back({r, death});
+        }
+    }
+    std::sort(pairs.begin(), pairs.end());
+    for (size_t i = 0; i < pairs.size() && (int64_t)i < cap; ++i) {
+        out[2 * i] = pairs[i].first;
+        out[2 * i + 1] = pairs[i].second;
+    }
+    return (int64_t)pairs.size();
 }
 
 }  // extern "C"

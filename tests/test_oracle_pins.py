@@ -323,6 +323,40 @@ def test_kruskal_d0_matches_oracle(field):
     assert d0 == [tuple(x) for x in oracle.bf_d0_kruskal(res.shape, res.rank).tolist()]
 
 
+@pytest.mark.parametrize("field", [sf.noise((16, 16, 16), 32), sf.gaussians((12, 14, 10), 3, 5, 0.01),
+                                   sf.radial((17, 17, 17)), sf.noise((2, 2, 9), 4), sf.noise((3, 17, 2), 5),
+                                   sf.with_infinities(sf.noise((6, 7, 5), 6), 6),
+                                   np.random.default_rng(7).integers(0, 3, size=(7, 6, 8)).astype(np.float32)])
+def test_dual_d2_matches_bruteforce_and_oracle(field):
+    """The dual union-find checker used at full size (every triangle and
+    tetrahedron, outside node, Sec. 5.2) gives the D2 of the full boundary
+    reduction, and the oracle's D2 equals both."""
+    res = oracle.run(field)
+    bp, _ = oracle.bf_diagram(res.shape, res.rank)
+    exp = sorted((int(b), int(d)) for dd, b, d in bp.tolist() if dd == 2)
+    got = [tuple(x) for x in oracle.bf_d2_dual(res.shape, res.rank).tolist()]
+    assert got == exp
+    fin, _ = oracle.order_space(res)
+    assert sorted((b, d) for (dim, b, d) in fin if dim == 2) == exp
+
+
+def test_dual_d2_every_order_of_one_cube_and_random_orders():
+    """Every vertex order of one cube (its D2 is a single void at most) and
+    random orders of small grids: dual union-find = full reduction."""
+    for perm in itertools.permutations(range(8)):
+        r = np.array(perm, dtype=np.uint32)
+        bp, _ = oracle.bf_diagram((2, 2, 2), r)
+        exp = sorted((int(b), int(d)) for dd, b, d in bp.tolist() if dd == 2)
+        assert [tuple(x) for x in oracle.bf_d2_dual((2, 2, 2), r).tolist()] == exp, perm
+    rng = np.random.default_rng(8)
+    for shape in [(3, 3, 3), (4, 3, 5), (2, 4, 3)]:
+        for _ in range(40):
+            r = rng.permutation(int(np.prod(shape))).astype(np.uint32)
+            bp, _ = oracle.bf_diagram(shape, r)
+            exp = sorted((int(b), int(d)) for dd, b, d in bp.tolist() if dd == 2)
+            assert [tuple(x) for x in oracle.bf_d2_dual(shape, r).tolist()] == exp, shape
+
+
 @pytest.mark.parametrize("field", [sf.noise((16, 16, 16), 0), sf.noise((24, 24, 24), 3),
                                    sf.gaussians((20, 22, 18), 7, k=8, noise_frac=0.01),
                                    np.random.default_rng(6).integers(0, 4, size=(9, 8, 7)).astype(np.float32)])
