@@ -23,6 +23,8 @@ paper resamples to 192^3, and for its "Elevation" and "Random" stress cases):
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 __all__ = ["noise", "gaussians", "elevation", "radial", "field_from_config",
@@ -39,29 +41,54 @@ def noise(shape, seed: int) -> np.ndarray:
     return rng.random(nz * ny * nx, dtype=np.float32).reshape(nz, ny, nx)
 
 
+def _quantise(v: np.ndarray) -> np.ndarray:
+    """Round to multiples of 2^-24: the exponential's last bits (which differ
+    between CPUs and numpy builds) then no longer reach the field."""
+    return np.round(v * 16777216.0) / 16777216.0
+
+
 def gaussians(shape, seed: int, k: int, noise_frac: float,
               sigma_range=(0.02, 0.15)) -> np.ndarray:
-    """Sum of k Gaussians plus uniform noise, evaluated separably."""
+    """Sum of k Gaussians plus uniform noise, evaluated separably.
+
+    The sum is taken term by term in a fixed order with elementwise float64
+    operations (no BLAS, whose summation order depends on the CPU), on
+    factors rounded to multiples of 2^-24, so that a seed gives the same
+    float32 field on every machine."""
     nz, ny, nx = shape
     rng = _rng(seed)
     xs = np.arange(nx, dtype=np.float64) / max(nx - 1, 1)
     ys = np.arange(ny, dtype=np.float64) / max(ny - 1, 1)
     zs = np.arange(nz, dtype=np.float64) / max(nz - 1, 1)
-    # g[z, y, x] = sum_i a_i gz_i[z] gy_i[y] gx_i[x], evaluated as one
-    # (nz x k) @ (k x ny*nx) product of the separable factors, slab by slab
-    A = np.empty((nz, k))
-    B = np.empty((k, ny, nx))
+    GX = np.empty((k, nx))
+    AZY = np.empty((k, nz, ny))  # a_i gz_i[z] gy_i[y]
     for i in range(k):
         c = rng.random(3)
         s = rng.uniform(sigma_range[0], sigma_range[1])
         a = rng.uniform(-1.0, 1.0)
         inv = 1.0 / (2.0 * s * s)
-        gx = np.exp(-((xs - c[0]) ** 2) * inv)
-        gy = np.exp(-((ys - c[1]) ** 2) * inv)
-        gz = np.exp(-((zs - c[2]) ** 2) * inv)
-        A[:, i] = a * gz
-        B[i] = gy[:, None] * gx[None, :]
-    g = (A @ B.reshape(k, ny * nx)).reshape(nz, ny, nx)
+        GX[i] = _quantise(np.exp(-((xs - c[0]) ** 2) * inv))
+        gy = _quantise(np.exp(-((ys - c[1]) ** 2) * inv))
+        gz = _quantise(np.exp(-((zs - c[2]) ** 2) * inv))
+        AZY[i] = (a * gz)[:, None] * gy[None, :]
+    g = np.empty((nz, ny, nx))
+
+    def slab(z0, z1):
+        acc = g[z0:z1]
+        acc[...] = 0.0
+        tmp = np.empty_like(acc)
+        for i in range(k):  # fixed order: the same sum everywhere
+            np.multiply(AZY[i, z0:z1, :, None], GX[i][None, None, :], out=tmp)
+            np.add(acc, tmp, out=acc)
+
+    step = max(1, (1 << 21) // max(1, ny * nx))
+    bounds = [(z0, min(nz, z0 + step)) for z0 in range(0, nz, step)]
+    if len(bounds) > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1, len(bounds))) as pool:
+            list(pool.map(lambda b: slab(*b), bounds))
+    else:
+        slab(0, nz)
     if noise_frac > 0.0:
         span = float(g.max() - g.min())
         step = max(1, (1 << 24) // max(1, ny * nx))

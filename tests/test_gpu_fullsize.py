@@ -9,8 +9,10 @@ whole field):
 * counting invariants of the whole diagram (Euler characteristic, one
   infinite class at the global minimum, |D0| = c0, |D2| = c3,
   |D1| = c1 - c0 + 1 = c2 - c3);
-* at 256^3, D0 in vertex-order space against Kruskal's union-find over every
-  edge of the triangulation (an independent computation of the definition);
+* the whole diagram against digests computed once on the CPU: the oracle's
+  pairs bit for bit (up to 256^3), D0 against Kruskal's union-find over every
+  edge and D2 against the dual union-find over every triangle and
+  tetrahedron (up to 512^3);
 * on the smooth fields, sampled persistent 1-cycle generators: cycles whose
   highest edge is the birth edge.
 """
@@ -116,14 +118,70 @@ def test_fullsize_gradient_samples_and_invariants(name):
         assert (np.diff(p[:, 0]) > 0).all()
     if name != "c_noise512":
         _check_generators_sampled(shape, rank, d1, ctx)
-    if name == "a_smooth256":
-        b = rank[d0[:-1, 0]].astype(np.int64)
-        ev = oracle.simplex_vertices(shape, 1, d0[:-1, 1])
-        d = rank[ev].max(axis=1).astype(np.int64)
-        keepp = b != d
-        mine = np.stack([b[keepp], d[keepp]], axis=1)
-        mine = mine[np.lexsort((mine[:, 1], mine[:, 0]))]
-        print("[fullsize] Kruskal D0", flush=True)
-        ref = oracle.bf_d0_kruskal(shape, rank)
-        assert np.array_equal(mine, ref)
     ctx.close()
+
+
+# ---- digests written once by tests/golden/make_fullsize_digests.py (oracle/ only) ----
+
+def _golden():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_digests.json")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def _sha(a):
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<i8").tobytes()).hexdigest()
+
+
+def _order_space(shape, rank, pairs, dim):
+    """Finite (birth, death) simplex pairs of dimension dim -> (rank of the
+    birth's highest vertex, rank of the death's highest vertex), pairs of zero
+    persistence dropped, sorted."""
+    fin = pairs[pairs[:, 1] >= 0]
+    b = oracle.max_vertex_rank(shape, rank, dim, fin[:, 0])
+    d = oracle.max_vertex_rank(shape, rank, dim + 1, fin[:, 1])
+    keep = b != d
+    m = np.stack([b[keep], d[keep]], axis=1)
+    return m[np.lexsort((m[:, 1], m[:, 0]))]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["noise128", "noise256", "noise512", "smooth256", "smooth512"])
+def test_fullsize_diagrams_against_oracle_digests(name):
+    """The whole diagram at full size, as bench.py times it (one dms_diagram
+    call on the field in HBM), against digests computed once on the CPU:
+    the oracle's D0, D1 and D2 simplex pairs bit for bit where the oracle
+    finishes (up to 256^3: the production D1 pass plan, heaps and workgroup
+    passes included), and D0 / D2 in vertex-order space against Kruskal's
+    union-find over every edge and the dual union-find over every triangle
+    and tetrahedron with an outside node (also at 512^3)."""
+    import hashlib
+    import torch
+    from paper_2206_13932_amd import dms
+    from tests.golden.make_fullsize_digests import field_of
+    gold = _golden()[name]
+    print(f"[fullsize-digest] workload={name}", flush=True)
+    f = field_of(name)
+    assert hashlib.sha256(np.ascontiguousarray(f).tobytes()).hexdigest() == gold["field"]["sha256"], \
+        "the generator did not reproduce the field the digests were computed on"
+    shape = f.shape
+    ctx = dms.Context(0)
+    out = ctx.diagram(torch.from_numpy(f).cuda())
+    pairs = [out[d].cpu().numpy().astype(np.int64) for d in range(3)]
+    st = ctx.debug(dms.BUF_STATS, np.uint64).tolist()
+    print(f"[fullsize-digest] pairs {[len(p) for p in pairs]}, D1 pass columns {st[10:20:2]}", flush=True)
+    ctx.close()
+    if "oracle" in gold:
+        for d in range(3):
+            g = gold["oracle"][f"d{d}"]
+            assert len(pairs[d]) == g["n"] and _sha(pairs[d]) == g["sha256"], (name, f"D{d}")
+    if "kruskal_d0" in gold or "dual_d2" in gold:
+        rank = oracle.vertex_order(f)
+        for key, d in (("kruskal_d0", 0), ("dual_d2", 2)):
+            if key in gold:
+                m = _order_space(shape, rank, pairs[d], d)
+                print(f"[fullsize-digest] {key}: {len(m)} pairs of positive persistence", flush=True)
+                assert len(m) == gold[key]["n"] and _sha(m) == gold[key]["sha256"], (name, key)
