@@ -517,8 +517,45 @@ int64_t bf_d2_dual(int64_t nx, int64_t ny, int64_t nz, const uint32_t* rank, int
         }
         return nzero && (pos || neg);
     };
+    const int zero[3] = {0, 0, 0};
     /* a tetrahedron = (lowest corner, order in which its chain takes the
-     * three axes): node anchor * 6 + one of the 6 axis orders */
+     * three axes): node anchor * 6 + code; from four corner offsets around
+     * the vertex, the anchor offset and the code */
+    auto tet_of = [&](const int pts[4][3], int anchor_off[3]) {
+        int idx[4] = {0, 1, 2, 3};
+        std::sort(idx, idx + 4, [&](int i, int j) {
+            return pts[i][0] + pts[i][1] + pts[i][2] < pts[j][0] + pts[j][1] + pts[j][2];
+        });
+        int axis[3] = {0, 0, 0};
+        for (int s = 0; s < 3; ++s)
+            for (int a = 0; a < 3; ++a)
+                if (pts[idx[s + 1]][a] != pts[idx[s]][a]) axis[s] = a;
+        for (int a = 0; a < 3; ++a) anchor_off[a] = pts[idx[0]][a];
+        return axis[0] * 2 + (axis[1] < axis[2] ? 0 : 1);
+    };
+    /* tables over the 14 neighbour offsets, derived from coordinates once:
+     * which pairs are joined, and for a joined pair (a, b) the (at most two)
+     * offsets c joined to 0, a and b, with the tetrahedron {0, a, b, c} */
+    bool J[14][14];
+    int ncof[14][14];
+    int cof[14][14][2], cof_code[14][14][2], cof_anchor[14][14][2][3];
+    for (int a = 0; a < 14; ++a)
+        for (int b = 0; b < 14; ++b) {
+            J[a][b] = a != b && joined(nb[a], nb[b]);
+            ncof[a][b] = 0;
+        }
+    for (int a = 0; a < 14; ++a)
+        for (int b = 0; b < 14; ++b) {
+            if (!J[a][b] || !joined(zero, nb[a]) || !joined(zero, nb[b])) continue;
+            for (int c = 0; c < 14; ++c) {
+                if (c == a || c == b || !J[c][a] || !J[c][b]) continue;
+                const int k = ncof[a][b]++;
+                cof[a][b][k] = c;
+                const int pts[4][3] = {{0, 0, 0}, {nb[a][0], nb[a][1], nb[a][2]}, {nb[b][0], nb[b][1], nb[b][2]},
+                                       {nb[c][0], nb[c][1], nb[c][2]}};
+                cof_code[a][b][k] = tet_of(pts, cof_anchor[a][b][k]);
+            }
+        }
     const int64_t OUT = 6 * V;
     std::vector<uint32_t> parent((size_t)(OUT + 1));
     for (int64_t i = 0; i <= OUT; ++i) parent[(size_t)i] = (uint32_t)i;
@@ -528,19 +565,6 @@ int64_t bf_d2_dual(int64_t nx, int64_t ny, int64_t nz, const uint32_t* rank, int
             a = parent[a];
         }
         return a;
-    };
-    auto tet_node = [&](int pts[4][3]) {
-        int idx[4] = {0, 1, 2, 3};
-        std::sort(idx, idx + 4, [&](int i, int j) {
-            return pts[i][0] + pts[i][1] + pts[i][2] < pts[j][0] + pts[j][1] + pts[j][2];
-        });
-        int axis[3];
-        for (int s = 0; s < 3; ++s)
-            for (int a = 0; a < 3; ++a)
-                if (pts[idx[s + 1]][a] != pts[idx[s]][a]) axis[s] = a;
-        const int code = axis[0] * 2 + (axis[1] < axis[2] ? 0 : 1);
-        const int* p = pts[idx[0]];
-        return (uint32_t)((p[0] + nx * (p[1] + ny * (int64_t)p[2])) * 6 + code);
     };
     /* age of a node: the ranks of its vertices, decreasing (outside: above all) */
     auto age = [&](uint32_t node, std::array<i64, 4>& k) {
@@ -568,42 +592,30 @@ int64_t bf_d2_dual(int64_t nx, int64_t ny, int64_t nz, const uint32_t* rank, int
     for (int64_t r = V - 1; r >= 0; --r) {
         const int64_t x = order[(size_t)r];
         const int cx[3] = {(int)(x % nx), (int)((x / nx) % ny), (int)(x / (nx * ny))};
-        int pts[14][3];
-        int64_t ids[14];
-        bool lower[14];
-        int np = 0;
+        bool in[14], lower[14];
+        i64 rk[14];
         for (int n = 0; n < 14; ++n) {
-            int q[3] = {cx[0] + nb[n][0], cx[1] + nb[n][1], cx[2] + nb[n][2]};
-            if (q[0] < 0 || q[1] < 0 || q[2] < 0 || q[0] >= nx || q[1] >= ny || q[2] >= nz) continue;
-            for (int a = 0; a < 3; ++a) pts[np][a] = q[a];
-            ids[np] = q[0] + nx * (q[1] + ny * (int64_t)q[2]);
-            lower[np] = rank[ids[np]] < (uint32_t)r;
-            ++np;
+            const int q[3] = {cx[0] + nb[n][0], cx[1] + nb[n][1], cx[2] + nb[n][2]};
+            in[n] = q[0] >= 0 && q[1] >= 0 && q[2] >= 0 && q[0] < nx && q[1] < ny && q[2] < nz;
+            rk[n] = in[n] ? rank[q[0] + nx * (q[1] + ny * (int64_t)q[2])] : -1;
+            lower[n] = in[n] && rk[n] < r;
         }
         tris.clear();
-        for (int i = 0; i < np; ++i)
-            for (int j = i + 1; j < np; ++j)
-                if (lower[i] && lower[j] && joined(pts[i], pts[j])) {
-                    const i64 ri = rank[ids[i]], rj = rank[ids[j]];
-                    tris.push_back({ri > rj ? ri : rj, ri > rj ? rj : ri, i, j});
-                }
+        for (int i = 0; i < 14; ++i)
+            for (int j = i + 1; j < 14; ++j)
+                if (lower[i] && lower[j] && J[i][j])
+                    tris.push_back({rk[i] > rk[j] ? rk[i] : rk[j], rk[i] > rk[j] ? rk[j] : rk[i], i, j});
         std::sort(tris.begin(), tris.end(), [](const Tri& u, const Tri& w) {
             return u.k1 != w.k1 ? u.k1 > w.k1 : u.k2 > w.k2;
         });
         for (const Tri& t : tris) {
             uint32_t side[2] = {(uint32_t)OUT, (uint32_t)OUT};
             int ns = 0;
-            for (int c = 0; c < np && ns < 2; ++c) {
-                if (c == t.a || c == t.b) continue;
-                if (!joined(pts[c], pts[t.a]) || !joined(pts[c], pts[t.b])) continue;
-                int tp[4][3];
-                for (int a = 0; a < 3; ++a) {
-                    tp[0][a] = cx[a];
-                    tp[1][a] = pts[t.a][a];
-                    tp[2][a] = pts[t.b][a];
-                    tp[3][a] = pts[c][a];
-                }
-                side[ns++] = tet_node(tp);
+            for (int k = 0; k < ncof[t.a][t.b]; ++k) {
+                if (!in[cof[t.a][t.b][k]]) continue;
+                const int* ao = cof_anchor[t.a][t.b][k];
+                const int64_t anchor = (cx[0] + ao[0]) + nx * ((cx[1] + ao[1]) + ny * (int64_t)(cx[2] + ao[2]));
+                side[ns++] = (uint32_t)(anchor * 6 + cof_code[t.a][t.b][k]);
             }
             const uint32_t ra = find(side[0]), rb = find(side[1]);
             if (ra == rb) continue;
