@@ -123,6 +123,8 @@ struct StarTables {
     int8_t al27[NSLOT];       // aoff.x + 3 aoff.y + 9 aoff.z
     uint8_t dim[NSLOT];
     uint8_t type[NSLOT];
+    uint64_t slnb_lo[NNB];    // slots (0..63) whose cell contains neighbour n
+    uint16_t slnb_hi[NNB];    // the same, slots 64..73 (bit s-64)
 };
 
 // Persistent work distribution: lanes that are idle take the next work item

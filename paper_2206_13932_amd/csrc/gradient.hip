@@ -2,14 +2,9 @@
 // critical-cell extraction -- the paper's Alg. "Zero-persistence skip" and
 // Sec. 2.6; parallel over vertices as in Sec. 7.2.
 //
-// One lane per vertex x. The lower star L(x) holds the cells of the open star
-// of x whose other vertices are all lower than x. With the lower neighbours
-// relabelled 0..k-1 by rank, a cell of L(x) is the bitmask of its lower
-// neighbours, and the lexicographic order of Sec. 2.2 restricted to L(x) is
-// the integer order of these masks (the highest differing vertex decides; a
-// face is a mask missing only lower bits). Both priority queues are then
-// 74-bit slot sets whose minimum is found by comparing 14-bit keys computed
-// from the labels, so the simulation is exact and needs no per-lane heap.
+// One lane per vertex x; the per-vertex algorithm is lower_star.h (slot sets
+// as priority queues, minimum by elimination over the rank labels of the
+// lower neighbours, labels from a sorting network).
 //
 // A workgroup owns 1024 consecutive vertices and hands them to its lanes in
 // order of lower-star size, so that the lanes of a wave, which run the
@@ -20,10 +15,11 @@
 //
 // Output: gradient byte planes (see dms_device.h) and the critical cells of
 // each dimension appended, with their packed lexicographic keys, to per-
-// dimension lists (one atomic per wavefront and dimension).
+// dimension lists (one atomic per workgroup and dimension).
 #include "dms_device.h"
 #include "dms_internal.h"
 #include "star_tables.h"
+#include "lower_star.h"
 
 namespace dms {
 
@@ -36,7 +32,8 @@ struct LdsTables {
     uint64_t cof_lo[NSLOT];
     uint16_t cof_hi[NSLOT];
     uint16_t cellnb[NSLOT];
-    uint16_t knb[NSLOT];  // the slot's neighbours a | b << 4 | c << 8 (repeated when fewer)
+    uint64_t slnb_lo[NNB];  // slots holding neighbour n (0..63, then 64..73)
+    uint16_t slnb_hi[NNB];
     uint8_t plane[NSLOT];
     int8_t al27[NSLOT];
     int8_t l27[NNB];
@@ -60,6 +57,8 @@ __device__ inline uint32_t wave_exclusive(uint32_t v, uint32_t& total) {
 }
 
 
+// PACKED: ranks below 2^28 (the labels come from one 32-bit sorting network)
+template <bool PACKED>
 __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_gradient(GridDev g, const uint32_t* __restrict__ rank,
                                                  uint8_t* __restrict__ G, int bpr, CritLists cl) {
     __shared__ LdsTables T;
@@ -73,16 +72,13 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         T.cof_lo[i] = kStar.cof_lo[i];
         T.cof_hi[i] = kStar.cof_hi[i];
         T.cellnb[i] = kStar.cellnb[i];
-        {
-            const uint32_t nb = kStar.cellnb[i], nb2 = nb & (nb - 1), nb3 = nb2 & (nb2 - 1);
-            const uint32_t a = __builtin_ctz(nb), b = nb2 ? __builtin_ctz(nb2) : a, c = nb3 ? __builtin_ctz(nb3) : b;
-            T.knb[i] = (uint16_t)(a | b << 4 | c << 8);
-        }
         T.plane[i] = kStar.plane[i];
         T.al27[i] = kStar.al27[i];
         T.aofflin[i] = (int64_t)kStar.aoff[i][0] + kStar.aoff[i][1] * g.sy + kStar.aoff[i][2] * g.sz;
     }
     for (int i = tid; i < NNB; i += GB) {
+        T.slnb_lo[i] = kStar.slnb_lo[i];
+        T.slnb_hi[i] = kStar.slnb_hi[i];
         T.l27[i] = kStar.l27[i];
         T.lessc[i] = kStar.lessc[i];
         T.cpos_pos[i] = kStar.cpos_pos[i];
@@ -121,20 +117,6 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         }
         return lower;
     };
-    // cells of L(v): the slots whose neighbour sets are lower
-    auto cells_of = [&](uint32_t lower, uint64_t& in_lo, uint32_t& in_hi) {
-        in_lo = 0;
-        in_hi = 0;
-#pragma unroll
-        for (int s = 0; s < NSLOT; ++s) {
-            const uint32_t nb = kStar.cellnb[s];
-            if ((nb & ~lower) == 0) {
-                if (s < 64) in_lo |= (uint64_t)1 << s;
-                else in_hi |= 1u << (s - 64);
-            }
-        }
-    };
-
     // ---- 1. own vertex: lower star size, grid-boundary codes, lane assignment ----
     // Lanes of a wave run the lower-star loop in lockstep, so its cost is the
     // largest lower star in the wave. The vertices of the block are handed to
@@ -159,7 +141,7 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
                 for (int t = 0; t < 6; ++t) G[tet_code_at(V, xo, t)] = CODE_NONE;
             }
             if (lower) {
-                cells_of(lower, own_lo, own_hi);
+                star_cells(lower, own_lo, own_hi);
                 ncell = (uint32_t)(popc64(own_lo) + __builtin_popcount(own_hi));
             }
         }
@@ -200,105 +182,14 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         } else {
             uint64_t in_lo;
             uint32_t in_hi;
-            cells_of(lower, in_lo, in_hi);
-            // relabel the lower neighbours by rank: rel[n] = #lower neighbours below n
-            int n0 = 0;
-#pragma unroll
-            for (int n = 0; n < NNB; ++n) {
-                uint32_t c = 0;
-#pragma unroll
-                for (int m = 0; m < NNB; ++m)
-                    if (m != n) c += ((lower >> m) & 1) && r[m] < r[n];
-                relpack |= (uint64_t)c << (4 * n);
-                if (((lower >> n) & 1) && c == 0) n0 = n;
-            }
-            // key of a cell of L(x): bitmask of its lower neighbours' rank labels
-            auto label = [&](uint32_t n) { return (uint32_t)(relpack >> (4 * n)) & 15u; };
-            auto key_of = [&](int s) {
-                const uint32_t q = T.knb[s];
-                return (1u << label(q & 15u)) | (1u << label((q >> 4) & 15u)) | (1u << label(q >> 8));
-            };
-            auto gput = [&](int s, uint8_t code) { CODE(s) = code; };
-            auto unpaired = [&](int s, uint64_t cls_lo) { return popc64(T.face[s] & ~cls_lo); };
-            // pair (p, a): p is a facet of a; w = the neighbour of a not in p
-            auto pair_cells = [&](int p, int a) {
-                const uint32_t w = __builtin_ctz((uint32_t)(T.cellnb[a] & ~T.cellnb[p]));
-                const int pos = __builtin_popcount(T.cellnb[a] & T.lessc[w]) + T.cpos_pos[w];
-                gput(a, (uint8_t)(0x80 | pos));
-                gput(p, (uint8_t)(13 + T.l27[w] - T.al27[p]));
-            };
-            // x pairs with its lowest edge delta = {x, n0}
-            G[x] = (uint8_t)(13 + T.l27[n0]);
-            gput(n0, (uint8_t)(0x80 | T.cpos_pos[n0]));
-            uint64_t cls_lo = (uint64_t)1 << n0;
-            uint32_t cls_hi = 0;
-            uint64_t z_lo = (in_lo & 0x3FFFull) & ~cls_lo;  // other edges
-            uint32_t z_hi = 0;
-            uint64_t o_lo = 0;
-            uint32_t o_hi = 0;
-            auto push_cofaces = [&](int s) {
-                uint64_t c = T.cof_lo[s] & in_lo & ~cls_lo;
-                while (c) {
-                    const int b = __builtin_ctzll(c);
-                    c &= c - 1;
-                    if (unpaired(b, cls_lo) == 1) o_lo |= (uint64_t)1 << b;
-                }
-                uint32_t ch = T.cof_hi[s] & in_hi & ~cls_hi;
-                while (ch) {
-                    const int b = __builtin_ctz(ch);
-                    ch &= ch - 1;
-                    if (unpaired(64 + b, cls_lo) == 1) o_hi |= 1u << b;
-                }
-            };
-            auto pop_min = [&](uint64_t& lo, uint32_t& hi) {
-                int best = -1;
-                uint32_t bk = 0xFFFFFFFFu;
-                uint64_t m = lo;
-                while (m) {
-                    const int s = __builtin_ctzll(m);
-                    m &= m - 1;
-                    const uint32_t k = key_of(s);
-                    if (k < bk) { bk = k; best = s; }
-                }
-                uint32_t h = hi;
-                while (h) {
-                    const int s = 64 + __builtin_ctz(h);
-                    h &= h - 1;
-                    const uint32_t k = key_of(s);
-                    if (k < bk) { bk = k; best = s; }
-                }
-                if (best < 64) lo &= ~((uint64_t)1 << best);
-                else hi &= ~(1u << (best - 64));
-                return best;
-            };
-            push_cofaces(n0);
-            for (int guard = 0; guard < 4 * NSLOT; ++guard) {
-                while (o_lo | o_hi) {
-                    const int a = pop_min(o_lo, o_hi);
-                    const bool done = a < 64 ? ((cls_lo >> a) & 1) : ((cls_hi >> (a - 64)) & 1);
-                    if (done) continue;
-                    const uint64_t u = T.face[a] & ~cls_lo;
-                    if (u == 0) {
-                        if (a < 64) z_lo |= (uint64_t)1 << a;
-                        else z_hi |= 1u << (a - 64);
-                        continue;
-                    }
-                    const int p = __builtin_ctzll(u);
-                    pair_cells(p, a);
-                    cls_lo |= (uint64_t)1 << p;
-                    if (a < 64) cls_lo |= (uint64_t)1 << a;
-                    else cls_hi |= 1u << (a - 64);
-                    z_lo &= ~((uint64_t)1 << p);
-                    push_cofaces(a);
-                    push_cofaces(p);
-                }
-                if (!(z_lo | z_hi)) break;
-                const int c = pop_min(z_lo, z_hi);
-                if (c < 64) { cls_lo |= (uint64_t)1 << c; crit_lo |= (uint64_t)1 << c; }
-                else { cls_hi |= 1u << (c - 64); crit_hi |= 1u << (c - 64); }
-                gput(c, CODE_CRIT);
-                push_cofaces(c);
-            }
+            star_cells(lower, in_lo, in_hi);
+            uint32_t inv0, inv1;
+            relabel<PACKED>(r, lower, inv0, inv1, relpack);
+            uint8_t xcode;
+            lower_star_gradient(
+                T, in_lo, in_hi, __builtin_popcount(lower), inv0, inv1,
+                [&](int s, uint8_t code) { CODE(s) = code; }, xcode, crit_lo, crit_hi);
+            G[x] = xcode;
         }
     }
     __syncthreads();
@@ -307,11 +198,13 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     // consecutive lanes -> consecutive bytes ----
     {
         const uint32_t col = own_lane;
+#pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
             const bool w = s < 64 ? ((own_lo >> s) & 1) : ((own_hi >> (s - 64)) & 1);
             if (w) {
-                const int pl = T.plane[s];  // the same in every lane
-                const int64_t a = xo + T.aofflin[s];
+                constexpr int64_t zero = 0;
+                const int pl = kStar.plane[s];  // compile-time after unrolling
+                const int64_t a = xo + (zero + kStar.aoff[s][0]) + kStar.aoff[s][1] * g.sy + kStar.aoff[s][2] * g.sz;
                 G[pl < 20 ? (int64_t)pl * V + a : tet_code_at(V, a, pl - 20)] = scode[s * GB + col];
             }
         }
@@ -430,7 +323,10 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
 void launch_gradient(const GridDev& g, const uint32_t* rank, uint8_t* G, int bpr, const CritLists& cl,
                      hipStream_t st) {
     const int64_t blocks = (g.V + GB - 1) / GB;
-    hipLaunchKernelGGL(k_gradient, dim3((unsigned)blocks), dim3(GB), 0, st, g, rank, G, bpr, cl);
+    if (g.V <= ((int64_t)1 << 28))  // ranks fit 28 bits: (rank << 4 | neighbour) sorts in 32 bits
+        hipLaunchKernelGGL(k_gradient<true>, dim3((unsigned)blocks), dim3(GB), 0, st, g, rank, G, bpr, cl);
+    else
+        hipLaunchKernelGGL(k_gradient<false>, dim3((unsigned)blocks), dim3(GB), 0, st, g, rank, G, bpr, cl);
 }
 
 }  // namespace dms

@@ -1,0 +1,216 @@
+// ProcessLowerStars on one vertex (Robins et al., as the paper's Alg.
+// "Zero-persistence skip" and Sec. 2.6 use it), written for one GPU lane.
+//
+// Notation. x is the vertex, its lower neighbours are relabelled 0..k-1 by
+// rank (the label of a neighbour is its place among them), and a cell of the
+// lower star L(x) is the set of its lower neighbours. The lexicographic order
+// of Sec. 2.2 restricted to L(x) is the integer order of the cells' label
+// bitmasks: the highest differing vertex decides, and a face is a mask that
+// lacks only lower bits.
+//
+// Cells are the 74 slots of the open star (star_tables.h); both priority
+// queues are slot sets. The minimum of a set is found by elimination from
+// the highest label down: at label j, if some member lacks j, the members
+// that hold j go; the last member standing has the smallest mask. The slots
+// holding a neighbour are one table row, so a level costs a few bit
+// operations whatever the set's size, and the work stops as soon as one
+// member is left.
+#pragma once
+#include "dms_device.h"
+
+namespace dms {
+
+// ---- Batcher's odd-even merge sort on 16 keys (63 compare-exchanges) ----
+struct SortNet16 {
+    uint8_t a[64], b[64];
+    int n = 0;
+};
+constexpr SortNet16 make_sortnet16() {
+    SortNet16 s{};
+    // iterative form of Batcher's network for N = 16
+    for (int p = 1; p < 16; p <<= 1)
+        for (int k = p; k >= 1; k >>= 1)
+            for (int j = k % p; j + k < 16; j += 2 * k)
+                for (int i = 0; i < k && i + j + k < 16; ++i)
+                    if ((i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+                        s.a[s.n] = (uint8_t)(i + j);
+                        s.b[s.n] = (uint8_t)(i + j + k);
+                        ++s.n;
+                    }
+    return s;
+}
+constexpr SortNet16 kSortNet16 = make_sortnet16();
+static_assert(kSortNet16.n == 63, "Batcher's network on 16 keys has 63 comparators");
+
+// Labels of the lower neighbours from their ranks r[n] (lower: bit n set).
+// Out: inv0 / inv1 = the neighbour holding label j, 4 bits per label (labels
+// 0..7, then 8..13); relpack = the label of neighbour n at bits 4n (lower
+// neighbours only). PACKED: ranks below 2^28, so (rank << 4 | n) sorts in 32
+// bits; otherwise each label is counted.
+template <bool PACKED>
+__host__ __device__ inline void relabel(const uint32_t (&r)[NNB], uint32_t lower, uint32_t& inv0, uint32_t& inv1,
+                                        uint64_t& relpack) {
+    inv0 = 0;
+    inv1 = 0;
+    relpack = 0;
+    if (PACKED) {
+        uint32_t a[16];
+#pragma unroll
+        for (int n = 0; n < NNB; ++n) a[n] = ((lower >> n) & 1) ? (r[n] << 4) | (uint32_t)n : 0xFFFFFFFFu;
+        a[14] = 0xFFFFFFFFu;
+        a[15] = 0xFFFFFFFFu;
+#pragma unroll
+        for (int c = 0; c < kSortNet16.n; ++c) {
+            const uint32_t u = a[kSortNet16.a[c]], v = a[kSortNet16.b[c]];
+            a[kSortNet16.a[c]] = u < v ? u : v;
+            a[kSortNet16.b[c]] = u < v ? v : u;
+        }
+#pragma unroll
+        for (int j = 0; j < NNB; ++j) {
+            const uint32_t n = a[j] & 15u;  // 15 past the last lower neighbour
+            if (j < 8) inv0 |= n << (4 * j);
+            else inv1 |= n << (4 * (j - 8));
+            if (a[j] != 0xFFFFFFFFu) relpack |= (uint64_t)j << (4 * n);
+        }
+    } else {
+#pragma unroll
+        for (int n = 0; n < NNB; ++n) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int m = 0; m < NNB; ++m)
+                if (m != n) c += ((lower >> m) & 1) && r[m] < r[n];
+            if ((lower >> n) & 1) {
+                relpack |= (uint64_t)c << (4 * n);
+                if (c < 8) inv0 |= (uint32_t)n << (4 * c);
+                else inv1 |= (uint32_t)n << (4 * (c - 8));
+            }
+        }
+    }
+}
+
+// The cells of L(x): every slot minus those holding a neighbour that is not
+// lower (or not in the grid).
+__host__ __device__ inline void star_cells(uint32_t lower, uint64_t& in_lo, uint32_t& in_hi) {
+    uint64_t rm_lo = 0;
+    uint32_t rm_hi = 0;
+#pragma unroll
+    for (int n = 0; n < NNB; ++n)
+        if (!((lower >> n) & 1)) {
+            rm_lo |= kStar.slnb_lo[n];
+            rm_hi |= kStar.slnb_hi[n];
+        }
+    in_lo = ~rm_lo;
+    in_hi = ((1u << (NSLOT - 64)) - 1) & ~rm_hi;
+}
+
+__host__ __device__ inline int popc64_(uint64_t v) { return __builtin_popcountll(v); }
+
+// ProcessLowerStars on a vertex with k >= 1 lower neighbours.
+// T: star tables (face, cof_lo, cof_hi, cellnb, lessc, cpos_pos, l27, al27,
+// slnb_lo, slnb_hi); put(slot, code) receives the partner code of every cell
+// of L(x) that is paired (codes as in dms_device.h); xcode = the code of x;
+// crit_lo / crit_hi = the critical cells.
+template <class Tab, class Put>
+__host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo, uint32_t in_hi, int k,
+                                                    uint32_t inv0, uint32_t inv1, Put put, uint8_t& xcode,
+                                                    uint64_t& crit_lo, uint32_t& crit_hi) {
+    auto nb_of = [&](int j) { return (int)((j < 8 ? inv0 >> (4 * j) : inv1 >> (4 * (j - 8))) & 15u); };
+    crit_lo = 0;
+    crit_hi = 0;
+    uint64_t cls_lo;
+    uint32_t cls_hi = 0;
+    // pair (p, a): p is a facet of a; w = the neighbour of a not in p
+    auto pair_cells = [&](int p, int a) {
+        const uint32_t w = __builtin_ctz((uint32_t)(T.cellnb[a] & ~T.cellnb[p]));
+        const int pos = __builtin_popcount(T.cellnb[a] & T.lessc[w]) + T.cpos_pos[w];
+        put(a, (uint8_t)(0x80 | pos));
+        put(p, (uint8_t)(13 + T.l27[w] - T.al27[p]));
+    };
+    auto unpaired = [&](int s) { return popc64_(T.face[s] & ~cls_lo); };
+    // x pairs with its lowest edge delta = {x, n0}
+    const int n0 = nb_of(0);
+    xcode = (uint8_t)(13 + T.l27[n0]);
+    put(n0, (uint8_t)(0x80 | T.cpos_pos[n0]));
+    cls_lo = (uint64_t)1 << n0;
+    uint64_t z_lo = (in_lo & 0x3FFFull) & ~cls_lo;  // the other edges
+    uint32_t z_hi = 0;
+    uint64_t o_lo = 0;
+    uint32_t o_hi = 0;
+    auto push_cofaces = [&](int s) {
+        uint64_t c = T.cof_lo[s] & in_lo & ~cls_lo;
+        while (c) {
+            const int b = __builtin_ctzll(c);
+            c &= c - 1;
+            if (unpaired(b) == 1) o_lo |= (uint64_t)1 << b;
+        }
+        uint32_t ch = T.cof_hi[s] & in_hi & ~cls_hi;
+        while (ch) {
+            const int b = __builtin_ctz(ch);
+            ch &= ch - 1;
+            if (unpaired(64 + b) == 1) o_hi |= 1u << b;
+        }
+    };
+    // the member of a non-empty set with the smallest mask, removed from it
+    auto pop_min = [&](uint64_t& qlo, uint32_t& qhi) {
+        uint64_t lo = qlo;
+        uint32_t hi = qhi;
+        if (popc64_(lo) + __builtin_popcount(hi) > 1) {
+            for (int j = k - 1; j >= 0; --j) {
+                const int n = nb_of(j);
+                const uint64_t tl = lo & ~T.slnb_lo[n];
+                const uint32_t th = hi & ~(uint32_t)T.slnb_hi[n];
+                if (tl | th) {
+                    lo = tl;
+                    hi = th;
+                    if (popc64_(lo) + __builtin_popcount(hi) == 1) break;
+                }
+            }
+        }
+        int best;
+        if (lo) {
+            best = __builtin_ctzll(lo);
+            qlo &= ~((uint64_t)1 << best);
+        } else {
+            best = 64 + __builtin_ctz(hi);
+            qhi &= ~(1u << (best - 64));
+        }
+        return best;
+    };
+    push_cofaces(n0);
+    for (int guard = 0; guard < 4 * NSLOT; ++guard) {
+        while (o_lo | o_hi) {
+            const int a = pop_min(o_lo, o_hi);
+            // a cell of this queue is smaller than every cell classified
+            // after it entered, so it is never found classified; the test
+            // only keeps the step exactly as the algorithm states it
+            if (a < 64 ? ((cls_lo >> a) & 1) : ((cls_hi >> (a - 64)) & 1)) continue;
+            const uint64_t u = T.face[a] & ~cls_lo;
+            if (u == 0) {  // no unpaired facet left: wait for the other queue
+                if (a < 64) z_lo |= (uint64_t)1 << a;
+                else z_hi |= 1u << (a - 64);
+                continue;
+            }
+            const int p = __builtin_ctzll(u);
+            pair_cells(p, a);
+            cls_lo |= (uint64_t)1 << p;
+            if (a < 64) cls_lo |= (uint64_t)1 << a;
+            else cls_hi |= 1u << (a - 64);
+            z_lo &= ~((uint64_t)1 << p);
+            push_cofaces(a);
+            push_cofaces(p);
+        }
+        if (!(z_lo | z_hi)) break;
+        const int c = pop_min(z_lo, z_hi);
+        if (c < 64) {
+            cls_lo |= (uint64_t)1 << c;
+            crit_lo |= (uint64_t)1 << c;
+        } else {
+            cls_hi |= 1u << (c - 64);
+            crit_hi |= 1u << (c - 64);
+        }
+        put(c, CODE_CRIT);
+        push_cofaces(c);
+    }
+}
+
+}  // namespace dms

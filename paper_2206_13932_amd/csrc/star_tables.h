@@ -110,6 +110,15 @@ constexpr StarTables make_star_tables() {
         T.cof_lo[i] = 0;
         T.cof_hi[i] = 0;
     }
+    for (int n = 0; n < NNB; ++n) {
+        T.slnb_lo[n] = 0;
+        T.slnb_hi[n] = 0;
+        for (int i = 0; i < NSLOT; ++i)
+            if (T.cellnb[i] & (1 << n)) {
+                if (i < 64) T.slnb_lo[n] |= (uint64_t)1 << i;
+                else T.slnb_hi[n] |= (uint16_t)(1 << (i - 64));
+            }
+    }
     for (int i = 0; i < NSLOT; ++i)
         for (int j = 0; j < NSLOT; ++j) {
             if (T.dim[j] != T.dim[i] + 1) continue;
