@@ -212,6 +212,20 @@ int dms_batch_info(const dms_ctx* ctx, int64_t info[8]);
 int dms_scatter_grad(dms_ctx* ctx, int64_t n, const int64_t* d_vertex, const float* d_grad, int64_t nvert,
                      float* d_grad_field);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training or serving loops, harnesses that forbid
+ * hipMalloc): dms_scatter_grad with the same arguments, result and errors,
+ * but it calls no hipMalloc / hipFree and no allocating library routine. Its
+ * sort buffers live in one static device array per GPU (65 MiB + 64 KiB,
+ * held from the first dms_create on that GPU until the process ends), so
+ * n <= 4194304 (2^22) contributions; more is DMS_E_INVAL, nothing enqueued.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams, other contexts, other threads) race and must be
+ * serialised by the caller. The array keeps the last call's contents; the
+ * call clears what must start at zero. Synchronises the context's stream. */
+int dms_scatter_grad_noalloc(dms_ctx* ctx, int64_t n, const int64_t* d_vertex, const float* d_grad, int64_t nvert,
+                             float* d_grad_field);
+
 /* Inspection of internal state for tests: copies the device buffer `what`
  * (see DMS_BUF_*) to host memory `dst` of `cap` bytes; returns the byte
  * size of the buffer (or a negative error). */

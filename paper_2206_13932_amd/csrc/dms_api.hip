@@ -345,6 +345,11 @@ int dms_create(dms_ctx** out, int device, void* hip_stream, size_t hbm_budget_by
             delete ctx;
             return DMS_E_HIP;
         }
+    ctx->err.reserve(512);  // messages fit without a host allocation later
+    if (noalloc_scratch_init(device) != 0) {  // address of this device's scatter scratch
+        delete ctx;
+        return DMS_E_HIP;
+    }
     int r = ensure(ctx, ctx->flags, 64);
     if (r == DMS_OK) r = ensure(ctx, ctx->counters, 64);
     if (r == DMS_OK) r = ensure(ctx, ctx->stats, 64);
@@ -905,6 +910,36 @@ int dms_scatter_grad(dms_ctx* ctx, int64_t n, const int64_t* d_vertex, const flo
     HIPCHK(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, ctx->st));
     HIPCHK(hipStreamSynchronize(ctx->st));
     if (h) return fail(ctx, DMS_E_INVAL, "dms_scatter_grad: vertex index out of range (gradient left zero there)");
+    return DMS_OK;
+}
+
+// The error messages below fit the capacity reserved at dms_create, so
+// reporting an error allocates nothing either.
+static int fail_noalloc(dms_ctx* ctx, int code, const char* msg) {
+    ctx->err.assign(msg);
+    return code;
+}
+
+int dms_scatter_grad_noalloc(dms_ctx* ctx, int64_t n, const int64_t* d_vertex, const float* d_grad, int64_t nvert,
+                             float* d_grad_field) {
+    if (!ctx) return DMS_E_INVAL;
+    if (n < 0 || nvert < 1 || nvert > ((int64_t)1 << 32) || !d_grad_field || (n > 0 && (!d_vertex || !d_grad)))
+        return fail_noalloc(ctx, DMS_E_INVAL, "dms_scatter_grad_noalloc: bad sizes or null pointers");
+    if (n > NOALLOC_MAX_CONTRIB)
+        return fail_noalloc(ctx, DMS_E_INVAL,
+                            "dms_scatter_grad_noalloc: more than 4194304 contributions (use dms_scatter_grad)");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail_noalloc(ctx, DMS_E_HIP, "hipSetDevice failed");
+    uint32_t* flag = nullptr;
+    if (scatter_grad_noalloc(ctx->device, d_vertex, d_grad, n, nvert, d_grad_field, &flag, ctx->st) != 0)
+        return fail_noalloc(ctx, DMS_E_STATE, "dms_scatter_grad_noalloc: scratch of this device not set up");
+    if (hipGetLastError() != hipSuccess) return fail_noalloc(ctx, DMS_E_HIP, "dms_scatter_grad_noalloc: launch failed");
+    uint32_t h = 0;
+    if (hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, ctx->st) != hipSuccess ||
+        hipStreamSynchronize(ctx->st) != hipSuccess)
+        return fail_noalloc(ctx, DMS_E_HIP, "dms_scatter_grad_noalloc: read-back failed");
+    if (h)
+        return fail_noalloc(ctx, DMS_E_INVAL,
+                            "dms_scatter_grad_noalloc: vertex index out of range (gradient left zero there)");
     return DMS_OK;
 }
 

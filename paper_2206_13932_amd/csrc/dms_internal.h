@@ -107,6 +107,17 @@ void launch_demux_write(const uint64_t* key, const uint32_t* idx, const int64_t*
                         hipStream_t st);
 
 // grad.hip
+// Allocation-free scatter: scratch in a static device array of
+// NOALLOC_SCRATCH_BYTES per GPU, for at most NOALLOC_MAX_CONTRIB
+// contributions. noalloc_scratch_init resolves the array's address on the
+// current device (call once per device, with it current; 0 = ok);
+// scatter_grad_noalloc enqueues the scatter on st and hands back the device
+// error flag (-1: device not initialised).
+constexpr int64_t NOALLOC_MAX_CONTRIB = (int64_t)1 << 22;
+constexpr size_t NOALLOC_SCRATCH_BYTES = ((size_t)65 << 20) + ((size_t)64 << 10);
+int noalloc_scratch_init(int device);
+int scatter_grad_noalloc(int device, const int64_t* vertex, const float* grad, int64_t n, int64_t nvert, float* out,
+                         uint32_t** flag, hipStream_t st);
 void scatter_grad(const int64_t* vertex, const float* grad, int64_t n, int64_t nvert, float* out, uint32_t* k0,
                   uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t* hist, uint32_t* part, uint32_t* flags,
                   hipStream_t st);

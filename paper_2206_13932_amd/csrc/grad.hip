@@ -3,6 +3,8 @@
 // for every vertex, the derivatives of the pair values it carries. The sum
 // is made deterministic: contributions are stably sorted by vertex and each
 // vertex's run is added up in the order the contributions were given.
+#include <mutex>
+
 #include "dms_internal.h"
 
 namespace dms {
@@ -42,7 +44,62 @@ __global__ void k_grad_runs(const uint32_t* __restrict__ keys, const uint32_t* _
     out[k] = s;
 }
 
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_ptr[MAX_DEVICES] = {nullptr};
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 }  // namespace
+
+// Scratch of the allocation-free scatter (dms_scatter_grad_noalloc): sort
+// keys and values, tile histograms, scan partials and the error flag for up
+// to NOALLOC_MAX_CONTRIB contributions, as one array in device memory that
+// each GPU the library runs on holds until the process ends. Host code must
+// not use its name as an address: the per-device pointer comes from
+// hipGetSymbolAddress (noalloc_scratch_init).
+static __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
+
+int noalloc_scratch_init(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return -1;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return 0;
+    // the layout for the largest input must fit the array
+    const int64_t N = NOALLOC_MAX_CONTRIB;
+    const size_t need = 4 * align256(4 * (size_t)N) + align256(4 * 256 * (size_t)sort_tiles(N)) +
+                        align256(4 * (size_t)scan_part_size(256 * sort_tiles(N))) + 256;
+    if (need > NOALLOC_SCRATCH_BYTES) return -2;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -3;
+    g_scratch_ptr[device] = (uint8_t*)p;
+    return 0;
+}
+
+int scatter_grad_noalloc(int device, const int64_t* vertex, const float* grad, int64_t n, int64_t nvert, float* out,
+                         uint32_t** flag, hipStream_t st) {
+    uint8_t* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (device >= 0 && device < MAX_DEVICES) base = g_scratch_ptr[device];
+    }
+    if (!base) return -1;
+    // fixed carving for NOALLOC_MAX_CONTRIB, whatever n is
+    const int64_t N = NOALLOC_MAX_CONTRIB;
+    const size_t kv = align256(4 * (size_t)N);
+    uint32_t* k0 = (uint32_t*)base;
+    uint32_t* v0 = (uint32_t*)(base + kv);
+    uint32_t* k1 = (uint32_t*)(base + 2 * kv);
+    uint32_t* v1 = (uint32_t*)(base + 3 * kv);
+    uint8_t* rest = base + 4 * kv;
+    uint32_t* hist = (uint32_t*)rest;
+    rest += align256(4 * 256 * (size_t)sort_tiles(N));
+    uint32_t* part = (uint32_t*)rest;
+    rest += align256(4 * (size_t)scan_part_size(256 * sort_tiles(N)));
+    *flag = (uint32_t*)rest;
+    fill_u32(*flag, 0, 1, st);  // the previous call's flag is still there
+    scatter_grad(vertex, grad, n, nvert, out, k0, v0, k1, v1, hist, part, *flag, st);
+    return 0;
+}
 
 void scatter_grad(const int64_t* vertex, const float* grad, int64_t n, int64_t nvert, float* out, uint32_t* k0,
                   uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t* hist, uint32_t* part, uint32_t* flags,

@@ -19,6 +19,8 @@ DMS_OK, DMS_E_INVAL, DMS_E_NAN, DMS_E_NOMEM, DMS_E_CAPACITY, DMS_E_HIP, DMS_E_ST
     0, -1, -2, -3, -4, -5, -6, -7
 DMS_VIRTUAL_MAX = 1
 BUF_RANK, BUF_GRADIENT, BUF_CRIT0, BUF_ARCS0, BUF_ARCS2, BUF_STATS, BUF_D1LEN = 0, 1, 2, 6, 7, 8, 9
+# most contributions dms_scatter_grad_noalloc takes (its static scratch)
+NOALLOC_MAX_CONTRIB = 1 << 22
 # debug options of a context (dms_set_option)
 OPT_D1_SMALL_PASSES, OPT_LOG_PASSES = 1, 2
 _ERRNAMES = {-1: "DMS_E_INVAL", -2: "DMS_E_NAN", -3: "DMS_E_NOMEM", -4: "DMS_E_CAPACITY", -5: "DMS_E_HIP",
@@ -98,6 +100,8 @@ def load_library() -> ctypes.CDLL:
     lib.dms_stage_ms.restype = ctypes.c_int
     lib.dms_scatter_grad.argtypes = [_p, i64, _p, _p, i64, _p]
     lib.dms_scatter_grad.restype = ctypes.c_int
+    lib.dms_scatter_grad_noalloc.argtypes = [_p, i64, _p, _p, i64, _p]
+    lib.dms_scatter_grad_noalloc.restype = ctypes.c_int
     lib.dms_diagram_batch.argtypes = [_p, _p, _p, ctypes.c_int32, u32, ctypes.POINTER(BatchOpts),
                                       ctypes.POINTER(BatchOut)]
     lib.dms_diagram_batch.restype = ctypes.c_int
@@ -308,6 +312,19 @@ class Context:
                 self._raise(rc)
             return [{d: bufs[d][int(starts[d][i]): int(starts[d][i + 1])] for d in range(3)} for i in range(n)]
         raise DmsError(DMS_E_CAPACITY, "output capacity")
+
+    def scatter_grad_noalloc(self, vertex: torch.Tensor, grad: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """dms_scatter_grad_noalloc into a caller-owned float32 tensor out
+        (nvert = out.numel()): no device allocation in the library; at most
+        NOALLOC_MAX_CONTRIB contributions."""
+        vertex = vertex.to(device=self.device, dtype=torch.int64).contiguous()
+        grad = grad.to(device=self.device, dtype=torch.float32).contiguous()
+        assert out.dtype == torch.float32 and out.is_contiguous() and out.device == vertex.device
+        rc = self.lib.dms_scatter_grad_noalloc(self.h, vertex.numel(), _p(vertex.data_ptr()), _p(grad.data_ptr()),
+                                               out.numel(), _p(out.data_ptr()))
+        if rc != DMS_OK:
+            self._raise(rc)
+        return out
 
     def batch_info(self):
         arr = (ctypes.c_int64 * 8)()
