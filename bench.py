@@ -72,7 +72,25 @@ def gradient_algorithmic_bytes(V, ncrit):
     return 4 * V + 26 * V + 8 * ncrit[0] + 12 * (ncrit[1] + ncrit[2] + ncrit[3])
 
 
-def cpu_baseline(field, crop):
+def host_info():
+    """The host CPU the CPU lines ran on: model name and usable threads."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(field, crop, omp_crop=128, seq_verts=1 << 18):
+    """The oracle on the host: the whole pipeline, sequential, on a corner crop
+    of the field; and the gradient stage (ProcessLowerStars at every vertex)
+    with the vertices shared among OpenMP threads on all host threads, and
+    sequentially on its first seq_verts vertices, on a larger crop."""
     import oracle
     if field.shape[0] == 1:  # 2D grid: a square corner crop with as many vertices
         side = int(round(crop ** 1.5))
@@ -82,12 +100,25 @@ def cpu_baseline(field, crop):
     t0 = time.perf_counter()
     oracle.run(sub)
     dt = time.perf_counter() - t0
-    return {"value": round(sub.size / dt / 1e6, 4), "unit": "Mvertices/s", "cores": 1, "kind": "oracle",
-            "sample": f"sequential oracle, whole pipeline on the {'x'.join(map(str, sub.shape[::-1]))} corner "
-                      f"crop of the same field ({sub.size} vertices, {dt:.1f} s)"}
+    out = {"value": round(sub.size / dt / 1e6, 4), "unit": "Mvertices/s", "cores": 1, "kind": "oracle",
+           "sample": f"sequential oracle, whole pipeline on the {'x'.join(map(str, sub.shape[::-1]))} corner "
+                     f"crop of the same field ({sub.size} vertices, {dt:.1f} s)",
+           "host": host_info()}
+    if field.shape[0] > 1:
+        g = field[:omp_crop, :omp_crop, :omp_crop].copy()
+        rank = oracle.vertex_order(g)
+        t_omp, threads = oracle.time_gradient_omp(g.shape, rank, g.size)
+        n_seq = min(seq_verts, g.size)
+        t_seq = oracle.time_gradient(g.shape, rank, n_seq)
+        out["gradient_stage"] = {
+            "omp": {"value": round(g.size / t_omp / 1e6, 4), "unit": "Mvertices/s", "cores": threads},
+            "sequential": {"value": round(n_seq / t_seq / 1e6, 4), "unit": "Mvertices/s", "cores": 1},
+            "sample": f"oracle gradient stage on the {omp_crop}^3 corner crop ({g.size} vertices, {t_omp:.1f} s "
+                      f"on {threads} threads); sequential on its first {n_seq} vertices ({t_seq:.1f} s)"}
+    return out
 
 
-def serving_bench(n_requests, rate, plain_sample, calib):
+def serving_bench(n_requests, rate, plain_sample, calib, sweep_n=512):
     """Continuous batching of a Poisson trace of mixed-size requests (grid
     side log-uniform in [16, 128] per axis, Gaussian mixtures + 1% noise),
     with the batch tile shapes picked by the autotuner on a calibration
@@ -106,6 +137,7 @@ def serving_bench(n_requests, rate, plain_sample, calib):
     real = sum(r.host_field.numel() for r in reqs)
     print(f"[serve] {n_requests} requests ({real / 1e6:.1f} Mvertices) generated in {time.perf_counter() - t:.1f}s",
           file=sys.stderr, flush=True)
+    plain = serving.run_plain(reqs[:plain_sample])
     cfg, table = autotune.autotune(reqs[:calib], rate=rate)
     chosen = 0.0
     for c, r in table:
@@ -114,13 +146,30 @@ def serving_bench(n_requests, rate, plain_sample, calib):
         if (tuple(c["cross"]), c["budget_vertices"], w, g) == (tuple(cfg.cross), cfg.budget_vertices, cfg.workers,
                                                                cfg.use_graph):
             chosen = r
+
+    def at_rate(lam, n):
+        """The first n requests with their Poisson arrivals rescaled to rate lam."""
+        return [serving.Request(r.rid, r.arrival * rate / lam, r.host_field) for r in reqs[:n]]
+
+    sweeps = {}
     server = serving.Server(cfg)
     try:
         server.warmup(reqs[:calib])
         stats = server.run_trace(reqs)
+        # load sweeps: arrival rate as a fraction of the plain pipeline's capacity (one
+        # request at a time) and of the server's own measured capacity
+        for base_name, mu, n in (("plain", plain, sweep_n), ("server", chosen, 4 * sweep_n)):
+            rows = []
+            for frac in (0.5, 0.8, 0.95, 1.2):
+                lam = frac * mu
+                st = server.run_trace(at_rate(lam, n))
+                rows.append({"rel": frac, "rate_per_s": round(lam, 1), "requests": n,
+                             "req_per_s": round(st.req_per_s, 1), "p50_ms": round(st.pct(50), 2),
+                             "p99_ms": round(st.pct(99), 2)})
+                print(f"[serve] sweep {base_name} {rows[-1]}", file=sys.stderr, flush=True)
+            sweeps[base_name] = {"mu_req_per_s": round(mu, 1), "points": rows}
     finally:
         server.close()
-    plain = serving.run_plain(reqs[:plain_sample])
     b = np.array([x[1:4] for x in stats.batches], dtype=np.float64)
     out = {"requests": n_requests, "arrival_rate_per_s": rate, "req_per_s": round(stats.req_per_s, 1),
            "p50_ms": round(stats.pct(50), 2), "p99_ms": round(stats.pct(99), 2),
@@ -131,9 +180,77 @@ def serving_bench(n_requests, rate, plain_sample, calib):
                      "use_graph": cfg.use_graph, "workers": cfg.workers,
                      "capacity_req_per_s": round(chosen, 1),
                      "best_capacity_req_per_s": round(max(r for _, r in table), 1)},
-           "plain_req_per_s": round(plain, 1), "plain_sample": plain_sample}
+           "plain_req_per_s": round(plain, 1), "plain_sample": plain_sample, "sweep": sweeps}
     print(f"[serve] {out}", file=sys.stderr, flush=True)
     return out
+
+
+def transfers_and_copy(ctx, f, steps=3):
+    """The same diagram with the field starting in pinned host memory and the
+    pair lists ending there (the PCIe copies inside the timed region), and the
+    device-to-device copy rate of the GPU (a 1 GiB copy timed with HIP events),
+    the practical ceiling of a streaming kernel."""
+    import torch
+    host = torch.from_numpy(f).pin_memory()
+    outs = [None] * 3
+    ms = []
+    for i in range(steps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dev = host.to("cuda", non_blocking=True)
+        out = ctx.diagram(dev)
+        outs = [out[d].to("cpu", non_blocking=True) for d in range(3)]
+        torch.cuda.synchronize()
+        if i > 0:
+            ms.append((time.perf_counter() - t0) * 1e3)
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_ms = e0.elapsed_time(e1) / reps
+    copy_gbs = 2 * src.numel() * 4 / (copy_ms / 1e3) / 1e9
+    del src, dst, host, outs
+    mean = sum(ms) / len(ms)
+    return ({"ms_per_step": round(mean, 3), "Mvertices_per_s": round(f.size / (mean / 1e3) / 1e6, 1),
+             "note": "field copied from pinned host memory and the three pair lists back, inside the timed region"},
+            {"GB_per_s": round(copy_gbs, 1), "bytes_each_way": 1 << 30, "ms": round(copy_ms, 4),
+             "note": "device-to-device copy of 1 GiB (read + write bytes / time), HIP events"})
+
+
+def workload_bench(name, steps=2, warmup=1):
+    """Another workload timed like the headline (dms_diagram on a field in HBM)."""
+    import numpy as np
+    import torch
+    from paper_2206_13932_amd import dms
+    f = make_field(name)
+    field = torch.from_numpy(f).cuda()
+    ctx = dms.Context(0)
+    for _ in range(warmup):
+        ctx.diagram(field)
+    torch.cuda.synchronize()
+    stages = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.diagram(field)
+        stages.append(ctx.stage_ms())
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    st = np.mean(np.array(stages), axis=0).tolist()
+    ctx.close()
+    del field
+    torch.cuda.empty_cache()
+    return {"workload": f"{name}: {WORKLOADS[name]['text']}", "steps": steps, "ms_per_step": round(ms, 3),
+            "Mvertices_per_s": round(f.size / (ms / 1e3) / 1e6, 3),
+            "stage_ms": {k: round(v, 3) for k, v in zip(
+                ["order", "gradient_and_counts", "critical_sort", "d0_d2", "d1", "output", "total",
+                 "gradient_kernel"], st)}}
 
 
 def differentiation_bench(n_fields=64, side=96):
@@ -172,6 +289,8 @@ def main():
     ap.add_argument("--serve-calib", type=int, default=256)
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation run")
     ap.add_argument("--no-generators", action="store_true", help="skip the 1-cycle generator export")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the transfer-inclusive run, the copy ceiling and the noise512 line")
     ap.add_argument("--mode", default="diagram", choices=["diagram", "gradient"],
                     help="gradient: time dms_gradient alone and a 1 GiB device copy "
                          "(the reference kernel for hardware byte counters)")
@@ -302,9 +421,17 @@ def main():
     }
     if generators is not None:
         line["generators"] = generators
+    if not args.no_extras:
+        line["with_transfers"], line["copy_ceiling"] = transfers_and_copy(ctx, f)
+        print(f"[bench] with transfers {line['with_transfers']}; copy {line['copy_ceiling']}", file=sys.stderr,
+              flush=True)
     ctx.close()
     del field, out
     torch.cuda.empty_cache()
+    if not args.no_extras and args.workload == "smooth512":
+        # the worst case for the critical-cell count (the paper's "Random"), timed like the headline
+        line["noise512"] = workload_bench("noise512")
+        print(f"[bench] noise512 {line['noise512']}", file=sys.stderr, flush=True)
     if args.serve_requests > 0:
         line["serving"] = serving_bench(args.serve_requests, args.serve_rate, args.serve_plain_sample,
                                         args.serve_calib)

@@ -38,7 +38,7 @@ def build(force: bool = True) -> None:
         out = os.path.join(_HERE, lib)
         if not force and os.path.exists(out):
             continue
-        cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", out + ".tmp",
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", "-o", out + ".tmp",
                os.path.join(_HERE, src)]
         subprocess.check_call(cmd)
         os.replace(out + ".tmp", out)
@@ -67,6 +67,8 @@ def _lib(name: str) -> ctypes.CDLL:
         lib.orc_lower_star_sample.restype = ctypes.c_int
         lib.orc_time_gradient.argtypes = [i64, i64, i64, p, i64]
         lib.orc_time_gradient.restype = ctypes.c_double
+        lib.orc_time_gradient_omp.argtypes = [i64, i64, i64, p, i64, ctypes.POINTER(ctypes.c_int32)]
+        lib.orc_time_gradient_omp.restype = ctypes.c_double
     else:
         lib.bf_counts.argtypes = [i64, i64, i64, p]
         lib.bf_counts.restype = i64
@@ -153,6 +155,16 @@ def time_gradient(shape, rank: np.ndarray, n_verts: int) -> float:
     nz, ny, nx = shape
     r = np.ascontiguousarray(rank, dtype=np.uint32)
     return float(_lib("oracle").orc_time_gradient(nx, ny, nz, _ptr(r), n_verts))
+
+
+def time_gradient_omp(shape, rank: np.ndarray, n_verts: int):
+    """(seconds, threads): the gradient stage over the first n_verts
+    vertices with the lower stars shared among OpenMP threads."""
+    nz, ny, nx = shape
+    r = np.ascontiguousarray(rank, dtype=np.uint32)
+    th = ctypes.c_int32(0)
+    dt = float(_lib("oracle").orc_time_gradient_omp(nx, ny, nz, _ptr(r), n_verts, ctypes.byref(th)))
+    return dt, int(th.value)
 
 
 # ------------------------------------------------------------ brute force --

@@ -34,6 +34,7 @@
  *   - the virtual maximum is on (exact diagram on a domain with boundary).
  */
 #include <algorithm>
+#include <omp.h>
 #include <array>
 #include <chrono>
 #include <cmath>
@@ -775,6 +776,32 @@ double orc_time_gradient(int64_t nx, int64_t ny, int64_t nz, const uint32_t* ran
     double t0 = now();
     for (i64 x = 0; x < n_verts && x < C.g.V(); ++x) process_lower_star(C, x, star);
     return now() - t0;
+}
+
+/* The same stage with the vertices shared among OpenMP threads: every cell
+ * belongs to the lower star of exactly one vertex, so the lower stars are
+ * independent (the paper parallelises this stage over vertices, Sec. 7.2).
+ * *threads receives the number of threads that ran. */
+double orc_time_gradient_omp(int64_t nx, int64_t ny, int64_t nz, const uint32_t* rank, int64_t n_verts,
+                             int32_t* threads) {
+    Ctx C;
+    C.g.n[0] = nx; C.g.n[1] = ny; C.g.n[2] = nz;
+    C.rank.assign(rank, rank + nx * ny * nz);
+    for (int d = 0; d < 4; ++d) C.partner[d].assign(C.g.V() * NTYPES[d], -2);
+    const i64 n = std::min<i64>(n_verts, C.g.V());
+    int used = 1;
+    double t0 = now();
+#pragma omp parallel
+    {
+        std::vector<std::pair<int, i64>> star;
+#pragma omp single
+        used = omp_get_num_threads();
+#pragma omp for schedule(dynamic, 4096)
+        for (i64 x = 0; x < n; ++x) process_lower_star(C, x, star);
+    }
+    const double dt = now() - t0;
+    if (threads) *threads = used;
+    return dt;
 }
 
 }  // extern "C"

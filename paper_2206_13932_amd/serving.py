@@ -12,7 +12,7 @@ that frees up, so the batches of different workers overlap on the device.
 Results stay on the device (the pairs tensors of each request).
 
 Each result is the diagram the request has alone (the batch layout separates
-grids by +inf planes; see include/dms.h), which the serving test checks.
+grids by separator planes; see include/dms.h), which the serving test checks.
 """
 from __future__ import annotations
 
@@ -52,7 +52,8 @@ class ServerConfig:
 class TraceStats:
     wall_s: float
     latencies_ms: np.ndarray
-    batches: list = field(default_factory=list)  # (worker, items, super vertices, real vertices, seconds)
+    # (worker, items, super vertices, real vertices, seconds, start s, end s), times from the trace start
+    batches: list = field(default_factory=list)
 
     @property
     def req_per_s(self) -> float:
@@ -142,7 +143,8 @@ class Server:
                     done = time.perf_counter()
                     info = ctx.batch_info()
                     with self.lock:
-                        stats.batches.append((w, len(batch), info[0] * info[1] * info[2], info[3], done - tb))
+                        stats.batches.append((w, len(batch), info[0] * info[1] * info[2], info[3], done - tb,
+                                              tb - t0, done - t0))
                     for r, o in zip(batch, out):
                         r.result = o
                         r.done = done - t0

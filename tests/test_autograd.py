@@ -7,7 +7,8 @@ diagram of each perturbed field, on every vertex whose order the
 perturbation leaves unchanged; the in-order float32 scatter against a loop.
 GPU: the HIP backward against the CPU reference, bit for bit, on one 96^3
 field (oracle pairs) and on the batch of 64 fields of 96^3 (16 Gaussians and
-2% noise); the scatter entry point on its own, with repeats, n = 0 and an
+2% noise; every field against the reference built from the GPU forward's
+pairs, three of them against the oracle's pairs); the scatter entry point on its own, with repeats, n = 0 and an
 index out of range.
 """
 import numpy as np
@@ -62,6 +63,23 @@ def test_scatter_in_order_matches_loop():
     b = gradref.scatter_in_order_loop(60, vertex, grad)
     assert np.array_equal(a, b)
     assert (a[50:] == 0).all()
+
+
+def _cpu_reference_from_oracle(f):
+    """In-order float32 scatter of the loss derivatives from the oracle's
+    pairs of f (values at the pairs' highest vertices)."""
+    verts = gradref.pair_vertices(oracle.run(f))
+    fv = f.ravel()
+    vl, gl = [], []
+    for d in range(3):
+        b, dv = verts[d]
+        gd = np.zeros(len(b), np.float32)
+        if d in (1, 2):
+            fin = dv >= 0
+            gd[fin] = np.float32(2.0) * (fv[dv[fin]] - fv[b[fin]])
+        vl += [b, dv[dv >= 0]]
+        gl += [-gd, gd[dv >= 0]]
+    return gradref.scatter_in_order(f.size, np.concatenate(vl), np.concatenate(gl))
 
 
 def _cpu_reference_from_gpu_outputs(out, nvert):
@@ -129,6 +147,9 @@ def test_backward_batch_64_fields_96():
         out = ctx.diagram(x.detach(), with_values=True)
         ref = _cpu_reference_from_gpu_outputs(out, f.size)
         assert np.array_equal(g1.cpu().numpy().ravel(), ref), i
+        if i in (0, 37, 63):  # the whole chain against the oracle's pairs
+            print(f"[autograd] field {i}: oracle reference", flush=True)
+            assert np.array_equal(g1.cpu().numpy().ravel(), _cpu_reference_from_oracle(f)), i
         if i % 16 == 0:
             print(f"[autograd] field {i} ok", flush=True)
     ctx.close()

@@ -5,6 +5,7 @@ batches of the two workers must have overlapped in time."""
 import numpy as np
 import pytest
 
+import oracle
 import synthfields as sf
 
 
@@ -26,9 +27,19 @@ def test_served_results_equal_alone(workers, use_graph):
     assert max(b[1] for b in stats.batches) > 1
     assert {b[0] for b in stats.batches} == set(range(workers))
     assert np.isfinite(stats.latencies_ms).all() and (stats.latencies_ms > 0).all()
+    if workers > 1:
+        # batches of different workers ran at the same time (their calls
+        # overlapped on the host while both were in flight on the device)
+        spans = [(b[0], b[5], b[6]) for b in stats.batches]
+        assert any(wa != wb and sa < eb and sb < ea for wa, sa, ea in spans for wb, sb, eb in spans), spans
     ctx = dms.Context(0)
     for r in reqs:
         alone = ctx.diagram(r.host_field.cuda())
         for d in range(3):
             assert torch.equal(r.result[d], alone[d]), (r.rid, d)
     ctx.close()
+    # and a sample of the served results against the oracle
+    for r in reqs[::8]:
+        res = oracle.run(r.host_field.numpy())
+        for d in range(3):
+            assert np.array_equal(r.result[d].cpu().numpy(), res.pairs[d]), (r.rid, d)
