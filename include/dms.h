@@ -84,9 +84,21 @@ enum {
     DMS_E_INTERNAL = -7  /* an internal consistency check failed                     */
 };
 
+/* flags of dms_gradient / dms_diagram (other bits: DMS_E_INVAL).
+ * DMS_VIRTUAL_MAX set: the outside of the domain is one maximum of value
+ *   +inf (Sec. 5.2, "Domains with boundary"): the exact diagrams of the
+ *   lower-star filtration of the grid. The usual choice.
+ * DMS_VIRTUAL_MAX clear: the adjustment is off (App. A, "Boundary
+ *   perturbations"; the paper's more stable option for the global maximum):
+ *   the outside is no node of the dual union-find, so a 2-saddle whose stable
+ *   set reaches the boundary joins nothing there. The rest runs as is; what
+ *   stays unpaired is a class of infinite persistence (Sec. 6): a 2-saddle
+ *   whose boundary reduces to zero in D1 is an infinite D2 class (3D), such a
+ *   1-saddle an infinite D1 class (2D); maxima never killed are infinite D2
+ *   classes on a 2D grid and are not reported on a 3D grid (there is no D3).
+ *   D0 is the same in both modes. dms_diagram_batch requires the flag. */
 enum {
-    DMS_VIRTUAL_MAX = 1u << 0 /* outside of the domain = one maximum of value +inf
-                                 (Sec. 5.2, domains with boundary); required */
+    DMS_VIRTUAL_MAX = 1u << 0
 };
 
 /* Create a context on `device`, enqueuing on `hip_stream` (NULL = the null
@@ -108,7 +120,9 @@ int dms_gradient(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t fla
 
 /* D0 (Sec. 5.1) and D2 (Sec. 5.2) from the gradient left by dms_gradient.
  * On a 2D grid the stable sets of the 1-saddles are traced here as well and
- * D2 holds only maxima no saddle kills (none with DMS_VIRTUAL_MAX).
+ * D2 holds only maxima no saddle kills (none with DMS_VIRTUAL_MAX). Without
+ * DMS_VIRTUAL_MAX the infinite D2 classes of a 3D grid come with D1 (the
+ * 2-saddles left after it), so this call reports none.
  * Writes the pairs (sorted, infinite classes last) to d0 / d2 (device).
  * On DMS_E_CAPACITY the required counts are in *n0 / *n2 and nothing is
  * written. Returns DMS_E_STATE without a prior dms_gradient. */

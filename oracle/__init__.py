@@ -114,16 +114,19 @@ class OracleResult:
         self.gen1_edges = get(ORC_GEN1_EDGES, np.int64)
 
 
-def run(field: np.ndarray, sandwich: bool = True) -> OracleResult:
+def run(field: np.ndarray, sandwich: bool = True, virtual_max: bool = True) -> OracleResult:
     """Run the whole oracle pipeline on a float32 field shaped [nz, ny, nx].
     sandwich=False: the ablation of Sec. 3, D1 over every critical triangle
-    instead of those D2 left unpaired (the diagrams must not change)."""
+    instead of those D2 left unpaired (the diagrams must not change).
+    virtual_max=False: the optional boundary adjustment of Sec. 5.2 is off
+    (the outside is no node of the dual union-find; App. A)."""
     f = np.ascontiguousarray(field, dtype=np.float32)
     nz, ny, nx = f.shape
     lib = _lib("oracle")
     h = ctypes.c_void_p()
     err = ctypes.create_string_buffer(512)
-    rc = lib.orc_run_opts(nx, ny, nz, _ptr(f), 0 if sandwich else 1, ctypes.byref(h), err, 512)
+    flags = (0 if sandwich else 1) | (0 if virtual_max else 2)
+    rc = lib.orc_run_opts(nx, ny, nz, _ptr(f), flags, ctypes.byref(h), err, 512)
     if rc != 0:
         raise ValueError(err.value.decode())
     try:

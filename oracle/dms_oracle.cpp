@@ -475,7 +475,16 @@ void diagram0(Ctx& C, std::vector<char>& edge_paired, std::vector<char>& min_pai
  * the 1-saddles (edges into triangles), where no sandwich is needed (Sec. 3). */
 const i64 VIRTUAL = -1;
 
-void diagram_dual(Ctx& C, int d, std::vector<char>& saddle_paired, std::vector<i64>& pairs) {
+/* virtual_max = false: the optional adjustment of Sec. 5.2 is off -- the
+ * outside is no node: an arc that reaches it joins nothing, and its saddle
+ * stays unpaired here. */
+/* skip (optional, virtual maximum off): saddles to leave out, by position in
+ * C.crit[d] -- on a 2D grid the 1-saddles D0 already paired: with the
+ * virtual maximum they join two triangles of one component anyway (so the
+ * rule leaves them out by itself), without it they could join two, and a
+ * saddle is the birth or the death of one class only. */
+void diagram_dual(Ctx& C, int d, std::vector<char>& saddle_paired, std::vector<i64>& pairs, bool virtual_max = true,
+                  const std::vector<char>* skip = nullptr) {
     const int top = d + 1;
     std::vector<i64> cof;
     auto other_side = [&](i64 facet, i64 cell) {
@@ -504,6 +513,8 @@ void diagram_dual(Ctx& C, int d, std::vector<char>& saddle_paired, std::vector<i
         C.arcs2.push_back(ma);
         C.arcs2.push_back(mb);
         C.arcs2.push_back(t);
+        if (!virtual_max && (ma == VIRTUAL || mb == VIRTUAL)) continue;
+        if (skip && (*skip)[kk]) continue;
         i64 ra = uf.find(ma), rb = uf.find(mb);
         if (ra == rb) continue;
         i64 young;
@@ -529,8 +540,11 @@ void diagram_dual(Ctx& C, int d, std::vector<char>& saddle_paired, std::vector<i
 /* sandwich = false: the ablation without the sandwich (Sec. 3): every
  * critical triangle is processed, and one whose boundary reduces to zero
  * (a triangle D2 pairs with a tetrahedron) is skipped. */
+/* virtual_max = false: D2 left unpaired the 2-saddles whose arcs reached
+ * the outside; those that create a 2-cycle reduce to zero here and stay
+ * unpaired (classes of infinite persistence, Sec. 6). */
 void diagram1(Ctx& C, const std::vector<char>& edge_paired0, const std::vector<char>& tri_paired2,
-              bool sandwich = true) {
+              bool sandwich = true, bool virtual_max = true) {
     typedef std::pair<std::pair<i64, i64>, i64> EK;  /* ((rank max, rank min), edge id) */
     auto ekey = [&](i64 e) {
         Key k = C.key(1, e);
@@ -557,7 +571,7 @@ void diagram1(Ctx& C, const std::vector<char>& edge_paired0, const std::vector<c
         i64 guard = 0;
         for (;;) {
             if (B.empty()) {
-                if (sandwich) throw std::runtime_error("D1: boundary vanished on an unpaired 2-saddle");
+                if (sandwich && virtual_max) throw std::runtime_error("D1: boundary vanished on an unpaired 2-saddle");
                 break;  /* a positive triangle: no D1 pair */
             }
             if (++guard > (i64)4e9) throw std::runtime_error("D1: no progress");
@@ -607,7 +621,7 @@ void sort_pairs(std::vector<i64>& p) {
     }
 }
 
-void run(Ctx& C, const float* f, bool sandwich = true) {
+void run(Ctx& C, const float* f, bool sandwich = true, bool virtual_max = true) {
     double t0 = now();
     if (!vertex_order(f, C.g.V(), C.rank)) throw std::invalid_argument("NaN in the scalar field");
     double t1 = now();
@@ -618,10 +632,10 @@ void run(Ctx& C, const float* f, bool sandwich = true) {
     std::vector<char> e0, m0, t2p, e1p;
     const bool flat = C.g.n[2] == 1;  /* a 2D grid: the plane z = 0 */
     diagram0(C, e0, m0);
-    if (flat) diagram_dual(C, 1, e1p, C.d1);
-    else diagram_dual(C, 2, t2p, C.d2);
+    if (flat) diagram_dual(C, 1, e1p, C.d1, virtual_max, virtual_max ? nullptr : &e0);
+    else diagram_dual(C, 2, t2p, C.d2, virtual_max);
     double t4 = now();
-    if (!flat) diagram1(C, e0, t2p, sandwich);
+    if (!flat) diagram1(C, e0, t2p, sandwich, virtual_max);
     double t5 = now();
     /* Sec. 6: what stays unpaired is a class of infinite persistence */
     for (size_t k = 0; k < C.crit[0].size(); ++k)
@@ -670,7 +684,8 @@ enum {
     ORC_GEN1_EDGES = 16    /* i64 edge ids of the D1 generators         */
 };
 
-/* flags bit 0: D1 without the sandwich (the ablation of Sec. 3) */
+/* flags bit 0: D1 without the sandwich (the ablation of Sec. 3);
+ * bit 1: no virtual maximum on the domain boundary (Sec. 5.2, App. A) */
 int orc_run_opts(int64_t nx, int64_t ny, int64_t nz, const float* f, int flags, void** out, char* err,
                  int errlen) {
     Ctx* C = new Ctx();
@@ -678,7 +693,7 @@ int orc_run_opts(int64_t nx, int64_t ny, int64_t nz, const float* f, int flags, 
     try {
         if (nx < 2 || ny < 2 || nz < 1)
             throw std::invalid_argument("nx and ny must be >= 2, nz >= 1 (nz = 1: a 2D grid)");
-        run(*C, f, !(flags & 1));
+        run(*C, f, !(flags & 1), !(flags & 2));
     } catch (const std::exception& e) {
         if (err && errlen > 0) { std::strncpy(err, e.what(), errlen - 1); err[errlen - 1] = 0; }
         delete C;

@@ -49,6 +49,7 @@ struct dms_ctx {
     // D1
     D1State d1;
     bool opt_d1_small = false, opt_log = false;  // debug options (dms_set_option)
+    bool virtual_max = true;  // DMS_VIRTUAL_MAX of the last gradient call (Sec. 5.2)
     // output staging
     Buf ob, od, okey, ocnt;
     // gradient scatter
@@ -495,7 +496,7 @@ static int check_grid(dms_ctx* ctx, dms_grid grid, uint32_t flags) {
         return fail(ctx, DMS_E_INVAL, "nx and ny must be >= 2 and nz >= 1 (nz = 1: a 2D grid)");
     const int64_t V = (int64_t)grid.nx * grid.ny * grid.nz;
     if (12 * V >= (int64_t)0xFFFFFFFFll) return fail(ctx, DMS_E_INVAL, "grid too large: 12*V must stay below 2^32");
-    if (!(flags & DMS_VIRTUAL_MAX)) return fail(ctx, DMS_E_INVAL, "DMS_VIRTUAL_MAX is required");
+    if (flags & ~(uint32_t)DMS_VIRTUAL_MAX) return fail(ctx, DMS_E_INVAL, "unknown flags");
     return DMS_OK;
 }
 
@@ -507,6 +508,7 @@ int dms_gradient(dms_ctx* ctx, const float* d_field, dms_grid grid, uint32_t fla
     HIPCHK(hipSetDevice(ctx->device));
     ctx->batched = false;
     ctx->flat = grid.nz == 1;
+    ctx->virtual_max = (flags & DMS_VIRTUAL_MAX) != 0;
     for (int attempt = 0; attempt < 2; ++attempt) {
         r = gradient_setup(ctx, grid);
         if (r != DMS_OK) return r;
@@ -562,7 +564,11 @@ static int run_d0_d2(dms_ctx* ctx) {
         fill_u64(P<uint64_t>(ctx->jump2), EMPTY64, m2 + 1, st);
         reduce_pairs(P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2), m1, P<uint32_t>(ctx->owner2),
                      P<uint64_t>(ctx->bnd2), P<uint64_t>(ctx->jump2), P<uint32_t>(ctx->flags), stats + 2, next + 3,
-                     st);
+                     st, !ctx->virtual_max,
+                     // without the virtual maximum a 1-saddle D0 paired could join two components
+                     // here; it is the death of its D0 pair and is left out (with it, the rule
+                     // leaves it out by itself)
+                     ctx->virtual_max ? nullptr : P<uint8_t>(ctx->paired1));
         settled_columns(P<uint64_t>(ctx->bnd2), P<uint32_t>(ctx->owner2), m1, P<uint8_t>(ctx->paired2), st);
         (void)m3;
         return DMS_OK;
@@ -582,7 +588,7 @@ static int run_d0_d2(dms_ctx* ctx) {
     fill_u64(P<uint64_t>(ctx->bnd2), EMPTY64, m2, st);
     fill_u64(P<uint64_t>(ctx->jump2), EMPTY64, m3 + 1, st);
     reduce_pairs(P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2), m2, P<uint32_t>(ctx->owner2), P<uint64_t>(ctx->bnd2),
-                 P<uint64_t>(ctx->jump2), P<uint32_t>(ctx->flags), stats + 2, next + 3, st);
+                 P<uint64_t>(ctx->jump2), P<uint32_t>(ctx->flags), stats + 2, next + 3, st, !ctx->virtual_max);
     settled_columns(P<uint64_t>(ctx->bnd2), P<uint32_t>(ctx->owner2), m2, P<uint8_t>(ctx->paired2), st);
     (void)m0;
     return DMS_OK;
@@ -1002,6 +1008,11 @@ int dms_diagram_batch(dms_ctx* ctx, const float* d_fields, const dms_item* items
     const dms_grid sg = {L.X, L.Y, L.Z};
     r = check_grid(ctx, sg, flags);
     if (r != DMS_OK) return r;
+    // the separator region closes every box the way the virtual maximum
+    // closes a grid, so a batch computes the diagrams with it on
+    if (!(flags & DMS_VIRTUAL_MAX))
+        return fail(ctx, DMS_E_INVAL, "dms_diagram_batch: DMS_VIRTUAL_MAX is required");
+    ctx->virtual_max = true;
     const int64_t V = (int64_t)L.X * L.Y * L.Z;
     ENSURE(ctx->bfield, 4 * V);
     ENSURE(ctx->bowner, 4 * V);

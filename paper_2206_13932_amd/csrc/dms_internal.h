@@ -79,9 +79,12 @@ void tri_positions_flat(const uint32_t* c2_sorted, int64_t m, uint32_t* tri2pos,
 void trace_flat(const GridDev& g, const uint8_t* G, const uint32_t* tri2pos, const uint32_t* c1, const uint32_t* pos,
                 int64_t m, uint32_t* na, uint32_t* nb, uint32_t* flags, unsigned long long* next, hipStream_t st);
 // jump: one u64 per node, all EMPTY64 (path-halving shortcuts, written by the kernel)
+// drop_node0: a column with node 0 (the virtual maximum of the dual
+// reductions) is left unpaired, as if the outside were no node; skip_rev
+// (optional): column k is left unpaired when skip_rev[m - 1 - k] is set
 void reduce_pairs(const uint32_t* na, const uint32_t* nb, int64_t m, uint32_t* owner, uint64_t* bnd,
                   uint64_t* jump, uint32_t* flags, unsigned long long* stats, unsigned long long* next,
-                  hipStream_t st);
+                  hipStream_t st, bool drop_node0 = false, const uint8_t* skip_rev = nullptr);
 void settled_columns(const uint64_t* bnd, const uint32_t* owner, int64_t m, uint8_t* paired, hipStream_t st);
 
 // batch.hip: one box of the batch layout (origin in the super grid, source

@@ -362,7 +362,8 @@ __device__ inline bool cas32(uint32_t* p, uint32_t expect, uint32_t desired) {
 __global__ __launch_bounds__(PB) void k_reduce_pairs(const uint32_t* __restrict__ na,
                                                      const uint32_t* __restrict__ nb, int64_t m, uint32_t* owner,
                                                      uint64_t* bnd, uint64_t* jump, uint32_t* flags,
-                                                     unsigned long long* stats, unsigned long long* next) {
+                                                     unsigned long long* stats, unsigned long long* next,
+                                                     bool drop_node0, const uint8_t* __restrict__ skip_rev) {
     const int64_t limit = (int64_t)1 << 26;
     unsigned long long steps = 0, evictions = 0;
     bool have = false;
@@ -382,6 +383,10 @@ __global__ __launch_bounds__(PB) void k_reduce_pairs(const uint32_t* __restrict_
             }
             guard = 0;
             pp = EMPTY32;
+            // without the virtual maximum an arc that reaches the outside
+            // joins nothing: its column is left unpaired (bnd stays empty) and
+            // the lane takes the next one at once
+            if ((drop_node0 && q == 0) || (skip_rev && skip_rev[m - 1 - k])) continue;
             have = true;
         }
         if (++guard > limit) {
@@ -491,10 +496,10 @@ void trace_flat(const GridDev& g, const uint8_t* G, const uint32_t* tri2pos, con
 }
 void reduce_pairs(const uint32_t* na, const uint32_t* nb, int64_t m, uint32_t* owner, uint64_t* bnd,
                   uint64_t* jump, uint32_t* flags, unsigned long long* stats, unsigned long long* next,
-                  hipStream_t st) {
+                  hipStream_t st, bool drop_node0, const uint8_t* skip_rev) {
     if (m > 0)
         hipLaunchKernelGGL(k_reduce_pairs, dim3(trace_blocks(m)), dim3(PB), 0, st, na, nb, m, owner, bnd, jump,
-                           flags, stats, next);
+                           flags, stats, next, drop_node0, skip_rev);
 }
 void settled_columns(const uint64_t* bnd, const uint32_t* owner, int64_t m, uint8_t* paired, hipStream_t st) {
     if (m > 0) hipLaunchKernelGGL(k_settled, dim3(nblocks(m)), dim3(PB), 0, st, bnd, owner, m, paired);

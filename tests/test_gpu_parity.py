@@ -277,3 +277,56 @@ def test_parity_d1_every_deferral_pass():
         ctx.set_option(99, 1)
     ctx.close()
     plain.close()
+
+
+# ---- without the virtual maximum on the domain boundary (Sec. 5.2, App. A) ----
+
+OFF_FIELDS = dict(SMALL_FIELDS)
+OFF_FIELDS.update({
+    "noise40": lambda: sf.noise((40, 40, 40), 11),
+    "smooth_tiles": lambda: sf.gaussians((33, 47, 61), 12, k=10, noise_frac=0.01),
+    "noise_2d": lambda: sf.noise((1, 64, 53), 13),
+    "smooth_2d": lambda: sf.gaussians((1, 96, 80), 14, k=8, noise_frac=0.01),
+    "radial_2d": lambda: sf.radial((1, 17, 17)),
+})
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", sorted(OFF_FIELDS))
+def test_parity_virtual_max_off(name):
+    """flags = 0: the dual union-find has no outside node; D0, D1, D2 with
+    their infinite classes bit for bit against the oracle in the same mode,
+    through dms_diagram and through the staged calls."""
+    torch, dms, ctx = _gpu_ctx()
+    f = OFF_FIELDS[name]()
+    print(f"[parity-off] case={name} shape={f.shape}", flush=True)
+    res = oracle.run(f, virtual_max=False)
+    ft = torch.from_numpy(f).cuda()
+    out = ctx.diagram(ft, flags=0)
+    for d in (0, 2, 1):  # D2 first: it decides which 2-saddles D1 takes
+        assert np.array_equal(out[d].cpu().numpy(), res.pairs[d]), (name, d)
+    ctx.gradient(ft, flags=0)
+    d0, d2 = ctx.pairs_d0_d2()
+    assert np.array_equal(d0.cpu().numpy(), res.pairs[0]), name
+    if f.shape[0] > 1:  # the staged D2 call reports the finite pairs (the infinite ones come after D1)
+        assert np.array_equal(d2.cpu().numpy(), res.pairs[2][res.pairs[2][:, 1] >= 0]), name
+        d1 = ctx.pairs_d1()
+        assert np.array_equal(d1.cpu().numpy(), res.pairs[1]), name
+    # the mode belongs to the call: the default comes back with the flag
+    on = ctx.diagram(ft)
+    ref = oracle.run(f)
+    for d in range(3):
+        assert np.array_equal(on[d].cpu().numpy(), ref.pairs[d]), (name, "on", d)
+    ctx.close()
+
+
+@pytest.mark.gpu
+def test_virtual_max_off_is_refused_in_batches_and_unknown_flags():
+    torch, dms, ctx = _gpu_ctx()
+    f = torch.from_numpy(sf.noise((8, 9, 10), 0)).cuda()
+    with pytest.raises(dms.DmsError):
+        ctx.diagram_batch([f], flags=0)
+    with pytest.raises(dms.DmsError):
+        ctx.diagram(f, flags=4)
+    assert np.array_equal(ctx.diagram(f)[0].cpu().numpy(), oracle.run(f.cpu().numpy()).pairs[0])
+    ctx.close()

@@ -18,7 +18,7 @@ import synthfields as sf
 EMPTY = -1
 
 
-def _reduce_interleaved(na, nb, lanes, rng, bound=True):
+def _reduce_interleaved(na, nb, lanes, rng, bound=True, drop=None):
     m = len(na)
     owner = {}
     bnd = [None] * m
@@ -31,6 +31,8 @@ def _reduce_interleaved(na, nb, lanes, rng, bound=True):
         if nxt < m:
             idle = [i for i in range(lanes) if state[i] is None]
             for i in idle:
+                while nxt < m and drop is not None and drop(nxt):
+                    nxt += 1  # a column left out: unpaired, the lane takes the next one
                 if nxt < m:
                     p, q = max(na[nxt], nb[nxt]), min(na[nxt], nb[nxt])
                     state[i] = [nxt, p, q, EMPTY, 0]
@@ -108,3 +110,25 @@ def test_the_column_bound_of_the_shortcuts_is_needed():
         except AssertionError:  # no progress
             wrong += 1
     assert wrong > 0
+
+
+@pytest.mark.parametrize("virtual_max", [True, False])
+@pytest.mark.parametrize("field,lanes", [(sf.noise((10, 10, 10), 1), 16), (sf.noise((12, 11, 10), 2), 64),
+                                         (sf.with_infinities(sf.noise((7, 8, 9), 9), 9), 32)])
+def test_dual_reduction_both_boundary_modes(field, lanes, virtual_max):
+    """The D2 arcs reduced the same way, the outside as node 0 (the oldest):
+    with the virtual maximum every column takes part; without it a column
+    with an end outside is left out (the lane takes the next column at once).
+    The pairs equal the oracle's dual union-find in the same mode."""
+    res = oracle.run(field, virtual_max=virtual_max)
+    tets = res.crit[3]
+    age = {int(t): len(tets) - i for i, t in enumerate(tets)}  # 1 = the highest maximum
+    na = [0 if a < 0 else age[int(a)] for a in res.arcs2[:, 0]]
+    nb = [0 if b < 0 else age[int(b)] for b in res.arcs2[:, 1]]
+    tri = res.arcs2[:, 2]
+    expect = {(int(t), int(T)) for t, T in res.pairs[2] if T >= 0}
+    drop = None if virtual_max else (lambda c: na[c] == 0 or nb[c] == 0)
+    for seed in range(3):
+        owner = _reduce_interleaved(na, nb, lanes, np.random.default_rng(seed), drop=drop)
+        got = {(int(tri[c]), int(tets[len(tets) - p])) for p, c in owner.items() if p != 0}
+        assert got == expect, (lanes, seed, virtual_max)
