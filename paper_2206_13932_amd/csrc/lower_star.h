@@ -13,8 +13,7 @@
 // the highest label down: at label j, if some member lacks j, the members
 // that hold j go; the last member standing has the smallest mask. The slots
 // holding a neighbour are one table row, so a level costs a few bit
-// operations whatever the set's size, and the work stops as soon as one
-// member is left.
+// operations whatever the set's size.
 #pragma once
 #include "dms_device.h"
 
@@ -150,19 +149,22 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
             if (unpaired(64 + b) == 1) o_hi |= 1u << b;
         }
     };
-    // the member of a non-empty set with the smallest mask, removed from it
+    // the member of a non-empty set with the smallest mask, removed from it.
+    // Every level runs: the lanes of a wave go through the levels together,
+    // and testing after each level whether one member is left cost more than
+    // the levels it saved.
+    const uint64_t inv = inv0 | (uint64_t)inv1 << 32;
     auto pop_min = [&](uint64_t& qlo, uint32_t& qhi) {
         uint64_t lo = qlo;
         uint32_t hi = qhi;
         if (popc64_(lo) + __builtin_popcount(hi) > 1) {
             for (int j = k - 1; j >= 0; --j) {
-                const int n = nb_of(j);
+                const int n = (int)((inv >> (4 * j)) & 15u);
                 const uint64_t tl = lo & ~T.slnb_lo[n];
                 const uint32_t th = hi & ~(uint32_t)T.slnb_hi[n];
                 if (tl | th) {
                     lo = tl;
                     hi = th;
-                    if (popc64_(lo) + __builtin_popcount(hi) == 1) break;
                 }
             }
         }
