@@ -104,6 +104,14 @@ __device__ inline bool is_nan_bits(float f) {
     return (b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu) != 0;
 }
 
+// a set of slots of the open star: bits 0..63 in lo, slots 64..73 in hi
+// (16 bytes, so that one LDS read fetches it)
+struct alignas(16) SlotMask {
+    uint64_t lo;
+    uint32_t hi;
+    uint32_t pad;
+};
+
 // ---- star tables (computed at compile time, star_tables.h) -----------------
 // Neighbour n of x: offset nbv[n] = +mask(n+1) for n < 7, -mask(n-6) else.
 // Slot s of the open star: 0..13 edge {x, n}; 14..49 triangle {x, a, b}
@@ -123,8 +131,10 @@ struct StarTables {
     int8_t al27[NSLOT];       // aoff.x + 3 aoff.y + 9 aoff.z
     uint8_t dim[NSLOT];
     uint8_t type[NSLOT];
-    uint64_t slnb_lo[NNB];    // slots (0..63) whose cell contains neighbour n
-    uint16_t slnb_hi[NNB];    // the same, slots 64..73 (bit s-64)
+    SlotMask slnb[NNB];       // slots whose cell contains neighbour n
+    // packed for one read when a pair is recorded:
+    uint32_t slrec[NSLOT];    // cellnb | (al27 + 13) << 16
+    uint32_t nbrec[NNB];      // lessc | cpos_pos << 14 | (l27 + 13) << 16
 };
 
 // Persistent work distribution: lanes that are idle take the next work item

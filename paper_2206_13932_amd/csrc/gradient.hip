@@ -32,8 +32,9 @@ struct LdsTables {
     uint64_t cof_lo[NSLOT];
     uint16_t cof_hi[NSLOT];
     uint16_t cellnb[NSLOT];
-    uint64_t slnb_lo[NNB];  // slots holding neighbour n (0..63, then 64..73)
-    uint16_t slnb_hi[NNB];
+    SlotMask slnb[NNB];  // slots holding neighbour n
+    uint32_t slrec[NSLOT];
+    uint32_t nbrec[NNB];
     uint8_t plane[NSLOT];
     int8_t al27[NSLOT];
     int8_t l27[NNB];
@@ -72,13 +73,14 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         T.cof_lo[i] = kStar.cof_lo[i];
         T.cof_hi[i] = kStar.cof_hi[i];
         T.cellnb[i] = kStar.cellnb[i];
+        T.slrec[i] = kStar.slrec[i];
         T.plane[i] = kStar.plane[i];
         T.al27[i] = kStar.al27[i];
         T.aofflin[i] = (int64_t)kStar.aoff[i][0] + kStar.aoff[i][1] * g.sy + kStar.aoff[i][2] * g.sz;
     }
     for (int i = tid; i < NNB; i += GB) {
-        T.slnb_lo[i] = kStar.slnb_lo[i];
-        T.slnb_hi[i] = kStar.slnb_hi[i];
+        T.slnb[i] = kStar.slnb[i];
+        T.nbrec[i] = kStar.nbrec[i];
         T.l27[i] = kStar.l27[i];
         T.lessc[i] = kStar.lessc[i];
         T.cpos_pos[i] = kStar.cpos_pos[i];

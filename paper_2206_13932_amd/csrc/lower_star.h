@@ -95,8 +95,8 @@ __host__ __device__ inline void star_cells(uint32_t lower, uint64_t& in_lo, uint
 #pragma unroll
     for (int n = 0; n < NNB; ++n)
         if (!((lower >> n) & 1)) {
-            rm_lo |= kStar.slnb_lo[n];
-            rm_hi |= kStar.slnb_hi[n];
+            rm_lo |= kStar.slnb[n].lo;
+            rm_hi |= kStar.slnb[n].hi;
         }
     in_lo = ~rm_lo;
     in_hi = ((1u << (NSLOT - 64)) - 1) & ~rm_hi;
@@ -105,8 +105,8 @@ __host__ __device__ inline void star_cells(uint32_t lower, uint64_t& in_lo, uint
 __host__ __device__ inline int popc64_(uint64_t v) { return __builtin_popcountll(v); }
 
 // ProcessLowerStars on a vertex with k >= 1 lower neighbours.
-// T: star tables (face, cof_lo, cof_hi, cellnb, lessc, cpos_pos, l27, al27,
-// slnb_lo, slnb_hi); put(slot, code) receives the partner code of every cell
+// T: star tables (face, cof_lo, cof_hi, slrec, nbrec, l27, cpos_pos, slnb);
+// put(slot, code) receives the partner code of every cell
 // of L(x) that is paired (codes as in dms_device.h); xcode = the code of x;
 // crit_lo / crit_hi = the critical cells.
 template <class Tab, class Put>
@@ -120,10 +120,12 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
     uint32_t cls_hi = 0;
     // pair (p, a): p is a facet of a; w = the neighbour of a not in p
     auto pair_cells = [&](int p, int a) {
-        const uint32_t w = __builtin_ctz((uint32_t)(T.cellnb[a] & ~T.cellnb[p]));
-        const int pos = __builtin_popcount(T.cellnb[a] & T.lessc[w]) + T.cpos_pos[w];
+        const uint32_t ra = T.slrec[a], rp = T.slrec[p];
+        const uint32_t w = __builtin_ctz(ra & ~rp & 0x3FFFu);
+        const uint32_t rw = T.nbrec[w];
+        const int pos = __builtin_popcount(ra & rw & 0x3FFFu) + (int)((rw >> 14) & 1);
         put(a, (uint8_t)(0x80 | pos));
-        put(p, (uint8_t)(13 + T.l27[w] - T.al27[p]));
+        put(p, (uint8_t)(13 + (int)(rw >> 16) - (int)(rp >> 16)));  // 13 + l27[w] - al27[p]
     };
     auto unpaired = [&](int s) { return popc64_(T.face[s] & ~cls_lo); };
     // x pairs with its lowest edge delta = {x, n0}
@@ -135,14 +137,15 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
     uint32_t z_hi = 0;
     uint64_t o_lo = 0;
     uint32_t o_hi = 0;
-    auto push_cofaces = [&](int s) {
-        uint64_t c = T.cof_lo[s] & in_lo & ~cls_lo;
+    // push the cofacets of s and t (s == t: of s) that have one unpaired facet
+    auto push_cofaces2 = [&](int s, int t) {
+        uint64_t c = (T.cof_lo[s] | T.cof_lo[t]) & in_lo & ~cls_lo;
         while (c) {
             const int b = __builtin_ctzll(c);
             c &= c - 1;
             if (unpaired(b) == 1) o_lo |= (uint64_t)1 << b;
         }
-        uint32_t ch = T.cof_hi[s] & in_hi & ~cls_hi;
+        uint32_t ch = (uint32_t)(T.cof_hi[s] | T.cof_hi[t]) & in_hi & ~cls_hi;
         while (ch) {
             const int b = __builtin_ctz(ch);
             ch &= ch - 1;
@@ -160,8 +163,9 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
         if (popc64_(lo) + __builtin_popcount(hi) > 1) {
             for (int j = k - 1; j >= 0; --j) {
                 const int n = (int)((inv >> (4 * j)) & 15u);
-                const uint64_t tl = lo & ~T.slnb_lo[n];
-                const uint32_t th = hi & ~(uint32_t)T.slnb_hi[n];
+                const SlotMask m = T.slnb[n];
+                const uint64_t tl = lo & ~m.lo;
+                const uint32_t th = hi & ~m.hi;
                 if (tl | th) {
                     lo = tl;
                     hi = th;
@@ -178,7 +182,7 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
         }
         return best;
     };
-    push_cofaces(n0);
+    push_cofaces2(n0, n0);
     for (int guard = 0; guard < 4 * NSLOT; ++guard) {
         while (o_lo | o_hi) {
             const int a = pop_min(o_lo, o_hi);
@@ -198,8 +202,7 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
             if (a < 64) cls_lo |= (uint64_t)1 << a;
             else cls_hi |= 1u << (a - 64);
             z_lo &= ~((uint64_t)1 << p);
-            push_cofaces(a);
-            push_cofaces(p);
+            push_cofaces2(a, p);
         }
         if (!(z_lo | z_hi)) break;
         const int c = pop_min(z_lo, z_hi);
@@ -211,7 +214,7 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
             crit_hi |= 1u << (c - 64);
         }
         put(c, CODE_CRIT);
-        push_cofaces(c);
+        push_cofaces2(c, c);
     }
 }
 

@@ -110,13 +110,15 @@ constexpr StarTables make_star_tables() {
         T.cof_lo[i] = 0;
         T.cof_hi[i] = 0;
     }
+    for (int i = 0; i < NSLOT; ++i) T.slrec[i] = (uint32_t)T.cellnb[i] | (uint32_t)(T.al27[i] + 13) << 16;
+    for (int n = 0; n < NNB; ++n)
+        T.nbrec[n] = (uint32_t)T.lessc[n] | (uint32_t)T.cpos_pos[n] << 14 | (uint32_t)(T.l27[n] + 13) << 16;
     for (int n = 0; n < NNB; ++n) {
-        T.slnb_lo[n] = 0;
-        T.slnb_hi[n] = 0;
+        T.slnb[n] = SlotMask{0, 0, 0};
         for (int i = 0; i < NSLOT; ++i)
             if (T.cellnb[i] & (1 << n)) {
-                if (i < 64) T.slnb_lo[n] |= (uint64_t)1 << i;
-                else T.slnb_hi[n] |= (uint16_t)(1 << (i - 64));
+                if (i < 64) T.slnb[n].lo |= (uint64_t)1 << i;
+                else T.slnb[n].hi |= 1u << (i - 64);
             }
     }
     for (int i = 0; i < NSLOT; ++i)
