@@ -186,12 +186,18 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
             uint32_t in_hi;
             star_cells(lower, in_lo, in_hi);
             uint32_t inv0, inv1;
-            relabel<PACKED>(r, lower, inv0, inv1, relpack);
+            uint64_t rp;
+            relabel<PACKED>(r, lower, inv0, inv1, rp);
+            const int k = __builtin_popcount(lower);
+            // x pairs with its lowest edge (the code is known before the loop)
+            G[x] = (uint8_t)(13 + T.l27[inv0 & 15u]);
             uint8_t xcode;
             lower_star_gradient(
-                T, in_lo, in_hi, __builtin_popcount(lower), inv0, inv1,
-                [&](int s, uint8_t code) { CODE(s) = code; }, xcode, crit_lo, crit_hi);
-            G[x] = xcode;
+                T, in_lo, in_hi, k, inv0, inv1, [&](int s, uint8_t code) { CODE(s) = code; }, xcode, crit_lo,
+                crit_hi);
+            // the labels again, for the keys of the critical cells (not kept
+            // in registers through the loop)
+            relpack = labels_of(inv0, inv1, k);
         }
     }
     __syncthreads();

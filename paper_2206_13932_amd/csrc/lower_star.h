@@ -104,6 +104,16 @@ __host__ __device__ inline void star_cells(uint32_t lower, uint64_t& in_lo, uint
 
 __host__ __device__ inline int popc64_(uint64_t v) { return __builtin_popcountll(v); }
 
+// The label of each lower neighbour (bits 4n) from inv0 / inv1.
+__host__ __device__ inline uint64_t labels_of(uint32_t inv0, uint32_t inv1, int k) {
+    const uint64_t inv = inv0 | (uint64_t)inv1 << 32;
+    uint64_t relpack = 0;
+#pragma unroll
+    for (int j = 0; j < NNB; ++j)
+        if (j < k) relpack |= (uint64_t)j << (4 * ((inv >> (4 * j)) & 15u));
+    return relpack;
+}
+
 // ProcessLowerStars on a vertex with k >= 1 lower neighbours.
 // T: star tables (face, cof_lo, cof_hi, slrec, nbrec, l27, cpos_pos, slnb);
 // put(slot, code) receives the partner code of every cell
@@ -113,13 +123,15 @@ template <class Tab, class Put>
 __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo, uint32_t in_hi, int k,
                                                     uint32_t inv0, uint32_t inv1, Put put, uint8_t& xcode,
                                                     uint64_t& crit_lo, uint32_t& crit_hi) {
-    auto nb_of = [&](int j) { return (int)((j < 8 ? inv0 >> (4 * j) : inv1 >> (4 * (j - 8))) & 15u); };
+    auto nb_of = [&](int j) __attribute__((always_inline)) { return (int)((j < 8 ? inv0 >> (4 * j) : inv1 >> (4 * (j - 8))) & 15u); };
     crit_lo = 0;
     crit_hi = 0;
+    // classified cells; the slots outside L(x) count as classified from the
+    // start, so that no test needs the star's mask again
     uint64_t cls_lo;
-    uint32_t cls_hi = 0;
+    uint32_t cls_hi = ~in_hi;
     // pair (p, a): p is a facet of a; w = the neighbour of a not in p
-    auto pair_cells = [&](int p, int a) {
+    auto pair_cells = [&](int p, int a) __attribute__((always_inline)) {
         const uint32_t ra = T.slrec[a], rp = T.slrec[p];
         const uint32_t w = __builtin_ctz(ra & ~rp & 0x3FFFu);
         const uint32_t rw = T.nbrec[w];
@@ -127,29 +139,40 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
         put(a, (uint8_t)(0x80 | pos));
         put(p, (uint8_t)(13 + (int)(rw >> 16) - (int)(rp >> 16)));  // 13 + l27[w] - al27[p]
     };
-    auto unpaired = [&](int s) { return popc64_(T.face[s] & ~cls_lo); };
+    auto unpaired = [&](int s) __attribute__((always_inline)) { return popc64_(T.face[s] & ~cls_lo); };
     // x pairs with its lowest edge delta = {x, n0}
     const int n0 = nb_of(0);
     xcode = (uint8_t)(13 + T.l27[n0]);
     put(n0, (uint8_t)(0x80 | T.cpos_pos[n0]));
-    cls_lo = (uint64_t)1 << n0;
-    uint64_t z_lo = (in_lo & 0x3FFFull) & ~cls_lo;  // the other edges
+    cls_lo = ~in_lo | (uint64_t)1 << n0;
+    uint64_t z_lo = 0x3FFFull & ~cls_lo;  // the other edges
     uint32_t z_hi = 0;
     uint64_t o_lo = 0;
     uint32_t o_hi = 0;
-    // push the cofacets of s and t (s == t: of s) that have one unpaired facet
-    auto push_cofaces2 = [&](int s, int t) {
-        uint64_t c = (T.cof_lo[s] | T.cof_lo[t]) & in_lo & ~cls_lo;
+    // push the cofacets of s and t (s == t: of s) that have one unpaired
+    // facet. A cofacet with none left was pushed when it had one; it would
+    // leave the queue for the other one when popped, with no other effect,
+    // so it moves there now and costs no pop.
+    auto push_cofaces2 = [&](int s, int t) __attribute__((always_inline)) {
+        uint64_t c = (T.cof_lo[s] | T.cof_lo[t]) & ~cls_lo;
         while (c) {
             const int b = __builtin_ctzll(c);
             c &= c - 1;
-            if (unpaired(b) == 1) o_lo |= (uint64_t)1 << b;
+            const int u = unpaired(b);
+            const uint64_t bit = (uint64_t)1 << b;
+            const uint64_t one = u == 1 ? bit : 0, none = u == 0 ? bit : 0;
+            o_lo = (o_lo | one) & ~none;
+            z_lo |= none;
         }
-        uint32_t ch = (uint32_t)(T.cof_hi[s] | T.cof_hi[t]) & in_hi & ~cls_hi;
+        uint32_t ch = (uint32_t)(T.cof_hi[s] | T.cof_hi[t]) & ~cls_hi;
         while (ch) {
             const int b = __builtin_ctz(ch);
             ch &= ch - 1;
-            if (unpaired(64 + b) == 1) o_hi |= 1u << b;
+            const int u = unpaired(64 + b);
+            const uint32_t bit = 1u << b;
+            const uint32_t one = u == 1 ? bit : 0, none = u == 0 ? bit : 0;
+            o_hi = (o_hi | one) & ~none;
+            z_hi |= none;
         }
     };
     // the member of a non-empty set with the smallest mask, removed from it.
@@ -157,9 +180,8 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
     // and testing after each level whether one member is left cost more than
     // the levels it saved.
     const uint64_t inv = inv0 | (uint64_t)inv1 << 32;
-    auto pop_min = [&](uint64_t& qlo, uint32_t& qhi) {
-        uint64_t lo = qlo;
-        uint32_t hi = qhi;
+    // (its slot; the caller removes it)
+    auto pop_min = [&](uint64_t lo, uint32_t hi) __attribute__((always_inline)) {
         if (popc64_(lo) + __builtin_popcount(hi) > 1) {
             for (int j = k - 1; j >= 0; --j) {
                 const int n = (int)((inv >> (4 * j)) & 15u);
@@ -172,20 +194,14 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
                 }
             }
         }
-        int best;
-        if (lo) {
-            best = __builtin_ctzll(lo);
-            qlo &= ~((uint64_t)1 << best);
-        } else {
-            best = 64 + __builtin_ctz(hi);
-            qhi &= ~(1u << (best - 64));
-        }
-        return best;
+        return lo ? __builtin_ctzll(lo) : 64 + __builtin_ctz(hi);
     };
     push_cofaces2(n0, n0);
     for (int guard = 0; guard < 4 * NSLOT; ++guard) {
         while (o_lo | o_hi) {
             const int a = pop_min(o_lo, o_hi);
+            if (a < 64) o_lo &= ~((uint64_t)1 << a);
+            else o_hi &= ~(1u << (a - 64));
             // a cell of this queue is smaller than every cell classified
             // after it entered, so it is never found classified; the test
             // only keeps the step exactly as the algorithm states it
@@ -206,6 +222,8 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
         }
         if (!(z_lo | z_hi)) break;
         const int c = pop_min(z_lo, z_hi);
+        if (c < 64) z_lo &= ~((uint64_t)1 << c);
+        else z_hi &= ~(1u << (c - 64));
         if (c < 64) {
             cls_lo |= (uint64_t)1 << c;
             crit_lo |= (uint64_t)1 << c;
