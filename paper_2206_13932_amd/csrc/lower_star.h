@@ -196,41 +196,42 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
         }
         return lo ? __builtin_ctzll(lo) : 64 + __builtin_ctz(hi);
     };
+    // slot s as a two-word bit (no branch on the word)
+    auto bits_of = [&](int s, uint64_t& blo, uint32_t& bhi) __attribute__((always_inline)) {
+        blo = s < 64 ? (uint64_t)1 << (s & 63) : 0;
+        bhi = s < 64 ? 0 : 1u << ((s - 64) & 31);
+    };
     push_cofaces2(n0, n0);
     for (int guard = 0; guard < 4 * NSLOT; ++guard) {
         while (o_lo | o_hi) {
             const int a = pop_min(o_lo, o_hi);
-            if (a < 64) o_lo &= ~((uint64_t)1 << a);
-            else o_hi &= ~(1u << (a - 64));
-            // a cell of this queue is smaller than every cell classified
-            // after it entered, so it is never found classified; the test
-            // only keeps the step exactly as the algorithm states it
-            if (a < 64 ? ((cls_lo >> a) & 1) : ((cls_hi >> (a - 64)) & 1)) continue;
-            const uint64_t u = T.face[a] & ~cls_lo;
-            if (u == 0) {  // no unpaired facet left: wait for the other queue
-                if (a < 64) z_lo |= (uint64_t)1 << a;
-                else z_hi |= 1u << (a - 64);
-                continue;
-            }
-            const int p = __builtin_ctzll(u);
+            uint64_t alo;
+            uint32_t ahi;
+            bits_of(a, alo, ahi);
+            o_lo &= ~alo;
+            o_hi &= ~ahi;
+            // A cell of this queue is unclassified (it is smaller than every
+            // cell classified after it entered), and it has one unpaired facet
+            // (the classification that takes its last one moves it to the other
+            // queue), so it pairs with that facet.
+            const int p = __builtin_ctzll(T.face[a] & ~cls_lo);
             pair_cells(p, a);
-            cls_lo |= (uint64_t)1 << p;
-            if (a < 64) cls_lo |= (uint64_t)1 << a;
-            else cls_hi |= 1u << (a - 64);
+            cls_lo |= alo | (uint64_t)1 << p;
+            cls_hi |= ahi;
             z_lo &= ~((uint64_t)1 << p);
             push_cofaces2(a, p);
         }
         if (!(z_lo | z_hi)) break;
         const int c = pop_min(z_lo, z_hi);
-        if (c < 64) z_lo &= ~((uint64_t)1 << c);
-        else z_hi &= ~(1u << (c - 64));
-        if (c < 64) {
-            cls_lo |= (uint64_t)1 << c;
-            crit_lo |= (uint64_t)1 << c;
-        } else {
-            cls_hi |= 1u << (c - 64);
-            crit_hi |= 1u << (c - 64);
-        }
+        uint64_t clo;
+        uint32_t chi;
+        bits_of(c, clo, chi);
+        z_lo &= ~clo;
+        z_hi &= ~chi;
+        cls_lo |= clo;
+        cls_hi |= chi;
+        crit_lo |= clo;
+        crit_hi |= chi;
         put(c, CODE_CRIT);
         push_cofaces2(c, c);
     }
