@@ -36,9 +36,7 @@ struct LdsTables {
     uint32_t slrec[NSLOT];
     uint32_t nbrec[NNB];
     uint8_t plane[NSLOT];
-    int8_t al27[NSLOT];
     int8_t l27[NNB];
-    uint16_t lessc[NNB];
     uint8_t cpos_pos[NNB];
     int64_t aofflin[NSLOT];
 };
@@ -75,14 +73,12 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         T.cellnb[i] = kStar.cellnb[i];
         T.slrec[i] = kStar.slrec[i];
         T.plane[i] = kStar.plane[i];
-        T.al27[i] = kStar.al27[i];
         T.aofflin[i] = (int64_t)kStar.aoff[i][0] + kStar.aoff[i][1] * g.sy + kStar.aoff[i][2] * g.sz;
     }
     for (int i = tid; i < NNB; i += GB) {
         T.slnb[i] = kStar.slnb[i];
         T.nbrec[i] = kStar.nbrec[i];
         T.l27[i] = kStar.l27[i];
-        T.lessc[i] = kStar.lessc[i];
         T.cpos_pos[i] = kStar.cpos_pos[i];
     }
     for (int i = tid; i <= NSLOT; i += GB) bins[i] = 0;
