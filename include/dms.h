@@ -265,7 +265,10 @@ enum {
                               scan, slot assignment, batched loads, sort, low
                               merge, top merge, owner rule, additions, claims
                               and reloads, refills), then their rounds and
-                              additions; additions made by one full merge       */
+                              additions; additions made by one full merge;
+                              the sixth D1 pass (columns, microseconds);
+                              cooperative full merges, their parts merged by
+                              helping workgroups                                */
     DMS_BUF_D1LEN = 9      /* u64 per D1 column: last cached boundary
                               (offset << 24 | length)                             */
 };

@@ -51,8 +51,8 @@ struct D1State {
     // [3] deferrals, [4] published entries, [5] restarts
     uint64_t stats[6] = {0, 0, 0, 0, 0, 0};
     // per pass: columns to process, microseconds
-    uint64_t pass_work[5] = {0, 0, 0, 0, 0};
-    uint64_t pass_us[5] = {0, 0, 0, 0, 0};
+    uint64_t pass_work[6] = {0, 0, 0, 0, 0, 0};
+    uint64_t pass_us[6] = {0, 0, 0, 0, 0, 0};
     // workgroup passes: rounds, edges expanded, boundary entries moved by merges
     uint64_t wide[4] = {0, 0, 0, 0};
     // workgroup passes, per column taken from the queue: longest (us), total (us),
@@ -63,6 +63,8 @@ struct D1State {
     // the top, owner rule, cached-boundary additions, claims and reloads,
     // refills; then those columns' rounds and additions
     uint64_t wide_ph[12] = {0};
+    // cooperative full merges, and their parts merged by helping workgroups
+    uint64_t coop[2] = {0, 0};
     // per-run data for emission
     GridDev g{};
     const uint32_t* order = nullptr;

@@ -43,7 +43,14 @@ namespace {
 constexpr int DB = 256;
 constexpr uint32_t OWN_D0 = 0xFFFFFFFEu;
 constexpr uint64_t NONE = ~0ull;
-constexpr int MAX_PASSES = 5;
+constexpr int MAX_PASSES = 6;
+// one pass of the D1 plan: heap capacity (keys), lanes or workgroups, block
+// size, thread-per-column or not, heaps in LDS or not
+struct PassPlan {
+    int64_t k, t;
+    int db;
+    bool lane, lds;
+};
 constexpr int LDS_K = 20;   // keys per thread in the first pass (LDS heaps)
 constexpr int LDS_K2 = 48;  // ... and in the second
 constexpr uint32_t MAX_RETRIES = 1u << 16;  // consecutive look-agains before a column is declared corrupt
@@ -52,13 +59,25 @@ inline unsigned nblocks(int64_t n) { return (unsigned)((n + DB - 1) / DB); }
 // counters in D1State::ctrs
 enum { C_HEAP = 0, C_NEXT = 1, C_DEFER = 2, C_STEPS = 3, C_EVICT = 4, C_ADDS = 5, C_ROUNDS = 6, C_EXPANDED = 7,
        C_MOVED = 8, C_TMAX = 9, C_TSUM = 10, C_RMAX = 11, C_AMAX = 12, C_NMAX = 13, C_SLOW = 14, C_LONG = 15, C_PHASE = 16,
-       N_PHASE = 10, N_CTRS = 32 };
+       N_PHASE = 10, C_RSTOP = 28, C_RCAP = 29, C_RTAKEN = 30, C_ACTIVE = 31, N_CTRS = 32 };
 // The publication heap is split into NSEG segments with one bump counter each
 // (counters 128 bytes apart, after the N_CTRS counters above), so that
 // millions of publications do not serialise on one atomic.
 constexpr int NSEG = 64;
 constexpr int SEG_STRIDE = 16;
 constexpr int SEG_BASE = N_CTRS;
+// Job board of the cooperative merges (after the segment counters): NJ slots
+// of BSLOT words (one 128-byte line each): [0] control (sequence << 32 | next
+// part), [1] parts done, [2] holder (0 = free), [3] sequence << 32 | parts,
+// [4] A, [5] |A|, [6] B (stored decreasing), [7] |B|, [8] output, [9] part
+// status words, [10] part span. An odd sequence marks an open job.
+constexpr int NJ = 64;
+constexpr int BSLOT = 16;
+constexpr int BOARD_BASE = SEG_BASE + SEG_STRIDE * NSEG;
+// own line: open jobs, then (counted over a run) parts merged by helpers and
+// cooperative merges
+constexpr int OPEN_JOBS = BOARD_BASE + NJ * BSLOT, HELPED_PARTS = OPEN_JOBS + 1, COOP_MERGES = OPEN_JOBS + 2;
+constexpr int N_CTR_WORDS = OPEN_JOBS + 16;
 
 struct D1K {
     GridDev g;
@@ -86,6 +105,11 @@ struct D1K {
     int64_t nthreads;
     int lds;  // working heaps in LDS (K entries per thread) instead of global scratch
     uint32_t long_add;  // cached boundaries longer than this are added by one full merge
+    int64_t nslots;     // workgroups of a workgroup pass that take columns; the others only help
+    uint32_t part_span; // merged positions per part of a cooperative merge
+    uint64_t coop_min;  // full merges of at least this many entries are split into parts
+    int coop_always;    // split them even when no idle workgroup may help (debug)
+    uint32_t pcap;      // pending keys that trigger a flush into low (PCAP; smaller for debugging)
     unsigned long long* ctrs;
     uint32_t* flags;
 };
@@ -528,6 +552,9 @@ struct WideShared {
     uint32_t wend[NWAVE];
     int ints[8];
     uint64_t u64s[4];
+    uint64_t srch[4];   // search ranges of the part bounds, then the bounds
+    uint32_t wcount[NWAVE];
+    uint64_t job[12];   // the job a helper works on
 };
 
 // inclusive prefix sum over the 64 lanes of a wave with DPP row shifts and
@@ -731,6 +758,17 @@ __device__ uint32_t merge_seg(WideShared& L, const uint64_t* X, uint32_t len, co
     return r;
 }
 
+// cooperative full merge (defined below with the job board)
+__device__ __noinline__ uint32_t coop_merge(WideShared& L, unsigned long long* ctrs, uint32_t* flags, const uint64_t* b,
+                                            uint32_t span, const uint64_t* low, uint32_t na, uint32_t nb, uint64_t* tmp,
+                                            uint64_t* stat, uint64_t* X);
+// may other workgroups help with a merge now? (the pass has dedicated
+// helpers, or its queue of columns is exhausted)
+__device__ inline bool coop_possible(const D1K& P) {
+    return P.coop_always || (int64_t)gridDim.x > P.nslots ||
+           ld_rlx64((const uint64_t*)&P.ctrs[C_NEXT]) >= (uint64_t)P.nwork;
+}
+
 // low[0..n) ^= S[0..m) (S in LDS; both ascending, unique), in place in global
 // memory; returns the new size. Only the suffix from S[0] changes. The top
 // TOPCAP entries of low are staged in LDS (in stg); when the suffix lies
@@ -739,9 +777,9 @@ __device__ uint32_t merge_seg(WideShared& L, const uint64_t* X, uint32_t len, co
 // below the next segment's first key) into tmp. Then either the merged
 // suffix is copied back, or, when the unchanged prefix is shorter, the prefix
 // is copied in front of it and the two buffers swap roles.
-__device__ __forceinline__ uint32_t merge_low(WideShared& L, uint64_t*& low, uint32_t n, const uint64_t* S,
-                                              uint32_t m, uint64_t*& tmp, uint64_t* stg,
-                                              unsigned long long& moved) {
+__device__ __forceinline__ uint32_t merge_low(const D1K& P, WideShared& L, uint64_t*& low, uint32_t n, const uint64_t* S,
+                                              uint32_t m, uint64_t*& tmp, uint64_t* stg, uint64_t* sbuf,
+                                              uint64_t* stat, unsigned long long& moved) {
     const uint32_t t = threadIdx.x;
     if (m == 0) return n;
     uint32_t sp;
@@ -758,6 +796,20 @@ __device__ __forceinline__ uint32_t merge_low(WideShared& L, uint64_t*& low, uin
     const uint32_t p = count_less_block(L, low, n, S[0]);
     uint64_t* Bp = low + p;
     const uint32_t len = n - p;
+    if (len >= P.coop_min && coop_possible(P)) {
+        // a long suffix changes: merge all of low with S by parts into tmp. S is
+        // staged decreasing in sbuf (coherent stores: parts read it coherently)
+        for (uint32_t k = t; k < m; k += WB) st_rlx64(sbuf + (m - 1 - k), S[k]);
+        __syncthreads();
+        moved += n + m;
+        const uint32_t out = coop_merge(L, P.ctrs, P.flags, sbuf, P.part_span, low, n, m, tmp, stat, stg);
+        if (out == ~0u) return 0;  // a wait ran out; the consistency flag is set
+        uint64_t* w = low;
+        low = tmp;
+        tmp = w;
+        __syncthreads();
+        return out;
+    }
     const bool swap = p < len;
     uint64_t* dst = swap ? tmp + p : tmp;
     moved += len;
@@ -1012,7 +1064,8 @@ struct Col {
 };
 
 // Merge pend into low: sort and cancel it in LDS, then one low merge.
-__device__ __forceinline__ void flush(WideShared& L, Col& C, uint64_t*& low, const uint64_t* pend, uint64_t*& tmp,
+__device__ __forceinline__ void flush(const D1K& P, WideShared& L, Col& C, uint64_t*& low, uint64_t* pend, uint64_t*& tmp,
+                                      uint64_t* stat,
                       unsigned long long& moved) {
     if (C.np == 0) return;
     const uint32_t t = threadIdx.x;
@@ -1035,7 +1088,7 @@ __device__ __forceinline__ void flush(WideShared& L, Col& C, uint64_t*& low, con
     const uint32_t m = sort_cancel(L, C.np, L.raw);
     C.np = 0;
     if (m == 0) return;
-    C.nl = merge_low(L, low, C.nl, L.raw, m, tmp, L.top[C.cur ^ 1], moved);
+    C.nl = merge_low(P, L, low, C.nl, L.raw, m, tmp, L.top[C.cur ^ 1], pend, stat, moved);
     C.lmax = C.nl ? low[C.nl - 1] : 0;
     __syncthreads();
 }
@@ -1046,7 +1099,8 @@ __device__ __forceinline__ void flush(WideShared& L, Col& C, uint64_t*& low, con
 // outgrows TOPCAP.
 // t_low and t_top accumulate the time of the two parts (100 MHz clock ticks
 // since tp, which is advanced).
-__device__ __forceinline__ void merge_col(WideShared& L, Col& C, uint64_t*& low, uint64_t* pend, uint32_t m, uint64_t*& tmp,
+__device__ __forceinline__ void merge_col(const D1K& P, WideShared& L, Col& C, uint64_t*& low, uint64_t* pend,
+                                          uint64_t* stat, uint32_t m, uint64_t*& tmp,
                           unsigned long long& moved, uint64_t& t_low, uint64_t& t_top, uint64_t& tp) {
     auto lap = [&](uint64_t& acc) {
         const uint64_t now = __builtin_amdgcn_s_memrealtime();
@@ -1057,8 +1111,8 @@ __device__ __forceinline__ void merge_col(WideShared& L, Col& C, uint64_t*& low,
     const uint32_t t = threadIdx.x;
     uint32_t s0 = C.nl ? count_less<uint64_t>(L.src, m, C.lmax + 1) : 0u;
     if (s0 > 0) {
-        if (C.np + s0 > (uint32_t)PCAP) {
-            flush(L, C, low, pend, tmp, moved);
+        if (C.np + s0 > P.pcap) {
+            flush(P, L, C, low, pend, tmp, stat, moved);
             s0 = C.nl ? count_less<uint64_t>(L.src, m, C.lmax + 1) : 0u;
         }
         for (uint32_t i = t; i < s0; i += WB) pend[C.np + i] = L.src[i];
@@ -1132,9 +1186,10 @@ __device__ __forceinline__ void load_col(WideShared& L, Col& C, uint64_t* low, c
 
 // Flush pend, then move the largest low entries below the top until it holds
 // TOPKEEP more entries (or low is empty).
-__device__ __forceinline__ void refill(WideShared& L, Col& C, uint64_t*& low, const uint64_t* pend, uint64_t*& tmp,
+__device__ __forceinline__ void refill(const D1K& P, WideShared& L, Col& C, uint64_t*& low, uint64_t* pend, uint64_t*& tmp,
+                                       uint64_t* stat,
                        unsigned long long& moved) {
-    flush(L, C, low, pend, tmp, moved);
+    flush(P, L, C, low, pend, tmp, stat, moved);
     if (C.nl == 0) return;
     const uint32_t t = threadIdx.x;
     const uint32_t r = min(C.nl, (uint32_t)TOPKEEP);
@@ -1152,9 +1207,10 @@ __device__ __forceinline__ void refill(WideShared& L, Col& C, uint64_t*& low, co
 // Flush pend and save the boundary (C.n() entries afterwards) to the
 // publication heap in the decreasing layout; returns the offset or PAD when
 // the heap is full.
-__device__ __forceinline__ uint64_t save_col(const D1K& P, WideShared& L, Col& C, uint64_t*& low, const uint64_t* pend,
+__device__ __forceinline__ uint64_t save_col(const D1K& P, WideShared& L, Col& C, uint64_t*& low, uint64_t* pend,
+                                             uint64_t* stat,
                              uint64_t*& tmp, unsigned long long& moved) {
-    flush(L, C, low, pend, tmp, moved);
+    flush(P, L, C, low, pend, tmp, stat, moved);
     const uint32_t t = threadIdx.x;
     const uint32_t n = C.n();
     if (t == 0) L.u64s[1] = heap_alloc(P, blockIdx.x, n);
@@ -1170,6 +1226,377 @@ __device__ __forceinline__ uint64_t save_col(const D1K& P, WideShared& L, Col& C
     return off;
 }
 
+// ---- cooperative full merges ------------------------------------------------
+// A full merge low ^ B (both ascending and unique, B stored decreasing) is cut
+// into parts of part_span consecutive positions of the merged order (merge
+// path), moved by one so that two equal keys, which cancel, always fall in the
+// same part. Each part is merged in LDS by one workgroup; the parts' output
+// offsets come from a single-pass scan with decoupled look-back over one
+// status word per part (flag << 62 | count: 1 = the part's own count, 2 = the
+// count of every part up to it). The column's workgroup posts the job on the
+// board and takes parts itself; workgroups without a column take parts of
+// open jobs. A part waits only for the statuses of lower parts, which were
+// taken earlier by running workgroups, so every wait ends. Data moves between
+// workgroups with agent-scope release fences (after the writes) and acquire
+// fences (before the reads) around the board's atomics.
+constexpr uint64_t ST_AGG = 1ull << 62, ST_INC = 2ull << 62, ST_VAL = (1ull << 62) - 1;
+constexpr uint32_t PART_SPAN = 2040;   // positions per part: a part's A and B entries fit in TOPCAP LDS keys
+constexpr uint32_t SUB = 8;            // positions per thread inside a part
+constexpr uint64_t COOP_MIN = 1u << 16;  // smaller full merges stay with the column's workgroup
+constexpr uint32_t WAIT_SPIN = 1u << 24;  // bounded waits of the look-back and of the job's end
+constexpr uint32_t HELP_SPIN = 1u << 22;  // polls of an idle helper before it gives up helping
+static_assert(WB * SUB == TOPCAP && PART_SPAN + 1 <= TOPCAP, "a part fits one top buffer");
+static_assert(offsetof(WideShared, flag) + sizeof(uint32_t) * NW - offsetof(WideShared, surv) >= 8 * TOPCAP,
+              "the part output stage (surv .. flag) holds a part");
+
+struct Job {
+    const uint64_t* a;
+    uint64_t na;
+    const uint64_t* b;  // decreasing: ascending entry j is b[nb - 1 - j]
+    uint64_t nb;
+    uint64_t* out;
+    uint64_t* stat;
+    uint32_t span, nparts;
+    int coh;  // a helper: A is read and the output written with coherent accesses
+};
+__device__ inline uint64_t aget(const Job& J, uint64_t i) { return J.coh ? ld_rlx64(J.a + i) : J.a[i]; }
+// B lives in the publication heap: read coherently (a line of it may have
+// been cached before it was published)
+__device__ inline uint64_t bget(const Job& J, uint64_t j) { return ld_rlx64(J.b + (J.nb - 1 - j)); }
+
+// Bounds (i, j) of the merged prefixes of d0 and d1 positions (A entries
+// before equal B entries, then an equal pair kept together), by two 128-ary
+// searches over A, one per half of the block.
+__device__ void part_bounds(WideShared& L, const Job& J, uint64_t d0, uint64_t d1) {
+    const uint32_t t = threadIdx.x, h = t >> 7, k = t & 127;
+    const uint64_t d = h ? d1 : d0;
+    if (k == 0) {
+        L.srch[2 * h] = d > J.nb ? d - J.nb : 0;
+        L.srch[2 * h + 1] = d < J.na ? d : J.na;
+    }
+    __syncthreads();
+    for (;;) {
+        const uint64_t lo = L.srch[2 * h], hi = L.srch[2 * h + 1];
+        if (L.srch[0] >= L.srch[1] && L.srch[2] >= L.srch[3]) break;  // both found
+        // f(i) = A[i] <= B[d - 1 - i] holds for a prefix of the range: the
+        // answer is the first i where it fails
+        const uint64_t n = hi - lo, step = (n + 127) / 128;
+        bool f = false;
+        if (n > 0) {
+            const uint64_t i = lo + k * step;
+            if (i < hi) f = aget(J, i) <= bget(J, d - 1 - i);
+        }
+        const uint64_t bal = __ballot(f);
+        if ((t & 63) == 0) L.wcount[t >> 6] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        if (k == 0 && n > 0) {
+            const uint64_t c = L.wcount[2 * h] + L.wcount[2 * h + 1];
+            if (c == 0) {
+                L.srch[2 * h + 1] = lo;
+            } else {
+                L.srch[2 * h] = lo + (c - 1) * step + 1;
+                L.srch[2 * h + 1] = min(hi, lo + c * step);
+            }
+        }
+        __syncthreads();
+    }
+    if (k == 0) {
+        const uint64_t i = L.srch[2 * h];
+        uint64_t j = d - i;
+        if (i > 0 && j < J.nb && aget(J, i - 1) == bget(J, j)) ++j;  // the equal pair stays together
+        L.srch[2 * h + 1] = j;
+    }
+    __syncthreads();
+}
+
+// the same inside a part held in LDS (XA[0..la), XB[0..lb) ascending), for one
+// thread: bounds of the first e merged positions
+__device__ inline void local_bound(const uint64_t* XA, uint32_t la, const uint64_t* XB, uint32_t lb, uint32_t e,
+                                   uint32_t& i, uint32_t& j) {
+    uint32_t lo = e > lb ? e - lb : 0, hi = min(e, la);
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (XA[mid] <= XB[e - 1 - mid]) lo = mid + 1;
+        else hi = mid;
+    }
+    i = lo;
+    j = e - lo;
+    if (i > 0 && j < lb && XA[i - 1] == XB[j]) ++j;
+}
+
+// Merge part p of job J (by the whole block) into J.out at its scanned offset.
+// Returns false when a look-back wait ran out (the kernel's consistency flag
+// is then set).
+__device__ __noinline__ bool merge_part(WideShared& L, const Job J, uint32_t p, uint32_t* flags, uint64_t* X) {
+    const uint32_t t = threadIdx.x;
+    const uint64_t tot = J.na + J.nb;
+    const uint64_t d0 = (uint64_t)p * J.span, d1 = min(tot, d0 + J.span);
+    part_bounds(L, J, d0, d1);
+    const uint64_t i0 = L.srch[0], j0 = L.srch[1], i1 = L.srch[2], j1 = L.srch[3];
+    const uint32_t la = (uint32_t)(i1 - i0), lb = (uint32_t)(j1 - j0);
+    // X (a free top buffer): A entries, then B entries (ascending)
+    for (uint32_t q = t; q < la; q += WB) X[q] = aget(J, i0 + q);
+    for (uint32_t q = t; q < lb; q += WB) X[la + q] = bget(J, j0 + q);
+    __syncthreads();
+    const uint64_t* XA = X;
+    const uint64_t* XB = X + la;
+    const uint32_t n = la + lb;
+    uint32_t si, sj, ei, ej;
+    local_bound(XA, la, XB, lb, min(t * SUB, n), si, sj);
+    local_bound(XA, la, XB, lb, min(t * SUB + SUB, n), ei, ej);
+    // count, then write: a thread's range holds at most SUB + 1 entries
+    uint32_t cnt = 0;
+    {
+        uint32_t i = si, j = sj;
+        for (uint32_t q = 0; q <= SUB; ++q) {
+            if (i < ei || j < ej) {
+                const uint64_t a = i < ei ? XA[i] : PAD, b = j < ej ? XB[j] : PAD;
+                if (a < b) { ++cnt; ++i; }
+                else if (b < a) { ++cnt; ++j; }
+                else { ++i; ++j; }
+            }
+        }
+    }
+    uint32_t total;
+    const uint32_t off = block_excl_scan(L.ws[WS_SORT], cnt, total);
+    // decoupled look-back by wave 0: 64 predecessors per step; the nearest
+    // inclusive status ends it, a missing one closer than that is waited for
+    bool ok = true;
+    if (t < 64) {
+        const uint32_t lane = t;
+        uint64_t excl = 0;
+        if (p == 0) {
+            if (lane == 0) st_rlx64(&J.stat[0], ST_INC | total);
+        } else {
+            if (lane == 0) st_rlx64(&J.stat[p], ST_AGG | total);
+            int64_t q = (int64_t)p - 1;  // the window is q, q - 1, ..., q - 63
+            uint32_t spin = 0;
+            for (;;) {
+                const int64_t r = q - (int64_t)lane;
+                const uint64_t w = r >= 0 ? ld_rlx64(&J.stat[r]) : ST_INC;  // before part 0: an empty prefix
+                const uint64_t inc = __ballot((w & ~ST_VAL) == ST_INC), miss = __ballot(w == 0);
+                const uint32_t first = inc ? (uint32_t)__builtin_ctzll(inc) : 64u;
+                const uint64_t below = first == 64 ? ~0ull : ((2ull << first) - 1);  // lanes 0 .. first
+                if (miss & below) {
+                    if (++spin > WAIT_SPIN) {
+                        ok = false;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                uint64_t v = ((below >> lane) & 1) ? (w & ST_VAL) : 0;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) v += lane_xor64(v, (uint32_t)d);
+                excl += v;
+                if (first < 64) break;
+                q -= 64;
+            }
+            if (lane == 0) {
+                if (ok) st_rlx64(&J.stat[p], ST_INC | (excl + total));
+                else atomicOr(flags, FLAG_GUARD);
+            }
+        }
+        if (lane == 0) {
+            L.u64s[0] = excl;
+            L.ints[0] = ok ? 1 : 0;
+        }
+    }
+    // output stage: surv .. flag (src may hold a round's new keys while its
+    // column flushes pend)
+    uint64_t* O = &L.surv[0];
+    {
+        uint32_t i = si, j = sj, o = off;
+        for (uint32_t q = 0; q <= SUB; ++q) {
+            if (i < ei || j < ej) {
+                const uint64_t a = i < ei ? XA[i] : PAD, b = j < ej ? XB[j] : PAD;
+                if (a < b) { O[o++] = a; ++i; }
+                else if (b < a) { O[o++] = b; ++j; }
+                else { ++i; ++j; }
+            }
+        }
+    }
+    __syncthreads();
+    const uint64_t base = L.u64s[0];
+    ok = L.ints[0] != 0;
+    if (J.coh) {
+        for (uint32_t q = t; q < total; q += WB) st_rlx64(J.out + base + q, O[q]);
+        wait_stores();  // complete before the part is counted as done
+    } else {
+        for (uint32_t q = t; q < total; q += WB) J.out[base + q] = O[q];
+    }
+    __syncthreads();
+    return ok;
+}
+
+__device__ inline uint64_t* board_slot(unsigned long long* ctrs, int s) { return (uint64_t*)ctrs + BOARD_BASE + s * BSLOT; }
+
+// low[0..na) ^ b (nb keys stored decreasing) -> tmp by parts, with idle
+// workgroups helping when a board slot is free. Returns the output length, or
+// ~0u when a wait ran out.
+__device__ __noinline__ uint32_t coop_merge(WideShared& L, unsigned long long* ctrs, uint32_t* flags, const uint64_t* b,
+                                            uint32_t span, const uint64_t* low, uint32_t na, uint32_t nb, uint64_t* tmp,
+                                            uint64_t* stat, uint64_t* X) {
+    const uint32_t t = threadIdx.x;
+    Job J;
+    J.a = low;
+    J.na = na;
+    J.b = b;
+    J.nb = nb;
+    J.out = tmp;
+    J.stat = stat;
+    J.span = span;
+    J.coh = 0;
+    J.nparts = (uint32_t)((na + (uint64_t)nb + J.span - 1) / J.span);
+    if (t == 0) atomicAdd(&ctrs[COOP_MERGES], 1ull);
+    for (uint32_t q = t; q < J.nparts; q += WB) st_rlx64(&stat[q], 0);
+    // every wave: its stores (low, the staged B, the cleared statuses) are
+    // complete and written back before the job opens (a barrier waits for LDS
+    // operations only)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (t == 0) {
+        int slot = -1;
+        for (int k = 0; k < NJ; ++k) {
+            const int q = (int)((blockIdx.x + k) % NJ);
+            if (atomicCAS((unsigned long long*)&board_slot(ctrs, q)[2], 0ull, 1ull) == 0ull) {
+                slot = q;
+                break;
+            }
+        }
+        if (slot >= 0) {
+            uint64_t* B = board_slot(ctrs, slot);
+            const uint64_t seq = (ld_rlx64(&B[0]) >> 32) + 1;  // odd: open
+            st_rlx64(&B[1], 0);
+            st_rlx64(&B[3], (seq << 32) | J.nparts);
+            st_rlx64(&B[4], (uint64_t)J.a);
+            st_rlx64(&B[5], J.na);
+            st_rlx64(&B[6], (uint64_t)J.b);
+            st_rlx64(&B[7], J.nb);
+            st_rlx64(&B[8], (uint64_t)J.out);
+            st_rlx64(&B[9], (uint64_t)J.stat);
+            st_rlx64(&B[10], J.span);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            atomicExch((unsigned long long*)&B[0], (unsigned long long)(seq << 32));
+            atomicAdd(&ctrs[OPEN_JOBS], 1ull);
+        }
+        L.ints[1] = slot;
+    }
+    __syncthreads();
+    const int slot = L.ints[1];
+    __syncthreads();
+    uint64_t* B = slot >= 0 ? board_slot(ctrs, slot) : nullptr;
+    bool ok = true;
+    for (uint32_t next = 0;;) {
+        if (t == 0) {
+            uint32_t k = next++;
+            if (B) k = (uint32_t)atomicAdd((unsigned long long*)&B[0], 1ull);
+            L.ints[2] = (int)min(k, J.nparts);
+        }
+        __syncthreads();
+        const uint32_t k = (uint32_t)L.ints[2];
+        __syncthreads();
+        if (k >= J.nparts) break;
+        ok = merge_part(L, J, k, flags, X) && ok;
+        if (B && t == 0) atomicAdd((unsigned long long*)&B[1], 1ull);
+    }
+    if (t == 0 && B) {
+        // every part taken by a helper ends: wait for them, then close the job
+        for (uint32_t spin = 0; ld_rlx64(&B[1]) < J.nparts; ++spin) {
+            if (spin > WAIT_SPIN) {
+                atomicOr(flags, FLAG_GUARD);
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        const uint64_t seq = ld_rlx64(&B[0]) >> 32;
+        atomicExch((unsigned long long*)&B[0], (unsigned long long)((seq + 1) << 32));  // even: closed
+        atomicAdd(&ctrs[OPEN_JOBS], ~0ull);
+        atomicExch((unsigned long long*)&B[2], 0ull);
+    }
+    if (t == 0) L.ints[3] = ok ? (int)(uint32_t)(ld_rlx64(&stat[J.nparts - 1]) & ST_VAL) : -1;
+    __syncthreads();
+    if (B) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the helpers' output, before it is read
+    const int r = L.ints[3];
+    __syncthreads();
+    return r < 0 ? ~0u : (uint32_t)r;
+}
+
+// Take parts of open jobs until the pass has no column left in work (or
+// nothing to take for a long time, after which helping stops).
+__device__ __noinline__ void help(WideShared& L, unsigned long long* ctrs, int64_t nwork, uint32_t* flags) {
+    const uint32_t t = threadIdx.x;
+    for (uint32_t idle = 0;;) {
+        if (t == 0) L.ints[4] = ld_rlx64((const uint64_t*)&ctrs[OPEN_JOBS]) != 0;
+        __syncthreads();
+        const bool any = L.ints[4] != 0;
+        __syncthreads();
+        if (!any) {
+            if (t == 0)
+                L.ints[5] = ld_rlx64((const uint64_t*)&ctrs[C_NEXT]) >= (uint64_t)nwork &&
+                            ld_rlx64((const uint64_t*)&ctrs[C_ACTIVE]) == 0;
+            __syncthreads();
+            const bool fin = L.ints[5] != 0;
+            __syncthreads();
+            if (fin || ++idle > HELP_SPIN) break;
+            __builtin_amdgcn_s_sleep(32);
+            continue;
+        }
+        if (t < 64) {
+            const int s = (int)((t + blockIdx.x) % NJ);
+            const uint64_t* B = board_slot(ctrs, s);
+            const uint64_t c = ld_rlx64(&B[0]), sp = ld_rlx64(&B[3]);
+            const bool cand = ((c >> 32) & 1) && (c >> 32) == (sp >> 32) && (uint32_t)c < (uint32_t)sp;
+            const uint64_t bal = __ballot(cand);
+            if (t == 0) {
+                int part = -1, slot = -1, done = 0;
+                if (bal) {
+                    slot = (int)((__builtin_ctzll(bal) + blockIdx.x) % NJ);
+                    uint64_t* Bs = board_slot(ctrs, slot);
+                    const uint64_t r = atomicAdd((unsigned long long*)&Bs[0], 1ull);
+                    if ((r >> 32) & 1) {
+                        const uint64_t sp2 = ld_rlx64(&Bs[3]);
+                        if ((sp2 >> 32) == (r >> 32) && (uint32_t)r < (uint32_t)sp2) {
+                            part = (int)(uint32_t)r;
+                            for (int q = 0; q < 12; ++q) L.job[q] = ld_rlx64(&Bs[q]);
+                        }
+                    }
+                }
+                L.ints[0] = part;
+                L.ints[1] = slot;
+                L.ints[2] = done;
+            }
+        }
+        __syncthreads();
+        const int part = L.ints[0], slot = L.ints[1], done = L.ints[2];
+        Job J;
+        if (part >= 0) {
+            J.a = (const uint64_t*)L.job[4];
+            J.na = L.job[5];
+            J.b = (const uint64_t*)L.job[6];
+            J.nb = L.job[7];
+            J.out = (uint64_t*)L.job[8];
+            J.stat = (uint64_t*)L.job[9];
+            J.span = (uint32_t)L.job[10];
+            J.nparts = (uint32_t)L.job[3];
+            J.coh = 1;
+        }
+        __syncthreads();
+        if (part >= 0) {
+            merge_part(L, J, (uint32_t)part, flags, L.top[0]);
+            if (t == 0) {  // the part's coherent stores are complete (merge_part waited)
+                atomicAdd((unsigned long long*)&board_slot(ctrs, slot)[1], 1ull);
+                atomicAdd(&ctrs[HELPED_PARTS], 1ull);
+            }
+            idle = 0;
+            continue;
+        }
+        if (done || ++idle > HELP_SPIN) break;
+        __builtin_amdgcn_s_sleep(4);
+    }
+}
+
 // Boundary ^= the cached boundary stored decreasingly at P.heap[aoff ..
 // aoff + alen), by one merge of the whole column: pend is flushed, the top
 // is appended to low, and low and the cached boundary are merged into tmp,
@@ -1178,10 +1605,10 @@ __device__ __forceinline__ uint64_t save_col(const D1K& P, WideShared& L, Col& C
 // last keys, so equal keys are always in the same step and every step
 // consumes a full segment of one side. Adding a long boundary in NW-key
 // chunks instead rewrites the low part once per chunk.
-__device__ __forceinline__ void add_long(const D1K& P, WideShared& L, Col& C, uint64_t*& low, uint64_t*& tmp, const uint64_t* pend,
-                         uint64_t aoff, uint32_t alen, unsigned long long& moved) {
+__device__ __forceinline__ bool add_long(const D1K& P, WideShared& L, Col& C, uint64_t*& low, uint64_t*& tmp, uint64_t* pend,
+                         uint64_t* stat, uint64_t aoff, uint32_t alen, unsigned long long& moved) {
     const uint32_t t = threadIdx.x;
-    flush(L, C, low, pend, tmp, moved);
+    flush(P, L, C, low, pend, tmp, stat, moved);
     {
         const uint64_t* T = L.top[C.cur];
         for (uint32_t i = t; i < C.nt; i += WB) low[C.nl + i] = T[i];
@@ -1189,6 +1616,34 @@ __device__ __forceinline__ void add_long(const D1K& P, WideShared& L, Col& C, ui
         C.nt = 0;
     }
     __syncthreads();
+    // a long merge is split into parts when other workgroups may help: the
+    // pass has dedicated helpers, or its queue of columns is exhausted
+    if ((uint64_t)C.nl + alen >= P.coop_min && coop_possible(P)) {
+        const uint64_t* b = P.heap + aoff;
+        uint32_t nb = alen;
+        if (alen <= (uint32_t)NW) {
+            // possibly a lane pass's unsorted copy: sorted and cancelled, then
+            // staged decreasing in pend (empty after the flush above)
+            for (uint32_t k = t; k < alen; k += WB) L.raw[k] = ld_rlx64(P.heap + aoff + k);
+            __syncthreads();
+            nb = sort_cancel(L, alen, L.src);
+            // (coherent stores: the parts read B with coherent loads)
+            for (uint32_t k = t; k < nb; k += WB) st_rlx64(pend + (nb - 1 - k), L.src[k]);
+            __syncthreads();
+            b = pend;
+        }
+        moved += C.nl + alen;
+        if (nb == 0) return true;  // everything cancelled
+        const uint32_t out = coop_merge(L, P.ctrs, P.flags, b, P.part_span, low, C.nl, nb, tmp, stat, L.top[0]);
+        if (out == ~0u) return false;
+        uint64_t* sw = low;
+        low = tmp;
+        tmp = sw;
+        C.nl = out;
+        C.lmax = out ? low[out - 1] : 0;
+        __syncthreads();
+        return true;
+    }
     // a boundary of up to NW entries may be a lane pass's unsorted copy: it is
     // sorted and cancelled into L.src once; a longer one is stored decreasing
     const bool small = alen <= (uint32_t)NW;
@@ -1237,18 +1692,24 @@ __device__ __forceinline__ void add_long(const D1K& P, WideShared& L, Col& C, ui
     C.nl = out;
     C.lmax = out ? low[out - 1] : 0;
     __syncthreads();
+    return true;
 }
 
-__global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
+__global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
     __shared__ WideShared L;
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
-    uint64_t* low = P.scratch + (int64_t)blockIdx.x * (2 * P.K + PCAP);
+    // per column slot: low, tmp, pend, and the part statuses of cooperative merges
+    const int64_t slot_words = 2 * P.K + PCAP + P.K / P.part_span + 2;
+    uint64_t* low = P.scratch + (int64_t)blockIdx.x * slot_words;
     uint64_t* tmp = low + P.K;
     uint64_t* pend = tmp + P.K;
+    uint64_t* stat = pend + PCAP;
     const int64_t V = P.g.V;
     unsigned long long steps = 0, evictions = 0, adds = 0, rounds = 0, expanded = 0, moved = 0, longs = 0;
+    unsigned long long r_stop = 0, r_cap = 0, r_taken = 0;  // rounds ended at an edge / by the merge list; entries taken
     for (;;) {
+        if ((int64_t)blockIdx.x >= P.nslots) break;  // a helper only
         if (t == 0) L.u64s[0] = atomicAdd(&P.ctrs[C_NEXT], 1ull);
         __syncthreads();
         const uint64_t next = L.u64s[0];
@@ -1280,6 +1741,7 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
                 if (t == 0) atomicOr(P.flags, FLAG_WORK);
                 break;
             }
+            if (t == 0) atomicAdd(&P.ctrs[C_ACTIVE], 1ull);
             load_col(L, C, low, P.heap + off, n0);
         }
         bool stop = false;
@@ -1293,7 +1755,7 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
             ++steps;
             if (C.n() == 0) break;  // zero column
             if (C.nt < (uint32_t)WB && (C.nl > 0 || C.np > 0)) {
-                refill(L, C, low, pend, tmp, moved);
+                refill(P, L, C, low, pend, tmp, stat, moved);
                 lap(9);
                 if (C.n() == 0) break;  // everything cancelled in the flush
             }
@@ -1448,7 +1910,7 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
                 ++rounds;
                 if ((int64_t)(C.n() - stop_at) + m > P.K) {
                     // no room: save the column unchanged for the next pass
-                    const uint64_t off = save_col(P, L, C, low, pend, tmp, moved);
+                    const uint64_t off = save_col(P, L, C, low, pend, stat, tmp, moved);
                     if (off == PAD) {
                         if (t == 0) atomicOr(P.flags, FLAG_HEAP);
                         stop = true;
@@ -1457,8 +1919,11 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
                     if (t == 0) defer_column(P, c, off, C.n());
                     break;
                 }
+                r_stop += stop0 < k ? 1 : 0;
+                r_cap += stop_at < stop0 ? 1 : 0;
+                r_taken += stop_at;
                 C.nt -= stop_at;  // the window entries above the stop leave
-                merge_col(L, C, low, pend, m, tmp, moved, ph[4], ph[5], tp);
+                merge_col(P, L, C, low, pend, stat, m, tmp, moved, ph[4], ph[5], tp);
                 nmax = max(nmax, C.n());
                 continue;
             }
@@ -1493,7 +1958,7 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
                 break;
             }
             if (action == 1) {
-                const uint64_t off = save_col(P, L, C, low, pend, tmp, moved);
+                const uint64_t off = save_col(P, L, C, low, pend, stat, tmp, moved);
                 const uint32_t n = C.n();
                 if (off == PAD) {
                     if (t == 0) atomicOr(P.flags, FLAG_HEAP);
@@ -1547,7 +2012,7 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
             const uint32_t alen = (uint32_t)(b & 0xFFFFFF);
             if ((int64_t)C.n() + alen > P.K) {
                 // the sum might not fit: hand the column, unchanged, to the next pass
-                const uint64_t off = save_col(P, L, C, low, pend, tmp, moved);
+                const uint64_t off = save_col(P, L, C, low, pend, stat, tmp, moved);
                 if (off == PAD) {
                     if (t == 0) atomicOr(P.flags, FLAG_HEAP);
                     stop = true;
@@ -1559,7 +2024,10 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
             ++adds;
             if (alen > P.long_add) {
                 ++longs;
-                add_long(P, L, C, low, tmp, pend, aoff, alen, moved);
+                if (!add_long(P, L, C, low, tmp, pend, stat, aoff, alen, moved)) {
+                    stop = true;
+                    break;
+                }
                 nmax = max(nmax, C.n());
                 lap(7);
                 continue;
@@ -1569,7 +2037,7 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
                 __syncthreads();
                 const uint32_t m = sort_cancel(L, alen, L.src);
                 uint64_t tq = 0, u0 = 0, u1 = 0;
-                merge_col(L, C, low, pend, m, tmp, moved, u0, u1, tq);
+                merge_col(P, L, C, low, pend, stat, m, tmp, moved, u0, u1, tq);
                 nmax = max(nmax, C.n());
                 lap(7);
                 continue;
@@ -1590,13 +2058,14 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
                 __syncthreads();
                 uint64_t tq = 0;
                 uint64_t u0 = 0, u1 = 0;
-                merge_col(L, C, low, pend, m, tmp, moved, u0, u1, tq);
+                merge_col(P, L, C, low, pend, stat, m, tmp, moved, u0, u1, tq);
             }
             nmax = max(nmax, C.n());
             lap(7);
         }
         __syncthreads();
         if (t == 0) {
+            atomicAdd(&P.ctrs[C_ACTIVE], ~0ull);  // this column is done
             const uint64_t dt = __builtin_amdgcn_s_memrealtime() - t0;
             atomicMax(&P.ctrs[C_TMAX], (unsigned long long)dt);
             atomicAdd(&P.ctrs[C_TSUM], (unsigned long long)dt);
@@ -1612,6 +2081,7 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
         }
         if (stop) break;
     }
+    help(L, P.ctrs, P.nwork, P.flags);
     if (expanded) atomicAdd(&P.ctrs[C_EXPANDED], expanded);
     if (t == 0) {
         atomicAdd(&P.ctrs[C_STEPS], steps);
@@ -1620,6 +2090,9 @@ __global__ __launch_bounds__(WB) void k_d1_wide(D1K P) {
         atomicAdd(&P.ctrs[C_ROUNDS], rounds);
         atomicAdd(&P.ctrs[C_MOVED], moved);
         atomicAdd(&P.ctrs[C_LONG], longs);
+        atomicAdd(&P.ctrs[C_RSTOP], r_stop);
+        atomicAdd(&P.ctrs[C_RCAP], r_cap);
+        atomicAdd(&P.ctrs[C_RTAKEN], r_taken);
     }
 }
 
@@ -1806,17 +2279,18 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         err = std::string("D1: cannot allocate ") + what;
         return -3;  // DMS_E_NOMEM
     };
-    const size_t ctr_bytes = 8 * (SEG_BASE + SEG_STRIDE * NSEG);
+    const size_t ctr_bytes = 8 * (size_t)N_CTR_WORDS;
     if (!s.ctrs && hipMalloc(&s.ctrs, ctr_bytes) != hipSuccess) return oom("counters");
     if (grow(s.colflag, s.colflag_cap, 4 * (m2 + 1), s.bytes, s.limit)) return oom("column flags");
     if (grow(s.cols, s.cols_cap, 4 * (m2 + 1), s.bytes, s.limit)) return oom("columns");
     if (grow(s.scanpart, s.scanpart_cap, 4 * scan_part_size(m2 + 1), s.bytes, s.limit)) return oom("scan");
     if (grow(s.owner1, s.owner1_cap, 4 * 7 * V, s.bytes, s.limit)) return oom("owners");
     for (int d = 0; d < 6; ++d) s.stats[d] = 0;
-    for (int d = 0; d < 5; ++d) s.pass_work[d] = s.pass_us[d] = 0;
+    for (int d = 0; d < MAX_PASSES; ++d) s.pass_work[d] = s.pass_us[d] = 0;
     for (int d = 0; d < 4; ++d) s.wide[d] = 0;
     for (int d = 0; d < 6; ++d) s.wide_t[d] = 0;
     for (int d = 0; d < 12; ++d) s.wide_ph[d] = 0;
+    s.coop[0] = s.coop[1] = 0;
     // unpaired 2-saddles, ascending
     uint32_t* flag = (uint32_t*)s.colflag;
     uint32_t* cols = (uint32_t*)s.cols;
@@ -1869,31 +2343,55 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         int cur = 0;
         bool overflow = false;
         unsigned long long hc[N_CTRS] = {0};
-        // pass plan: thread-per-column with heaps of plan_k keys (in LDS, then in
-        // global scratch), then one workgroup per column with boundaries of up to
-        // plan_k entries (lengths stay below 2^24: the cached length field)
-        int64_t plan_k[MAX_PASSES] = {LDS_K, LDS_K2, (int64_t)1 << 15, (int64_t)1 << 20, ((int64_t)1 << 24) - 1024};
-        // lane passes: as many lanes as the LDS heaps leave resident (160 KB
-        // per CU: 4 workgroups of 256 lanes x 20 keys, or 6 of 64 lanes x 48
-        // keys); workgroup passes: workgroups
-        int64_t plan_t[MAX_PASSES] = {256 * 4 * 256, 256 * 6 * 64, 1024, 512, 64};
-        const int plan_db[MAX_PASSES] = {256, 64, WB, WB, WB};
-        uint32_t long_add = LONG_ADD;
-        const int lane_passes = 2;  // passes 0 and 1 are thread-per-column
+        // pass plan: thread-per-column with heaps of k keys (lane passes, in LDS
+        // or in global scratch), then one workgroup per column with boundaries
+        // of up to k entries (lengths stay below 2^24: the cached length field).
+        // t = lanes or workgroups: as many lanes as the LDS heaps leave resident
+        // (160 KB per CU: 4 workgroups of 256 lanes x 20 keys, or 6 of 64 lanes x
+        // 48 keys).
+        PassPlan plan[MAX_PASSES] = {
+            {LDS_K, 256 * 4 * 256, 256, true, true},
+            {LDS_K2, 256 * 6 * 64, 64, true, true},
+            {(int64_t)1 << 15, 1024, WB, false, false},
+            {(int64_t)1 << 20, 512, WB, false, false},
+            {((int64_t)1 << 24) - 1024, 64, WB, false, false},
+            {0, 0, 0, false, false},
+        };
+        uint32_t long_add = LONG_ADD, part_span = PART_SPAN;
+        uint64_t coop_min = COOP_MIN;
+        int coop_always = 0;
+        uint32_t pcap = PCAP;
         if (in.small_passes) {  // debug option: tiny capacities, every pass used
-            plan_k[0] = 3;
-            plan_k[1] = 4;
-            plan_k[2] = 24;
+            plan[0].k = 3;
+            plan[1].k = 4;
+            plan[2].k = 24;
             long_add = 2;
+            part_span = 40;
+            coop_min = 4;
+            coop_always = 1;
+            pcap = 8;
+        }
+        // workgroup passes run at least two workgroups per compute unit: the
+        // ones beyond the column slots only help with long merges
+        int ncu = 256;
+        {
+            int dev = 0;
+            if (hipGetDevice(&dev) == hipSuccess) {
+                int v = 0;
+                if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+                    ncu = v;
+            }
         }
         for (int pass = 0; pass < MAX_PASSES && nwork > 0; ++pass) {
-            const int64_t K = plan_k[pass];
+            const int64_t K = plan[pass].k;
             if (K == 0) break;
-            const int64_t T = std::max<int64_t>(1, std::min<int64_t>(nwork, plan_t[pass]));
+            const int64_t T = std::max<int64_t>(1, std::min<int64_t>(nwork, plan[pass].t));
             const auto t_pass = std::chrono::steady_clock::now();
-            const bool lane_pass = pass < lane_passes;
-            const bool in_lds = lane_pass;
-            const size_t need = in_lds ? 8 : lane_pass ? (size_t)8 * T * K : (size_t)8 * T * (2 * K + PCAP);
+            const bool lane_pass = plan[pass].lane;
+            const bool in_lds = plan[pass].lds;
+            const size_t need = in_lds      ? 8
+                                : lane_pass ? (size_t)8 * T * K
+                                            : (size_t)8 * T * (2 * K + PCAP + K / part_span + 2);
             if (grow(s.scratch, s.scratch_cap, need, s.bytes, s.limit)) return oom("working boundaries");
             D1K P;
             P.g = in.g;
@@ -1920,6 +2418,11 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             P.nthreads = T;
             P.lds = in_lds ? 1 : 0;
             P.long_add = long_add;
+            P.nslots = T;
+            P.part_span = part_span;
+            P.coop_min = coop_min;
+            P.coop_always = coop_always;
+            P.pcap = pcap;
             P.ctrs = (unsigned long long*)s.ctrs;
             P.flags = in.flags;
             // fresh work cursor, deferral count and work counters for this pass
@@ -1928,10 +2431,10 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
                 return -5;
             }
             if (lane_pass)
-                hipLaunchKernelGGL(k_d1, dim3((unsigned)((T + plan_db[pass] - 1) / plan_db[pass])),
-                                   dim3(plan_db[pass]), in_lds ? (size_t)8 * plan_db[pass] * K : 0, st, P);
+                hipLaunchKernelGGL(k_d1, dim3((unsigned)((T + plan[pass].db - 1) / plan[pass].db)),
+                                   dim3(plan[pass].db), in_lds ? (size_t)8 * plan[pass].db * K : 0, st, P);
             else
-                hipLaunchKernelGGL(k_d1_wide, dim3((unsigned)T), dim3(WB), 0, st, P);
+                hipLaunchKernelGGL(k_d1_wide, dim3((unsigned)std::max<int64_t>(T, 2 * ncu)), dim3(WB), 0, st, P);
             uint32_t f = 0;
             if (hipMemcpyAsync(&f, in.flags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
                 hipMemcpyAsync(hc, s.ctrs, sizeof(hc), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -1943,11 +2446,25 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
                 err = "D1: consistency check failed";
                 return -7;
             }
-            if (in.log_passes)
+            if (in.log_passes) {
                 std::fprintf(stderr, "[dms] D1 pass %d: %lld columns, heap %lld entries/thread, %.1f ms\n", pass,
                              (long long)nwork, (long long)K,
                              std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_pass)
                                  .count());
+                if (!lane_pass) {
+                    std::fprintf(stderr,
+                                 "[dms]   rounds %llu (at an edge %llu, merge list full %llu, entries %llu), adds %llu "
+                                 "(full merges %llu), keys moved %llu, deferred %llu\n",
+                                 hc[C_ROUNDS], hc[C_RSTOP], hc[C_RCAP], hc[C_RTAKEN], hc[C_ADDS], hc[C_LONG],
+                                 hc[C_MOVED], hc[C_DEFER]);
+                    std::fprintf(stderr,
+                                 "[dms]   longest column %.3f ms, max rounds %llu, max adds %llu, max length %llu, "
+                                 "columns over 1 ms %llu; their us per phase:",
+                                 hc[C_TMAX] / 1e5, hc[C_RMAX], hc[C_AMAX], hc[C_NMAX], hc[C_SLOW]);
+                    for (int i = 0; i < N_PHASE; ++i) std::fprintf(stderr, " %llu", hc[C_PHASE + i] / 100);
+                    std::fprintf(stderr, "\n");
+                }
+            }
             s.pass_work[pass] = (uint64_t)nwork;
             s.pass_us[pass] = (uint64_t)std::chrono::duration_cast<std::chrono::microseconds>(
                                   std::chrono::steady_clock::now() - t_pass)
@@ -1986,6 +2503,15 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             }
             for (int q = 0; q < NSEG; ++q) used += segs[SEG_STRIDE * q];
             hc[C_HEAP] = used;
+            uint64_t coop[3];
+            if (hipMemcpyAsync(coop, (unsigned long long*)s.ctrs + OPEN_JOBS, sizeof(coop), hipMemcpyDeviceToHost,
+                               st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                err = "D1: counter read-back failed";
+                return -5;
+            }
+            s.coop[0] = coop[2];
+            s.coop[1] = coop[1];
         }
         s.stats[4] = hc[C_HEAP];
         s.stats[5] = restart;

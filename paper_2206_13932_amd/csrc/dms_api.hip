@@ -847,6 +847,10 @@ int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap) {
             for (int i = 0; i < 6; ++i) h[23 + i] = ctx->d1.wide_t[i];
             for (int i = 0; i < 12; ++i) h[29 + i] = ctx->d1.wide_ph[i];
             h[41] = ctx->d1.wide[3];
+            h[42] = ctx->d1.pass_work[5];
+            h[43] = ctx->d1.pass_us[5];
+            h[44] = ctx->d1.coop[0];
+            h[45] = ctx->d1.coop[1];
             return bytes;
         }
         case DMS_BUF_D1LEN: {

@@ -244,12 +244,14 @@ def test_parity_d1_every_deferral_pass():
     all D1 passes (LDS heaps of two sizes, then workgroup passes), and every
     cached boundary longer than two entries is added by the full merge; pairs
     must not change, and the cycles published by every kind of pass must be
-    valid generators. A second context without the option, used in between,
+    valid generators. Those full merges are split into parts of 40 merged
+    positions (one cooperative merge per addition, helped by idle workgroups
+    of the pass). A second context without the option, used in between,
     keeps the production plan."""
     torch, dms, ctx = _gpu_ctx()
     ctx.set_option(dms.OPT_D1_SMALL_PASSES, 1)
     plain = dms.Context(0)
-    longs = 0
+    longs = coop = 0
     for name, f in [("noise24", sf.noise((24, 24, 24), 3)),
                     ("smooth40", sf.gaussians((40, 36, 32), 4, k=12, noise_frac=0.01))]:
         print(f"[parity] case=d1_small_passes/{name}", flush=True)
@@ -257,9 +259,11 @@ def test_parity_d1_every_deferral_pass():
         ft = torch.from_numpy(f).cuda()
         out = ctx.diagram(ft)
         st = ctx.debug(dms.BUF_STATS, np.uint64).tolist()
-        print(name, "deferrals", st[7], "passes", st[10:20], "full-merge additions", st[41], flush=True)
+        print(name, "deferrals", st[7], "passes", st[10:20], "full-merge additions", st[41],
+              "cooperative merges", st[44], "helped parts", st[45], flush=True)
         assert st[7] > 0
         longs += st[41]
+        coop += st[44]
         for d in range(3):
             assert np.array_equal(out[d].cpu().numpy(), res.pairs[d]), (name, d)
         off, edges = ctx.d1_generators()
@@ -272,7 +276,7 @@ def test_parity_d1_every_deferral_pass():
         assert pst[7] < st[7], (name, pst[7], st[7])  # the option stays with its context
         for d in range(3):
             assert np.array_equal(ref[d].cpu().numpy(), res.pairs[d]), (name, "plain", d)
-    assert longs > 0
+    assert longs > 0 and coop > 0
     with pytest.raises(dms.DmsError):
         ctx.set_option(99, 1)
     ctx.close()
