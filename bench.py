@@ -37,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # Counters of one gradient-kernel launch on smooth512 (profiles/gradient_hbm_counters_smooth512.md),
 # valid for the kernel sources with this hash only: HBM bytes from FETCH_SIZE (x2 calibration) and
 # WRITE_SIZE, and the VALU wave instructions issued
-GRADIENT_COUNTERS = {"sources_sha256_16": "8c5e16c82ab5aae1", "workload": "smooth512",
-                     "traffic_bytes": 1608969989 + 6572305152, "valu_wave_insts": 29029037958}
+GRADIENT_COUNTERS = {"sources_sha256_16": "bb3d503025448236", "workload": "smooth512",
+                     "traffic_bytes": 1608894976 + 6573797478, "valu_wave_insts": 15859068506}
 # VALU issue ceiling for the plain (non-packed) 32-bit integer and bit operations the gradient
 # kernel runs: the fp64 vector peak, 78.6 TFLOP/s = 2 FLOP x 64 lanes per CU per clock at 256 CUs
 # x 2.4 GHz, i.e. 16-lane SIMDs taking 4 cycles per wave64 instruction: one wave64 instruction
@@ -51,7 +51,7 @@ def gradient_sources_hash():
     import hashlib
     here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2206_13932_amd", "csrc")
     h = hashlib.sha256()
-    for name in ("gradient.hip", "star_tables.h", "dms_device.h"):
+    for name in ("gradient.hip", "lower_star.h", "star_tables.h", "dms_device.h"):
         with open(os.path.join(here, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -291,9 +291,10 @@ def main():
     ap.add_argument("--no-generators", action="store_true", help="skip the 1-cycle generator export")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the transfer-inclusive run, the copy ceiling and the noise512 line")
-    ap.add_argument("--mode", default="diagram", choices=["diagram", "gradient"],
+    ap.add_argument("--mode", default="diagram", choices=["diagram", "gradient", "counters"],
                     help="gradient: time dms_gradient alone and a 1 GiB device copy "
-                         "(the reference kernel for hardware byte counters)")
+                         "(the reference kernel for hardware byte counters); counters: "
+                         "warmup + steps plain dms_diagram calls, then the same copy")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the method's pipeline is built and measured on a single "
@@ -327,6 +328,21 @@ def main():
         gbytes = gradient_algorithmic_bytes(V, ncrit)
         print(json.dumps({"mode": "gradient", "workload": args.workload, "gradient_kernel_ms": round(g_ms, 4),
                           "algorithmic_bytes": int(gbytes), "n_crit": ncrit,
+                          "copy_bytes_each_way": int(src.numel() * 4)}), flush=True)
+        ctx.close()
+        return
+
+    if args.mode == "counters":
+        for i in range(args.warmup + args.steps):
+            ctx.diagram(field)
+            torch.cuda.synchronize()
+            print(f"[bench] diagram {i} ms={ctx.stage_ms()}", file=sys.stderr, flush=True)
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "counters", "workload": args.workload, "stage_ms": ctx.stage_ms(),
                           "copy_bytes_each_way": int(src.numel() * 4)}), flush=True)
         ctx.close()
         return
