@@ -26,6 +26,11 @@ WORKLOADS = {
                       text="256^3 float32, 32 Gaussians + 1% uniform noise, seed 0"),
     "noise256": dict(shape=(256, 256, 256), kind="noise", seed=0,
                      text="256^3 float32 i.i.d. uniform noise, seed 0"),
+    # the resolution of the paper's variant curves (Sec. 9.2), for --ablation
+    "smooth192": dict(shape=(192, 192, 192), kind="gaussians", k=32, r=0.01, seed=0,
+                      text="192^3 float32, 32 Gaussians + 1% uniform noise, seed 0"),
+    "noise192": dict(shape=(192, 192, 192), kind="noise", seed=0,
+                     text="192^3 float32 i.i.d. uniform noise, seed 0"),
     # 2D grids (nz = 1) at the paper's 2D resolution, 4096^2
     "smooth4096_2d": dict(shape=(1, 4096, 4096), kind="gaussians", k=64, r=0.005, seed=0,
                           text="4096^2 float32 (2D), 64 Gaussians + 0.5% uniform noise, seed 0"),
@@ -253,6 +258,50 @@ def workload_bench(name, steps=2, warmup=1):
                  "gradient_kernel"], st)}}
 
 
+def ablation_bench(names=("smooth192", "noise192"), steps=2):
+    """The variant curves of Sec. 9.2 on synthetic fields: D1 (PairCriticalSimplices)
+    with and without the sandwich and with and without boundary caching, each
+    checked to give the plain variant's diagrams. One context per workload (its
+    buffers are sized once); the D1 stage is timed with the library's HIP events
+    (milliseconds, the mean of `steps` calls after one warmup call)."""
+    import numpy as np
+    import torch
+    from paper_2206_13932_amd import dms
+    variants = {"sandwich+cache": [], "no_sandwich": [dms.OPT_D1_NO_SANDWICH], "no_cache": [dms.OPT_D1_NO_CACHE],
+                "neither": [dms.OPT_D1_NO_SANDWICH, dms.OPT_D1_NO_CACHE]}
+    out = {}
+    for name in names:
+        field = torch.from_numpy(make_field(name)).cuda()
+        ctx = dms.Context(0)
+        ref = None
+        rows = {}
+        for v, opts in variants.items():
+            if v == "neither" and WORKLOADS[name]["kind"] == "noise":
+                continue  # both off on noise: over the boundary storage already at 128^3
+            for o in (dms.OPT_D1_NO_SANDWICH, dms.OPT_D1_NO_CACHE):
+                ctx.set_option(o, 1 if o in opts else 0)
+            try:
+                ctx.diagram(field)
+                d1, adds = [], 0
+                for _ in range(steps):
+                    res = ctx.diagram(field)
+                    d1.append(ctx.stage_ms()[4])
+                    adds = int(ctx.debug(dms.BUF_STATS, np.uint64)[6])
+                pairs = [res[d].cpu().numpy() for d in range(3)]
+                if ref is None:
+                    ref = pairs
+                same = all(np.array_equal(a, b) for a, b in zip(pairs, ref))
+                rows[v] = {"d1_ms": round(float(np.mean(d1)), 2), "additions": adds, "same_diagrams": same}
+            except dms.DmsError as e:
+                rows[v] = {"error": str(e)}
+            print(f"[bench] ablation {name} {v}: {rows[v]}", file=sys.stderr, flush=True)
+        ctx.close()
+        del field
+        torch.cuda.empty_cache()
+        out[name] = rows
+    return out
+
+
 def differentiation_bench(n_fields=64, side=96):
     """Forward + backward of the loss sum over D1, D2 of (death - birth)^2 on a
     batch of 96^3 fields (16 Gaussians + 2% noise)."""
@@ -291,6 +340,8 @@ def main():
     ap.add_argument("--no-generators", action="store_true", help="skip the 1-cycle generator export")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the transfer-inclusive run, the copy ceiling and the noise512 line")
+    ap.add_argument("--ablation", action="store_true",
+                    help="only the D1 variant curves (sandwich / caching on and off) on smooth192 and noise192")
     ap.add_argument("--mode", default="diagram", choices=["diagram", "gradient", "counters"],
                     help="gradient: time dms_gradient alone and a 1 GiB device copy "
                          "(the reference kernel for hardware byte counters); counters: "
@@ -304,6 +355,10 @@ def main():
     import numpy as np
     import torch
     from paper_2206_13932_amd import dms
+
+    if args.ablation:
+        print(json.dumps({"mode": "ablation", "unit": "ms (D1 stage)", "curves": ablation_bench()}), flush=True)
+        return
 
     t_gen = time.perf_counter()
     f = make_field(args.workload)

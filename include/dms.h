@@ -268,21 +268,43 @@ enum {
                               additions; additions made by one full merge;
                               the sixth D1 pass (columns, microseconds);
                               cooperative full merges, their parts merged by
-                              helping workgroups                                */
+                              helping workgroups; additions made with the cached
+                              boundary under DMS_OPT_D1_NO_CACHE                */
     DMS_BUF_D1LEN = 9      /* u64 per D1 column: last cached boundary
                               (offset << 24 | length)                             */
 };
 int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap);
 
-/* Debug options of a context (inspection and tests; a new context has all
- * of them 0). They change no result, only how the work is split or logged:
+/* Debug and ablation options of a context (inspection, tests and the
+ * variant measurements of Sec. 9.2; a new context has all of them 0). They
+ * change no result, only how the work is split, logged or how much of it
+ * there is:
  *   DMS_OPT_D1_SMALL_PASSES  value != 0: the D1 passes get tiny capacities
  *       (lane heaps of 3 and 4 keys, first workgroup pass 24 keys, cached
  *       boundaries of more than 2 keys added by full merges), so that small
  *       grids go through every pass of PairCriticalSimplices;
- *   DMS_OPT_LOG_PASSES       value != 0: one line per D1 pass on stderr.
+ *   DMS_OPT_LOG_PASSES       value != 0: one line per D1 pass on stderr;
+ *   DMS_OPT_D1_NO_SANDWICH   value != 0: PairCriticalSimplices without the
+ *       sandwich (Sec. 3): every 2-saddle is a column, also those D2 already
+ *       paired (their columns reduce to zero), and 1-saddles paired by D0 are
+ *       not set aside (they never become a pivot). Defined with
+ *       DMS_VIRTUAL_MAX only: a D1 call without it returns DMS_E_INVAL
+ *       (without the outside node, D2 from the dual union-find is not the
+ *       plain reduction's, so D1 over every 2-saddle would differ);
+ *   DMS_OPT_D1_NO_CACHE      value != 0: PairCriticalSimplices without
+ *       boundary caching (Sec. 4.1(b)): when a column's top is the pivot of an
+ *       earlier column, the boundary of that column's 2-saddle (its three
+ *       edges) is added and reduced again instead of the earlier column's
+ *       cached reduced boundary. In the lock-free reduction that
+ *       re-reduction follows the owners of the moment, which evictions may
+ *       have changed since the earlier column's own reduction, so it can miss
+ *       the pivot: a column re-reduces only below every pivot it re-reduced
+ *       before, and pivots met inside a re-reduction, or one that comes back,
+ *       are added with cached boundaries (counted in DMS_BUF_STATS). The work
+ *       can grow steeply on noisy fields; the kernels' step bounds then end
+ *       the call with DMS_E_INTERNAL.
  * Returns DMS_OK, or DMS_E_INVAL for an unknown option or a NULL ctx. */
-enum { DMS_OPT_D1_SMALL_PASSES = 1, DMS_OPT_LOG_PASSES = 2 };
+enum { DMS_OPT_D1_SMALL_PASSES = 1, DMS_OPT_LOG_PASSES = 2, DMS_OPT_D1_NO_SANDWICH = 3, DMS_OPT_D1_NO_CACHE = 4 };
 int dms_set_option(dms_ctx* ctx, int32_t option, int64_t value);
 
 /* Milliseconds of the last call's stages, measured with HIP events on the

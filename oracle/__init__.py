@@ -28,7 +28,7 @@ _loaded = {}
 
 ORC_RANK, ORC_PARTNER0, ORC_CRIT0 = 0, 1, 5
 ORC_D0, ORC_D1, ORC_D2, ORC_ARCS0, ORC_ARCS2, ORC_TIMES = 9, 10, 11, 12, 13, 14
-ORC_GEN1_OFF, ORC_GEN1_EDGES = 15, 16
+ORC_GEN1_OFF, ORC_GEN1_EDGES, ORC_D1_ADDS = 15, 16, 17
 NTYPES = (1, 7, 12, 6)
 
 
@@ -112,12 +112,19 @@ class OracleResult:
         # gen1_edges[gen1_off[i]:gen1_off[i + 1]] (edge ids, ascending)
         self.gen1_off = get(ORC_GEN1_OFF, np.int64)
         self.gen1_edges = get(ORC_GEN1_EDGES, np.int64)
+        # D1 steps that added an earlier 2-saddle's (cached or own) boundary
+        self.d1_adds = int(get(ORC_D1_ADDS, np.int64)[0])
 
 
-def run(field: np.ndarray, sandwich: bool = True, virtual_max: bool = True) -> OracleResult:
+def run(field: np.ndarray, sandwich: bool = True, virtual_max: bool = True, cache: bool = True) -> OracleResult:
     """Run the whole oracle pipeline on a float32 field shaped [nz, ny, nx].
     sandwich=False: the ablation of Sec. 3, D1 over every critical triangle
-    instead of those D2 left unpaired (the diagrams must not change).
+    instead of those D2 left unpaired (the diagrams must not change); defined
+    with the virtual maximum only (without it the dual union-find's D2 is not
+    the plain reduction's).
+    cache=False: the ablation of Sec. 4.1(b), an earlier 2-saddle's own
+    boundary added and reduced again instead of its cached one (the diagrams
+    must not change; the work can grow steeply).
     virtual_max=False: the optional boundary adjustment of Sec. 5.2 is off
     (the outside is no node of the dual union-find; App. A)."""
     f = np.ascontiguousarray(field, dtype=np.float32)
@@ -125,7 +132,7 @@ def run(field: np.ndarray, sandwich: bool = True, virtual_max: bool = True) -> O
     lib = _lib("oracle")
     h = ctypes.c_void_p()
     err = ctypes.create_string_buffer(512)
-    flags = (0 if sandwich else 1) | (0 if virtual_max else 2)
+    flags = (0 if sandwich else 1) | (0 if virtual_max else 2) | (0 if cache else 4)
     rc = lib.orc_run_opts(nx, ny, nz, _ptr(f), flags, ctypes.byref(h), err, 512)
     if rc != 0:
         raise ValueError(err.value.decode())

@@ -215,6 +215,7 @@ struct Ctx {
     std::map<i64, std::vector<i64>> gen1;
     std::vector<i64> gen1_off, gen1_edges; /* per finite D1 pair, in output order */
     double times[6] = {0, 0, 0, 0, 0, 0};  /* order, gradient, sort, D0+D2, D1, total */
+    i64 d1_adds = 0;                       /* D1 steps that added an earlier 2-saddle's boundary */
     std::string err;
 
     Key key(int dim, i64 id) const {
@@ -543,8 +544,11 @@ void diagram_dual(Ctx& C, int d, std::vector<char>& saddle_paired, std::vector<i
 /* virtual_max = false: D2 left unpaired the 2-saddles whose arcs reached
  * the outside; those that create a 2-cycle reduce to zero here and stay
  * unpaired (classes of infinite persistence, Sec. 6). */
+/* cache = false: the ablation without boundary caching (Sec. 4.1(b)); when
+ * the top is the pivot of an earlier 2-saddle, that 2-saddle's own boundary
+ * is added and reduced again instead of its cached reduced boundary. */
 void diagram1(Ctx& C, const std::vector<char>& edge_paired0, const std::vector<char>& tri_paired2,
-              bool sandwich = true, bool virtual_max = true) {
+              bool sandwich = true, bool virtual_max = true, bool cache = true) {
     typedef std::pair<std::pair<i64, i64>, i64> EK;  /* ((rank max, rank min), edge id) */
     auto ekey = [&](i64 e) {
         Key k = C.key(1, e);
@@ -590,7 +594,13 @@ void diagram1(Ctx& C, const std::vector<char>& edge_paired0, const std::vector<c
                     C.d1.push_back(sigma);
                     break;
                 }
-                for (i64 e : cached.at(ow->second)) toggle(e);
+                if (cache) {
+                    for (i64 e : cached.at(ow->second)) toggle(e);
+                } else {
+                    C.facets(2, ow->second, fs);
+                    for (i64 e : fs) toggle(e);
+                }
+                ++C.d1_adds;
             } else {
                 if ((p & 3) != 2) throw std::runtime_error("D1: pivot edge is paired with a vertex");
                 C.facets(2, p / 4, fs);
@@ -621,7 +631,7 @@ void sort_pairs(std::vector<i64>& p) {
     }
 }
 
-void run(Ctx& C, const float* f, bool sandwich = true, bool virtual_max = true) {
+void run(Ctx& C, const float* f, bool sandwich = true, bool virtual_max = true, bool cache = true) {
     double t0 = now();
     if (!vertex_order(f, C.g.V(), C.rank)) throw std::invalid_argument("NaN in the scalar field");
     double t1 = now();
@@ -635,7 +645,7 @@ void run(Ctx& C, const float* f, bool sandwich = true, bool virtual_max = true) 
     if (flat) diagram_dual(C, 1, e1p, C.d1, virtual_max, virtual_max ? nullptr : &e0);
     else diagram_dual(C, 2, t2p, C.d2, virtual_max);
     double t4 = now();
-    if (!flat) diagram1(C, e0, t2p, sandwich, virtual_max);
+    if (!flat) diagram1(C, e0, t2p, sandwich, virtual_max, cache);
     double t5 = now();
     /* Sec. 6: what stays unpaired is a class of infinite persistence */
     for (size_t k = 0; k < C.crit[0].size(); ++k)
@@ -681,7 +691,8 @@ enum {
     ORC_ARCS0 = 12, ORC_ARCS2 = 13,       /* i64 (a, b, saddle)        */
     ORC_TIMES = 14,        /* f64[6]                                   */
     ORC_GEN1_OFF = 15,     /* i64 offsets of the D1 generators (n1 + 1) */
-    ORC_GEN1_EDGES = 16    /* i64 edge ids of the D1 generators         */
+    ORC_GEN1_EDGES = 16,   /* i64 edge ids of the D1 generators         */
+    ORC_D1_ADDS = 17       /* i64[1] additions of earlier boundaries in D1 */
 };
 
 /* flags bit 0: D1 without the sandwich (the ablation of Sec. 3);
@@ -693,7 +704,11 @@ int orc_run_opts(int64_t nx, int64_t ny, int64_t nz, const float* f, int flags, 
     try {
         if (nx < 2 || ny < 2 || nz < 1)
             throw std::invalid_argument("nx and ny must be >= 2, nz >= 1 (nz = 1: a 2D grid)");
-        run(*C, f, !(flags & 1), !(flags & 2));
+        /* the ablation without the sandwich (Sec. 3) equals the sandwich only
+         * when D2 is the plain reduction's, i.e. with the virtual maximum */
+        if ((flags & 1) && (flags & 2))
+            throw std::invalid_argument("the ablation without the sandwich needs the virtual maximum");
+        run(*C, f, !(flags & 1), !(flags & 2), !(flags & 4));
     } catch (const std::exception& e) {
         if (err && errlen > 0) { std::strncpy(err, e.what(), errlen - 1); err[errlen - 1] = 0; }
         delete C;
@@ -722,6 +737,7 @@ int64_t orc_size(void* h, int what) {
         case ORC_TIMES: return 6;
         case ORC_GEN1_OFF: return (int64_t)C->gen1_off.size();
         case ORC_GEN1_EDGES: return (int64_t)C->gen1_edges.size();
+        case ORC_D1_ADDS: return 1;
     }
     return -1;
 }
@@ -741,6 +757,7 @@ void orc_copy(void* h, int what, void* dst) {
         case ORC_TIMES: std::memcpy(dst, C->times, sizeof(C->times)); break;
         case ORC_GEN1_OFF: cp(C->gen1_off); break;
         case ORC_GEN1_EDGES: cp(C->gen1_edges); break;
+        case ORC_D1_ADDS: std::memcpy(dst, &C->d1_adds, sizeof(i64)); break;
     }
 }
 

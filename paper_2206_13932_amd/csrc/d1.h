@@ -24,6 +24,8 @@ struct D1Inputs {
     uint32_t* flags;
     bool small_passes = false;  // debug: tiny pass capacities, every pass used
     bool log_passes = false;    // debug: one stderr line per pass
+    bool no_sandwich = false;   // ablation: every 2-saddle is a column, no D0 set-aside
+    bool no_cache = false;      // ablation: add earlier owners' 2-saddle boundaries, not their cached ones
 };
 
 struct D1State {
@@ -65,6 +67,8 @@ struct D1State {
     uint64_t wide_ph[12] = {0};
     // cooperative full merges, and their parts merged by helping workgroups
     uint64_t coop[2] = {0, 0};
+    bool all_cols = false;  // last run had every 2-saddle as a column (no sandwich)
+    uint64_t nc_fallbacks = 0;  // ablation without caching: pivots that came back and got the cached boundary
     // per-run data for emission
     GridDev g{};
     const uint32_t* order = nullptr;

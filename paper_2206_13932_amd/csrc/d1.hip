@@ -76,8 +76,25 @@ constexpr int BSLOT = 16;
 constexpr int BOARD_BASE = SEG_BASE + SEG_STRIDE * NSEG;
 // own line: open jobs, then (counted over a run) parts merged by helpers and
 // cooperative merges
-constexpr int OPEN_JOBS = BOARD_BASE + NJ * BSLOT, HELPED_PARTS = OPEN_JOBS + 1, COOP_MERGES = OPEN_JOBS + 2;
+constexpr int OPEN_JOBS = BOARD_BASE + NJ * BSLOT, HELPED_PARTS = OPEN_JOBS + 1, COOP_MERGES = OPEN_JOBS + 2,
+              GUARD_REASON = OPEN_JOBS + 3,  // the first consistency check that failed (one of G_*)
+              NC_FALLBACKS = OPEN_JOBS + 4;  // uncached additions whose pivot came back (ablation)
 constexpr int N_CTR_WORDS = OPEN_JOBS + 16;
+
+// consistency checks of the D1 kernels
+enum : uint32_t { G_STEPS = 1, G_RETRIES, G_KEY, G_VPARTNER, G_D0, G_EVICT_HEAD, G_WSTEPS, G_WRETRIES, G_WTOP,
+                  G_LOOKBACK, G_JOBWAIT, G_COUNT };
+static const char* const kGuardName[G_COUNT] = {
+    "unknown", "a column ran out of steps", "a look-again did not resolve", "a key is no edge",
+    "a vertex's partner edge at the top", "a D0-paired edge at the top", "an evicted column's cached head moved",
+    "a workgroup column ran out of steps", "a workgroup look-again did not resolve",
+    "a workgroup column's top is no critical edge", "a merge part's look-back wait ran out",
+    "a merge job's wait for its parts ran out"};
+// record the first failed check and flag the call
+__device__ inline void guard_fail(unsigned long long* ctrs, uint32_t* flags, uint32_t why) {
+    atomicCAS(&ctrs[GUARD_REASON], 0ull, (unsigned long long)why);
+    atomicOr(flags, FLAG_GUARD);
+}
 
 struct D1K {
     GridDev g;
@@ -110,6 +127,7 @@ struct D1K {
     uint64_t coop_min;  // full merges of at least this many entries are split into parts
     int coop_always;    // split them even when no idle workgroup may help (debug)
     uint32_t pcap;      // pending keys that trigger a flush into low (PCAP; smaller for debugging)
+    int no_cache;       // ablation: add the boundary of an earlier owner's 2-saddle, not its cached one
     unsigned long long* ctrs;
     uint32_t* flags;
 };
@@ -261,6 +279,18 @@ struct Heap {
     }
 };
 
+// keys of the three edges of triangle t (the boundary of a 2-saddle)
+__device__ __forceinline__ void tri_edge_keys(const D1K& P, uint32_t t, uint64_t (&k)[3]) {
+    const int64_t a = t / 12;
+    const int ty = t % 12;
+    const int64_t v1 = a + lin_of_mask(P.g, tri_step(ty, 0));
+    const int64_t v2 = v1 + lin_of_mask(P.g, tri_step(ty, 1));
+    const uint32_t r0 = P.rank[a], r1 = P.rank[v1], r2 = P.rank[v2];
+    k[0] = ekey_r(P.bpr, r0, r1);
+    k[1] = ekey_r(P.bpr, r1, r2);
+    k[2] = ekey_r(P.bpr, r0, r2);
+}
+
 // Reserve len entries of the publication heap, in segment seg or, when it is
 // full, in the following ones; NONE when every segment is full.
 __device__ inline uint64_t heap_alloc(const D1K& P, uint32_t seg, uint64_t len) {
@@ -306,6 +336,7 @@ __device__ inline void defer_column(const D1K& P, uint32_t c, uint64_t off, uint
 // the lane's column, and a lane whose column is done takes the next one at
 // once (one atomic per wavefront for all lanes that need work), so the lanes
 // of a wavefront do not wait for each other's columns.
+template <bool NC>  // NC: the ablation without caching
 __global__ __launch_bounds__(DB) void k_d1(D1K P) {
     extern __shared__ uint64_t lds_heaps[];
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -334,12 +365,14 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
     // keys of the last two edges pushed by an expansion, with their endpoints
     // (va: the endpoint of the higher rank)
     uint64_t hint_key[2] = {NONE, NONE};
+    uint64_t nc_min = NONE;  // ablation without caching: the lowest pivot re-reduced in place
+    uint32_t fallbacks = 0;
     int64_t hint_va[2] = {0, 0}, hint_vb[2] = {0, 0};
 
     // one step of column c: 0 = go on, 1 = the column is done, 2 = error
     auto step = [&]() -> int {
         if (++guard > ((int64_t)1 << 24) || retries > MAX_RETRIES) {
-            atomicOr(P.flags, FLAG_GUARD);
+            guard_fail(P.ctrs, P.flags, retries > MAX_RETRIES ? G_RETRIES : G_STEPS);
             return 2;
         }
         ++steps;
@@ -355,14 +388,14 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
                           : tau == hint_key[1] ? edecode_ids(P.g, P.bpr, tau, hint_va[1], hint_vb[1])
                                                : edecode(P.g, P.order, P.bpr, tau);
         if (e.mask == 0) {  // not an edge: corrupted key
-            atomicOr(P.flags, FLAG_GUARD);
+            guard_fail(P.ctrs, P.flags, G_KEY);
             return 2;
         }
         const uint8_t code = P.G[(int64_t)e.mask * V + e.lo];
         bool defer = false;
         if (code != CODE_CRIT) {
             if (code >= 27) {  // the top of a cycle cannot be a vertex's partner
-                atomicOr(P.flags, FLAG_GUARD);
+                guard_fail(P.ctrs, P.flags, G_VPARTNER);
                 return 2;
             }
             const int64_t w = e.lo + lin27(P.g, code);
@@ -383,7 +416,7 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
         } else {
             const uint32_t o = ld_rlx(&P.owner1[e.id]);
             if (o == OWN_D0) {
-                atomicOr(P.flags, FLAG_GUARD);
+                guard_fail(P.ctrs, P.flags, G_D0);
                 return 2;
             }
             if (o == EMPTY32 || o > c) {
@@ -406,11 +439,12 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
                 const uint64_t* B = P.heap + (bo >> 24);
                 const int64_t bl = (int64_t)(bo & 0xFFFFFF);
                 if (ld_rlx64(&B[0]) != tau) {
-                    atomicOr(P.flags, FLAG_GUARD);
+                    guard_fail(P.ctrs, P.flags, G_EVICT_HEAD);
                     return 2;
                 }
                 c = o;
                 retries = 0;
+                nc_min = NONE;
                 if (bl > H.K) {  // too large for this pass: defer it as it stands
                     defer_column(P, c, bo >> 24, bl);
                     return 1;
@@ -420,23 +454,48 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
                 have = true;  // tau (= B[0]) is its top
                 return 0;
             }
-            // o < c: add the cached boundary of the earlier owner
-            const uint64_t b = ld_rlx64(&P.bndptr[o]);
-            if (b == EMPTY64) {
-                ++retries;
-                return 0;
-            }
-            const uint64_t* B = P.heap + (b >> 24);
-            const int64_t bl = (int64_t)(b & 0xFFFFFF);
-            if (ld_rlx64(&B[0]) != tau) {  // o moved on: look again
-                ++retries;
-                return 0;
+            // o < c: add the cached boundary of the earlier owner, or, in the
+            // ablation without caching, the boundary of o's 2-saddle (its top
+            // is at or above tau), which is then reduced again: tau goes back
+            // into the heap and cancels when that reduction brings it back.
+            // The re-reduction follows the owners of the moment, which
+            // evictions may have changed since o's own reduction, so it can
+            // miss tau; so re-reduction happens only below every pivot
+            // re-reduced before in this column: pivots met inside it, and a
+            // pivot that comes back, get cached boundaries (the uncached
+            // pivots then strictly decrease, and the loop ends).
+            const bool uncached = NC && tau < nc_min;
+            fallbacks += (NC && !uncached) ? 1 : 0;
+            const uint64_t* B = nullptr;
+            int64_t need = 4;
+            if (!uncached) {
+                const uint64_t b = ld_rlx64(&P.bndptr[o]);
+                if (b == EMPTY64) {
+                    ++retries;
+                    return 0;
+                }
+                B = P.heap + (b >> 24);
+                if (ld_rlx64(&B[0]) != tau) {  // o moved on: look again
+                    ++retries;
+                    return 0;
+                }
+                need = (int64_t)(b & 0xFFFFFF) - 1;
             }
             retries = 0;
-            if (H.room(bl - 1)) {
+            if (H.room(need)) {
                 have = false;
                 ++adds;
-                for (int64_t i = 1; i < bl; ++i) H.push(ld_rlx64(&B[i]));
+                if (B) {
+                    for (int64_t i = 1; i <= need; ++i) H.push(ld_rlx64(&B[i]));
+                } else {
+                    uint64_t k3[3];
+                    tri_edge_keys(P, P.cols[o], k3);
+                    nc_min = tau;
+                    H.push(tau);
+                    H.push(k3[0]);
+                    H.push(k3[1]);
+                    H.push(k3[2]);
+                }
                 return 0;
             }
             defer = true;
@@ -466,18 +525,15 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
             have = false;
             guard = 0;
             retries = 0;
+            nc_min = NONE;
             active = true;
             if (!P.work) {
                 c = (uint32_t)next;
-                const uint32_t t = P.cols[c];
-                const int64_t a = t / 12;
-                const int ty = t % 12;
-                const int64_t v1 = a + lin_of_mask(P.g, tri_step(ty, 0));
-                const int64_t v2 = v1 + lin_of_mask(P.g, tri_step(ty, 1));
-                const uint32_t r0 = P.rank[a], r1 = P.rank[v1], r2 = P.rank[v2];
-                H.push(ekey_r(P.bpr, r0, r1));
-                H.push(ekey_r(P.bpr, r1, r2));
-                H.push(ekey_r(P.bpr, r0, r2));
+                uint64_t k3[3];
+                tri_edge_keys(P, P.cols[c], k3);
+                H.push(k3[0]);
+                H.push(k3[1]);
+                H.push(k3[2]);
             } else {
                 // resume a deferred column from its saved boundary
                 c = P.work_col[next];
@@ -503,6 +559,7 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
     atomicAdd(&P.ctrs[C_STEPS], steps);
     atomicAdd(&P.ctrs[C_EVICT], evictions);
     atomicAdd(&P.ctrs[C_ADDS], adds);
+    if (fallbacks) atomicAdd(&P.ctrs[NC_FALLBACKS], (unsigned long long)fallbacks);
 }
 
 
@@ -1327,7 +1384,8 @@ __device__ inline void local_bound(const uint64_t* XA, uint32_t la, const uint64
 // Merge part p of job J (by the whole block) into J.out at its scanned offset.
 // Returns false when a look-back wait ran out (the kernel's consistency flag
 // is then set).
-__device__ __noinline__ bool merge_part(WideShared& L, const Job J, uint32_t p, uint32_t* flags, uint64_t* X) {
+__device__ __noinline__ bool merge_part(WideShared& L, const Job J, uint32_t p, unsigned long long* ctrs, uint32_t* flags,
+                                        uint64_t* X) {
     const uint32_t t = threadIdx.x;
     const uint64_t tot = J.na + J.nb;
     const uint64_t d0 = (uint64_t)p * J.span, d1 = min(tot, d0 + J.span);
@@ -1394,7 +1452,7 @@ __device__ __noinline__ bool merge_part(WideShared& L, const Job J, uint32_t p, 
             }
             if (lane == 0) {
                 if (ok) st_rlx64(&J.stat[p], ST_INC | (excl + total));
-                else atomicOr(flags, FLAG_GUARD);
+                else guard_fail(ctrs, flags, G_LOOKBACK);
             }
         }
         if (lane == 0) {
@@ -1497,14 +1555,14 @@ __device__ __noinline__ uint32_t coop_merge(WideShared& L, unsigned long long* c
         const uint32_t k = (uint32_t)L.ints[2];
         __syncthreads();
         if (k >= J.nparts) break;
-        ok = merge_part(L, J, k, flags, X) && ok;
+        ok = merge_part(L, J, k, ctrs, flags, X) && ok;
         if (B && t == 0) atomicAdd((unsigned long long*)&B[1], 1ull);
     }
     if (t == 0 && B) {
         // every part taken by a helper ends: wait for them, then close the job
         for (uint32_t spin = 0; ld_rlx64(&B[1]) < J.nparts; ++spin) {
             if (spin > WAIT_SPIN) {
-                atomicOr(flags, FLAG_GUARD);
+                guard_fail(ctrs, flags, G_JOBWAIT);
                 ok = false;
                 break;
             }
@@ -1584,7 +1642,7 @@ __device__ __noinline__ void help(WideShared& L, unsigned long long* ctrs, int64
         }
         __syncthreads();
         if (part >= 0) {
-            merge_part(L, J, (uint32_t)part, flags, L.top[0]);
+            merge_part(L, J, (uint32_t)part, ctrs, flags, L.top[0]);
             if (t == 0) {  // the part's coherent stores are complete (merge_part waited)
                 atomicAdd((unsigned long long*)&board_slot(ctrs, slot)[1], 1ull);
                 atomicAdd(&ctrs[HELPED_PARTS], 1ull);
@@ -1732,6 +1790,7 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
         };
         const unsigned long long rounds0 = rounds, adds0 = adds;
         uint32_t nmax = 0;
+        uint64_t nc_min = PAD;  // ablation without caching: the lowest pivot re-reduced in place
         Col C;
         C.cur = 0;
         {
@@ -1748,7 +1807,7 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
         uint32_t retries = 0;
         for (int64_t guard = 0;; ++guard) {
             if (guard > ((int64_t)1 << 24)) {
-                if (t == 0) atomicOr(P.flags, FLAG_GUARD);
+                if (t == 0) guard_fail(P.ctrs, P.flags, G_WSTEPS);
                 stop = true;
                 break;
             }
@@ -1762,7 +1821,7 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
             // a look-again (an owner that moved on, a lost claim) resolves once the
             // other column has published; a long run of them means corrupted state
             if (retries > MAX_RETRIES) {
-                if (t == 0) atomicOr(P.flags, FLAG_GUARD);
+                if (t == 0) guard_fail(P.ctrs, P.flags, G_WRETRIES);
                 stop = true;
                 break;
             }
@@ -1798,7 +1857,7 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
                 } else if (code == CODE_CRIT) {
                     if (o == OWN_D0) {
                         cls = 2;
-                    } else if (o != EMPTY32 && o < c && t > 0) {
+                    } else if (o != EMPTY32 && o < c && t > 0 && !P.no_cache) {
                         // (a critical top goes through the owner rule below). The
                         // cached boundary's head is checked against wkey when its
                         // entries are loaded.
@@ -1953,7 +2012,7 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
             __syncthreads();
             lap(6);
             if (action < 0) {
-                if (t == 0) atomicOr(P.flags, FLAG_GUARD);
+                if (t == 0) guard_fail(P.ctrs, P.flags, G_WTOP);
                 stop = true;
                 break;
             }
@@ -1983,6 +2042,7 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
                 if (o == EMPTY32) break;  // settled
                 ++evictions;
                 c = o;
+                nc_min = PAD;
                 const uint32_t bl = (uint32_t)(bo & 0xFFFFFF);
                 const uint64_t boff = bo >> 24;
                 if ((int64_t)bl > P.K) {
@@ -1991,6 +2051,39 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
                 }
                 load_col(L, C, low, P.heap + boff, bl);
                 lap(8);
+                continue;
+            }
+            if (P.no_cache && tau >= nc_min && t == 0) atomicAdd(&P.ctrs[NC_FALLBACKS], 1ull);
+            if (P.no_cache && tau < nc_min) {
+                // ablation without caching: add the boundary of o's 2-saddle
+                // (its three edges, the top at or above tau) and reduce it
+                // again, below every pivot re-reduced before in this column
+                // (the re-reduction follows owners that evictions may have
+                // changed: pivots met inside it, and one that comes back, get
+                // cached boundaries)
+                nc_min = tau;
+                if ((int64_t)C.n() + 3 > P.K) {
+                    const uint64_t off = save_col(P, L, C, low, pend, stat, tmp, moved);
+                    if (off == PAD) {
+                        if (t == 0) atomicOr(P.flags, FLAG_HEAP);
+                        stop = true;
+                        break;
+                    }
+                    if (t == 0) defer_column(P, c, off, C.n());
+                    break;
+                }
+                ++adds;
+                if (t < 3) {
+                    uint64_t k3[3];
+                    tri_edge_keys(P, P.cols[o], k3);
+                    L.raw[t] = t == 0 ? k3[0] : t == 1 ? k3[1] : k3[2];
+                }
+                __syncthreads();
+                const uint32_t m = sort_cancel(L, 3, L.src);
+                uint64_t tq = 0, u0 = 0, u1 = 0;
+                merge_col(P, L, C, low, pend, stat, m, tmp, moved, u0, u1, tq);
+                nmax = max(nmax, C.n());
+                lap(7);
                 continue;
             }
             // action 2: boundary += Boundary(o), merged in chunks (largest keys first)
@@ -2096,20 +2189,22 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
     }
 }
 
+// paired1 null (no sandwich): no 1-saddle is set aside
 __global__ void k_init_owner(const uint32_t* c1, const uint8_t* paired1, int64_t m1, uint32_t* owner1) {
     const int64_t i = (int64_t)blockIdx.x * DB + threadIdx.x;
-    if (i < m1) owner1[c1[i]] = paired1[i] ? OWN_D0 : EMPTY32;
+    if (i < m1) owner1[c1[i]] = (paired1 && paired1[i]) ? OWN_D0 : EMPTY32;
 }
 
+// paired2_desc null (no sandwich): every 2-saddle is a column
 __global__ void k_colflags(const uint8_t* paired2_desc, int64_t m2, uint32_t* flag) {
     const int64_t k = (int64_t)blockIdx.x * DB + threadIdx.x;
-    if (k < m2) flag[k] = paired2_desc[m2 - 1 - k] ? 0u : 1u;
+    if (k < m2) flag[k] = (paired2_desc && paired2_desc[m2 - 1 - k]) ? 0u : 1u;
 }
 
 __global__ void k_compact(const uint32_t* c2, const uint8_t* paired2_desc, const uint32_t* pos, int64_t m2,
                           uint32_t* cols) {
     const int64_t k = (int64_t)blockIdx.x * DB + threadIdx.x;
-    if (k < m2 && !paired2_desc[m2 - 1 - k]) cols[pos[k]] = c2[k];
+    if (k < m2 && !(paired2_desc && paired2_desc[m2 - 1 - k])) cols[pos[k]] = c2[k];
 }
 
 constexpr int EMIT_ITEMS = 16;  // columns per lane of k_emit_pairs: one list atomic per 4096 columns
@@ -2143,11 +2238,14 @@ __global__ void k_emit_ess1(const uint32_t* c1, const uint8_t* paired1, int64_t 
     death[at] = EMPTY32;
 }
 
+// paired2_desc non-null: the columns are every 2-saddle (no sandwich), and
+// those D2 paired are no essential class
 __global__ void k_emit_ess2(GridDev g, const uint32_t* order, int bpr, const uint32_t* cols, int64_t ncols,
-                            const uint64_t* bndptr, const uint64_t* heap, const uint32_t* owner1, uint64_t* key,
-                            uint32_t* death, uint32_t* cnt) {
+                            const uint64_t* bndptr, const uint64_t* heap, const uint32_t* owner1,
+                            const uint8_t* paired2_desc, uint64_t* key, uint32_t* death, uint32_t* cnt) {
     const int64_t c = (int64_t)blockIdx.x * DB + threadIdx.x;
     if (c >= ncols) return;
+    if (paired2_desc && paired2_desc[ncols - 1 - c]) return;
     const uint64_t b = bndptr[c];
     if (b != EMPTY64) {
         const EdgeDec e = edecode(g, order, bpr, heap[b >> 24]);
@@ -2291,12 +2389,16 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
     for (int d = 0; d < 6; ++d) s.wide_t[d] = 0;
     for (int d = 0; d < 12; ++d) s.wide_ph[d] = 0;
     s.coop[0] = s.coop[1] = 0;
-    // unpaired 2-saddles, ascending
+    s.nc_fallbacks = 0;
+    // unpaired 2-saddles (every 2-saddle without the sandwich), ascending
+    const uint8_t* p2 = in.no_sandwich ? nullptr : in.paired2_desc;
+    const uint8_t* p1 = in.no_sandwich ? nullptr : in.paired1;
+    s.all_cols = in.no_sandwich;
     uint32_t* flag = (uint32_t*)s.colflag;
     uint32_t* cols = (uint32_t*)s.cols;
     int64_t ncols = 0;
     if (m2 > 0) {
-        hipLaunchKernelGGL(k_colflags, dim3(nblocks(m2)), dim3(DB), 0, st, in.paired2_desc, m2, flag);
+        hipLaunchKernelGGL(k_colflags, dim3(nblocks(m2)), dim3(DB), 0, st, p2, m2, flag);
         uint32_t* pos = cols;  // scan output; the compacted list goes through flag's buffer
         exclusive_scan_u32(flag, pos, m2, (uint32_t*)s.scanpart, st);
         uint32_t last_pos = 0, last_flag = 0;
@@ -2307,7 +2409,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             return -5;
         }
         ncols = (int64_t)last_pos + last_flag;
-        hipLaunchKernelGGL(k_compact, dim3(nblocks(m2)), dim3(DB), 0, st, in.c2, in.paired2_desc, pos, m2, flag);
+        hipLaunchKernelGGL(k_compact, dim3(nblocks(m2)), dim3(DB), 0, st, in.c2, p2, pos, m2, flag);
         if (ncols > 0 && hipMemcpyAsync(cols, flag, 4 * ncols, hipMemcpyDeviceToDevice, st) != hipSuccess) {
             err = "D1: copy failed";
             return -5;
@@ -2322,7 +2424,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             return oom("boundary heap");
     }
     if (in.m1 > 0)
-        hipLaunchKernelGGL(k_init_owner, dim3(nblocks(in.m1)), dim3(DB), 0, st, in.c1, in.paired1, in.m1,
+        hipLaunchKernelGGL(k_init_owner, dim3(nblocks(in.m1)), dim3(DB), 0, st, in.c1, p1, in.m1,
                            (uint32_t*)s.owner1);
     if (ncols == 0) return 0;
     for (int restart = 0; restart < 4; ++restart) {
@@ -2332,7 +2434,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         }
         fill_u64((uint64_t*)s.bndptr, EMPTY64, ncols, st);
         if (restart > 0 && in.m1 > 0)
-            hipLaunchKernelGGL(k_init_owner, dim3(nblocks(in.m1)), dim3(DB), 0, st, in.c1, in.paired1, in.m1,
+            hipLaunchKernelGGL(k_init_owner, dim3(nblocks(in.m1)), dim3(DB), 0, st, in.c1, p1, in.m1,
                                (uint32_t*)s.owner1);
         uint64_t* q[2] = {(uint64_t*)s.dq, (uint64_t*)s.dq + (ncols + 1)};
         uint32_t* qlen = (uint32_t*)((uint64_t*)s.dq + 2 * (ncols + 1));
@@ -2423,6 +2525,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             P.coop_min = coop_min;
             P.coop_always = coop_always;
             P.pcap = pcap;
+            P.no_cache = in.no_cache ? 1 : 0;
             P.ctrs = (unsigned long long*)s.ctrs;
             P.flags = in.flags;
             // fresh work cursor, deferral count and work counters for this pass
@@ -2431,8 +2534,9 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
                 return -5;
             }
             if (lane_pass)
-                hipLaunchKernelGGL(k_d1, dim3((unsigned)((T + plan[pass].db - 1) / plan[pass].db)),
-                                   dim3(plan[pass].db), in_lds ? (size_t)8 * plan[pass].db * K : 0, st, P);
+                hipLaunchKernelGGL(in.no_cache ? k_d1<true> : k_d1<false>,
+                                   dim3((unsigned)((T + plan[pass].db - 1) / plan[pass].db)), dim3(plan[pass].db),
+                                   in_lds ? (size_t)8 * plan[pass].db * K : 0, st, P);
             else
                 hipLaunchKernelGGL(k_d1_wide, dim3((unsigned)std::max<int64_t>(T, 2 * ncu)), dim3(WB), 0, st, P);
             uint32_t f = 0;
@@ -2443,7 +2547,13 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
                 return -5;
             }
             if (f & FLAG_GUARD) {
-                err = "D1: consistency check failed";
+                unsigned long long why = 0;
+                if (hipMemcpyAsync(&why, (unsigned long long*)s.ctrs + GUARD_REASON, 8, hipMemcpyDeviceToHost, st) !=
+                        hipSuccess ||
+                    hipStreamSynchronize(st) != hipSuccess)
+                    why = 0;
+                err = std::string("D1: consistency check failed (") + kGuardName[why < G_COUNT ? why : 0] +
+                      ", pass " + std::to_string(pass) + ")";
                 return -7;
             }
             if (in.log_passes) {
@@ -2503,7 +2613,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             }
             for (int q = 0; q < NSEG; ++q) used += segs[SEG_STRIDE * q];
             hc[C_HEAP] = used;
-            uint64_t coop[3];
+            uint64_t coop[5];
             if (hipMemcpyAsync(coop, (unsigned long long*)s.ctrs + OPEN_JOBS, sizeof(coop), hipMemcpyDeviceToHost,
                                st) != hipSuccess ||
                 hipStreamSynchronize(st) != hipSuccess) {
@@ -2512,6 +2622,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             }
             s.coop[0] = coop[2];
             s.coop[1] = coop[1];
+            s.nc_fallbacks = coop[4];
         }
         s.stats[4] = hc[C_HEAP];
         s.stats[5] = restart;
@@ -2544,13 +2655,13 @@ void d1_emit(D1State& s, int64_t m1, const uint8_t* paired1, const uint32_t* c1,
 
 void d1_emit_essential2(D1State& s, int64_t m2, const uint8_t* paired2_desc, const uint32_t* c2, uint64_t* key,
                         uint32_t* death, uint32_t* cnt, hipStream_t st) {
-    (void)m2;
-    (void)paired2_desc;
     (void)c2;
+    // without the sandwich the columns are all m2 2-saddles in C2 order
+    const uint8_t* p2 = (s.all_cols && s.ncols == m2) ? paired2_desc : nullptr;
     if (s.ncols > 0)
         hipLaunchKernelGGL(k_emit_ess2, dim3(nblocks(s.ncols)), dim3(DB), 0, st, s.g, s.order, s.bpr,
                            (const uint32_t*)s.cols, s.ncols, (const uint64_t*)s.bndptr, (const uint64_t*)s.heap,
-                           (const uint32_t*)s.owner1, key, death, cnt);
+                           (const uint32_t*)s.owner1, p2, key, death, cnt);
 }
 
 int d1_generators(D1State& s, int64_t* offsets, int64_t cap_off, int64_t* edges, int64_t cap_edges,

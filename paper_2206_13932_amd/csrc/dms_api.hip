@@ -49,6 +49,7 @@ struct dms_ctx {
     // D1
     D1State d1;
     bool opt_d1_small = false, opt_log = false;  // debug options (dms_set_option)
+    bool opt_no_sandwich = false, opt_no_cache = false;  // ablation variants of D1 (dms_set_option)
     bool virtual_max = true;  // DMS_VIRTUAL_MAX of the last gradient call (Sec. 5.2)
     // output staging
     Buf ob, od, okey, ocnt;
@@ -681,6 +682,11 @@ static int run_d1(dms_ctx* ctx) {
         ctx->d1.gen_n = -1;
         return DMS_OK;
     }
+    // Without the virtual maximum, D2 from the dual union-find is not the
+    // plain reduction's D2 (reading of Sec. 5.2 / App. A), so D1 over every
+    // 2-saddle would give other pairs: the ablation is defined with it only.
+    if (ctx->opt_no_sandwich && !ctx->virtual_max)
+        return fail(ctx, DMS_E_INVAL, "DMS_OPT_D1_NO_SANDWICH needs DMS_VIRTUAL_MAX");
     D1Inputs in;
     in.g = ctx->g;
     in.G = P<uint8_t>(ctx->G);
@@ -696,6 +702,8 @@ static int run_d1(dms_ctx* ctx) {
     in.flags = P<uint32_t>(ctx->flags);
     in.small_passes = ctx->opt_d1_small;
     in.log_passes = ctx->opt_log;
+    in.no_sandwich = ctx->opt_no_sandwich;
+    in.no_cache = ctx->opt_no_cache;
     std::string err;
     int r = d1_run(ctx->d1, in, ctx->st, d1_limit(ctx), err);
     if (r != DMS_OK) return fail(ctx, r, err);
@@ -851,6 +859,7 @@ int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap) {
             h[43] = ctx->d1.pass_us[5];
             h[44] = ctx->d1.coop[0];
             h[45] = ctx->d1.coop[1];
+            h[46] = ctx->d1.nc_fallbacks;
             return bytes;
         }
         case DMS_BUF_D1LEN: {
@@ -1165,6 +1174,8 @@ int dms_set_option(dms_ctx* ctx, int32_t option, int64_t value) {
     switch (option) {
         case DMS_OPT_D1_SMALL_PASSES: ctx->opt_d1_small = value != 0; return DMS_OK;
         case DMS_OPT_LOG_PASSES: ctx->opt_log = value != 0; return DMS_OK;
+        case DMS_OPT_D1_NO_SANDWICH: ctx->opt_no_sandwich = value != 0; return DMS_OK;
+        case DMS_OPT_D1_NO_CACHE: ctx->opt_no_cache = value != 0; return DMS_OK;
         default: return fail(ctx, DMS_E_INVAL, "dms_set_option: unknown option");
     }
 }

@@ -283,6 +283,43 @@ def test_parity_d1_every_deferral_pass():
     plain.close()
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("variant", ["no_sandwich", "no_cache", "neither"])
+def test_parity_d1_ablation_variants(variant):
+    """PairCriticalSimplices without the sandwich (every 2-saddle a column,
+    no 1-saddle set aside) and/or without boundary caching (an earlier owner's
+    2-saddle boundary re-reduced) gives the same pairs as the oracle: with the
+    virtual maximum (and without it for the variant without caching; the one
+    without the sandwich is refused there), and through every D1 pass (small
+    capacities)."""
+    torch, dms, ctx = _gpu_ctx()
+    opts = {"no_sandwich": [dms.OPT_D1_NO_SANDWICH], "no_cache": [dms.OPT_D1_NO_CACHE],
+            "neither": [dms.OPT_D1_NO_SANDWICH, dms.OPT_D1_NO_CACHE]}[variant]
+    for o in opts:
+        ctx.set_option(o, 1)
+    cases = [("noise16_s0", SMALL_FIELDS["noise16_s0"](), True), ("smooth20", SMALL_FIELDS["smooth20"](), True),
+             ("ties", SMALL_FIELDS["ties"](), True), ("noise_aniso", SMALL_FIELDS["noise_aniso"](), True),
+             ("noise16_s1 off", SMALL_FIELDS["noise16_s1"](), False), ("infinities off", SMALL_FIELDS["infinities"](), False)]
+    for small in (False, True):
+        ctx.set_option(dms.OPT_D1_SMALL_PASSES, 1 if small else 0)
+        for name, f, vmax in cases:
+            print(f"[ablation] variant={variant} case={name} small={small}", flush=True)
+            ft = torch.from_numpy(f).cuda()
+            if not vmax and variant != "no_cache":
+                # without the virtual maximum the sandwich is part of the mode's
+                # definition: the ablation is refused
+                with pytest.raises(dms.DmsError):
+                    ctx.diagram(ft, flags=0)
+                continue
+            res = oracle.run(f, virtual_max=vmax)
+            out = ctx.diagram(ft, flags=dms.DMS_VIRTUAL_MAX if vmax else 0)
+            for d in range(3):
+                assert np.array_equal(out[d].cpu().numpy(), res.pairs[d]), (variant, name, small, d)
+    st = ctx.debug(dms.BUF_STATS, np.uint64).tolist()
+    assert st[6] > 0  # boundary additions happened
+    ctx.close()
+
+
 # ---- without the virtual maximum on the domain boundary (Sec. 5.2, App. A) ----
 
 OFF_FIELDS = dict(SMALL_FIELDS)

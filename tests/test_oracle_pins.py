@@ -370,3 +370,25 @@ def test_sandwich_does_not_change_d1(field):
         assert np.array_equal(a.pairs[d], b.pairs[d])
     st = oracle.bf_check_cycles(a.shape, a.rank, b.pairs[1][b.pairs[1][:, 1] >= 0], b.gen1_off, b.gen1_edges)
     assert (st == 0).all()
+
+
+@pytest.mark.parametrize("field", [sf.noise((16, 16, 16), 0), sf.gaussians((20, 22, 18), 7, k=8, noise_frac=0.01),
+                                   np.random.default_rng(6).integers(0, 4, size=(9, 8, 7)).astype(np.float32)])
+def test_caching_does_not_change_d1(field):
+    """Sec. 4.1(b): adding an earlier 2-saddle's own boundary and reducing it
+    again gives the pairs of adding its cached reduced boundary, with or
+    without the sandwich; it only takes more additions."""
+    a = oracle.run(field)
+    for sandwich in (True, False):
+        b = oracle.run(field, sandwich=sandwich, cache=False)
+        for d in range(3):
+            assert np.array_equal(a.pairs[d], b.pairs[d]), (sandwich, d)
+        assert b.d1_adds >= oracle.run(field, sandwich=sandwich).d1_adds
+
+
+def test_sandwich_ablation_needs_the_virtual_maximum():
+    """Without the outside node (App. A) D2 from the dual union-find is not
+    the plain reduction's, so D1 over every critical triangle is another
+    computation: the oracle refuses the combination."""
+    with pytest.raises(ValueError):
+        oracle.run(sf.noise((6, 6, 6), 0), sandwich=False, virtual_max=False)
