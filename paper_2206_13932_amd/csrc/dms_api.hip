@@ -28,6 +28,10 @@ enum { EV_START = 0, EV_ORDER, EV_GK, EV_GRAD, EV_SORT, EV_D02, EV_D1, EV_OUT, N
 struct dms_ctx {
     int device = 0;
     hipStream_t st = nullptr;
+    // a second stream of the context's own (default priority) and the events
+    // that fork D0 onto it and join it back: D0 and D2 run concurrently
+    hipStream_t st2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     size_t budget = 0;
     size_t used = 0;
     std::string err;
@@ -386,6 +390,12 @@ void dms_destroy(dms_ctx* ctx) {
     d1_free(ctx->d1);
     for (int i = 0; i < NEV; ++i)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    if (ctx->st2) {
+        (void)hipStreamSynchronize(ctx->st2);
+        (void)hipStreamDestroy(ctx->st2);
+    }
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     delete ctx;
 }
 
@@ -537,15 +547,38 @@ static int run_d0_d2(dms_ctx* ctx) {
     ENSURE(ctx->owner0, 4 * V);
     ENSURE(ctx->bnd0, 8 * m1);
     ENSURE(ctx->paired1, m1);
-    trace_d0(ctx->g, P<uint8_t>(ctx->G), P<uint32_t>(ctx->rank), P<uint32_t>(ctx->cid[1]), P<uint32_t>(ctx->cpos[1]),
-             m1, P<uint32_t>(ctx->na0), P<uint32_t>(ctx->nb0), P<uint32_t>(ctx->flags), next, st);
     ENSURE(ctx->jump0, 8 * V);
-    fill_u32(P<uint32_t>(ctx->owner0), EMPTY32, V, st);
-    fill_u64(P<uint64_t>(ctx->bnd0), EMPTY64, m1, st);
-    fill_u64(P<uint64_t>(ctx->jump0), EMPTY64, V, st);
+    // In 3D, D0 and D2 only share read-only inputs and the error flags until
+    // D1: D0 runs on the context's second stream, concurrently with D2 on the
+    // main one (their tails and gathers overlap). Every buffer of both chains
+    // is sized before the fork, so nothing is freed or allocated while the
+    // second stream runs and no early return leaves it running.
+    hipStream_t d0_st = st;
+    if (!ctx->flat) {
+        ENSURE(ctx->tet2pos, 4 * 6 * V);
+        ENSURE(ctx->na2, 4 * m2);
+        ENSURE(ctx->nb2, 4 * m2);
+        ENSURE(ctx->owner2, 4 * (m3 + 1));
+        ENSURE(ctx->bnd2, 8 * m2);
+        ENSURE(ctx->paired2, m2);
+        ENSURE(ctx->jump2, 8 * (m3 + 1));
+        if (!ctx->st2) {
+            HIPCHK(hipStreamCreateWithFlags(&ctx->st2, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+        }
+        HIPCHK(hipEventRecord(ctx->ev_fork, st));
+        HIPCHK(hipStreamWaitEvent(ctx->st2, ctx->ev_fork, 0));
+        d0_st = ctx->st2;
+    }
+    trace_d0(ctx->g, P<uint8_t>(ctx->G), P<uint32_t>(ctx->rank), P<uint32_t>(ctx->cid[1]), P<uint32_t>(ctx->cpos[1]),
+             m1, P<uint32_t>(ctx->na0), P<uint32_t>(ctx->nb0), P<uint32_t>(ctx->flags), next, d0_st);
+    fill_u32(P<uint32_t>(ctx->owner0), EMPTY32, V, d0_st);
+    fill_u64(P<uint64_t>(ctx->bnd0), EMPTY64, m1, d0_st);
+    fill_u64(P<uint64_t>(ctx->jump0), EMPTY64, V, d0_st);
     reduce_pairs(P<uint32_t>(ctx->na0), P<uint32_t>(ctx->nb0), m1, P<uint32_t>(ctx->owner0), P<uint64_t>(ctx->bnd0),
-                 P<uint64_t>(ctx->jump0), P<uint32_t>(ctx->flags), stats, next + 2, st);
-    settled_columns(P<uint64_t>(ctx->bnd0), P<uint32_t>(ctx->owner0), m1, P<uint8_t>(ctx->paired1), st);
+                 P<uint64_t>(ctx->jump0), P<uint32_t>(ctx->flags), stats, next + 2, d0_st);
+    settled_columns(P<uint64_t>(ctx->bnd0), P<uint32_t>(ctx->owner0), m1, P<uint8_t>(ctx->paired1), d0_st);
     if (ctx->flat) {
         // 2D: the maxima's diagram is D1, from the stable sets of the 1-saddles
         // (Sec. 5.2 one dimension down; no sandwich, Sec. 3); virtual maximum = age 0
@@ -574,23 +607,20 @@ static int run_d0_d2(dms_ctx* ctx) {
         (void)m3;
         return DMS_OK;
     }
-    // D2 (Sec. 5.2), virtual maximum = age 0
-    ENSURE(ctx->tet2pos, 4 * 6 * V);
-    ENSURE(ctx->na2, 4 * m2);
-    ENSURE(ctx->nb2, 4 * m2);
-    ENSURE(ctx->owner2, 4 * (m3 + 1));
-    ENSURE(ctx->bnd2, 8 * m2);
-    ENSURE(ctx->paired2, m2);
+    // D2 (Sec. 5.2), virtual maximum = age 0 (buffers sized before the fork)
     tet_positions(P<uint32_t>(ctx->csorted[3]), m3, P<uint32_t>(ctx->tet2pos), st);
     trace_d2(ctx->g, P<uint8_t>(ctx->G), P<uint32_t>(ctx->tet2pos), P<uint32_t>(ctx->cid[2]), P<uint32_t>(ctx->cpos[2]),
              m2, P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2), P<uint32_t>(ctx->flags), next + 1, st);
-    ENSURE(ctx->jump2, 8 * (m3 + 1));
     fill_u32(P<uint32_t>(ctx->owner2), EMPTY32, m3 + 1, st);
     fill_u64(P<uint64_t>(ctx->bnd2), EMPTY64, m2, st);
     fill_u64(P<uint64_t>(ctx->jump2), EMPTY64, m3 + 1, st);
     reduce_pairs(P<uint32_t>(ctx->na2), P<uint32_t>(ctx->nb2), m2, P<uint32_t>(ctx->owner2), P<uint64_t>(ctx->bnd2),
                  P<uint64_t>(ctx->jump2), P<uint32_t>(ctx->flags), stats + 2, next + 3, st, !ctx->virtual_max);
     settled_columns(P<uint64_t>(ctx->bnd2), P<uint32_t>(ctx->owner2), m2, P<uint8_t>(ctx->paired2), st);
+    if (d0_st != st) {  // D1 needs D0: join the second stream
+        HIPCHK(hipEventRecord(ctx->ev_join, d0_st));
+        HIPCHK(hipStreamWaitEvent(st, ctx->ev_join, 0));
+    }
     (void)m0;
     return DMS_OK;
 }
