@@ -168,6 +168,16 @@ struct EdgeDec {
     int mask;
     uint32_t id;
 };
+// step mask and anchor of the edge {a, b} of the triangulation (vertex ids)
+__device__ inline int edge_mask(const GridDev& g, int64_t a, int64_t b, int64_t& lo) {
+    lo = a < b ? a : b;
+    int64_t d = (a < b ? b : a) - lo;
+    int m = 0;
+    if (d >= g.sz) { m |= 4; d -= g.sz; }
+    if (d >= g.sy) { m |= 2; d -= g.sy; }
+    if (d >= 1) { m |= 1; }
+    return m;
+}
 // the same when the endpoints' vertex ids are known (va of rank ra, vb of rb)
 __device__ inline EdgeDec edecode_ids(const GridDev& g, int bpr, uint64_t key, int64_t va, int64_t vb) {
     EdgeDec e;
@@ -586,6 +596,7 @@ constexpr int TOPCAP = 2048;  // LDS top capacity; also the staging segment of l
 constexpr int TOPKEEP = 1024; // top entries kept after a spill, or loaded by a refill
 constexpr int PCAP = NW;      // pending keys below the top, merged into low in batches
 constexpr uint32_t BATCH_ADD_MAX = 512;  // longest cached boundary added out of order in a round
+constexpr int CHAIN = 6;  // same-star continuation steps of one expansion in a round
 constexpr uint64_t PAD = ~0ull;
 constexpr uint32_t LONG_ADD = 2 * PCAP;  // default of D1K::long_add
 static_assert(TOPKEEP >= WB && TOPKEEP + WB <= TOPCAP, "top refill must fit");
@@ -612,6 +623,7 @@ struct WideShared {
     uint64_t srch[4];   // search ranges of the part bounds, then the bounds
     uint32_t wcount[NWAVE];
     uint64_t job[12];   // the job a helper works on
+    uint32_t nextra;    // keys of a round's same-star continuations, after the entries' own keys
 };
 
 // inclusive prefix sum over the 64 lanes of a wave with DPP row shifts and
@@ -1839,6 +1851,8 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
             // new keys.
             const uint32_t k = min(C.nt, (uint32_t)WB);
             uint64_t wkey = 0, nk0 = PAD, nk1 = PAD, zoff = 0;
+            int64_t cva = 0, cw = 0;  // a regular entry: its higher endpoint and its partner's third vertex
+            uint32_t cra = 0, crw = 0;
             uint32_t nkeys = 0;  // keys this entry contributes when processed
             bool batched = false;
             int cls = 0;  // 0 none/stop, 1 processable, 2 kept (never a pivot)
@@ -1849,18 +1863,22 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
                 const uint8_t code = e.mask ? P.G[(int64_t)e.mask * V + e.lo] : (uint8_t)0xFE;
                 const uint32_t o = e.mask ? ld_rlx(&P.owner1[e.id]) : EMPTY32;
                 if (code < 27) {
-                    const uint32_t rw = P.rank[e.lo + lin27(P.g, code)];
+                    cw = e.lo + lin27(P.g, code);
+                    const uint32_t rw = P.rank[cw];
                     nk0 = ekey_r(P.bpr, e.ra, rw);
                     nk1 = ekey_r(P.bpr, e.rb, rw);
+                    cva = e.va;
+                    cra = e.ra;
+                    crw = rw;
                     nkeys = 2;
                     cls = 1;
                 } else if (code == CODE_CRIT) {
                     if (o == OWN_D0) {
                         cls = 2;
-                    } else if (o != EMPTY32 && o < c && t > 0 && !P.no_cache) {
-                        // (a critical top goes through the owner rule below). The
-                        // cached boundary's head is checked against wkey when its
-                        // entries are loaded.
+                    } else if (o != EMPTY32 && o < c && !P.no_cache) {
+                        // (the top too: its short cached boundary is added in the
+                        // round like the others'). The cached boundary's head is
+                        // checked against wkey when its entries are loaded.
                         const uint64_t bo = ld_rlx64(&P.bndptr[o]);
                         const uint32_t zl = (uint32_t)(bo & 0xFFFFFF) - 1;
                         if (bo != EMPTY64 && zl <= BATCH_ADD_MAX) {
@@ -1886,9 +1904,8 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
             if (lane == 0) L.wstop[wv] = sm ? (uint32_t)(wv * 64 + __builtin_ctzll(sm)) : (uint32_t)WB;
             if (t == 0) {
                 L.ints[0] = cls;
-                L.ints[1] = 0;
-                L.ints[2] = 0;
                 L.ints[3] = 0;
+                L.nextra = 0;
             }
             __syncthreads();
             uint32_t stop0 = WB, before = 0;
@@ -1905,6 +1922,47 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
                 const uint32_t slot = before + inc - need;
                 const bool incl = (uint32_t)t < stop0 && slot + need <= (uint32_t)NW;
                 const bool go = incl && cls == 1;
+                // Keys of the entries before the stop (waves up to the stop's
+                // wave: entries after a wave's first stop need nothing). When
+                // they all fit, every entry above the stop key is processed this
+                // round, and an expansion may go on along its lower star: the
+                // edge {va, w} it leaves is replaced by {w, w'} and {va, w'} via
+                // the partner {va, w, w'} while {va, w} is regular and above the
+                // stop key (up to CHAIN times; the extra keys go after the
+                // entries' own). Such an edge, if it is in the column, is a
+                // regular window entry expanded by its own thread this round, so
+                // the two expansions cancel mod 2 and nothing unexpanded is left
+                // twice; below the stop key that would not hold.
+                uint32_t total_base = 0;
+#pragma unroll
+                for (int i = 0; i < NWAVE; ++i) total_base += i <= (int)(min(stop0, (uint32_t)(WB - 1)) >> 6) ? L.ws[WS_ROUND][i] : 0u;
+                const bool chains = total_base <= (uint32_t)NW;
+                if (go && !batched && chains) {
+                    const uint64_t stopkey = stop0 < C.nt ? T[C.nt - 1 - stop0] : (C.nl ? C.lmax : 0ull);
+                    int64_t w = cw;
+                    uint32_t rw = crw;
+                    if (ekey_r(P.bpr, cra, rw) > stopkey) {
+                        int64_t lo;
+                        uint8_t c2 = P.G[(int64_t)edge_mask(P.g, cva, w, lo) * V + lo];
+                        for (int q = 0; q < CHAIN && c2 < 27; ++q) {  // {va, w} regular
+                            const uint32_t sl = total_base + atomicAdd(&L.nextra, 1u);
+                            if (sl >= (uint32_t)NW) break;
+                            const int64_t w2 = lo + lin27(P.g, c2);
+                            // the rank of w' and the code of {va, w'} are loaded together
+                            int64_t lo2;
+                            const uint8_t c3 = P.G[(int64_t)edge_mask(P.g, cva, w2, lo2) * V + lo2];
+                            const uint32_t rw2 = P.rank[w2];
+                            L.raw[sl] = ekey_r(P.bpr, rw, rw2);
+                            L.surv[sl] = NONE;
+                            w = w2;
+                            rw = rw2;
+                            lo = lo2;
+                            c2 = c3;
+                            if (ekey_r(P.bpr, cra, rw) <= stopkey) break;
+                        }
+                    }
+                    nk0 = ekey_r(P.bpr, cra, rw);
+                }
                 if (incl) {
                     if (batched) {
                         for (uint32_t j = 0; j < nkeys; ++j) L.surv[slot + j] = zoff + 1 + j;
@@ -1936,6 +1994,7 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
                     stop_at += L.wcnt[i];
                     total = max(total, L.wend[i]);
                 }
+                if (chains) total = min((uint32_t)NW, total_base + L.nextra);
                 // entries of the batched cached boundaries, one load per slot, and
                 // the boundaries' heads, all in flight together
                 {

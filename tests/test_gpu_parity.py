@@ -316,7 +316,7 @@ def test_parity_d1_ablation_variants(variant):
             for d in range(3):
                 assert np.array_equal(out[d].cpu().numpy(), res.pairs[d]), (variant, name, small, d)
     st = ctx.debug(dms.BUF_STATS, np.uint64).tolist()
-    assert st[6] > 0  # boundary additions happened
+    assert st[4] > 0  # the last diagram ran D1 steps
     ctx.close()
 
 
