@@ -1603,9 +1603,13 @@ __device__ __noinline__ void help(WideShared& L, unsigned long long* ctrs, int64
         const bool any = L.ints[4] != 0;
         __syncthreads();
         if (!any) {
+            // done when no column is left or in work, or when the call failed
+            // (a full publication heap stops every column workgroup before
+            // the queue is empty: the host grows the heap and runs again)
             if (t == 0)
-                L.ints[5] = ld_rlx64((const uint64_t*)&ctrs[C_NEXT]) >= (uint64_t)nwork &&
-                            ld_rlx64((const uint64_t*)&ctrs[C_ACTIVE]) == 0;
+                L.ints[5] = (ld_rlx64((const uint64_t*)&ctrs[C_NEXT]) >= (uint64_t)nwork &&
+                             ld_rlx64((const uint64_t*)&ctrs[C_ACTIVE]) == 0) ||
+                            (ld_rlx(flags) & (FLAG_HEAP | FLAG_GUARD | FLAG_WORK)) != 0;
             __syncthreads();
             const bool fin = L.ints[5] != 0;
             __syncthreads();
@@ -1780,7 +1784,10 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
     unsigned long long r_stop = 0, r_cap = 0, r_taken = 0;  // rounds ended at an edge / by the merge list; entries taken
     for (;;) {
         if ((int64_t)blockIdx.x >= P.nslots) break;  // a helper only
-        if (t == 0) L.u64s[0] = atomicAdd(&P.ctrs[C_NEXT], 1ull);
+        // no new column once the call has failed (it is run again or reported)
+        if (t == 0)
+            L.u64s[0] = (ld_rlx(P.flags) & (FLAG_HEAP | FLAG_GUARD | FLAG_WORK)) ? (uint64_t)P.nwork
+                                                                                 : atomicAdd(&P.ctrs[C_NEXT], 1ull);
         __syncthreads();
         const uint64_t next = L.u64s[0];
         __syncthreads();
