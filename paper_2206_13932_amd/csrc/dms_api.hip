@@ -43,6 +43,7 @@ struct dms_ctx {
     int64_t ncrit[4] = {0, 0, 0, 0};
     uint32_t cap[4] = {0, 0, 0, 0};
     Buf rank, keysA, keysB, valsA, valsB, G, hist, part, flags, counters, stats;
+    Buf keysA2, keysB2, valsA2, valsB2, hist2, part2;  // a second sort's scratch (concurrent critical sorts)
     Buf cid[4], ck[4];          // unsorted critical ids and their keys (CritLists)
     Buf csorted[4];             // ids sorted by the lexicographic order
     Buf cpos[4];                // cpos[d][i] = sorted position of cid[d][i] (d = 1, 2)
@@ -265,36 +266,51 @@ __global__ void k_write_pairs(const uint64_t* key_sorted, const uint32_t* idx, c
 
 // ---- internal helpers used by the entry points --------------------------------
 
-static int sort_ids(dms_ctx* ctx, int d) {
+// the context's second stream and the events that fork work onto it and join it back
+static int ensure_second_stream(dms_ctx* ctx) {
+    if (ctx->st2) return DMS_OK;
+    HIPCHK(hipStreamCreateWithFlags(&ctx->st2, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+    return DMS_OK;
+}
+
+// the scratch of one sort: keys, values (double-buffered), tile histograms, scan partials
+struct SortScratch {
+    Buf *keysA, *keysB, *valsA, *valsB, *hist, *part;
+};
+
+static int sort_scratch(dms_ctx* ctx, const SortScratch& S, int64_t m) {
+    ENSURE(*S.keysA, 8 * m);
+    ENSURE(*S.keysB, 8 * m);
+    ENSURE(*S.valsA, 4 * m);
+    ENSURE(*S.valsB, 4 * m);
+    ENSURE(*S.hist, 4 * 256 * sort_tiles(m));
+    ENSURE(*S.part, 4 * scan_part_size(256 * sort_tiles(m)));
+    return DMS_OK;
+}
+
+// sort C_d by the lexicographic order on stream st with scratch S (sized
+// beforehand with sort_scratch)
+static int sort_ids_on(dms_ctx* ctx, int d, hipStream_t st, const SortScratch& S) {
     const int64_t m = ctx->ncrit[d];
-    hipStream_t st = ctx->st;
-    ENSURE(ctx->csorted[d], 4 * m);
     if (m == 0) return DMS_OK;
-    ENSURE(ctx->keysA, 8 * m);
-    ENSURE(ctx->keysB, 8 * m);
-    ENSURE(ctx->valsA, 4 * m);
-    ENSURE(ctx->valsB, 4 * m);
-    ENSURE(ctx->hist, 4 * 256 * sort_tiles(m));
-    ENSURE(ctx->part, 4 * scan_part_size(256 * sort_tiles(m)));
-    uint32_t* hist = P<uint32_t>(ctx->hist);
-    uint32_t* part = P<uint32_t>(ctx->part);
+    uint32_t* hist = P<uint32_t>(*S.hist);
+    uint32_t* part = P<uint32_t>(*S.part);
     const int bpr = ctx->bpr;
     uint32_t* perm = nullptr;
     if (d == 0) {
-        int r = radix_sort_pairs<uint32_t>(P<uint32_t>(ctx->ck[0]), P<uint32_t>(ctx->valsA), P<uint32_t>(ctx->keysA),
-                                           P<uint32_t>(ctx->valsB), m, 0, bpr, true, hist, part, st);
-        perm = r ? P<uint32_t>(ctx->valsB) : P<uint32_t>(ctx->valsA);
+        int r = radix_sort_pairs<uint32_t>(P<uint32_t>(ctx->ck[0]), P<uint32_t>(*S.valsA), P<uint32_t>(*S.keysA),
+                                           P<uint32_t>(*S.valsB), m, 0, bpr, true, hist, part, st);
+        perm = r ? P<uint32_t>(*S.valsB) : P<uint32_t>(*S.valsA);
     } else {
         // rank of the highest vertex, then 4-bit labels of the others (CritLists)
-        int r = radix_sort_pairs<uint64_t>(P<uint64_t>(ctx->ck[d]), P<uint32_t>(ctx->valsA), P<uint64_t>(ctx->keysA),
-                                           P<uint32_t>(ctx->valsB), m, 0, bpr + 4 * d, true, hist, part, st);
-        perm = r ? P<uint32_t>(ctx->valsB) : P<uint32_t>(ctx->valsA);
+        int r = radix_sort_pairs<uint64_t>(P<uint64_t>(ctx->ck[d]), P<uint32_t>(*S.valsA), P<uint64_t>(*S.keysA),
+                                           P<uint32_t>(*S.valsB), m, 0, bpr + 4 * d, true, hist, part, st);
+        perm = r ? P<uint32_t>(*S.valsB) : P<uint32_t>(*S.valsA);
     }
     gather_u32(P<uint32_t>(ctx->cid[d]), perm, P<uint32_t>(ctx->csorted[d]), m, st);
-    if (d == 1 || d == 2) {
-        ENSURE(ctx->cpos[d], 4 * m);
-        inverse_perm(perm, m, P<uint32_t>(ctx->cpos[d]), st);
-    }
+    if (d == 1 || d == 2) inverse_perm(perm, m, P<uint32_t>(ctx->cpos[d]), st);
     return DMS_OK;
 }
 
@@ -373,7 +389,8 @@ void dms_destroy(dms_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->st);
     Buf* all[] = {&ctx->rank, &ctx->keysA, &ctx->keysB, &ctx->valsA, &ctx->valsB, &ctx->G, &ctx->hist,
-                  &ctx->part, &ctx->flags, &ctx->counters, &ctx->stats, &ctx->na0, &ctx->nb0, &ctx->owner0, &ctx->bnd0,
+                  &ctx->part, &ctx->flags, &ctx->counters, &ctx->stats, &ctx->keysA2, &ctx->keysB2, &ctx->valsA2,
+                  &ctx->valsB2, &ctx->hist2, &ctx->part2, &ctx->na0, &ctx->nb0, &ctx->owner0, &ctx->bnd0,
                   &ctx->paired1, &ctx->na2, &ctx->nb2, &ctx->owner2, &ctx->bnd2, &ctx->paired2, &ctx->tet2pos,
                   &ctx->jump0, &ctx->jump2, &ctx->ob, &ctx->od, &ctx->okey, &ctx->ocnt, &ctx->gk0, &ctx->gk1, &ctx->gv0, &ctx->gv1,
                   &ctx->ghist, &ctx->gpart, &ctx->gflag, &ctx->bfield, &ctx->bowner, &ctx->bslots, &ctx->bpairs[0],
@@ -489,9 +506,31 @@ static int gradient_finish(dms_ctx* ctx, dms_gradient_info* info) {
     int r = check_flags(ctx);
     if (r != DMS_OK) return r;
     // ---- a3: sort critical simplices by the lexicographic order ----
+    // Without an HBM budget the 2-saddles sort on the second stream, with a
+    // scratch of their own, while the other lists sort on the main stream.
+    const int64_t* m = ctx->ncrit;
     for (int d = 0; d < 4; ++d) {
-        r = sort_ids(ctx, d);
+        ENSURE(ctx->csorted[d], 4 * m[d]);
+        if (d == 1 || d == 2) ENSURE(ctx->cpos[d], 4 * m[d]);
+    }
+    const bool two = ctx->budget == 0 && m[2] > 0;
+    const SortScratch A{&ctx->keysA, &ctx->keysB, &ctx->valsA, &ctx->valsB, &ctx->hist, &ctx->part};
+    const SortScratch B{&ctx->keysA2, &ctx->keysB2, &ctx->valsA2, &ctx->valsB2, &ctx->hist2, &ctx->part2};
+    r = sort_scratch(ctx, A, std::max(std::max(m[0], m[1]), std::max(m[3], two ? (int64_t)0 : m[2])));
+    if (r != DMS_OK) return r;
+    if (two) {
+        r = sort_scratch(ctx, B, m[2]);
+        if (r == DMS_OK) r = ensure_second_stream(ctx);
         if (r != DMS_OK) return r;
+        HIPCHK(hipEventRecord(ctx->ev_fork, ctx->st));
+        HIPCHK(hipStreamWaitEvent(ctx->st2, ctx->ev_fork, 0));
+        sort_ids_on(ctx, 2, ctx->st2, B);
+    }
+    for (int d = 0; d < 4; ++d)
+        if (d != 2 || !two) sort_ids_on(ctx, d, ctx->st, A);
+    if (two) {
+        HIPCHK(hipEventRecord(ctx->ev_join, ctx->st2));
+        HIPCHK(hipStreamWaitEvent(ctx->st, ctx->ev_join, 0));
     }
     record(ctx, EV_SORT);
     HIPCHK(hipStreamSynchronize(ctx->st));
@@ -562,11 +601,8 @@ static int run_d0_d2(dms_ctx* ctx) {
         ENSURE(ctx->bnd2, 8 * m2);
         ENSURE(ctx->paired2, m2);
         ENSURE(ctx->jump2, 8 * (m3 + 1));
-        if (!ctx->st2) {
-            HIPCHK(hipStreamCreateWithFlags(&ctx->st2, hipStreamNonBlocking));
-            HIPCHK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
-            HIPCHK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
-        }
+        int r2 = ensure_second_stream(ctx);
+        if (r2 != DMS_OK) return r2;
         HIPCHK(hipEventRecord(ctx->ev_fork, st));
         HIPCHK(hipStreamWaitEvent(ctx->st2, ctx->ev_fork, 0));
         d0_st = ctx->st2;
