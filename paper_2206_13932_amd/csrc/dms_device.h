@@ -131,7 +131,7 @@ struct StarTables {
     int8_t al27[NSLOT];       // aoff.x + 3 aoff.y + 9 aoff.z
     uint8_t dim[NSLOT];
     uint8_t type[NSLOT];
-    SlotMask slnb[NNB];       // slots whose cell contains neighbour n
+    SlotMask slnb[16];        // slots whose cell contains neighbour n; rows 14, 15 empty
     // packed for one read when a pair is recorded:
     uint32_t slrec[NSLOT];    // cellnb | (al27 + 13) << 16
     uint32_t nbrec[NNB];      // lessc | cpos_pos << 14 | (l27 + 13) << 16

@@ -32,7 +32,7 @@ struct LdsTables {
     uint64_t cof_lo[NSLOT];
     uint16_t cof_hi[NSLOT];
     uint16_t cellnb[NSLOT];
-    SlotMask slnb[NNB];  // slots holding neighbour n
+    SlotMask slnb[16];  // slots holding neighbour n (rows 14, 15 empty)
     uint32_t slrec[NSLOT];
     uint32_t nbrec[NNB];
     uint8_t plane[NSLOT];
@@ -60,10 +60,19 @@ __device__ inline uint32_t wave_exclusive(uint32_t v, uint32_t& total) {
 template <bool PACKED>
 __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_gradient(GridDev g, const uint32_t* __restrict__ rank,
                                                  uint8_t* __restrict__ G, int bpr, CritLists cl) {
-    __shared__ LdsTables T;
-    __shared__ uint8_t scode[NSLOT * GB];  // partner code of each slot, by processing lane
-    __shared__ uint32_t bins[NSLOT + 1];   // lanes per lower-star size, then bin offsets
-    __shared__ uint16_t perm[GB];          // perm[lane] = the block-local vertex that lane processes
+    // one block of LDS with the tables first: their addresses stay below 64 KB,
+    // so table reads take the base as an instruction offset instead of adds
+    struct Shared {
+        LdsTables T;
+        uint8_t scode[NSLOT * GB];  // partner code of each slot, by processing lane
+        uint32_t bins[NSLOT + 1];   // lanes per lower-star size, then bin offsets
+        uint16_t perm[GB];          // perm[lane] = the block-local vertex that lane processes
+    };
+    __shared__ Shared S;
+    LdsTables& T = S.T;
+    uint8_t* const scode = S.scode;
+    uint32_t* const bins = S.bins;
+    uint16_t* const perm = S.perm;
     const int tid = threadIdx.x;
     // cooperative copy of the star tables into LDS
     for (int i = tid; i < NSLOT; i += GB) {
@@ -75,8 +84,8 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         T.plane[i] = kStar.plane[i];
         T.aofflin[i] = (int64_t)kStar.aoff[i][0] + kStar.aoff[i][1] * g.sy + kStar.aoff[i][2] * g.sz;
     }
+    for (int i = tid; i < 16; i += GB) T.slnb[i] = kStar.slnb[i];
     for (int i = tid; i < NNB; i += GB) {
-        T.slnb[i] = kStar.slnb[i];
         T.nbrec[i] = kStar.nbrec[i];
         T.l27[i] = kStar.l27[i];
         T.cpos_pos[i] = kStar.cpos_pos[i];
@@ -120,6 +129,12 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     // largest lower star in the wave. The vertices of the block are handed to
     // lanes in order of lower-star size (a counting sort in LDS), which keeps
     // the stores of each slot inside the block's span.
+    // The labels, the star's cells and the rank found here are handed to the
+    // lane that processes the vertex through the code buffer, free until the
+    // lower-star loop (words of 1024 lanes: inv0, inv1, rank, lower | in_hi
+    // << 16, in_lo low, in_lo high).
+    uint32_t* const stash = (uint32_t*)scode;
+    static_assert(6 * GB * 4 <= NSLOT * GB, "the hand-over fits the code buffer");
     const int64_t xo = x0 + tid;
     uint64_t own_lo = 0;
     uint32_t own_hi = 0;
@@ -130,6 +145,7 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
             uint32_t rv, r[NNB];
             int cx, cy, cz;
             const uint32_t lower = lower_of(xo, rv, r, cx, cy, cz);
+            uint32_t inv0 = 0, inv1 = 0;
             // non-existent simplices anchored at x (upper faces of the grid)
             if (cx == g.nx - 1 || cy == g.ny - 1 || cz == g.nz - 1) {
                 for (int t = 0; t < 7; ++t)
@@ -141,7 +157,19 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
             if (lower) {
                 star_cells(lower, own_lo, own_hi);
                 ncell = (uint32_t)(popc64(own_lo) + __builtin_popcount(own_hi));
+                uint64_t rp;
+                relabel<PACKED>(r, lower, inv0, inv1, rp);
+                // x pairs with its lowest edge (the code is known before the loop)
+                G[xo] = (uint8_t)(13 + T.l27[inv0 & 15u]);
+            } else {
+                G[xo] = CODE_CRIT;  // minimum
             }
+            stash[0 * GB + tid] = inv0;
+            stash[1 * GB + tid] = inv1;
+            stash[2 * GB + tid] = rv;
+            stash[3 * GB + tid] = lower | own_hi << 16;
+            stash[4 * GB + tid] = (uint32_t)own_lo;
+            stash[5 * GB + tid] = (uint32_t)(own_lo >> 32);
         }
         const uint32_t within = atomicAdd(&bins[ncell], 1u);
         __syncthreads();
@@ -170,26 +198,36 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     uint32_t rx = 0;
     uint64_t relpack = 0;  // 4-bit label of each lower neighbour: its rank order among them
 
+    uint32_t inv0 = 0, inv1 = 0, lower = 0;
+    uint64_t in_lo = 0;
+    uint32_t in_hi = 0;
     if (active) {
-        uint32_t r[NNB];
-        int cx, cy, cz;
-        const uint32_t lower = lower_of(x, rx, r, cx, cy, cz);
+        const int v = perm[tid];
+        inv0 = stash[0 * GB + v];
+        inv1 = stash[1 * GB + v];
+        rx = stash[2 * GB + v];
+        const uint32_t w3 = stash[3 * GB + v];
+        lower = w3 & 0xFFFFu;
+        in_hi = w3 >> 16;
+        in_lo = stash[4 * GB + v] | (uint64_t)stash[5 * GB + v] << 32;
+    }
+    __syncthreads();  // the code buffer is written from here on
+    if (active) {
         if (lower == 0) {
-            G[x] = CODE_CRIT;  // minimum
             crit_vertex = true;
         } else {
-            uint64_t in_lo;
-            uint32_t in_hi;
-            star_cells(lower, in_lo, in_hi);
-            uint32_t inv0, inv1;
-            uint64_t rp;
-            relabel<PACKED>(r, lower, inv0, inv1, rp);
             const int k = __builtin_popcount(lower);
-            // x pairs with its lowest edge (the code is known before the loop)
-            G[x] = (uint8_t)(13 + T.l27[inv0 & 15u]);
+            // the largest k among the lanes here (k <= 14): the minimum
+            // searches of the wave run that many levels in every lane, as
+            // scalar branches
+            int kw = 0;
+#pragma unroll
+            for (int step = 8; step >= 1; step >>= 1)
+                if (__builtin_amdgcn_ballot_w64(k >= kw + step)) kw += step;
+            kw = __builtin_amdgcn_readfirstlane(kw);
             uint8_t xcode;
             lower_star_gradient(
-                T, in_lo, in_hi, k, inv0, inv1, [&](int s, uint8_t code) { CODE(s) = code; }, xcode, crit_lo,
+                T, in_lo, in_hi, kw, inv0, inv1, [&](int s, uint8_t code) { CODE(s) = code; }, xcode, crit_lo,
                 crit_hi);
             // the labels again, for the keys of the critical cells (not kept
             // in registers through the loop)
@@ -200,16 +238,21 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
 
     // ---- 3. gradient codes of the own vertex's lower star: one store per slot,
     // consecutive lanes -> consecutive bytes ----
+    // The plane and the anchor offset of a slot are the same in every lane:
+    // the address is a base common to the workgroup plus the lane's own
+    // offset (tid bytes; 6 tid in the tetrahedron plane, 6 bytes per anchor).
     {
         const uint32_t col = own_lane;
+        const uint32_t ve = tid, vt = 6 * tid;
 #pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
             const bool w = s < 64 ? ((own_lo >> s) & 1) : ((own_hi >> (s - 64)) & 1);
             if (w) {
                 constexpr int64_t zero = 0;
                 const int pl = kStar.plane[s];  // compile-time after unrolling
-                const int64_t a = xo + (zero + kStar.aoff[s][0]) + kStar.aoff[s][1] * g.sy + kStar.aoff[s][2] * g.sz;
-                G[pl < 20 ? (int64_t)pl * V + a : tet_code_at(V, a, pl - 20)] = scode[s * GB + col];
+                const int64_t a0 = x0 + (zero + kStar.aoff[s][0]) + kStar.aoff[s][1] * g.sy + kStar.aoff[s][2] * g.sz;
+                uint8_t* const base = G + (pl < 20 ? (int64_t)pl * V + a0 : tet_code_at(V, a0, pl - 20));
+                base[pl < 20 ? ve : vt] = scode[s * GB + col];
             }
         }
     }

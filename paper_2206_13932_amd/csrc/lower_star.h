@@ -43,9 +43,10 @@ static_assert(kSortNet16.n == 63, "Batcher's network on 16 keys has 63 comparato
 
 // Labels of the lower neighbours from their ranks r[n] (lower: bit n set).
 // Out: inv0 / inv1 = the neighbour holding label j, 4 bits per label (labels
-// 0..7, then 8..13); relpack = the label of neighbour n at bits 4n (lower
-// neighbours only). PACKED: ranks below 2^28, so (rank << 4 | n) sorts in 32
-// bits; otherwise each label is counted.
+// 0..7, then 8..13; 15 for a label past the last lower neighbour); relpack =
+// the label of neighbour n at bits 4n (lower neighbours only). PACKED: ranks
+// below 2^28, so (rank << 4 | n) sorts in 32 bits; otherwise each label is
+// counted.
 template <bool PACKED>
 __host__ __device__ inline void relabel(const uint32_t (&r)[NNB], uint32_t lower, uint32_t& inv0, uint32_t& inv1,
                                         uint64_t& relpack) {
@@ -84,6 +85,9 @@ __host__ __device__ inline void relabel(const uint32_t (&r)[NNB], uint32_t lower
                 else inv1 |= (uint32_t)n << (4 * (c - 8));
             }
         }
+        const uint64_t past = ((1ull << (4 * NNB)) - 1) & ~((1ull << (4 * __builtin_popcount(lower))) - 1);
+        inv0 |= (uint32_t)past;
+        inv1 |= (uint32_t)(past >> 32);
     }
 }
 
@@ -116,11 +120,16 @@ __host__ __device__ inline uint64_t labels_of(uint32_t inv0, uint32_t inv1, int 
 
 // ProcessLowerStars on a vertex with k >= 1 lower neighbours.
 // T: star tables (face, cof_lo, cof_hi, slrec, nbrec, l27, cpos_pos, slnb);
+// inv0 / inv1 as relabel leaves them (15 past label k-1); levels: the number
+// of labels the minimum searches go through, at least k (lanes that run in
+// lock-step pass the largest k among them, so that the searches' levels are
+// the same in every lane: a level past a lane's own labels reads the empty
+// row 15 of slnb and changes nothing);
 // put(slot, code) receives the partner code of every cell
 // of L(x) that is paired (codes as in dms_device.h); xcode = the code of x;
 // crit_lo / crit_hi = the critical cells.
 template <class Tab, class Put>
-__host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo, uint32_t in_hi, int k,
+__host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo, uint32_t in_hi, int levels,
                                                     uint32_t inv0, uint32_t inv1, Put put, uint8_t& xcode,
                                                     uint64_t& crit_lo, uint32_t& crit_hi) {
     auto nb_of = [&](int j) __attribute__((always_inline)) { return (int)((j < 8 ? inv0 >> (4 * j) : inv1 >> (4 * (j - 8))) & 15u); };
@@ -139,7 +148,6 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
         put(a, (uint8_t)(0x80 | pos));
         put(p, (uint8_t)(13 + (int)(rw >> 16) - (int)(rp >> 16)));  // 13 + l27[w] - al27[p]
     };
-    auto unpaired = [&](int s) __attribute__((always_inline)) { return popc64_(T.face[s] & ~cls_lo); };
     // x pairs with its lowest edge delta = {x, n0}
     const int n0 = nb_of(0);
     xcode = (uint8_t)(13 + T.l27[n0]);
@@ -149,48 +157,58 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
     uint32_t z_hi = 0;
     uint64_t o_lo = 0;
     uint32_t o_hi = 0;
-    // push the cofacets of s and t (s == t: of s) that have one unpaired
-    // facet. A cofacet with none left was pushed when it had one; it would
-    // leave the queue for the other one when popped, with no other effect,
-    // so it moves there now and costs no pop.
-    auto push_cofaces2 = [&](int s, int t) __attribute__((always_inline)) {
-        uint64_t c = (T.cof_lo[s] | T.cof_lo[t]) & ~cls_lo;
-        while (c) {
-            const int b = __builtin_ctzll(c);
-            c &= c - 1;
-            const int u = unpaired(b);
-            const uint64_t bit = (uint64_t)1 << b;
-            const uint64_t one = u == 1 ? bit : 0, none = u == 0 ? bit : 0;
-            o_lo = (o_lo | one) & ~none;
-            z_lo |= none;
-        }
-        uint32_t ch = (uint32_t)(T.cof_hi[s] | T.cof_hi[t]) & ~cls_hi;
-        while (ch) {
-            const int b = __builtin_ctz(ch);
-            ch &= ch - 1;
-            const int u = unpaired(64 + b);
-            const uint32_t bit = 1u << b;
-            const uint32_t one = u == 1 ? bit : 0, none = u == 0 ? bit : 0;
-            o_hi = (o_hi | one) & ~none;
-            z_hi |= none;
-        }
+    // The unpaired (unclassified) facets of every slot, a 2-bit count per
+    // slot kept in two bit planes (u0: bit 0, u1: bit 1). The facets inside
+    // the star of a cell of L(x) are cells of L(x): 2 for a triangle, 3 for a
+    // tetrahedron, none for an edge (x itself is paired apart). The counts of
+    // slots outside L(x) are never read (those slots count as classified).
+    uint64_t u0_lo = ~((1ull << 50) - 1), u1_lo = ~0x3FFFull;
+    uint32_t u0_hi = (1u << (NSLOT - 64)) - 1, u1_hi = u0_hi;
+    // m: the cofacets of the cells just classified (the cofacets of a cell
+    // and of its facet are disjoint, so every count drops by one). Those
+    // still unclassified go to the queue their count now names: one unpaired
+    // facet -> o, none -> z (and out of o). A cell with none left was pushed
+    // to o when it had one; it would leave o for z when popped, with no other
+    // effect, so it moves there now and costs no pop.
+    auto push_cofaces = [&](uint64_t m_lo, uint32_t m_hi) __attribute__((always_inline)) {
+        u1_lo ^= m_lo & ~u0_lo;
+        u0_lo ^= m_lo;
+        u1_hi ^= m_hi & ~u0_hi;
+        u0_hi ^= m_hi;
+        const uint64_t c_lo = m_lo & ~cls_lo & ~u1_lo;  // count 0 or 1
+        const uint32_t c_hi = m_hi & ~cls_hi & ~u1_hi;
+        o_lo = (o_lo | (c_lo & u0_lo)) & ~(c_lo & ~u0_lo);
+        o_hi = (o_hi | (c_hi & u0_hi)) & ~(c_hi & ~u0_hi);
+        z_lo |= c_lo & ~u0_lo;
+        z_hi |= c_hi & ~u0_hi;
     };
-    // the member of a non-empty set with the smallest mask, removed from it.
-    // Every level runs: the lanes of a wave go through the levels together,
-    // and testing after each level whether one member is left cost more than
-    // the levels it saved.
-    const uint64_t inv = inv0 | (uint64_t)inv1 << 32;
-    // (its slot; the caller removes it)
+    // the member of a non-empty set with the smallest mask (its slot; the
+    // caller removes it). Every level runs: the lanes of a wave go through
+    // the levels together, and testing after each level whether one member is
+    // left cost more than the levels it saved. The row of label j sits at byte
+    // offset 16 n(j) of slnb; the offsets are kept one byte per label, so that
+    // a level takes its row's address with one bit-field extract.
+    static_assert(sizeof(SlotMask) == 16, "one slnb row is 16 bytes");
+    uint32_t roff[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t q = (w < 2 ? inv0 >> (16 * w) : inv1 >> (16 * (w - 2))) & 0xFFFFu;
+        roff[w] = (q & 0xFu) << 4 | (q & 0xF0u) << 8 | (q & 0xF00u) << 12 | (q & 0xF000u) << 16;
+    }
+    const char* const rows = (const char*)&T.slnb[0];
     auto pop_min = [&](uint64_t lo, uint32_t hi) __attribute__((always_inline)) {
         if (popc64_(lo) + __builtin_popcount(hi) > 1) {
-            for (int j = k - 1; j >= 0; --j) {
-                const int n = (int)((inv >> (4 * j)) & 15u);
-                const SlotMask m = T.slnb[n];
-                const uint64_t tl = lo & ~m.lo;
-                const uint32_t th = hi & ~m.hi;
-                if (tl | th) {
-                    lo = tl;
-                    hi = th;
+#pragma unroll
+            for (int j = NNB - 1; j >= 0; --j) {
+                if (j < levels) {
+                    const uint32_t off = (roff[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+                    const SlotMask m = *(const SlotMask*)(rows + off);
+                    const uint64_t tl = lo & ~m.lo;
+                    const uint32_t th = hi & ~m.hi;
+                    if (tl | th) {
+                        lo = tl;
+                        hi = th;
+                    }
                 }
             }
         }
@@ -201,7 +219,7 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
         blo = s < 64 ? (uint64_t)1 << (s & 63) : 0;
         bhi = s < 64 ? 0 : 1u << ((s - 64) & 31);
     };
-    push_cofaces2(n0, n0);
+    push_cofaces(T.cof_lo[n0], T.cof_hi[n0]);
     for (int guard = 0; guard < 4 * NSLOT; ++guard) {
         while (o_lo | o_hi) {
             const int a = pop_min(o_lo, o_hi);
@@ -219,7 +237,7 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
             cls_lo |= alo | (uint64_t)1 << p;
             cls_hi |= ahi;
             z_lo &= ~((uint64_t)1 << p);
-            push_cofaces2(a, p);
+            push_cofaces(T.cof_lo[a] | T.cof_lo[p], (uint32_t)(T.cof_hi[a] | T.cof_hi[p]));
         }
         if (!(z_lo | z_hi)) break;
         const int c = pop_min(z_lo, z_hi);
@@ -233,7 +251,7 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
         crit_lo |= clo;
         crit_hi |= chi;
         put(c, CODE_CRIT);
-        push_cofaces2(c, c);
+        push_cofaces(T.cof_lo[c], T.cof_hi[c]);
     }
 }
 

@@ -113,7 +113,7 @@ constexpr StarTables make_star_tables() {
     for (int i = 0; i < NSLOT; ++i) T.slrec[i] = (uint32_t)T.cellnb[i] | (uint32_t)(T.al27[i] + 13) << 16;
     for (int n = 0; n < NNB; ++n)
         T.nbrec[n] = (uint32_t)T.lessc[n] | (uint32_t)T.cpos_pos[n] << 14 | (uint32_t)(T.l27[n] + 13) << 16;
-    for (int n = 0; n < NNB; ++n) {
+    for (int n = 0; n < 16; ++n) {  // cellnb has 14 bits: rows 14 and 15 stay empty
         T.slnb[n] = SlotMask{0, 0, 0};
         for (int i = 0; i < NSLOT; ++i)
             if (T.cellnb[i] & (1 << n)) {
