@@ -132,6 +132,7 @@ struct StarTables {
     uint8_t dim[NSLOT];
     uint8_t type[NSLOT];
     SlotMask slnb[16];        // slots whose cell contains neighbour n; rows 14, 15 empty
+    uint64_t slnbc[32];       // [2n]: the slots 14..73 of slnb[n] (bit s - 14); 16-byte rows
     // packed for one read when a pair is recorded:
     uint32_t slrec[NSLOT];    // cellnb | (al27 + 13) << 16
     uint32_t nbrec[NNB];      // lessc | cpos_pos << 14 | (l27 + 13) << 16

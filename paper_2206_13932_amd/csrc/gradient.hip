@@ -33,6 +33,7 @@ struct LdsTables {
     uint16_t cof_hi[NSLOT];
     uint16_t cellnb[NSLOT];
     SlotMask slnb[16];  // slots holding neighbour n (rows 14, 15 empty)
+    uint64_t slnbc[32];  // the same rows for slots 14..73, one word each (16-byte stride)
     uint32_t slrec[NSLOT];
     uint32_t nbrec[NNB];
     uint8_t plane[NSLOT];
@@ -85,6 +86,7 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         T.aofflin[i] = (int64_t)kStar.aoff[i][0] + kStar.aoff[i][1] * g.sy + kStar.aoff[i][2] * g.sz;
     }
     for (int i = tid; i < 16; i += GB) T.slnb[i] = kStar.slnb[i];
+    for (int i = tid; i < 32; i += GB) T.slnbc[i] = kStar.slnbc[i];
     for (int i = tid; i < NNB; i += GB) {
         T.nbrec[i] = kStar.nbrec[i];
         T.l27[i] = kStar.l27[i];

@@ -155,8 +155,12 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
     cls_lo = ~in_lo | (uint64_t)1 << n0;
     uint64_t z_lo = 0x3FFFull & ~cls_lo;  // the other edges
     uint32_t z_hi = 0;
-    uint64_t o_lo = 0;
-    uint32_t o_hi = 0;
+    // The first queue only ever holds cofacets (triangles and tetrahedra,
+    // slots 14..73): one word, bit s - 14.
+    uint64_t o = 0;
+    auto cof_word = [](uint64_t lo, uint32_t hi) __attribute__((always_inline)) {
+        return lo >> NNB | (uint64_t)hi << (64 - NNB);
+    };
     // The unpaired (unclassified) facets of every slot, a 2-bit count per
     // slot kept in two bit planes (u0: bit 0, u1: bit 1). The facets inside
     // the star of a cell of L(x) are cells of L(x): 2 for a triangle, 3 for a
@@ -177,17 +181,19 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
         u0_hi ^= m_hi;
         const uint64_t c_lo = m_lo & ~cls_lo & ~u1_lo;  // count 0 or 1
         const uint32_t c_hi = m_hi & ~cls_hi & ~u1_hi;
-        o_lo = (o_lo | (c_lo & u0_lo)) & ~(c_lo & ~u0_lo);
-        o_hi = (o_hi | (c_hi & u0_hi)) & ~(c_hi & ~u0_hi);
-        z_lo |= c_lo & ~u0_lo;
-        z_hi |= c_hi & ~u0_hi;
+        const uint64_t none_lo = c_lo & ~u0_lo;
+        const uint32_t none_hi = c_hi & ~u0_hi;
+        o = (o | cof_word(c_lo & u0_lo, c_hi & u0_hi)) & ~cof_word(none_lo, none_hi);
+        z_lo |= none_lo;
+        z_hi |= none_hi;
     };
-    // the member of a non-empty set with the smallest mask (its slot; the
-    // caller removes it). Every level runs: the lanes of a wave go through
-    // the levels together, and testing after each level whether one member is
-    // left cost more than the levels it saved. The row of label j sits at byte
-    // offset 16 n(j) of slnb; the offsets are kept one byte per label, so that
-    // a level takes its row's address with one bit-field extract.
+    // The member of a non-empty set with the smallest mask is what is left
+    // after the levels: a set of one bit. Every level runs: the lanes of a
+    // wave go through the levels together, and testing after each level
+    // whether one member is left cost more than the levels it saved. The rows
+    // of label j sit at byte offset 16 n(j) of slnb and of slnbc; the offsets
+    // are kept one byte per label, so that a level takes its row's address
+    // with one bit-field extract.
     static_assert(sizeof(SlotMask) == 16, "one slnb row is 16 bytes");
     uint32_t roff[4];
 #pragma unroll
@@ -195,14 +201,15 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
         const uint32_t q = (w < 2 ? inv0 >> (16 * w) : inv1 >> (16 * (w - 2))) & 0xFFFFu;
         roff[w] = (q & 0xFu) << 4 | (q & 0xF0u) << 8 | (q & 0xF00u) << 12 | (q & 0xF000u) << 16;
     }
+    auto row_off = [&](int j) __attribute__((always_inline)) { return (roff[j >> 2] >> (8 * (j & 3))) & 0xFFu; };
     const char* const rows = (const char*)&T.slnb[0];
-    auto pop_min = [&](uint64_t lo, uint32_t hi) __attribute__((always_inline)) {
+    const char* const rows_c = (const char*)&T.slnbc[0];
+    auto min_of = [&](uint64_t& lo, uint32_t& hi) __attribute__((always_inline)) {
         if (popc64_(lo) + __builtin_popcount(hi) > 1) {
 #pragma unroll
             for (int j = NNB - 1; j >= 0; --j) {
                 if (j < levels) {
-                    const uint32_t off = (roff[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-                    const SlotMask m = *(const SlotMask*)(rows + off);
+                    const SlotMask m = *(const SlotMask*)(rows + row_off(j));
                     const uint64_t tl = lo & ~m.lo;
                     const uint32_t th = hi & ~m.hi;
                     if (tl | th) {
@@ -212,40 +219,43 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
                 }
             }
         }
-        return lo ? __builtin_ctzll(lo) : 64 + __builtin_ctz(hi);
     };
-    // slot s as a two-word bit (no branch on the word)
-    auto bits_of = [&](int s, uint64_t& blo, uint32_t& bhi) __attribute__((always_inline)) {
-        blo = s < 64 ? (uint64_t)1 << (s & 63) : 0;
-        bhi = s < 64 ? 0 : 1u << ((s - 64) & 31);
+    auto min_of_cof = [&](uint64_t q) __attribute__((always_inline)) {
+        if (popc64_(q) > 1) {
+#pragma unroll
+            for (int j = NNB - 1; j >= 0; --j) {
+                if (j < levels) {
+                    const uint64_t t = q & ~*(const uint64_t*)(rows_c + row_off(j));
+                    if (t) q = t;
+                }
+            }
+        }
+        return q;
     };
     push_cofaces(T.cof_lo[n0], T.cof_hi[n0]);
     for (int guard = 0; guard < 4 * NSLOT; ++guard) {
-        while (o_lo | o_hi) {
-            const int a = pop_min(o_lo, o_hi);
-            uint64_t alo;
-            uint32_t ahi;
-            bits_of(a, alo, ahi);
-            o_lo &= ~alo;
-            o_hi &= ~ahi;
+        while (o) {
+            const uint64_t ab = min_of_cof(o);
+            o ^= ab;
+            const int a = NNB + __builtin_ctzll(ab);
             // A cell of this queue is unclassified (it is smaller than every
             // cell classified after it entered), and it has one unpaired facet
             // (the classification that takes its last one moves it to the other
             // queue), so it pairs with that facet.
             const int p = __builtin_ctzll(T.face[a] & ~cls_lo);
             pair_cells(p, a);
-            cls_lo |= alo | (uint64_t)1 << p;
-            cls_hi |= ahi;
+            cls_lo |= ab << NNB | (uint64_t)1 << p;
+            cls_hi |= (uint32_t)(ab >> (64 - NNB));
             z_lo &= ~((uint64_t)1 << p);
             push_cofaces(T.cof_lo[a] | T.cof_lo[p], (uint32_t)(T.cof_hi[a] | T.cof_hi[p]));
         }
         if (!(z_lo | z_hi)) break;
-        const int c = pop_min(z_lo, z_hi);
-        uint64_t clo;
-        uint32_t chi;
-        bits_of(c, clo, chi);
-        z_lo &= ~clo;
-        z_hi &= ~chi;
+        uint64_t clo = z_lo;
+        uint32_t chi = z_hi;
+        min_of(clo, chi);
+        const int c = clo ? __builtin_ctzll(clo) : 64 + __builtin_ctz(chi);
+        z_lo ^= clo;
+        z_hi ^= chi;
         cls_lo |= clo;
         cls_hi |= chi;
         crit_lo |= clo;

@@ -115,10 +115,13 @@ constexpr StarTables make_star_tables() {
         T.nbrec[n] = (uint32_t)T.lessc[n] | (uint32_t)T.cpos_pos[n] << 14 | (uint32_t)(T.l27[n] + 13) << 16;
     for (int n = 0; n < 16; ++n) {  // cellnb has 14 bits: rows 14 and 15 stay empty
         T.slnb[n] = SlotMask{0, 0, 0};
+        T.slnbc[2 * n] = 0;
+        T.slnbc[2 * n + 1] = 0;
         for (int i = 0; i < NSLOT; ++i)
             if (T.cellnb[i] & (1 << n)) {
                 if (i < 64) T.slnb[n].lo |= (uint64_t)1 << i;
                 else T.slnb[n].hi |= 1u << (i - 64);
+                if (i >= NNB) T.slnbc[2 * n] |= (uint64_t)1 << (i - NNB);
             }
     }
     for (int i = 0; i < NSLOT; ++i)
