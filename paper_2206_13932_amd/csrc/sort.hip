@@ -60,7 +60,16 @@ __global__ __launch_bounds__(SB) void k_scatter(const K* __restrict__ kin, const
     __shared__ uint32_t sv[TILE];
     for (int i = threadIdx.x; i < WAVES * 256; i += SB) (&wcnt[0][0])[i] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * TILE;
+    // Workgroups are dispatched to the 8 XCDs in turn, each with its own L2:
+    // XCD k takes the k-th eighth of the tiles, in order, so that the runs
+    // that neighbouring tiles write into one digit's bucket (consecutive
+    // addresses) meet in one L2 and leave it as whole lines.
+    int64_t tile;
+    {
+        const int64_t nt = gridDim.x, q = nt / 8, r = nt % 8, k = blockIdx.x % 8;
+        tile = k * q + (k < r ? k : r) + blockIdx.x / 8;
+    }
+    const int64_t base = tile * TILE;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     K kk[IPT];
@@ -127,7 +136,7 @@ __global__ __launch_bounds__(SB) void k_scatter(const K* __restrict__ kin, const
     for (int j = threadIdx.x; j < cnt; j += SB) {
         const K k = sk[j];
         const uint32_t d = digit_of(k, shift);
-        const int64_t dst = (int64_t)offs[(int64_t)d * nblk + blockIdx.x] + (j - dstart[d]);
+        const int64_t dst = (int64_t)offs[(int64_t)d * nblk + tile] + (j - dstart[d]);
         kout[dst] = k;
         vout[dst] = sv[j];
     }
