@@ -41,9 +41,9 @@ METRIC = "Mvertices/s full D0+D1+D2 (512^3 f32), % HBM peak; served req/s + p99"
 HBM_PEAK_GBS = 8000.0
 # Counters of one gradient-kernel launch on smooth512 (profiles/gradient_hbm_counters_smooth512.md),
 # valid for the kernel sources with this hash only: HBM bytes from FETCH_SIZE (x2 calibration) and
-# WRITE_SIZE (None: not taken for these sources), and the VALU wave instructions issued
+# WRITE_SIZE, and the VALU wave instructions issued
 GRADIENT_COUNTERS = {"sources_sha256_16": "3fe25cc2787f1d16", "workload": "smooth512",
-                     "traffic_bytes": None, "valu_wave_insts": 6864124958}
+                     "traffic_bytes": 1609067725 + 6572371866, "valu_wave_insts": 6864131217}
 # VALU issue ceiling for the plain (non-packed) 32-bit integer and bit operations the gradient
 # kernel runs: the fp64 vector peak, 78.6 TFLOP/s = 2 FLOP x 64 lanes per CU per clock at 256 CUs
 # x 2.4 GHz, i.e. 16-lane SIMDs taking 4 cycles per wave64 instruction: one wave64 instruction
