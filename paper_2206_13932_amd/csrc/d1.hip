@@ -45,11 +45,11 @@ constexpr uint32_t OWN_D0 = 0xFFFFFFFEu;
 constexpr uint64_t NONE = ~0ull;
 constexpr int MAX_PASSES = 6;
 // one pass of the D1 plan: heap capacity (keys), lanes or workgroups, block
-// size, thread-per-column or not, heaps in LDS or not
+// size, thread-per-column (heaps in LDS) or workgroup-per-column
 struct PassPlan {
     int64_t k, t;
     int db;
-    bool lane, lds;
+    bool lane;
 };
 constexpr int LDS_K = 20;   // keys per thread in the first pass (LDS heaps)
 constexpr int LDS_K2 = 48;  // ... and in the second
@@ -120,7 +120,6 @@ struct D1K {
     uint64_t* scratch;
     int64_t K;
     int64_t nthreads;
-    int lds;  // working heaps in LDS (K entries per thread) instead of global scratch
     uint32_t long_add;  // cached boundaries longer than this are added by one full merge
     int64_t nslots;     // workgroups of a workgroup pass that take columns; the others only help
     uint32_t part_span; // merged positions per part of a cooperative merge
@@ -212,17 +211,21 @@ __device__ inline EdgeDec edecode(const GridDev& g, const uint32_t* order, int b
     return e;
 }
 
-// ---- per-thread max-heap with mod-2 cancellation -----------------------------
+// ---- per-lane max-heap in LDS with mod-2 cancellation ------------------------
+// The lane passes' dynamic LDS: lane t's heap is lds_heaps[t K .. t K + K).
+// Elements are reached through the shared array itself (not through a
+// pointer that could be global memory), so that they compile to LDS
+// instructions, which wait apart from the lane's global loads.
+extern __shared__ uint64_t lds_heaps[];
 struct Heap {
-    uint64_t* base;  // element i at base[i * stride]
-    int64_t stride;
-    int64_t n;
-    int64_t K;
-    __device__ uint64_t& at(int64_t i) { return base[i * stride]; }
+    uint32_t base;  // element i at lds_heaps[base + i]
+    int32_t n;
+    int32_t K;
+    __device__ uint64_t& at(int32_t i) { return lds_heaps[base + (uint32_t)i]; }
     __device__ void push(uint64_t x) {
-        int64_t i = n++;
+        int32_t i = n++;
         while (i > 0) {
-            const int64_t p = (i - 1) >> 1;
+            const int32_t p = (i - 1) >> 1;
             const uint64_t hp = at(p);
             if (hp >= x) break;
             at(i) = hp;
@@ -233,11 +236,11 @@ struct Heap {
     __device__ uint64_t pop() {
         const uint64_t top = at(0);
         const uint64_t x = at(--n);
-        int64_t i = 0;
+        int32_t i = 0;
         for (;;) {
-            const int64_t l = 2 * i + 1;
+            const int32_t l = 2 * i + 1;
             if (l >= n) break;
-            int64_t c = l;
+            int32_t c = l;
             uint64_t hc = at(l);
             if (l + 1 < n) {
                 const uint64_t hr = at(l + 1);
@@ -266,20 +269,20 @@ struct Heap {
     // rewrite the heap as its cancelled contents sorted decreasingly (a
     // decreasing array is a valid max-heap)
     __device__ void compact() {
-        const int64_t n0 = n;
-        int64_t out = 0;
+        const int32_t n0 = n;
+        int32_t out = 0;
         for (;;) {
             const uint64_t t = extract_max();
             if (t == NONE) break;
             at(n0 - 1 - out) = t;
             ++out;
         }
-        for (int64_t i = 0; i < out / 2; ++i) {
+        for (int32_t i = 0; i < out / 2; ++i) {
             const uint64_t a = at(n0 - out + i);
             at(n0 - out + i) = at(n0 - 1 - i);
             at(n0 - 1 - i) = a;
         }
-        for (int64_t i = 0; i < out; ++i) at(i) = at(n0 - out + i);
+        for (int32_t i = 0; i < out; ++i) at(i) = at(n0 - out + i);
         n = out;
     }
     __device__ bool room(int64_t extra) {
@@ -348,20 +351,12 @@ __device__ inline void defer_column(const D1K& P, uint32_t c, uint64_t off, uint
 // of a wavefront do not wait for each other's columns.
 template <bool NC>  // NC: the ablation without caching
 __global__ __launch_bounds__(DB) void k_d1(D1K P) {
-    extern __shared__ uint64_t lds_heaps[];
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    // scratch exists for nthreads lanes only; the others take no work
+    // the lanes beyond nthreads take no work
     const bool real = tid < P.nthreads;
     Heap H;
-    if (P.lds) {
-        H.base = lds_heaps + (int64_t)threadIdx.x * P.K;
-        H.stride = 1;
-    } else {
-        // each lane's heap contiguous: its sift paths stay in its own cache lines
-        H.base = P.scratch + (real ? tid : 0) * P.K;
-        H.stride = 1;
-    }
-    H.K = P.K;
+    H.base = (uint32_t)(threadIdx.x * P.K);
+    H.K = (int32_t)P.K;
     H.n = 0;
     const int64_t V = P.g.V;
     unsigned long long steps = 0, evictions = 0, adds = 0;
@@ -459,8 +454,8 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
                     defer_column(P, c, bo >> 24, bl);
                     return 1;
                 }
-                for (int64_t i = 1; i < bl; ++i) H.at(i - 1) = ld_rlx64(&B[i]);
-                H.n = bl - 1;
+                for (int32_t i = 1; i < (int32_t)bl; ++i) H.at(i - 1) = ld_rlx64(&B[i]);
+                H.n = (int32_t)bl - 1;
                 have = true;  // tau (= B[0]) is its top
                 return 0;
             }
@@ -2511,19 +2506,19 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
         int cur = 0;
         bool overflow = false;
         unsigned long long hc[N_CTRS] = {0};
-        // pass plan: thread-per-column with heaps of k keys (lane passes, in LDS
-        // or in global scratch), then one workgroup per column with boundaries
+        // pass plan: thread-per-column with heaps of k keys in LDS (lane
+        // passes), then one workgroup per column with boundaries
         // of up to k entries (lengths stay below 2^24: the cached length field).
         // t = lanes or workgroups: as many lanes as the LDS heaps leave resident
         // (160 KB per CU: 4 workgroups of 256 lanes x 20 keys, or 6 of 64 lanes x
         // 48 keys).
         PassPlan plan[MAX_PASSES] = {
-            {LDS_K, 256 * 4 * 256, 256, true, true},
-            {LDS_K2, 256 * 6 * 64, 64, true, true},
-            {(int64_t)1 << 15, 1024, WB, false, false},
-            {(int64_t)1 << 20, 512, WB, false, false},
-            {((int64_t)1 << 24) - 1024, 64, WB, false, false},
-            {0, 0, 0, false, false},
+            {LDS_K, 256 * 4 * 256, 256, true},
+            {LDS_K2, 256 * 6 * 64, 64, true},
+            {(int64_t)1 << 15, 1024, WB, false},
+            {(int64_t)1 << 20, 512, WB, false},
+            {((int64_t)1 << 24) - 1024, 64, WB, false},
+            {0, 0, 0, false},
         };
         uint32_t long_add = LONG_ADD, part_span = PART_SPAN;
         uint64_t coop_min = COOP_MIN;
@@ -2556,10 +2551,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             const int64_t T = std::max<int64_t>(1, std::min<int64_t>(nwork, plan[pass].t));
             const auto t_pass = std::chrono::steady_clock::now();
             const bool lane_pass = plan[pass].lane;
-            const bool in_lds = plan[pass].lds;
-            const size_t need = in_lds      ? 8
-                                : lane_pass ? (size_t)8 * T * K
-                                            : (size_t)8 * T * (2 * K + PCAP + K / part_span + 2);
+            const size_t need = lane_pass ? 8 : (size_t)8 * T * (2 * K + PCAP + K / part_span + 2);
             if (grow(s.scratch, s.scratch_cap, need, s.bytes, s.limit)) return oom("working boundaries");
             D1K P;
             P.g = in.g;
@@ -2584,7 +2576,6 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             P.scratch = (uint64_t*)s.scratch;
             P.K = K;
             P.nthreads = T;
-            P.lds = in_lds ? 1 : 0;
             P.long_add = long_add;
             P.nslots = T;
             P.part_span = part_span;
@@ -2602,7 +2593,7 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
             if (lane_pass)
                 hipLaunchKernelGGL(in.no_cache ? k_d1<true> : k_d1<false>,
                                    dim3((unsigned)((T + plan[pass].db - 1) / plan[pass].db)), dim3(plan[pass].db),
-                                   in_lds ? (size_t)8 * plan[pass].db * K : 0, st, P);
+                                   (size_t)8 * plan[pass].db * K, st, P);
             else
                 hipLaunchKernelGGL(k_d1_wide, dim3((unsigned)std::max<int64_t>(T, 2 * ncu)), dim3(WB), 0, st, P);
             uint32_t f = 0;
