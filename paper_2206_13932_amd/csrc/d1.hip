@@ -825,7 +825,7 @@ __device__ uint32_t merge_seg(WideShared& L, const uint64_t* X, uint32_t len, co
 // cooperative full merge (defined below with the job board)
 __device__ __noinline__ uint32_t coop_merge(WideShared& L, unsigned long long* ctrs, uint32_t* flags, const uint64_t* b,
                                             uint32_t span, const uint64_t* low, uint32_t na, uint32_t nb, uint64_t* tmp,
-                                            uint64_t* stat, uint64_t* X);
+                                            uint64_t* stat, int xb);
 // may other workgroups help with a merge now? (the pass has dedicated
 // helpers, or its queue of columns is exhausted)
 __device__ inline bool coop_possible(const D1K& P) {
@@ -866,7 +866,8 @@ __device__ __forceinline__ uint32_t merge_low(const D1K& P, WideShared& L, uint6
         for (uint32_t k = t; k < m; k += WB) st_rlx64(sbuf + (m - 1 - k), S[k]);
         __syncthreads();
         moved += n + m;
-        const uint32_t out = coop_merge(L, P.ctrs, P.flags, sbuf, P.part_span, low, n, m, tmp, stat, stg);
+        const uint32_t out = coop_merge(L, P.ctrs, P.flags, sbuf, P.part_span, low, n, m, tmp, stat,
+                                        stg == L.top[1] ? 1 : 0);
         if (out == ~0u) return 0;  // a wait ran out; the consistency flag is set
         uint64_t* w = low;
         low = tmp;
@@ -1027,9 +1028,13 @@ __device__ inline void bitonic2(WideShared& L, uint64_t (&e)[2]) {
     }
 }
 
-__device__ uint32_t sort_cancel(WideShared& L, uint32_t total, uint64_t* out) {
+// the LDS buffer that receives sort_cancel's output (named, not passed as a
+// pointer, so that its stores compile to LDS instructions)
+enum SortOut { TO_RAW, TO_SRC, TO_TOP0, TO_TOP1 };
+__device__ uint32_t sort_cancel(WideShared& L, uint32_t total, SortOut to) {
     static_assert(IPW == 4 && WB == 256 && NW == 1024, "exchange distances assume 4 entries per thread");
     const uint32_t t = threadIdx.x;
+    uint64_t* const out = to == TO_RAW ? L.raw : to == TO_SRC ? L.src : L.top[to == TO_TOP1 ? 1 : 0];
     if (total <= (uint32_t)WB) {
         uint64_t x = t < total ? L.raw[t] : PAD;
         __syncthreads();  // raw is reused below
@@ -1149,7 +1154,7 @@ __device__ __forceinline__ void flush(const D1K& P, WideShared& L, Col& C, uint6
     }
     __syncthreads();
     // sorted in place: the low merge does not use raw
-    const uint32_t m = sort_cancel(L, C.np, L.raw);
+    const uint32_t m = sort_cancel(L, C.np, TO_RAW);
     C.np = 0;
     if (m == 0) return;
     C.nl = merge_low(P, L, low, C.nl, L.raw, m, tmp, L.top[C.cur ^ 1], pend, stat, moved);
@@ -1209,7 +1214,7 @@ __device__ __forceinline__ void load_col(WideShared& L, Col& C, uint64_t* low, c
     if (len <= (uint32_t)NW) {  // possibly a lane pass's unsorted copy: sort and cancel it
         for (uint32_t i = t; i < len; i += WB) L.raw[i] = ld_rlx64(src + i);
         __syncthreads();
-        C.nt = sort_cancel(L, len, L.top[C.cur]);
+        C.nt = sort_cancel(L, len, C.cur ? TO_TOP1 : TO_TOP0);
         C.nl = 0;
         C.np = 0;
         C.lmax = 0;
@@ -1388,12 +1393,14 @@ __device__ inline void local_bound(const uint64_t* XA, uint32_t la, const uint64
     if (i > 0 && j < lb && XA[i - 1] == XB[j]) ++j;
 }
 
-// Merge part p of job J (by the whole block) into J.out at its scanned offset.
-// Returns false when a look-back wait ran out (the kernel's consistency flag
-// is then set).
+// Merge part p of job J (by the whole block) into J.out at its scanned offset,
+// staging its entries in top buffer xb (named by index, so that its accesses
+// compile to LDS instructions). Returns false when a look-back wait ran out
+// (the kernel's consistency flag is then set).
 __device__ __noinline__ bool merge_part(WideShared& L, const Job J, uint32_t p, unsigned long long* ctrs, uint32_t* flags,
-                                        uint64_t* X) {
+                                        int xb) {
     const uint32_t t = threadIdx.x;
+    uint64_t* const X = L.top[xb];
     const uint64_t tot = J.na + J.nb;
     const uint64_t d0 = (uint64_t)p * J.span, d1 = min(tot, d0 + J.span);
     part_bounds(L, J, d0, d1);
@@ -1501,7 +1508,7 @@ __device__ inline uint64_t* board_slot(unsigned long long* ctrs, int s) { return
 // ~0u when a wait ran out.
 __device__ __noinline__ uint32_t coop_merge(WideShared& L, unsigned long long* ctrs, uint32_t* flags, const uint64_t* b,
                                             uint32_t span, const uint64_t* low, uint32_t na, uint32_t nb, uint64_t* tmp,
-                                            uint64_t* stat, uint64_t* X) {
+                                            uint64_t* stat, int xb) {
     const uint32_t t = threadIdx.x;
     Job J;
     J.a = low;
@@ -1562,7 +1569,7 @@ __device__ __noinline__ uint32_t coop_merge(WideShared& L, unsigned long long* c
         const uint32_t k = (uint32_t)L.ints[2];
         __syncthreads();
         if (k >= J.nparts) break;
-        ok = merge_part(L, J, k, ctrs, flags, X) && ok;
+        ok = merge_part(L, J, k, ctrs, flags, xb) && ok;
         if (B && t == 0) atomicAdd((unsigned long long*)&B[1], 1ull);
     }
     if (t == 0 && B) {
@@ -1653,7 +1660,7 @@ __device__ __noinline__ void help(WideShared& L, unsigned long long* ctrs, int64
         }
         __syncthreads();
         if (part >= 0) {
-            merge_part(L, J, (uint32_t)part, ctrs, flags, L.top[0]);
+            merge_part(L, J, (uint32_t)part, ctrs, flags, 0);
             if (t == 0) {  // the part's coherent stores are complete (merge_part waited)
                 atomicAdd((unsigned long long*)&board_slot(ctrs, slot)[1], 1ull);
                 atomicAdd(&ctrs[HELPED_PARTS], 1ull);
@@ -1695,7 +1702,7 @@ __device__ __forceinline__ bool add_long(const D1K& P, WideShared& L, Col& C, ui
             // staged decreasing in pend (empty after the flush above)
             for (uint32_t k = t; k < alen; k += WB) L.raw[k] = ld_rlx64(P.heap + aoff + k);
             __syncthreads();
-            nb = sort_cancel(L, alen, L.src);
+            nb = sort_cancel(L, alen, TO_SRC);
             // (coherent stores: the parts read B with coherent loads)
             for (uint32_t k = t; k < nb; k += WB) st_rlx64(pend + (nb - 1 - k), L.src[k]);
             __syncthreads();
@@ -1703,7 +1710,7 @@ __device__ __forceinline__ bool add_long(const D1K& P, WideShared& L, Col& C, ui
         }
         moved += C.nl + alen;
         if (nb == 0) return true;  // everything cancelled
-        const uint32_t out = coop_merge(L, P.ctrs, P.flags, b, P.part_span, low, C.nl, nb, tmp, stat, L.top[0]);
+        const uint32_t out = coop_merge(L, P.ctrs, P.flags, b, P.part_span, low, C.nl, nb, tmp, stat, 0);
         if (out == ~0u) return false;
         uint64_t* sw = low;
         low = tmp;
@@ -1720,7 +1727,7 @@ __device__ __forceinline__ bool add_long(const D1K& P, WideShared& L, Col& C, ui
     if (small) {
         for (uint32_t k = t; k < alen; k += WB) L.raw[k] = ld_rlx64(P.heap + aoff + k);
         __syncthreads();
-        nb = sort_cancel(L, alen, L.src);
+        nb = sort_cancel(L, alen, TO_SRC);
     }
     const uint32_t na = C.nl;
     uint64_t* X = L.top[0];
@@ -2025,7 +2032,7 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
                 }
                 retries = 0;
                 expanded += go ? 1 : 0;
-                const uint32_t m = sort_cancel(L, total, L.src);
+                const uint32_t m = sort_cancel(L, total, TO_SRC);
                 lap(3);
                 ++rounds;
                 if ((int64_t)(C.n() - stop_at) + m > P.K) {
@@ -2140,7 +2147,7 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
                     L.raw[t] = t == 0 ? k3[0] : t == 1 ? k3[1] : k3[2];
                 }
                 __syncthreads();
-                const uint32_t m = sort_cancel(L, 3, L.src);
+                const uint32_t m = sort_cancel(L, 3, TO_SRC);
                 uint64_t tq = 0, u0 = 0, u1 = 0;
                 merge_col(P, L, C, low, pend, stat, m, tmp, moved, u0, u1, tq);
                 nmax = max(nmax, C.n());
@@ -2189,7 +2196,7 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
             if (alen <= (uint32_t)NW) {  // possibly unsorted: sort and cancel, then merge
                 for (uint32_t k = t; k < alen; k += WB) L.raw[k] = ld_rlx64(P.heap + aoff + k);
                 __syncthreads();
-                const uint32_t m = sort_cancel(L, alen, L.src);
+                const uint32_t m = sort_cancel(L, alen, TO_SRC);
                 uint64_t tq = 0, u0 = 0, u1 = 0;
                 merge_col(P, L, C, low, pend, stat, m, tmp, moved, u0, u1, tq);
                 nmax = max(nmax, C.n());
