@@ -83,13 +83,13 @@ constexpr int N_CTR_WORDS = OPEN_JOBS + 16;
 
 // consistency checks of the D1 kernels
 enum : uint32_t { G_STEPS = 1, G_RETRIES, G_KEY, G_VPARTNER, G_D0, G_EVICT_HEAD, G_WSTEPS, G_WRETRIES, G_WTOP,
-                  G_LOOKBACK, G_JOBWAIT, G_COUNT };
+                  G_LOOKBACK, G_JOBWAIT, G_HEAPPTR, G_COUNT };
 static const char* const kGuardName[G_COUNT] = {
     "unknown", "a column ran out of steps", "a look-again did not resolve", "a key is no edge",
     "a vertex's partner edge at the top", "a D0-paired edge at the top", "an evicted column's cached head moved",
     "a workgroup column ran out of steps", "a workgroup look-again did not resolve",
     "a workgroup column's top is no critical edge", "a merge part's look-back wait ran out",
-    "a merge job's wait for its parts ran out"};
+    "a merge job's wait for its parts ran out", "a boundary pointer lies outside the publication heap"};
 // record the first failed check and flag the call
 __device__ inline void guard_fail(unsigned long long* ctrs, uint32_t* flags, uint32_t why) {
     atomicCAS(&ctrs[GUARD_REASON], 0ull, (unsigned long long)why);
@@ -194,19 +194,22 @@ __device__ inline EdgeDec edecode_ids(const GridDev& g, int bpr, uint64_t key, i
     e.id = (uint32_t)(e.lo * 7 + (m - 1));
     return e;
 }
+// (mask 0: the key holds a rank outside the grid or twice; the lookups then
+// read ranks 0 and 1 instead, so that no address depends on it)
 __device__ inline EdgeDec edecode(const GridDev& g, const uint32_t* order, int bpr, uint64_t key) {
     EdgeDec e;
     e.ra = (uint32_t)(key >> bpr);
     e.rb = (uint32_t)(key & ((1ull << bpr) - 1));
-    e.va = order[e.ra];
-    e.vb = order[e.rb];
+    const bool ok = !(key >> (2 * bpr)) && (int64_t)e.ra < g.V && (int64_t)e.rb < g.V && e.ra != e.rb;
+    e.va = order[ok ? e.ra : 0u];
+    e.vb = order[ok ? e.rb : 1u];
     e.lo = e.va < e.vb ? e.va : e.vb;
     int64_t d = (e.va < e.vb ? e.vb : e.va) - e.lo;
     int m = 0;
     if (d >= g.sz) { m |= 4; d -= g.sz; }
     if (d >= g.sy) { m |= 2; d -= g.sy; }
     if (d >= 1) { m |= 1; }
-    e.mask = m;
+    e.mask = ok ? m : 0;
     e.id = (uint32_t)(e.lo * 7 + (m - 1));
     return e;
 }
@@ -315,6 +318,14 @@ __device__ inline uint64_t heap_alloc(const D1K& P, uint32_t seg, uint64_t len) 
         if (off + len <= P.seg_cap) return (uint64_t)sg * P.seg_cap + off;
     }
     return NONE;
+}
+
+// A packed boundary pointer (offset << 24 | length) whose entries lie inside
+// the publication heap. Pointers come from other columns' publications; one
+// that does not is reported as a failed check instead of being followed.
+__device__ inline bool heap_span_ok(const D1K& P, uint64_t packed) {
+    const uint64_t off = packed >> 24, len = packed & 0xFFFFFF;
+    return packed != EMPTY64 && len > 0 && off + len <= (uint64_t)P.heap_cap;
 }
 
 // Copy {top (optional)} + the heap array as it stands to the publication
@@ -441,6 +452,10 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
                 // evicted o: carry on reducing it from its cached boundary
                 ++evictions;
                 const uint64_t bo = ld_rlx64(&P.bndptr[o]);
+                if (!heap_span_ok(P, bo)) {
+                    guard_fail(P.ctrs, P.flags, G_HEAPPTR);
+                    return 2;
+                }
                 const uint64_t* B = P.heap + (bo >> 24);
                 const int64_t bl = (int64_t)(bo & 0xFFFFFF);
                 if (ld_rlx64(&B[0]) != tau) {
@@ -478,6 +493,10 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
                 if (b == EMPTY64) {
                     ++retries;
                     return 0;
+                }
+                if (!heap_span_ok(P, b)) {
+                    guard_fail(P.ctrs, P.flags, G_HEAPPTR);
+                    return 2;
                 }
                 B = P.heap + (b >> 24);
                 if (ld_rlx64(&B[0]) != tau) {  // o moved on: look again
@@ -546,6 +565,10 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
                 const int64_t len = P.work_len[next];
                 if (len > H.K) {
                     atomicOr(P.flags, FLAG_WORK);
+                    active = false;
+                    stop = true;
+                } else if (off + (uint64_t)len > (uint64_t)P.heap_cap) {
+                    guard_fail(P.ctrs, P.flags, G_HEAPPTR);
                     active = false;
                     stop = true;
                 } else {
@@ -1821,6 +1844,10 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
                 if (t == 0) atomicOr(P.flags, FLAG_WORK);
                 break;
             }
+            if (off + n0 > (uint64_t)P.heap_cap) {
+                if (t == 0) guard_fail(P.ctrs, P.flags, G_HEAPPTR);
+                break;
+            }
             if (t == 0) atomicAdd(&P.ctrs[C_ACTIVE], 1ull);
             load_col(L, C, low, P.heap + off, n0);
         }
@@ -1890,7 +1917,9 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
                         // checked against wkey when its entries are loaded.
                         const uint64_t bo = ld_rlx64(&P.bndptr[o]);
                         const uint32_t zl = (uint32_t)(bo & 0xFFFFFF) - 1;
-                        if (bo != EMPTY64 && zl <= BATCH_ADD_MAX) {
+                        // (a pointer outside the heap is not batched: the
+                        // addition at the top reports it)
+                        if (heap_span_ok(P, bo) && zl <= BATCH_ADD_MAX) {
                             zoff = bo >> 24;
                             nkeys = zl;
                             batched = true;
@@ -2108,6 +2137,11 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
                     continue;
                 }
                 if (o == EMPTY32) break;  // settled
+                if (!heap_span_ok(P, bo)) {
+                    if (t == 0) guard_fail(P.ctrs, P.flags, G_HEAPPTR);
+                    stop = true;
+                    break;
+                }
                 ++evictions;
                 c = o;
                 nc_min = PAD;
@@ -2158,12 +2192,17 @@ __global__ __launch_bounds__(WB, 2) void k_d1_wide(D1K P) {
             if (t == 0) {
                 const uint64_t b = ld_rlx64(&P.bndptr[o]);
                 L.u64s[3] = b;
-                L.ints[7] = (b != EMPTY64 && ld_rlx64(P.heap + (b >> 24)) == tau) ? 1 : 0;
+                L.ints[7] = b == EMPTY64 ? 0 : !heap_span_ok(P, b) ? 2 : ld_rlx64(P.heap + (b >> 24)) == tau ? 1 : 0;
             }
             __syncthreads();
             const uint64_t b = L.u64s[3];
             const int ok = L.ints[7];
             __syncthreads();
+            if (ok == 2) {
+                if (t == 0) guard_fail(P.ctrs, P.flags, G_HEAPPTR);
+                stop = true;
+                break;
+            }
             if (!ok) {  // o moved on: look again
                 ++retries;
                 continue;
