@@ -488,7 +488,11 @@ def main():
                    "stage_ms": {k: round(v, 3) for k, v in zip(
                        ["order", "gradient_and_counts", "critical_sort", "d0_d2", "d1", "output", "total",
                         "gradient_kernel"], st)}},
-        "roofline": {"kernel": "k_gradient", "bound": "hbm", "achieved": round(achieved, 1),
+        "roofline": {"kernel": "k_gradient",
+                     "note": "the kernel with an algorithmic byte and instruction count; by time the D1 workgroup "
+                             "pass and the D2 tracer (dependent rounds and gathers, no algorithmic byte count) are "
+                             "larger: their fetched-line rates are in profiles/pairing_kernels_counters_smooth512.md",
+                     "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes": int(gbytes),
                      "avg_kernel_ms": round(g_avg_ms, 4), "valu_issue": valu},
