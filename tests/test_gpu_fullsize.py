@@ -197,3 +197,54 @@ def test_fullsize_diagrams_against_oracle_digests(name):
                 m = _order_space(shape, rank, pairs[d], d)
                 print(f"[fullsize-digest] {key}: {len(m)} pairs of positive persistence", flush=True)
                 assert len(m) == gold[key]["n"] and _sha(m) == gold[key]["sha256"], (name, key)
+
+
+@pytest.mark.gpu
+def test_largest_grid_counted_labels():
+    """A grid of 2^28 vertices or more (600 x 640 x 720 = 276.5 M, triangle ids up
+    to 3.3 * 10^9, above 2^31; the library's limit is 12 V < 2^32). Ranks then
+    no longer fit beside the neighbour index in one 32-bit sort word, so the
+    gradient kernel's instance that counts labels runs. Checked: the vertex
+    order against the oracle's, sampled lower stars against the oracle's
+    ProcessLowerStars, the Euler characteristic of the critical cells, and the
+    diagram's counts and canonical order."""
+    import torch
+    from paper_2206_13932_amd import dms
+    shape = (600, 640, 720)
+    V = shape[0] * shape[1] * shape[2]
+    assert V >= 1 << 28 and 12 * V < 1 << 32
+    print(f"[fullsize] largest grid {shape}: generating", flush=True)
+    f = sf.gaussians(shape, 1, 64, 0.005)
+    ctx = dms.Context(0)
+    field = torch.from_numpy(f).cuda()
+    print("[fullsize] largest grid: gradient", flush=True)
+    ncrit = ctx.gradient(field)
+    rank_gpu = ctx.debug(dms.BUF_RANK)
+    print("[fullsize] largest grid: oracle vertex order", flush=True)
+    rank = oracle.vertex_order(f)
+    assert np.array_equal(rank_gpu, rank)
+    del rank_gpu
+    G = ctx.debug(dms.BUF_GRADIENT, np.uint8).reshape(26, -1)
+    verts = _sample_vertices(shape, rank, np.random.default_rng(11))
+    print(f"[fullsize] largest grid: sampling {len(verts)} lower stars", flush=True)
+    recs = oracle.lower_star_sample(shape, rank, verts)
+    cells = recs[:, :, 0].ravel()
+    want = recs[:, :, 1].ravel()
+    keep = cells != -2
+    assert np.array_equal(H.decode_cells(shape, G, cells[keep]), want[keep])
+    del G
+    c = ncrit
+    assert c[0] - c[1] + c[2] - c[3] == 1
+    print("[fullsize] largest grid: whole diagram", flush=True)
+    out = ctx.diagram(field)
+    d0, d1, d2 = (out[d].cpu().numpy() for d in range(3))
+    print(f"[fullsize] largest grid: pairs {len(d0)} {len(d1)} {len(d2)}", flush=True)
+    assert len(d0) == c[0] and len(d2) == c[3] and len(d1) == c[1] - c[0] + 1 == c[2] - c[3]
+    assert (d0[:-1, 1] >= 0).all() and d0[-1, 1] == -1
+    assert rank[d0[-1, 0]] == 0
+    assert (d1[:, 1] >= 0).all() and (d2[:, 1] >= 0).all()
+    for p in (d0[:-1], d1, d2):
+        assert (np.diff(p[:, 0]) > 0).all()
+    # the death ids of D1 are triangle ids: some lie above 2^31 on a grid this size
+    assert d1[:, 1].max() < 12 * V
+    ctx.close()
