@@ -119,7 +119,7 @@ __host__ __device__ inline uint64_t labels_of(uint32_t inv0, uint32_t inv1, int 
 }
 
 // ProcessLowerStars on a vertex with k >= 1 lower neighbours.
-// T: star tables (face, cof_lo, cof_hi, slrec, nbrec, l27, cpos_pos, slnb);
+// T: star tables (face, cof_lo, cof_hi, slrec, nbrec, l27, cpos_pos, slnb, slnbc);
 // inv0 / inv1 as relabel leaves them (15 past label k-1); levels: the number
 // of labels the minimum searches go through, at least k (lanes that run in
 // lock-step pass the largest k among them, so that the searches' levels are
