@@ -424,8 +424,19 @@ __global__ __launch_bounds__(DB) void k_d1(D1K P) {
                 hint_vb[0] = e.ra > rw ? w : e.va;
                 hint_va[1] = e.rb > rw ? e.vb : w;
                 hint_vb[1] = e.rb > rw ? w : e.vb;
-                H.push(hint_key[0]);
-                H.push(hint_key[1]);
+                // The larger new key, when it is above every heap entry, is the
+                // boundary's highest key, present once: it is the next top as
+                // extract_max would return it, and it stays out of the heap
+                // (a push and the next step's pop saved).
+                const uint64_t kmax = hint_key[0] > hint_key[1] ? hint_key[0] : hint_key[1];
+                const uint64_t kmin = hint_key[0] > hint_key[1] ? hint_key[1] : hint_key[0];
+                H.push(kmin);
+                if (kmax > H.at(0)) {
+                    tau = kmax;
+                    have = true;
+                } else {
+                    H.push(kmax);
+                }
                 return 0;
             }
             defer = true;
