@@ -42,8 +42,8 @@ HBM_PEAK_GBS = 8000.0
 # Counters of one gradient-kernel launch on smooth512 (profiles/gradient_hbm_counters_smooth512.md),
 # valid for the kernel sources with this hash only: HBM bytes from FETCH_SIZE (x2 calibration) and
 # WRITE_SIZE, and the VALU wave instructions issued
-GRADIENT_COUNTERS = {"sources_sha256_16": "bc92c8fea7870f98", "workload": "smooth512",
-                     "traffic_bytes": 1609067725 + 6572371866, "valu_wave_insts": 6864131217}
+GRADIENT_COUNTERS = {"sources_sha256_16": "b910efd99829bc14", "workload": "smooth512",
+                     "traffic_bytes": 1609068339 + 6573050368, "valu_wave_insts": 6444384616}
 # VALU issue ceiling for the plain (non-packed) 32-bit integer and bit operations the gradient
 # kernel runs: the fp64 vector peak, 78.6 TFLOP/s = 2 FLOP x 64 lanes per CU per clock at 256 CUs
 # x 2.4 GHz, i.e. 16-lane SIMDs taking 4 cycles per wave64 instruction: one wave64 instruction

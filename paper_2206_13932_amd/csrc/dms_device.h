@@ -124,8 +124,7 @@ struct StarTables {
     uint8_t cpos_pos[NNB];    // 1 if the coordinate sum of n is > 0 (x precedes n)
     uint16_t cellnb[NSLOT];   // neighbour set of each slot
     uint64_t face[NSLOT];     // facets inside the star (slot bitmask, all < 64)
-    uint64_t cof_lo[NSLOT];   // cofacets inside the star, slots 0..63
-    uint16_t cof_hi[NSLOT];   // cofacets, slots 64..73 (bit s-64)
+    uint64_t cofc[NSLOT];     // cofacets inside the star (slots 14..73: bit s - 14)
     uint8_t plane[NSLOT];     // gradient byte plane of the slot's simplex
     int8_t aoff[NSLOT][3];    // anchor offset relative to x
     int8_t al27[NSLOT];       // aoff.x + 3 aoff.y + 9 aoff.z

@@ -29,8 +29,7 @@ constexpr int GB = 1024;  // threads per block (vertices handed to lanes by lowe
 
 struct LdsTables {
     uint64_t face[NSLOT];
-    uint64_t cof_lo[NSLOT];
-    uint16_t cof_hi[NSLOT];
+    uint64_t cofc[NSLOT];
     uint16_t cellnb[NSLOT];
     SlotMask slnb[16];  // slots holding neighbour n (rows 14, 15 empty)
     uint64_t slnbc[32];  // the same rows for slots 14..73, one word each (16-byte stride)
@@ -78,8 +77,7 @@ __global__ __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     // cooperative copy of the star tables into LDS
     for (int i = tid; i < NSLOT; i += GB) {
         T.face[i] = kStar.face[i];
-        T.cof_lo[i] = kStar.cof_lo[i];
-        T.cof_hi[i] = kStar.cof_hi[i];
+        T.cofc[i] = kStar.cofc[i];
         T.cellnb[i] = kStar.cellnb[i];
         T.slrec[i] = kStar.slrec[i];
         T.plane[i] = kStar.plane[i];

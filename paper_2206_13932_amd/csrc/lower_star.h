@@ -119,7 +119,7 @@ __host__ __device__ inline uint64_t labels_of(uint32_t inv0, uint32_t inv1, int 
 }
 
 // ProcessLowerStars on a vertex with k >= 1 lower neighbours.
-// T: star tables (face, cof_lo, cof_hi, slrec, nbrec, l27, cpos_pos, slnb, slnbc);
+// T: star tables (face, cofc, slrec, nbrec, l27, cpos_pos, slnb, slnbc);
 // inv0 / inv1 as relabel leaves them (15 past label k-1); levels: the number
 // of labels the minimum searches go through, at least k (lanes that run in
 // lock-step pass the largest k among them, so that the searches' levels are
@@ -155,37 +155,35 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
     cls_lo = ~in_lo | (uint64_t)1 << n0;
     uint64_t z_lo = 0x3FFFull & ~cls_lo;  // the other edges
     uint32_t z_hi = 0;
-    // The first queue only ever holds cofacets (triangles and tetrahedra,
-    // slots 14..73): one word, bit s - 14.
+    // Cofacets are triangles and tetrahedra (slots 14..73): sets of them are
+    // one word, bit s - 14 ("cofacet words"). The first queue only ever holds
+    // cofacets.
     uint64_t o = 0;
     auto cof_word = [](uint64_t lo, uint32_t hi) __attribute__((always_inline)) {
         return lo >> NNB | (uint64_t)hi << (64 - NNB);
     };
-    // The unpaired (unclassified) facets of every slot, a 2-bit count per
-    // slot kept in two bit planes (u0: bit 0, u1: bit 1). The facets inside
-    // the star of a cell of L(x) are cells of L(x): 2 for a triangle, 3 for a
-    // tetrahedron, none for an edge (x itself is paired apart). The counts of
+    // the classified cells among them (those outside L(x) count as classified)
+    uint64_t cls_c = ~cof_word(in_lo, in_hi);
+    // The unpaired (unclassified) facets of every cofacet slot, a 2-bit count
+    // kept in two bit planes of cofacet words (u0: bit 0, u1: bit 1). The
+    // facets inside the star of a cell of L(x) are cells of L(x): 2 for a
+    // triangle, 3 for a tetrahedron (x itself is paired apart). The counts of
     // slots outside L(x) are never read (those slots count as classified).
-    uint64_t u0_lo = ~((1ull << 50) - 1), u1_lo = ~0x3FFFull;
-    uint32_t u0_hi = (1u << (NSLOT - 64)) - 1, u1_hi = u0_hi;
+    uint64_t u0 = ~((1ull << (50 - NNB)) - 1), u1 = ~0ull;
     // m: the cofacets of the cells just classified (the cofacets of a cell
     // and of its facet are disjoint, so every count drops by one). Those
     // still unclassified go to the queue their count now names: one unpaired
     // facet -> o, none -> z (and out of o). A cell with none left was pushed
     // to o when it had one; it would leave o for z when popped, with no other
     // effect, so it moves there now and costs no pop.
-    auto push_cofaces = [&](uint64_t m_lo, uint32_t m_hi) __attribute__((always_inline)) {
-        u1_lo ^= m_lo & ~u0_lo;
-        u0_lo ^= m_lo;
-        u1_hi ^= m_hi & ~u0_hi;
-        u0_hi ^= m_hi;
-        const uint64_t c_lo = m_lo & ~cls_lo & ~u1_lo;  // count 0 or 1
-        const uint32_t c_hi = m_hi & ~cls_hi & ~u1_hi;
-        const uint64_t none_lo = c_lo & ~u0_lo;
-        const uint32_t none_hi = c_hi & ~u0_hi;
-        o = (o | cof_word(c_lo & u0_lo, c_hi & u0_hi)) & ~cof_word(none_lo, none_hi);
-        z_lo |= none_lo;
-        z_hi |= none_hi;
+    auto push_cofaces = [&](uint64_t m) __attribute__((always_inline)) {
+        u1 ^= m & ~u0;
+        u0 ^= m;
+        const uint64_t c = m & ~cls_c & ~u1;  // count 0 or 1
+        const uint64_t none = c & ~u0;
+        o = (o | c) & ~none;
+        z_lo |= none << NNB;
+        z_hi |= (uint32_t)(none >> (64 - NNB));
     };
     // The member of a non-empty set with the smallest mask is what is left
     // after the levels: a set of one bit. Every level runs: the lanes of a
@@ -232,7 +230,7 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
         }
         return q;
     };
-    push_cofaces(T.cof_lo[n0], T.cof_hi[n0]);
+    push_cofaces(T.cofc[n0]);
     for (int guard = 0; guard < 4 * NSLOT; ++guard) {
         while (o) {
             const uint64_t ab = min_of_cof(o);
@@ -246,8 +244,9 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
             pair_cells(p, a);
             cls_lo |= ab << NNB | (uint64_t)1 << p;
             cls_hi |= (uint32_t)(ab >> (64 - NNB));
+            cls_c |= ab | (p >= NNB ? (uint64_t)1 << (p - NNB) : 0);
             z_lo &= ~((uint64_t)1 << p);
-            push_cofaces(T.cof_lo[a] | T.cof_lo[p], (uint32_t)(T.cof_hi[a] | T.cof_hi[p]));
+            push_cofaces(T.cofc[a] | T.cofc[p]);
         }
         if (!(z_lo | z_hi)) break;
         uint64_t clo = z_lo;
@@ -258,10 +257,11 @@ __host__ __device__ inline void lower_star_gradient(const Tab& T, uint64_t in_lo
         z_hi ^= chi;
         cls_lo |= clo;
         cls_hi |= chi;
+        cls_c |= cof_word(clo, chi);
         crit_lo |= clo;
         crit_hi |= chi;
         put(c, CODE_CRIT);
-        push_cofaces(T.cof_lo[c], T.cof_hi[c]);
+        push_cofaces(T.cofc[c]);
     }
 }
 

@@ -107,8 +107,7 @@ constexpr StarTables make_star_tables() {
                     fill_slot(T, s++, (uint16_t)((1 << a) | (1 << b) | (1 << c)));
     for (int i = 0; i < NSLOT; ++i) {
         T.face[i] = 0;
-        T.cof_lo[i] = 0;
-        T.cof_hi[i] = 0;
+        T.cofc[i] = 0;
     }
     for (int i = 0; i < NSLOT; ++i) T.slrec[i] = (uint32_t)T.cellnb[i] | (uint32_t)(T.al27[i] + 13) << 16;
     for (int n = 0; n < NNB; ++n)
@@ -129,9 +128,8 @@ constexpr StarTables make_star_tables() {
             if (T.dim[j] != T.dim[i] + 1) continue;
             if ((T.cellnb[i] & T.cellnb[j]) != T.cellnb[i]) continue;
             // j is a cofacet of i, i a facet of j
-            T.face[j] |= (uint64_t)1 << i;  // facets always sit below slot 64
-            if (j < 64) T.cof_lo[i] |= (uint64_t)1 << j;
-            else T.cof_hi[i] |= (uint16_t)(1 << (j - 64));
+            T.face[j] |= (uint64_t)1 << i;   // facets always sit below slot 64
+            T.cofc[i] |= (uint64_t)1 << (j - NNB);  // cofacets always sit at slot 14 or above
         }
     return T;
 }
