@@ -302,9 +302,23 @@ int64_t dms_debug_copy(dms_ctx* ctx, int what, void* dst, int64_t cap);
  *       before, and pivots met inside a re-reduction, or one that comes back,
  *       are added with cached boundaries (counted in DMS_BUF_STATS). The work
  *       can grow steeply on noisy fields; the kernels' step bounds then end
- *       the call with DMS_E_INTERNAL.
+ *       the call with DMS_E_INTERNAL;
+ *   DMS_OPT_D1_HEAP_KEYS     value > 0: every later D1 run starts with a
+ *       publication heap (the cached boundaries) of that many keys, at least
+ *       64, instead of 32 keys per column with a floor of 4 M keys. A small
+ *       grid then overflows it and goes through D1's restart: the heap grows
+ *       and D1 runs again from its first pass, up to three times (DMS_E_NOMEM
+ *       after that); the restarts are counted in DMS_BUF_STATS. 0 restores the
+ *       default sizing (a heap larger than it is kept); a negative value
+ *       returns DMS_E_INVAL.
  * Returns DMS_OK, or DMS_E_INVAL for an unknown option or a NULL ctx. */
-enum { DMS_OPT_D1_SMALL_PASSES = 1, DMS_OPT_LOG_PASSES = 2, DMS_OPT_D1_NO_SANDWICH = 3, DMS_OPT_D1_NO_CACHE = 4 };
+enum {
+    DMS_OPT_D1_SMALL_PASSES = 1,
+    DMS_OPT_LOG_PASSES = 2,
+    DMS_OPT_D1_NO_SANDWICH = 3,
+    DMS_OPT_D1_NO_CACHE = 4,
+    DMS_OPT_D1_HEAP_KEYS = 5
+};
 int dms_set_option(dms_ctx* ctx, int32_t option, int64_t value);
 
 /* Milliseconds of the last call's stages, measured with HIP events on the

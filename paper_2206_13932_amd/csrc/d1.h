@@ -26,6 +26,7 @@ struct D1Inputs {
     bool log_passes = false;    // debug: one stderr line per pass
     bool no_sandwich = false;   // ablation: every 2-saddle is a column, no D0 set-aside
     bool no_cache = false;      // ablation: add earlier owners' 2-saddle boundaries, not their cached ones
+    int64_t heap_keys = 0;      // debug: the publication heap starts with this many keys (0: default sizing)
 };
 
 struct D1State {

@@ -2537,7 +2537,18 @@ int d1_run(D1State& s, const D1Inputs& in, hipStream_t st, size_t budget_left, s
     if (grow(s.bndptr, s.bndptr_cap, 8 * (ncols + 1), s.bytes, s.limit)) return oom("boundary pointers");
     // two deferral queues (this pass / next pass): u64 (column, offset) + u32 length
     if (grow(s.dq, s.dq_cap, 2 * (size_t)(ncols + 1) * 16, s.bytes, s.limit)) return oom("deferral queues");
-    if (s.heap_cap < (size_t)8 * 32 * ncols) {
+    if (in.heap_keys > 0) {
+        // debug: a heap of exactly the given size, so that small grids overflow
+        // it and go through the restart below
+        const size_t want = (size_t)8 * (size_t)std::max<int64_t>(in.heap_keys, 64);
+        if (s.heap_cap != want) {
+            if (s.heap) (void)hipFree(s.heap);
+            s.bytes -= s.heap_cap;
+            s.heap = nullptr;
+            s.heap_cap = 0;
+            if (grow(s.heap, s.heap_cap, want, s.bytes, s.limit)) return oom("boundary heap");
+        }
+    } else if (s.heap_cap < (size_t)8 * 32 * ncols) {
         if (grow(s.heap, s.heap_cap, std::max<size_t>((size_t)8 << 22, (size_t)8 * 32 * ncols), s.bytes, s.limit))
             return oom("boundary heap");
     }

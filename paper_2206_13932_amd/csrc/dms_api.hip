@@ -55,6 +55,7 @@ struct dms_ctx {
     D1State d1;
     bool opt_d1_small = false, opt_log = false;  // debug options (dms_set_option)
     bool opt_no_sandwich = false, opt_no_cache = false;  // ablation variants of D1 (dms_set_option)
+    int64_t opt_heap_keys = 0;  // debug: D1's first publication heap, in keys (0: default sizing)
     bool virtual_max = true;  // DMS_VIRTUAL_MAX of the last gradient call (Sec. 5.2)
     // output staging
     Buf ob, od, okey, ocnt;
@@ -770,6 +771,7 @@ static int run_d1(dms_ctx* ctx) {
     in.log_passes = ctx->opt_log;
     in.no_sandwich = ctx->opt_no_sandwich;
     in.no_cache = ctx->opt_no_cache;
+    in.heap_keys = ctx->opt_heap_keys;
     std::string err;
     int r = d1_run(ctx->d1, in, ctx->st, d1_limit(ctx), err);
     if (r != DMS_OK) return fail(ctx, r, err);
@@ -1242,6 +1244,10 @@ int dms_set_option(dms_ctx* ctx, int32_t option, int64_t value) {
         case DMS_OPT_LOG_PASSES: ctx->opt_log = value != 0; return DMS_OK;
         case DMS_OPT_D1_NO_SANDWICH: ctx->opt_no_sandwich = value != 0; return DMS_OK;
         case DMS_OPT_D1_NO_CACHE: ctx->opt_no_cache = value != 0; return DMS_OK;
+        case DMS_OPT_D1_HEAP_KEYS:
+            if (value < 0) return fail(ctx, DMS_E_INVAL, "dms_set_option: DMS_OPT_D1_HEAP_KEYS must be >= 0");
+            ctx->opt_heap_keys = value;
+            return DMS_OK;
         default: return fail(ctx, DMS_E_INVAL, "dms_set_option: unknown option");
     }
 }

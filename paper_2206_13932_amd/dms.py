@@ -22,7 +22,7 @@ BUF_RANK, BUF_GRADIENT, BUF_CRIT0, BUF_ARCS0, BUF_ARCS2, BUF_STATS, BUF_D1LEN = 
 # most contributions dms_scatter_grad_noalloc takes (its static scratch)
 NOALLOC_MAX_CONTRIB = 1 << 22
 # debug options of a context (dms_set_option)
-OPT_D1_SMALL_PASSES, OPT_LOG_PASSES, OPT_D1_NO_SANDWICH, OPT_D1_NO_CACHE = 1, 2, 3, 4
+OPT_D1_SMALL_PASSES, OPT_LOG_PASSES, OPT_D1_NO_SANDWICH, OPT_D1_NO_CACHE, OPT_D1_HEAP_KEYS = 1, 2, 3, 4, 5
 _ERRNAMES = {-1: "DMS_E_INVAL", -2: "DMS_E_NAN", -3: "DMS_E_NOMEM", -4: "DMS_E_CAPACITY", -5: "DMS_E_HIP",
              -6: "DMS_E_STATE", -7: "DMS_E_INTERNAL"}
 
@@ -333,8 +333,8 @@ class Context:
 
     def set_option(self, option: int, value: int = 1):
         """Debug and ablation options (OPT_D1_SMALL_PASSES, OPT_LOG_PASSES,
-        OPT_D1_NO_SANDWICH, OPT_D1_NO_CACHE); they change how D1 splits, logs
-        or repeats its work, never a result."""
+        OPT_D1_NO_SANDWICH, OPT_D1_NO_CACHE, OPT_D1_HEAP_KEYS); they change how
+        D1 splits, logs or repeats its work, never a result."""
         rc = self.lib.dms_set_option(self.h, int(option), int(value))
         if rc != DMS_OK:
             self._raise(rc)

@@ -284,6 +284,44 @@ def test_parity_d1_every_deferral_pass():
 
 
 @pytest.mark.gpu
+@pytest.mark.skip(reason="D1 restart path: added after the GPU budget of its change was spent; it has not "
+                         "run on a GPU yet, and the restart is a suspect of the quarantined 512^3 noise "
+                         "fault, so its first run is a run of its own")
+def test_parity_d1_restart():
+    """A publication heap smaller than the cached boundaries need (the
+    context's debug option) makes D1 overflow it, grow it and run again from
+    its first pass; the pairs must not change. The heap starts at half of what
+    a plain run publishes, so that it doubles once or twice."""
+    torch, dms, ctx = _gpu_ctx()
+    plain = dms.Context(0)
+    for name, f in [("noise40", sf.noise((40, 44, 48), 11)),
+                    ("smooth48", sf.gaussians((48, 48, 48), 5, k=12, noise_frac=0.02))]:
+        print(f"[parity] case=d1_restart/{name}", flush=True)
+        res = oracle.run(f)
+        ft = torch.from_numpy(f).cuda()
+        ref = plain.diagram(ft)
+        published = int(plain.debug(dms.BUF_STATS, np.uint64)[8])
+        assert published > 256, (name, published)
+        ctx.set_option(dms.OPT_D1_HEAP_KEYS, published // 2)
+        out = ctx.diagram(ft)
+        st = ctx.debug(dms.BUF_STATS, np.uint64).tolist()
+        print(name, "published", published, "restarts", st[9], flush=True)
+        assert 1 <= st[9] <= 3, (name, st[9])
+        for d in range(3):
+            assert np.array_equal(out[d].cpu().numpy(), res.pairs[d]), (name, d)
+            assert np.array_equal(ref[d].cpu().numpy(), res.pairs[d]), (name, "plain", d)
+        off, edges = ctx.d1_generators()
+        d1 = out[1].cpu().numpy()
+        fin = d1[d1[:, 1] >= 0]
+        status = oracle.bf_check_cycles(res.shape, res.rank, fin, off.cpu().numpy(), edges.cpu().numpy())
+        assert (status == 0).all(), (name, np.bincount(status))
+    with pytest.raises(dms.DmsError):
+        ctx.set_option(dms.OPT_D1_HEAP_KEYS, -1)
+    ctx.close()
+    plain.close()
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("variant", ["no_sandwich", "no_cache", "neither"])
 def test_parity_d1_ablation_variants(variant):
     """PairCriticalSimplices without the sandwich (every 2-saddle a column,
