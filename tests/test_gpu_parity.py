@@ -284,9 +284,8 @@ def test_parity_d1_every_deferral_pass():
 
 
 @pytest.mark.gpu
-@pytest.mark.skip(reason="D1 restart path: added after the GPU budget of its change was spent; it has not "
-                         "run on a GPU yet, and the restart is a suspect of the quarantined 512^3 noise "
-                         "fault, so its first run is a run of its own")
+@pytest.mark.skip(reason="not yet run on a GPU: the D1 restart it drives is a suspect of the quarantined "
+                         "512^3 noise fault, so its first run is a run of its own")
 def test_parity_d1_restart():
     """A publication heap smaller than the cached boundaries need (the
     context's debug option) makes D1 overflow it, grow it and run again from
