@@ -100,3 +100,26 @@ extern "C" int ls_host_gradient(int nx, int ny, int nz, const uint32_t* rank, ui
     return packed ? run<true>(nx, ny, nz, rank, offset, levels_mode, G, crit)
                   : run<false>(nx, ny, nz, rank, offset, levels_mode, G, crit);
 }
+
+// The rank sort's network (kSortNet16) against the 0-1 principle: a
+// comparator network sorts every input if it sorts every input of zeros and
+// ones, so all 2^16 of them are run. Returns the number that come out
+// unsorted.
+extern "C" int ls_host_sortnet_01() {
+    int bad = 0;
+    for (uint32_t bits = 0; bits < (1u << 16); ++bits) {
+        uint32_t a[16];
+        for (int i = 0; i < 16; ++i) a[i] = (bits >> i) & 1u;
+        for (int c = 0; c < kSortNet16.n; ++c) {
+            const uint32_t u = a[kSortNet16.a[c]], v = a[kSortNet16.b[c]];
+            a[kSortNet16.a[c]] = u < v ? u : v;
+            a[kSortNet16.b[c]] = u < v ? v : u;
+        }
+        for (int i = 0; i + 1 < 16; ++i)
+            if (a[i] > a[i + 1]) {
+                ++bad;
+                break;
+            }
+    }
+    return bad;
+}

@@ -12,6 +12,7 @@ checks cover:
   labels the kernel takes on larger grids (ranks shifted past 2^28 here);
 * minimum searches over more levels than a vertex has labels (the lanes of a
   wave pass the largest lower-star size among them);
+* the rank sort's comparator network on every input, by the 0-1 principle;
 * grids two vertices wide on each axis, where many neighbours are missing.
 """
 import ctypes
@@ -115,6 +116,13 @@ def test_fields_with_ties_and_smooth_fields(lib, seed):
         rank = oracle.vertex_order(f)
         for variant in (0, 2, 5):
             check_against_oracle(lib, shape, rank, **VARIANTS[variant])
+
+
+def test_rank_sorting_network_zero_one_principle(lib):
+    """The 16-key network behind the packed labels sorts all 2^16 inputs of
+    zeros and ones, so by the 0-1 principle it sorts every input."""
+    lib.ls_host_sortnet_01.restype = ctypes.c_int
+    assert lib.ls_host_sortnet_01() == 0
 
 
 def test_comparison_catches_a_wrong_order(lib):
